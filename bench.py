@@ -1,0 +1,258 @@
+"""Benchmark of the fused preconditioned GLBE step on one MI355X.
+
+Workload of the headline line: the square-duct flow on 64x64x64 (walls in y
+and z, periodic x) with F_x = F0 sin(2 pi y/Ly)(1 + cos(2 pi z/Lz)/2),
+F0 = 1e-5, nu = 0.131 (Ma ~ 0.01), FP32 deviation storage, gamma = 0.1.  One
+step = one fused stream-collide pass over all nodes (with the FP64 residual,
+mass and flow-rate reductions every 10th step).  Inputs are resident in HBM
+before the timed region.
+
+Prints ONE JSON line with MLUPS, the roofline of the step kernel (HIP events
+around every launch on the library's stream), and the FP64 CPU oracle timed on
+the host.  --extras adds time-to-residual (gamma sweep vs plain gamma = 1),
+256^3 throughput per storage type, the coupled MHD step and the adjoint.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_0809_4730_amd/csrc/kernels.hip", "paper_0809_4730_amd/csrc/collide.hpp",
+                  "paper_0809_4730_amd/csrc/common.hpp"]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes_per_node(storage_bytes, force_field, check_every, mhd=False):
+    """Bytes one node update must move: each population read once and written
+    once, the force field read once, and the FP64 velocity snapshot read and
+    written on every residual step."""
+    b = 2 * 19 * storage_bytes
+    if mhd:
+        b += 2 * 21 * 4 if storage_bytes == 4 else 2 * 21 * storage_bytes
+    if force_field:
+        b += 3 * (8 if storage_bytes == 8 else 4)
+    b += 2 * 3 * 8 / check_every
+    return b
+
+
+def make_sim(shape, storage, gamma, nu=0.131, F0=1e-5, bc=("periodic", "wall", "wall")):
+    import torch
+
+    import paper_0809_4730_amd as pkg
+    from paper_0809_4730_amd import inputs
+    dt = torch.float64 if storage == "f64" else torch.float32
+    F = torch.tensor(inputs.duct_force(shape, F0), dtype=dt, device="cuda")
+    s = pkg.default_rates(nu, gamma)
+    return pkg.Simulation(shape, bc, gamma, s, storage=storage, force=F)
+
+
+def measure(sim, steps, warmup):
+    """(MLUPS, wall seconds of the plain timed region, mean kernel us, event wall ms)."""
+    import torch
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    mean_us, ev_ms = sim.step_timed(steps)
+    return sim.N * steps / wall / 1e6, wall, mean_us, ev_ms
+
+
+def traffic_from_profiles(kernel_tag, khash):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, only if
+    it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        d = json.load(fh)
+    e = d.get(kernel_tag)
+    if not e or e.get("kernel_hash") != khash:
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(budget_s=12.0):
+    """The FP64 oracle (numpy) on the same duct workload, bounded sample."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import glbe
+    from paper_0809_4730_amd import inputs
+    shape = (64, 64, 64)
+    F = inputs.duct_force(shape)
+    fl = glbe.Flow(shape, ("periodic", "wall", "wall"), F, 0.1, glbe.rates(0.131, 0.1))
+    fl.step(1)
+    n, t0 = 0, time.perf_counter()
+    while True:
+        fl.step(1)
+        n += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or n >= 200:
+            break
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return {"value": round(64 ** 3 * n / el / 1e6, 4), "unit": "MLUPS", "cores": int(threads),
+            "kind": "oracle",
+            "sample": "%d steps of the 64^3 FP64 duct (numpy oracle, dense 19x19 transform); "
+                      "cores = BLAS threads" % n}
+
+
+def time_to_residual(shape, storage, gamma, tol, max_steps, mhd=None, **kw):
+    import torch
+    sim = make_sim(shape, storage, gamma, **kw) if mhd is None else mhd()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    try:
+        steps, r = sim.run_to_residual(tol, max_steps, poll_every=2000)
+        status = "ok" if steps > 0 else "not reached"
+    except Exception as e:  # unstable
+        steps, r, status = -1, float("nan"), "error: %s" % e
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    h = sim.history(64)
+    floor = float(h[:, 1].min()) if len(h) else float("nan")
+    return {"gamma": gamma, "storage": storage, "steps": int(steps), "wall_s": round(wall, 4),
+            "final_residual": r, "min_residual_seen": floor, "status": status, "steps_run": sim.t}
+
+
+def extras(args):
+    import numpy as np
+    import torch
+
+    import paper_0809_4730_amd as pkg
+    from paper_0809_4730_amd import inputs
+    out = {}
+    # time to residual 1e-8 on the 64^3 duct: gamma sweep vs plain gamma = 1 (FP64 and FP32)
+    tt = []
+    tt.append(time_to_residual((64, 64, 64), "f64", 1.0, 1e-8, 400000))
+    for g in (1.0, 0.5, 0.1, 0.05):
+        tt.append(time_to_residual((64, 64, 64), "f32", g, 1e-8, 400000))
+    out["time_to_residual_duct64"] = tt
+    ref = tt[0]
+    if ref["steps"] > 0:
+        for e in tt[1:]:
+            if e["steps"] > 0:
+                e["speedup_vs_f64_gamma1_wall"] = round(ref["wall_s"] / e["wall_s"], 3)
+                e["step_ratio_vs_f64_gamma1"] = round(ref["steps"] / e["steps"], 3)
+    # 256^3 throughput per storage type (kernel roofline at HBM scale)
+    big = []
+    for st, nb in (("f32", 4), ("bf16", 2), ("f16", 2), ("f64", 8)):
+        sim = make_sim((256, 256, 256), st, 1.0)
+        mlups, wall, us, _ = measure(sim, args.big_steps, 20)
+        bpn = algorithmic_bytes_per_node(nb, True, 10)
+        gbs = bpn * 256 ** 3 / (us * 1e-6) / 1e9
+        big.append({"storage": st, "MLUPS": round(mlups, 1), "kernel_us": round(us, 2),
+                    "alg_bytes_per_node": bpn, "achieved_GBs": round(gbs, 1),
+                    "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)})
+        del sim
+        torch.cuda.empty_cache()
+    out["duct256_throughput"] = big
+    # coupled MHD step on the Hartmann workload
+    cfg = inputs.HARTMANN
+    B0, chi = inputs.hartmann_parameters(10.0, 0.01, cfg["shape"][1], cfg["nu"], cfg["eta"])
+    mp = dict(gamma_m=cfg["gamma_m"], chi=chi, eta=cfg["eta"], B0=(0.0, B0, 0.0))
+
+    def hart(g=cfg["gamma"], gm=cfg["gamma_m"]):
+        mp2 = dict(mp, gamma_m=gm)
+        return pkg.Simulation(cfg["shape"], cfg["bc"], g, pkg.default_rates(cfg["nu"], g),
+                              storage="f32", force=cfg["F"], mhd=mp2)
+    sim = hart()
+    mlups, wall, us, _ = measure(sim, 1000, 100)
+    bpn = algorithmic_bytes_per_node(4, False, 10, mhd=True)
+    out["hartmann_mhd_step"] = {"shape": cfg["shape"], "MLUPS": round(mlups, 1),
+                                "kernel_us": round(us, 2), "alg_bytes_per_node": bpn,
+                                "achieved_GBs": round(bpn * sim.N / (us * 1e-6) / 1e9, 1)}
+    ttm = []
+    for g in (1.0, 0.1):
+        ttm.append(time_to_residual(None, "f32", g, 1e-8, 400000,
+                                    mhd=lambda g=g: hart(g, g)))
+    out["time_to_residual_hartmann_Ha10"] = ttm
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--big-steps", type=int, default=100)
+    ap.add_argument("--extras", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 256 MiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(got --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    import paper_0809_4730_amd as pkg
+    pkg.load_library()
+
+    shape, gamma, storage = (64, 64, 64), 0.1, "f32"
+    sim = make_sim(shape, storage, gamma)
+    mlups, wall, mean_us, ev_ms = measure(sim, args.steps, args.warmup)
+    N = sim.N
+    bpn = algorithmic_bytes_per_node(4, True, 10)
+    achieved = bpn * N / (mean_us * 1e-6) / 1e9
+    khash = kernel_hash()
+    traffic = traffic_from_profiles("glbe_step_f32_duct64", khash)
+    line = {
+        "metric": "MLUPS, % HBM roofline; wall time to 1e-8 residual, gamma<1 vs plain gamma=1",
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1000.0 * wall / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "square duct 64x64x64, D3Q19 preconditioned MRT-GLBE, "
+                               "spatially varying force F0=1e-5, nu=0.131, gamma=0.1, "
+                               "FP32 deviation storage, FP64 residual every 10 steps",
+                   "grid": list(shape), "gamma": gamma, "storage": storage},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "glbe_step<float>",
+                     "alg_bytes_per_node": bpn, "mean_kernel_us": round(mean_us, 3),
+                     "kernel_hash": khash},
+    }
+    del sim
+    torch.cuda.empty_cache()
+    if args.copy_probe:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_probe_bytes"] = src.numel() * 4
+        del src, dst
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline()
+    if args.extras:
+        line["extras"] = extras(args)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

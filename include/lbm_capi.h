@@ -1,0 +1,235 @@
+/*
+ * lbm_capi.h -- C ABI of the MI355X (gfx950) preconditioned GLBE library.
+ *
+ * What the library computes (Premnath, Pattison & Banerjee, "Steady state
+ * convergence acceleration of the generalized lattice Boltzmann equation with
+ * forcing term through preconditioning"):
+ *
+ *   * the preconditioned generalized (multiple-relaxation-time) lattice
+ *     Boltzmann equation with forcing on the D3Q19 lattice: effective collision
+ *     in moment space with gamma-preconditioned equilibrium moments, moment
+ *     source terms S^* = P_S S^ and preconditioned rates (Sec. 3, eqs.
+ *     ppostcollision, pstreaming, prelax_term, precondsourceterm), followed by
+ *     streaming along e_alpha (Sec. 2, eq. streaming);
+ *   * optionally coupled to the preconditioned, chi-scaled vector lattice
+ *     kinetic equation for the magnetic induction on the D3Q7 lattice, whose
+ *     Lorentz force J x B enters the GLBE force (Sec. 4, Sec. 4.1);
+ *   * the steady-state residual ||u(t) - u(t-10)||_2 (Sec. 5), relative, in FP64;
+ *   * FP64 global mass and flow-rate reductions;
+ *   * a discrete adjoint of the step for d(steady flow rate)/d(force field).
+ *
+ * Conventions (all entry points):
+ *   - Every function returns an lbm_status; no exception crosses the ABI.
+ *   - Device memory is owned by the caller.  The library allocates no device
+ *     memory: the caller provides one workspace (size from lbm_workspace_bytes)
+ *     and, for the adjoint, one adjoint workspace.  The library owns only the
+ *     host-side context object.
+ *   - All device work is enqueued on the caller's HIP stream given at
+ *     lbm_create.  Calls documented as "synchronizes" wait for that stream.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ *   - Grid layout: nodes are indexed (x, y, z) with x the unit-stride axis,
+ *     linear index n = x + nx*(y + ny*z), N = nx*ny*nz.  Population arrays
+ *     exchanged through the ABI are structure-of-arrays [q][N] (direction
+ *     outermost, unpadded).  Every node is a fluid node: walls sit half a
+ *     link outside the first and last node of a wall axis (halfway
+ *     bounce-back, Sec. 5).
+ *   - State: the stored populations are the post-collision values of the last
+ *     completed step, held as deviations from the rest state,
+ *     f~_alpha - w_alpha rho0.  The hydrodynamic fields "at the current time"
+ *     are those of the streamed populations, i.e. of the next collision.
+ *   - Direction ordering is given by lbm_lattice_velocities.
+ */
+#ifndef LBM_CAPI_H
+#define LBM_CAPI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,     /* invalid argument (message in lbm_last_error)            */
+  LBM_ENOWS = -2,      /* workspace missing, misaligned or too small              */
+  LBM_EHIP = -3,       /* a HIP runtime call failed (hipGetErrorString text kept) */
+  LBM_EUNSTABLE = -4,  /* non-finite values or residual blow-up detected          */
+  LBM_ESTATE = -5,     /* call not valid in the context's current state           */
+  LBM_EUNSUPPORTED = -6 /* valid request this build does not implement            */
+} lbm_status;
+
+/* Population storage type.  F64 storage computes in FP64; F32, BF16 and F16
+ * storage compute in FP32 (deviation storage, round-to-nearest-even on store). */
+typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_BF16 = 2, LBM_F16 = 3 } lbm_dtype;
+
+/* Per-axis boundary: periodic wrap, or a no-slip wall on both faces of the axis
+ * (halfway/link bounce-back for the flow, Sec. 5; anti-bounce-back Dirichlet
+ * B = B0 for the magnetic populations). */
+typedef enum { LBM_PERIODIC = 0, LBM_WALL = 1 } lbm_bc;
+
+typedef enum { LBM_FORCE_UNIFORM = 0, LBM_FORCE_FIELD = 1 } lbm_force_mode;
+
+typedef struct {
+  int32_t n[3];   /* nx, ny, nz >= 1; N = nx*ny*nz < 2^31 */
+  int32_t bc[3];  /* lbm_bc per axis */
+} lbm_grid;
+
+typedef struct {
+  int32_t storage;        /* lbm_dtype */
+  double gamma;           /* preconditioning parameter, 0 < gamma <= 1 (Sec. 3) */
+  double s[19];           /* preconditioned rates s*_k in moment order (Sec. 3);
+                             entries 0, 3, 5, 7 (conserved moments) are ignored;
+                             the others must lie in (0, 2).  lbm_default_rates fills them. */
+  double rho0;            /* reference density (1.0) */
+  int32_t force_mode;     /* lbm_force_mode */
+  double force_const[3];  /* uniform force (force_mode = UNIFORM) */
+  int32_t mhd;            /* 1: couple the D3Q7 vector induction LKE (Sec. 4) */
+  double gamma_m;         /* induction preconditioning parameter, 0 < gamma_m <= 1 */
+  double chi;             /* low-Pm scaling factor chi > 0 (Sec. 4.1) */
+  double eta;             /* magnetic diffusivity; tau_m* = eta/(gamma_m theta_m) + 1/2 */
+  double mu;              /* magnetic permeability (1 in lattice units) */
+  double B0[3];           /* applied field: initial state and wall value */
+  int32_t check_every;    /* residual / reductions every this many steps (10) */
+  int32_t history_len;    /* entries of the device residual history ring (>= 1) */
+} lbm_params;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* One residual-history record (all FP64), written on device every
+ * check_every steps.  residual = sqrt(du2 / u2), with du2 = sum |u(t)-u(t-k)|^2
+ * and u2 = sum |u(t)|^2 over all nodes and components (u(t-k) = 0 at the
+ * first check).  mass = sum (rho - rho0); flow = (1/nx) sum j_x (j includes
+ * F/(2 gamma)); nonfinite = count of nodes with a non-finite rho or j.  All of
+ * these are taken from the populations entering the collision of `step`. */
+typedef struct {
+  double step, residual, du2, u2, mass, flow, nonfinite, reserved;
+} lbm_record;
+
+/* Fill s_out[19] with the preconditioned D3Q19 rates of Sec. 3:
+ * shear modes 9, 11, 13, 14, 15: 1/s = 3 nu/gamma + 1/2; s1 = 1.19,
+ * s2 = s10 = s12 = 1.4; mode 0 ("paper"): s4 = s6 = s8 = 1.2, s16..18 = 1.98;
+ * mode 1 ("fixed Lambda"): s4 = s6 = s8 = s16 = s17 = s18 = s_q with
+ * (3 nu/gamma)(1/s_q - 1/2) = Lambda.  Conserved entries are set to 1.
+ * Errors: LBM_EINVAL for nu <= 0, gamma outside (0,1], Lambda <= 0 in mode 1. */
+lbm_status lbm_default_rates(double nu, double gamma, int32_t mode, double Lambda,
+                             double s_out[19]);
+
+/* Velocity set in the library's direction order: q = 19 (D3Q19, flow) or q = 7
+ * (D3Q7, induction); writes q*3 integers (ex, ey, ez per direction) to e_out
+ * (host memory).  Errors: LBM_EINVAL for another q or a NULL pointer. */
+lbm_status lbm_lattice_velocities(int32_t q, int32_t* e_out);
+
+/* Bytes of device workspace lbm_create needs for this grid and parameter set
+ * (host pointers in, host size_t out).  The workspace must be 256-byte aligned. */
+lbm_status lbm_workspace_bytes(const lbm_grid* grid, const lbm_params* params, size_t* bytes);
+
+/* Validate, lay out the workspace, initialise the rest state (populations
+ * f = w rho0, i.e. zero deviations; magnetic g = W B0, Sec. 4) and, for
+ * force_mode = FIELD, copy the force field (device pointer `force`, layout
+ * [3][N], FP64 for F64 storage, FP32 otherwise) into the workspace.
+ * `workspace` is a device pointer owned by the caller that must outlive the
+ * context; `hip_stream` is a hipStream_t (NULL = default stream).
+ * Errors: LBM_EINVAL (grid, rates, gamma, mhd parameters, unsupported
+ * combination), LBM_ENOWS, LBM_EHIP.  On error *out is NULL and the message
+ * is available from lbm_last_error(NULL). */
+lbm_status lbm_create(const lbm_grid* grid, const lbm_params* params, const void* force,
+                      void* workspace, size_t workspace_bytes, void* hip_stream,
+                      lbm_ctx** out);
+
+/* Release the host-side context (no device memory is freed). */
+void lbm_destroy(lbm_ctx* ctx);
+
+/* Replace the force field (device pointer, [3][N] in the compute type); only
+ * for force_mode = FIELD (else LBM_ESTATE).  Enqueued on the stream. */
+lbm_status lbm_set_force(lbm_ctx* ctx, const void* force);
+
+/* Enqueue n >= 0 time steps (stream, then collide).  Every check_every-th
+ * step also writes one lbm_record to the device history ring.  Asynchronous:
+ * does not synchronize and does not report instability (see lbm_residual). */
+lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
+
+/* Like lbm_step, but brackets every step kernel with HIP events on the stream,
+ * synchronizes, and returns the mean kernel duration in microseconds (events
+ * measure the kernel alone, not launch gaps) and the wall time of the whole
+ * call in milliseconds. */
+lbm_status lbm_step_timed(lbm_ctx* ctx, int64_t n, double* mean_kernel_us, double* wall_ms);
+
+/* Latest history record: residual and the step it was taken at.  Synchronizes.
+ * Returns LBM_ESTATE if no check has run yet, LBM_EUNSTABLE (after filling
+ * the outputs) if that record counted non-finite values. */
+lbm_status lbm_residual(lbm_ctx* ctx, double* residual, int64_t* at_step);
+
+/* Copy up to max_records most recent history records, oldest first, to host
+ * memory `out`; *n_out receives the count.  Synchronizes. */
+lbm_status lbm_history(lbm_ctx* ctx, lbm_record* out, int64_t max_records, int64_t* n_out);
+
+/* March until a record has residual < tol (finite), or max_steps steps have
+ * been taken in this call.  Steps are enqueued in chunks of at most
+ * poll_every steps (rounded to check_every) and the history is read after
+ * each chunk, so the crossing step is exact but up to one chunk of extra
+ * steps may run after it.  *steps_to_tol = step count (since create) of the
+ * first record below tol, or -1; *final_residual = that record's residual
+ * (or the last one).  Returns LBM_EUNSTABLE on non-finite values or when the
+ * residual exceeds 1e3 times its running minimum.  Synchronizes. */
+lbm_status lbm_run_to_residual(lbm_ctx* ctx, double tol, int64_t max_steps, int64_t poll_every,
+                               int64_t* steps_to_tol, double* final_residual);
+
+/* FP64 mass drift sum(rho - rho0) and flow rate (1/nx) sum j_x of the
+ * current state (streamed populations; j includes F/(2 gamma); with mhd the
+ * Lorentz force is included).  Synchronizes. */
+lbm_status lbm_reductions(lbm_ctx* ctx, double* mass_drift, double* flow_rate);
+
+/* Hydrodynamic fields of the current state into caller device buffers:
+ * rho [N], u [3][N] (physical velocity, F/(2 gamma) included), B [3][N]
+ * (mhd only; may be NULL).  out_dtype is LBM_F64 or LBM_F32.  Enqueued. */
+lbm_status lbm_moments(lbm_ctx* ctx, int32_t out_dtype, void* rho, void* u, void* B);
+
+/* Number of bytes of the state blob: populations [19][N] in the storage type,
+ * followed (mhd) by the magnetic populations [3][7][N] (field component
+ * outermost) in the compute type. */
+lbm_status lbm_state_bytes(const lbm_ctx* ctx, size_t* bytes);
+
+/* Copy the state blob to / from caller device memory, and read / set the step
+ * counter.  lbm_set_state also clears the residual snapshot and history. */
+lbm_status lbm_get_state(lbm_ctx* ctx, void* dst);
+lbm_status lbm_set_state(lbm_ctx* ctx, const void* src, int64_t step);
+lbm_status lbm_get_step(const lbm_ctx* ctx, int64_t* step);
+
+/* ---------------------------------------------------------------- adjoint ---
+ * Discrete adjoint of one step Phi(f~; F) = Collide(Stream(f~); F) for the
+ * flow rate Q = (1/nx) sum_x j_x of the streamed state (F64 or F32 storage,
+ * no mhd; LBM_EUNSUPPORTED otherwise).  Gradients are written to a caller
+ * device buffer dQdF [3][N] in the compute type. */
+
+/* Adjoint workspace bytes.  mode 0: steady (fixed-point) adjoint;
+ * mode 1: unrolled over n_steps with a checkpoint every ckpt_every steps. */
+lbm_status lbm_adjoint_workspace_bytes(const lbm_ctx* ctx, int32_t mode, int64_t n_steps,
+                                       int64_t ckpt_every, size_t* bytes);
+
+/* Steady adjoint at the current state (meant to be a converged steady state):
+ * iterates the transposed linearised step to its own fixed point (relative
+ * change of the adjoint below tol, checked every check_every iterations, at
+ * most max_iter iterations), then writes dQ/dF.  The mass direction, along
+ * which the steady state is not unique, is projected out.  Synchronizes. */
+lbm_status lbm_adjoint_steady(lbm_ctx* ctx, void* adj_ws, size_t adj_ws_bytes, double tol,
+                              int64_t max_iter, void* dQdF, int64_t* iters,
+                              double* final_change);
+
+/* Unrolled adjoint: marches n_steps forward from the current state
+ * (the state advances, as lbm_step would, storing a checkpoint every
+ * ckpt_every steps), then sweeps backwards recomputing each segment from its
+ * checkpoint, and writes dQ_N/dF for Q_N = Q of the state after n_steps.
+ * Synchronizes. */
+lbm_status lbm_adjoint_unrolled(lbm_ctx* ctx, void* adj_ws, size_t adj_ws_bytes, int64_t n_steps,
+                                int64_t ckpt_every, void* dQdF);
+
+/* Text of the last error on ctx, or (ctx = NULL) of the last failed
+ * lbm_create on this thread.  Never NULL. */
+const char* lbm_last_error(const lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_CAPI_H */

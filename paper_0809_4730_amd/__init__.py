@@ -1,0 +1,374 @@
+"""MI355X-native preconditioned generalized lattice Boltzmann equation with forcing.
+
+Thin Python binding of the C ABI in ``include/lbm_capi.h`` (``liblbm.so``,
+hand-written HIP kernels for gfx950).  This module only marshals arguments:
+every step of the computation runs in the library's kernels.  PyTorch supplies
+device memory (the workspace and the caller's buffers) and the HIP stream.
+
+The library must be built (``paper_0809_4730_amd.build.build()``); if it is
+missing, loading fails with an error instead of falling back to anything else.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = ["Simulation", "default_rates", "lattice_velocities", "LbmError", "library_path",
+           "load_library", "F64", "F32", "BF16", "F16", "PERIODIC", "WALL"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liblbm.so")
+
+F64, F32, BF16, F16 = 0, 1, 2, 3
+PERIODIC, WALL = 0, 1
+_DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "f16": F16}
+_STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOWS", -3: "LBM_EHIP", -4: "LBM_EUNSTABLE",
+           -5: "LBM_ESTATE", -6: "LBM_EUNSUPPORTED"}
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s: %s" % (_STATUS.get(status, status), message))
+        self.status = status
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("bc", ctypes.c_int32 * 3)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("storage", ctypes.c_int32),
+        ("gamma", ctypes.c_double),
+        ("s", ctypes.c_double * 19),
+        ("rho0", ctypes.c_double),
+        ("force_mode", ctypes.c_int32),
+        ("force_const", ctypes.c_double * 3),
+        ("mhd", ctypes.c_int32),
+        ("gamma_m", ctypes.c_double),
+        ("chi", ctypes.c_double),
+        ("eta", ctypes.c_double),
+        ("mu", ctypes.c_double),
+        ("B0", ctypes.c_double * 3),
+        ("check_every", ctypes.c_int32),
+        ("history_len", ctypes.c_int32),
+    ]
+
+
+class _Record(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in
+                ("step", "residual", "du2", "u2", "mass", "flow", "nonfinite", "reserved")]
+
+
+_lib = None
+
+
+def library_path():
+    return _LIB_PATH
+
+
+def load_library():
+    """Load liblbm.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError("liblbm.so is not built (expected at %s); run "
+                           "paper_0809_4730_amd.build.build()" % _LIB_PATH)
+    lib = ctypes.CDLL(_LIB_PATH)
+    c_int32, c_int64, c_double, c_size_t, c_void_p = (ctypes.c_int32, ctypes.c_int64,
+                                                      ctypes.c_double, ctypes.c_size_t,
+                                                      ctypes.c_void_p)
+    P = ctypes.POINTER
+    sig = {
+        "lbm_default_rates": [c_double, c_double, c_int32, c_double, P(c_double)],
+        "lbm_lattice_velocities": [c_int32, P(c_int32)],
+        "lbm_workspace_bytes": [P(_Grid), P(_Params), P(c_size_t)],
+        "lbm_create": [P(_Grid), P(_Params), c_void_p, c_void_p, c_size_t, c_void_p, P(c_void_p)],
+        "lbm_set_force": [c_void_p, c_void_p],
+        "lbm_step": [c_void_p, c_int64],
+        "lbm_step_timed": [c_void_p, c_int64, P(c_double), P(c_double)],
+        "lbm_residual": [c_void_p, P(c_double), P(c_int64)],
+        "lbm_history": [c_void_p, P(_Record), c_int64, P(c_int64)],
+        "lbm_run_to_residual": [c_void_p, c_double, c_int64, c_int64, P(c_int64), P(c_double)],
+        "lbm_reductions": [c_void_p, P(c_double), P(c_double)],
+        "lbm_moments": [c_void_p, c_int32, c_void_p, c_void_p, c_void_p],
+        "lbm_state_bytes": [c_void_p, P(c_size_t)],
+        "lbm_get_state": [c_void_p, c_void_p],
+        "lbm_set_state": [c_void_p, c_void_p, c_int64],
+        "lbm_get_step": [c_void_p, P(c_int64)],
+        "lbm_adjoint_workspace_bytes": [c_void_p, c_int32, c_int64, c_int64, P(c_size_t)],
+        "lbm_adjoint_steady": [c_void_p, c_void_p, c_size_t, c_double, c_int64, c_void_p,
+                               P(c_int64), P(c_double)],
+        "lbm_adjoint_unrolled": [c_void_p, c_void_p, c_size_t, c_int64, c_int64, c_void_p],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = c_int32
+    lib.lbm_destroy.argtypes = [c_void_p]
+    lib.lbm_destroy.restype = None
+    lib.lbm_last_error.argtypes = [c_void_p]
+    lib.lbm_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status, ctx=None):
+    if status != 0:
+        lib = load_library()
+        raise LbmError(status, lib.lbm_last_error(ctx).decode())
+
+
+def default_rates(nu, gamma, mode="paper", Lambda=1.0):
+    """Preconditioned D3Q19 rates (see lbm_default_rates)."""
+    lib = load_library()
+    out = (ctypes.c_double * 19)()
+    _check(lib.lbm_default_rates(nu, gamma, 0 if mode == "paper" else 1, Lambda, out))
+    return np.array(list(out))
+
+
+def lattice_velocities(q=19):
+    lib = load_library()
+    out = (ctypes.c_int32 * (3 * q))()
+    _check(lib.lbm_lattice_velocities(q, out))
+    return np.array(list(out), dtype=np.int64).reshape(q, 3)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _state_torch_dtype(storage):
+    torch = _torch()
+    return {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16, F16: torch.float16}[storage]
+
+
+def _compute_torch_dtype(storage):
+    torch = _torch()
+    return torch.float64 if storage == F64 else torch.float32
+
+
+class Simulation:
+    """One lattice on one GPU.
+
+    shape: (nx, ny, nz), x the unit-stride axis.  bc: three of "periodic"/"wall".
+    s: 19 preconditioned rates (default_rates).  storage: "f64", "f32", "bf16", "f16".
+    force: a 3-vector (uniform) or a device tensor (3, nz, ny, nx) in the compute
+    dtype (float64 for f64 storage, float32 otherwise).
+    mhd: None or dict(gamma_m=, chi=, eta=, B0=(..), mu=1.0).
+    """
+
+    def __init__(self, shape, bc, gamma, s, storage="f32", force=(0.0, 0.0, 0.0), rho0=1.0,
+                 mhd=None, check_every=10, history_len=4096, device="cuda", stream=None):
+        torch = _torch()
+        self._lib = load_library()
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device(self.device.type, torch.cuda.current_device())
+        self.shape = tuple(int(v) for v in shape)
+        self.storage = _DTYPES[storage] if isinstance(storage, str) else int(storage)
+        self._grid = _Grid()
+        for a in range(3):
+            self._grid.n[a] = self.shape[a]
+            b = bc[a]
+            self._grid.bc[a] = (WALL if b in ("wall", WALL) else PERIODIC)
+        p = _Params()
+        p.storage = self.storage
+        p.gamma = gamma
+        for k in range(19):
+            p.s[k] = float(s[k])
+        p.rho0 = rho0
+        self._force_tensor = None
+        if torch.is_tensor(force):
+            p.force_mode = 1
+            nx, ny, nz = self.shape
+            want = (3, nz, ny, nx)
+            if tuple(force.shape) != want:
+                raise ValueError("force field must have shape %s" % (want,))
+            if force.dtype != _compute_torch_dtype(self.storage) or force.device != self.device:
+                raise ValueError("force field must be a %s tensor on %s"
+                                 % (_compute_torch_dtype(self.storage), self.device))
+            self._force_tensor = force.contiguous()
+        else:
+            p.force_mode = 0
+            for a in range(3):
+                p.force_const[a] = float(force[a])
+        if mhd:
+            p.mhd = 1
+            p.gamma_m = mhd["gamma_m"]
+            p.chi = mhd["chi"]
+            p.eta = mhd["eta"]
+            p.mu = mhd.get("mu", 1.0)
+            for a in range(3):
+                p.B0[a] = float(mhd["B0"][a])
+        p.check_every = check_every
+        p.history_len = history_len
+        self._params = p
+        self.gamma = gamma
+        nbytes = ctypes.c_size_t()
+        _check(self._lib.lbm_workspace_bytes(ctypes.byref(self._grid), ctypes.byref(p),
+                                             ctypes.byref(nbytes)))
+        raw = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        base = raw.data_ptr()
+        off = (-base) % 256
+        self._ws_raw = raw
+        self._ws_ptr = base + off
+        self._ws_bytes = nbytes.value
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self._stream = stream
+        ctx = ctypes.c_void_p()
+        fptr = self._force_tensor.data_ptr() if self._force_tensor is not None else None
+        _check(self._lib.lbm_create(ctypes.byref(self._grid), ctypes.byref(p), fptr,
+                                    self._ws_ptr, self._ws_bytes, stream.cuda_stream,
+                                    ctypes.byref(ctx)))
+        self._ctx = ctx
+
+    # ----------------------------------------------------------- lifetime
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.lbm_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _c(self, status):
+        _check(status, self._ctx)
+
+    @property
+    def N(self):
+        nx, ny, nz = self.shape
+        return nx * ny * nz
+
+    # ------------------------------------------------------------- march
+    def step(self, n=1):
+        self._c(self._lib.lbm_step(self._ctx, int(n)))
+        return self
+
+    def step_timed(self, n):
+        us, ms = ctypes.c_double(), ctypes.c_double()
+        self._c(self._lib.lbm_step_timed(self._ctx, int(n), ctypes.byref(us), ctypes.byref(ms)))
+        return us.value, ms.value
+
+    def residual(self):
+        r, t = ctypes.c_double(), ctypes.c_int64()
+        self._c(self._lib.lbm_residual(self._ctx, ctypes.byref(r), ctypes.byref(t)))
+        return r.value, t.value
+
+    def history(self, max_records=None):
+        cap = self._params.history_len if max_records is None else int(max_records)
+        buf = (_Record * cap)()
+        n = ctypes.c_int64()
+        self._c(self._lib.lbm_history(self._ctx, buf, cap, ctypes.byref(n)))
+        return np.array([[getattr(buf[i], k) for k, _ in _Record._fields_]
+                         for i in range(n.value)]).reshape(n.value, 8)
+
+    def run_to_residual(self, tol, max_steps, poll_every=2000):
+        steps, r = ctypes.c_int64(), ctypes.c_double()
+        self._c(self._lib.lbm_run_to_residual(self._ctx, tol, int(max_steps), int(poll_every),
+                                              ctypes.byref(steps), ctypes.byref(r)))
+        return steps.value, r.value
+
+    @property
+    def t(self):
+        s = ctypes.c_int64()
+        self._c(self._lib.lbm_get_step(self._ctx, ctypes.byref(s)))
+        return s.value
+
+    # ------------------------------------------------------------ fields
+    def reductions(self):
+        m, q = ctypes.c_double(), ctypes.c_double()
+        self._c(self._lib.lbm_reductions(self._ctx, ctypes.byref(m), ctypes.byref(q)))
+        return m.value, q.value
+
+    def moments(self, dtype="f64"):
+        """(rho, u, B) device tensors of the current state; B is None without mhd."""
+        torch = _torch()
+        nx, ny, nz = self.shape
+        td = torch.float64 if dtype == "f64" else torch.float32
+        rho = torch.empty((nz, ny, nx), dtype=td, device=self.device)
+        u = torch.empty((3, nz, ny, nx), dtype=td, device=self.device)
+        B = torch.empty((3, nz, ny, nx), dtype=td, device=self.device) if self._params.mhd else None
+        self._c(self._lib.lbm_moments(self._ctx, F64 if dtype == "f64" else F32, rho.data_ptr(),
+                                      u.data_ptr(), B.data_ptr() if B is not None else None))
+        return rho, u, B
+
+    def set_force(self, force):
+        force = force.contiguous()
+        self._force_tensor = force
+        self._c(self._lib.lbm_set_force(self._ctx, force.data_ptr()))
+
+    # ------------------------------------------------------------- state
+    def get_state(self):
+        """Populations (19, nz, ny, nx) in the storage dtype, plus (mhd) the
+        magnetic populations (3, 7, nz, ny, nx); deviations from the rest state."""
+        torch = _torch()
+        nx, ny, nz = self.shape
+        f = torch.empty((19, nz, ny, nx), dtype=_state_torch_dtype(self.storage), device=self.device)
+        if self._params.mhd:
+            blob = torch.empty(19 * self.N * f.element_size() + 21 * self.N * f.element_size(),
+                               dtype=torch.uint8, device=self.device)
+            self._c(self._lib.lbm_get_state(self._ctx, blob.data_ptr()))
+            nf = 19 * self.N * f.element_size()
+            f = blob[:nf].view(f.dtype).reshape(19, nz, ny, nx)
+            g = blob[nf:].view(f.dtype).reshape(3, 7, nz, ny, nx)
+            return f, g
+        self._c(self._lib.lbm_get_state(self._ctx, f.data_ptr()))
+        return f
+
+    def set_state(self, f, g=None, step=0):
+        torch = _torch()
+        if self._params.mhd:
+            if g is None:
+                raise ValueError("mhd state needs g")
+            blob = torch.cat([f.contiguous().view(torch.uint8).reshape(-1),
+                              g.contiguous().view(torch.uint8).reshape(-1)])
+            self._c(self._lib.lbm_set_state(self._ctx, blob.data_ptr(), int(step)))
+            torch.cuda.current_stream(self.device).synchronize()
+            return
+        f = f.contiguous()
+        if f.dtype != _state_torch_dtype(self.storage):
+            raise ValueError("state dtype must be %s" % _state_torch_dtype(self.storage))
+        self._c(self._lib.lbm_set_state(self._ctx, f.data_ptr(), int(step)))
+
+    # ----------------------------------------------------------- adjoint
+    def _adj_ws(self, mode, n_steps=0, ckpt_every=1):
+        torch = _torch()
+        nbytes = ctypes.c_size_t()
+        self._c(self._lib.lbm_adjoint_workspace_bytes(self._ctx, mode, int(n_steps),
+                                                      int(ckpt_every), ctypes.byref(nbytes)))
+        raw = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        return raw, raw.data_ptr() + off, nbytes.value
+
+    def adjoint_steady(self, tol=1e-8, max_iter=10 ** 6):
+        """dQ/dF (3, nz, ny, nx) of the steady flow rate at the current state."""
+        torch = _torch()
+        raw, ptr, nbytes = self._adj_ws(0)
+        nx, ny, nz = self.shape
+        grad = torch.empty((3, nz, ny, nx), dtype=_compute_torch_dtype(self.storage),
+                           device=self.device)
+        iters, change = ctypes.c_int64(), ctypes.c_double()
+        self._c(self._lib.lbm_adjoint_steady(self._ctx, ptr, nbytes, tol, int(max_iter),
+                                             grad.data_ptr(), ctypes.byref(iters),
+                                             ctypes.byref(change)))
+        del raw
+        return grad, iters.value, change.value
+
+    def adjoint_unrolled(self, n_steps, ckpt_every):
+        """Advance n_steps and return dQ_N/dF (3, nz, ny, nx)."""
+        torch = _torch()
+        raw, ptr, nbytes = self._adj_ws(1, n_steps, ckpt_every)
+        nx, ny, nz = self.shape
+        grad = torch.empty((3, nz, ny, nx), dtype=_compute_torch_dtype(self.storage),
+                           device=self.device)
+        self._c(self._lib.lbm_adjoint_unrolled(self._ctx, ptr, nbytes, int(n_steps),
+                                               int(ckpt_every), grad.data_ptr()))
+        del raw
+        return grad

@@ -1,0 +1,471 @@
+// Discrete adjoint of the preconditioned GLBE step, for the gradient of the
+// flow rate Q = (1/nx) sum_x j_x with respect to the force field.
+//
+// Forward step on the stored post-collision state p:  f = S p (pull
+// streaming), p' = C(f; F) (collision).  Q is taken from f = S p.  The
+// adjoint is carried in the pre-collision variable mu (one 19-vector per node)
+// so that one kernel pass is a gather, like the forward step:
+//
+//   lam(x)    = (S^T mu)(x):  lam_b(x) = mu_b(x + e_b), or mu_opp(b)(x) when the
+//               link x -> x + e_b crosses a wall (the transpose of halfway
+//               bounce-back), periodic wrap otherwise;
+//   mu'(x)    = C_f(x)^T lam(x) + q,        q_a = e_ax / nx  (dQ/df);
+//   dQ/dF(x)  = C_F(x)^T lam(x) + x_hat / (2 gamma nx),
+//
+// with C_f, C_F the local Jacobians of the collision at f(x) = (S p*)(x),
+// recomputed from the forward state in the same pass (collide19_adjoint).
+//
+// Steady adjoint: iterate mu' = C_f^T S^T mu + q at the converged state.  The
+// step conserves mass, so 1 is an eigenvector of C_f^T S^T with eigenvalue 1
+// and C_F^T 1 = 0: the mean of mu drifts linearly without changing the
+// gradient.  The mean is removed every check and convergence is measured on
+// the gradient field itself.
+//
+// Unrolled adjoint over N steps from p_0: mu_{N+1} = q; for n = N..1,
+// lam_n = S^T mu_{n+1}, mu_n = C_f(f_n)^T lam_n, dQ/dF += C_F(f_n)^T lam_n with
+// f_n = S p_{n-1}; forward states are recomputed segment by segment from
+// checkpoints.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "collide.hpp"
+#include "ctx.hpp"
+
+namespace lbm {
+
+// ---------------------------------------------------------------- kernels --
+struct AdjNbr {
+  int32_t xm, xp, ym, yp, zm, zp;
+  bool bxm, bxp, bym, byp, bzm, bzp;
+};
+
+__device__ __forceinline__ AdjNbr adj_neighbours(const GridArgs& g, uint32_t n, int& x, int& y,
+                                                 int& z) {
+  const uint32_t yz = fdiv(n, g.div_nx);
+  const uint32_t zz = fdiv(n, g.div_nxny);
+  x = static_cast<int>(n - yz * static_cast<uint32_t>(g.nx));
+  y = static_cast<int>(yz - zz * static_cast<uint32_t>(g.ny));
+  z = static_cast<int>(zz);
+  const int sy = g.nx, sz = g.nx * g.ny;
+  AdjNbr b;
+  b.xm = (x == 0) ? (g.nx - 1) : -1;
+  b.xp = (x == g.nx - 1) ? -(g.nx - 1) : 1;
+  b.ym = (y == 0) ? (g.ny - 1) * sy : -sy;
+  b.yp = (y == g.ny - 1) ? -(g.ny - 1) * sy : sy;
+  b.zm = (z == 0) ? (g.nz - 1) * sz : -sz;
+  b.zp = (z == g.nz - 1) ? -(g.nz - 1) * sz : sz;
+  b.bxm = g.wall_x && x == 0;
+  b.bxp = g.wall_x && x == g.nx - 1;
+  b.bym = g.wall_y && y == 0;
+  b.byp = g.wall_y && y == g.ny - 1;
+  b.bzm = g.wall_z && z == 0;
+  b.bzp = g.wall_z && z == g.nz - 1;
+  return b;
+}
+
+// Offset to x - e (forward pull source) and whether that link crosses a wall.
+template <int EX, int EY, int EZ>
+__device__ __forceinline__ bool adj_link(const AdjNbr& b, int32_t& off) {
+  off = (EX > 0 ? b.xm : EX < 0 ? b.xp : 0) + (EY > 0 ? b.ym : EY < 0 ? b.yp : 0) +
+        (EZ > 0 ? b.zm : EZ < 0 ? b.zp : 0);
+  return (EX > 0 && b.bxm) || (EX < 0 && b.bxp) || (EY > 0 && b.bym) || (EY < 0 && b.byp) ||
+         (EZ > 0 && b.bzm) || (EZ < 0 && b.bzp);
+}
+
+template <typename R, int A = 0>
+__device__ __forceinline__ void gather_fwd(const R* __restrict__ p, int64_t st, uint32_t n,
+                                           const AdjNbr& b, R (&f)[Q19]) {
+  if constexpr (A < Q19) {
+    int32_t off;
+    const bool bb = adj_link<EX19[A], EY19[A], EZ19[A]>(b, off);
+    const int64_t idx = bb ? int64_t(OPP19(A)) * st + n : int64_t(A) * st + int64_t(n) + off;
+    f[A] = p[idx];
+    gather_fwd<R, A + 1>(p, st, n, b, f);
+  }
+}
+
+// lam_b(x) = mu_b(x + e_b), or mu_opp(b)(x) if that link crosses a wall.
+template <typename R, int A = 0>
+__device__ __forceinline__ void gather_transpose(const R* __restrict__ mu, int64_t st, uint32_t n,
+                                                 const AdjNbr& b, R shift, R (&lam)[Q19]) {
+  if constexpr (A < Q19) {
+    int32_t off;
+    const bool bb = adj_link<-EX19[A], -EY19[A], -EZ19[A]>(b, off);
+    const int64_t idx = bb ? int64_t(OPP19(A)) * st + n : int64_t(A) * st + int64_t(n) + off;
+    lam[A] = mu[idx] - shift;
+    gather_transpose<R, A + 1>(mu, st, n, b, shift, lam);
+  }
+}
+
+// GRAD: 0 none, 1 accumulate into grad, 2 overwrite grad (with the direct term)
+// and accumulate the change against its previous content.
+template <typename R, bool CHECK, int GRAD, bool FIELD>
+__global__ __launch_bounds__(kBlock) void adjoint_step(
+    GridArgs g, CollideArgs<R> c, const R* __restrict__ state, const R* __restrict__ force,
+    const R* __restrict__ mu_in, R* __restrict__ mu_out, R* __restrict__ grad,
+    int64_t grad_stride, const double* __restrict__ shift, R q_scale, R grad_direct,
+    double* __restrict__ partials) {
+  const int lb = logical_block(g);
+  if (lb >= g.nblocks) return;
+  const uint32_t n = static_cast<uint32_t>(lb) * kBlock + threadIdx.x;
+  double acc[kPartials] = {0, 0, 0, 0, 0, 0};
+  if (n < static_cast<uint32_t>(g.N)) {
+    int x, y, z;
+    const AdjNbr b = adj_neighbours(g, n, x, y, z);
+    R f[Q19];
+    gather_fwd<R>(state, g.stride, n, b, f);
+    const R sh = shift ? R(*shift) : R(0);
+    R lam[Q19];
+    gather_transpose<R>(mu_in, g.stride, n, b, sh, lam);
+    R Fx, Fy, Fz;
+    if (FIELD) {
+      Fx = force[n];
+      Fy = force[g.stride + n];
+      Fz = force[2 * g.stride + n];
+    } else {
+      Fx = c.F[0];
+      Fy = c.F[1];
+      Fz = c.F[2];
+    }
+    R nu[Q19], gx, gy, gz;
+    collide19_adjoint<R>(f, Fx, Fy, Fz, c, lam, nu, gx, gy, gz);
+#pragma unroll
+    for (int a = 0; a < Q19; ++a) {
+      const R v = nu[a] + q_scale * R(EX19[a]);
+      mu_out[int64_t(a) * g.stride + n] = v;
+      if (CHECK) acc[2] += static_cast<double>(v);
+    }
+    if constexpr (GRAD == 1) {
+      grad[n] += gx;
+      grad[grad_stride + n] += gy;
+      grad[2 * grad_stride + n] += gz;
+    } else if constexpr (GRAD == 2) {
+      const R gv[3] = {gx + grad_direct, gy, gz};
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int64_t i = k * grad_stride + n;
+        const double d = static_cast<double>(gv[k]) - static_cast<double>(grad[i]);
+        grad[i] = gv[k];
+        acc[0] += d * d;
+        acc[1] += static_cast<double>(gv[k]) * static_cast<double>(gv[k]);
+      }
+    }
+    if (CHECK) {
+      const bool fin = isfinite(static_cast<double>(gx)) && isfinite(static_cast<double>(gy)) &&
+                       isfinite(static_cast<double>(gz)) && isfinite(static_cast<double>(nu[0]));
+      acc[4] += fin ? 0.0 : 1.0;
+    }
+  }
+  if constexpr (CHECK) {
+    block_sum<kPartials>(acc);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int k = 0; k < kPartials; ++k) partials[int64_t(lb) * kPartials + k] = acc[k];
+    }
+  }
+}
+
+// record = {change = sqrt(sum dg^2 / sum g^2), sum g^2, mean(mu), nonfinite};
+// shift = mean(mu), subtracted on the next read of mu.
+__global__ __launch_bounds__(kBlock) void finalize_adjoint_kernel(const double* __restrict__ partials,
+                                                                  int nblocks, double inv_count,
+                                                                  double* __restrict__ record,
+                                                                  double* __restrict__ shift) {
+  double acc[kPartials] = {0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nblocks; b += kBlock) {
+#pragma unroll
+    for (int k = 0; k < kPartials; ++k) acc[k] += partials[int64_t(b) * kPartials + k];
+  }
+  block_sum<kPartials>(acc);
+  if (threadIdx.x == 0) {
+    record[0] = acc[1] > 0.0 ? sqrt(acc[0] / acc[1]) : (acc[0] == 0.0 ? 0.0 : INFINITY);
+    record[1] = acc[1];
+    record[2] = acc[2] * inv_count;
+    record[3] = acc[4];
+    shift[0] = acc[2] * inv_count;
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void fill_q(R* __restrict__ mu, int64_t stride, int N, R q_scale) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= N) return;
+#pragma unroll
+  for (int a = 0; a < Q19; ++a) mu[int64_t(a) * stride + i] = q_scale * R(EX19[a]);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void fill_grad(R* __restrict__ grad, int64_t stride, int N,
+                                                    R gx) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= N) return;
+  grad[i] = gx;
+  grad[stride + i] = R(0);
+  grad[2 * stride + i] = R(0);
+}
+
+__global__ void fill_f64(double* __restrict__ p, int count, double v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+template <typename R>
+hipError_t launch_adjoint(const GridArgs& g, const CollideArgs<R>& c, const void* state,
+                          const void* force, bool field, const void* mu_in, void* mu_out,
+                          void* grad, int64_t grad_stride, int grad_mode, const double* shift,
+                          R q_scale, R grad_direct, bool check, double* partials, hipStream_t st) {
+  const dim3 grid(kXcd * g.blocks_per_xcd);
+  const R* s = static_cast<const R*>(state);
+  const R* F = static_cast<const R*>(force);
+  const R* mi = static_cast<const R*>(mu_in);
+  R* mo = static_cast<R*>(mu_out);
+  R* gr = static_cast<R*>(grad);
+#define LBM_ADJ(CH, GM, FL)                                                                     \
+  adjoint_step<R, CH, GM, FL><<<grid, kBlock, 0, st>>>(g, c, s, F, mi, mo, gr, grad_stride, shift, \
+                                                        q_scale, grad_direct, partials)
+  if (check) {
+    if (field) LBM_ADJ(true, 2, true); else LBM_ADJ(true, 2, false);
+  } else if (grad_mode == 1) {
+    if (field) LBM_ADJ(false, 1, true); else LBM_ADJ(false, 1, false);
+  } else {
+    if (field) LBM_ADJ(false, 0, true); else LBM_ADJ(false, 0, false);
+  }
+#undef LBM_ADJ
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ host ---
+namespace {
+
+constexpr size_t kA = 256;
+size_t al(size_t v) { return (v + kA - 1) / kA * kA; }
+
+struct AdjLayout {
+  size_t mu[2] = {0, 0}, partials = 0, ring = 0, shift = 0, ckpt = 0, seg = 0, total = 0;
+  int64_t n_ckpt = 0, seg_len = 0;
+};
+constexpr int kAdjRing = 64;
+constexpr int kAdjRec = 4;
+
+AdjLayout adj_layout(const lbm_ctx* c, int mode, int64_t n_steps, int64_t ckpt_every) {
+  AdjLayout L;
+  const size_t cs = c->celem();
+  const size_t state = 19 * size_t(c->L.stride) * cs;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t at = off;
+    off = al(off + b);
+    return at;
+  };
+  L.mu[0] = take(state);
+  L.mu[1] = take(state);
+  L.partials = take(size_t(c->L.nblocks) * kPartials * sizeof(double));
+  L.ring = take(kAdjRing * kAdjRec * sizeof(double));
+  L.shift = take(2 * sizeof(double));
+  if (mode == 1) {
+    L.n_ckpt = (n_steps + ckpt_every - 1) / ckpt_every;
+    L.seg_len = std::min<int64_t>(ckpt_every, n_steps);
+    L.ckpt = take(size_t(L.n_ckpt) * state);
+    L.seg = take(size_t(L.seg_len) * state);
+  }
+  L.total = off;
+  return L;
+}
+
+lbm_status adj_common_checks(lbm_ctx* c) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (c->p.mhd) return fail(c, LBM_EUNSUPPORTED, "the adjoint covers the GLBE step without mhd");
+  if (c->p.storage != LBM_F64 && c->p.storage != LBM_F32)
+    return fail(c, LBM_EUNSUPPORTED, "the adjoint needs LBM_F64 or LBM_F32 storage");
+  return LBM_OK;
+}
+
+template <typename R>
+const CollideArgs<R>& cargs(const lbm_ctx* c);
+template <>
+const CollideArgs<double>& cargs<double>(const lbm_ctx* c) { return c->cd; }
+template <>
+const CollideArgs<float>& cargs<float>(const lbm_ctx* c) { return c->cf; }
+
+template <typename R>
+lbm_status steady_impl(lbm_ctx* c, char* ws, double tol, int64_t max_iter, void* dQdF,
+                       int64_t* iters, double* final_change) {
+  const AdjLayout L = adj_layout(c, 0, 0, 1);
+  const int64_t N = c->L.N, st = c->L.stride;
+  const int blocks = int((N + kBlock - 1) / kBlock);
+  void* mu[2] = {ws + L.mu[0], ws + L.mu[1]};
+  double* partials = reinterpret_cast<double*>(ws + L.partials);
+  double* ring = reinterpret_cast<double*>(ws + L.ring);
+  double* shift = reinterpret_cast<double*>(ws + L.shift);
+  const R q = R(1.0 / c->grid.n[0]);
+  const R direct = R(0.5 / (c->p.gamma * c->grid.n[0]));
+  hipLaunchKernelGGL(fill_q<R>, dim3(blocks), dim3(kBlock), 0, c->stream, static_cast<R*>(mu[0]),
+                     st, int(N), q);
+  hipLaunchKernelGGL(fill_grad<R>, dim3(blocks), dim3(kBlock), 0, c->stream,
+                     static_cast<R*>(dQdF), N, int(N), R(0));
+  hipLaunchKernelGGL(fill_f64, dim3(1), dim3(64), 0, c->stream, shift, 2, 0.0);
+  LBM_HIP(c, hipGetLastError(), "adjoint initialisation");
+  const int ce = c->p.check_every;
+  int cur = 0;
+  int64_t checks = 0, done = 0;
+  bool prev_check = false;
+  double change = INFINITY;
+  std::vector<double> host(kAdjRing * kAdjRec);
+  while (done < max_iter) {
+    const int64_t it = done + 1;
+    const bool check = (it % ce) == 0;
+    const double* sh = prev_check ? shift : nullptr;
+    LBM_HIP(c, launch_adjoint<R>(c->ga, cargs<R>(c), c->f(c->cur), c->force(), c->field(),
+                                 mu[cur], mu[cur ^ 1], dQdF, N, check ? 2 : 0, sh, q, direct,
+                                 check, partials, c->stream),
+            "adjoint launch");
+    cur ^= 1;
+    done = it;
+    prev_check = check;
+    if (check) {
+      hipLaunchKernelGGL(finalize_adjoint_kernel, dim3(1), dim3(kBlock), 0, c->stream, partials,
+                         c->L.nblocks, 1.0 / double(19 * N),
+                         ring + (checks % kAdjRing) * kAdjRec, shift);
+      LBM_HIP(c, hipGetLastError(), "adjoint finalize");
+      ++checks;
+      if (checks % kAdjRing == 0 || done >= max_iter) {
+        LBM_HIP(c, hipMemcpyAsync(host.data(), ring, host.size() * sizeof(double),
+                                  hipMemcpyDeviceToHost, c->stream),
+                "copy");
+        LBM_HIP(c, hipStreamSynchronize(c->stream), "sync");
+        const int64_t first = std::max<int64_t>(0, checks - kAdjRing);
+        for (int64_t k = first; k < checks; ++k) {
+          const double* r = &host[(k % kAdjRing) * kAdjRec];
+          if (r[3] > 0.0) return fail(c, LBM_EUNSTABLE, "non-finite adjoint values");
+          change = r[0];
+          if (k >= 1 && change < tol) {
+            *iters = done;
+            *final_change = host[((checks - 1) % kAdjRing) * kAdjRec];
+            return LBM_OK;
+          }
+        }
+      }
+    }
+  }
+  LBM_HIP(c, hipStreamSynchronize(c->stream), "sync");
+  if (checks > 0) {
+    LBM_HIP(c, hipMemcpy(host.data(), ring + ((checks - 1) % kAdjRing) * kAdjRec,
+                         kAdjRec * sizeof(double), hipMemcpyDeviceToHost),
+            "copy");
+    change = host[0];
+  }
+  *iters = done;
+  *final_change = change;
+  return LBM_OK;
+}
+
+template <typename R>
+lbm_status unrolled_impl(lbm_ctx* c, char* ws, int64_t n_steps, int64_t K, void* dQdF) {
+  const AdjLayout L = adj_layout(c, 1, n_steps, K);
+  const int64_t N = c->L.N, st = c->L.stride;
+  const size_t state_bytes = 19 * size_t(st) * sizeof(R);
+  const int blocks = int((N + kBlock - 1) / kBlock);
+  char* ckpt = ws + L.ckpt;
+  char* seg = ws + L.seg;
+  void* mu[2] = {ws + L.mu[0], ws + L.mu[1]};
+  // forward march with checkpoints p_0, p_K, p_2K, ...
+  for (int64_t n = 0; n < n_steps; ++n) {
+    if (n % K == 0)
+      LBM_HIP(c, hipMemcpyAsync(ckpt + size_t(n / K) * state_bytes, c->f(c->cur), state_bytes,
+                                hipMemcpyDeviceToDevice, c->stream),
+              "checkpoint copy");
+    const lbm_status s = one_step(c);
+    if (s != LBM_OK) return s;
+  }
+  const R q = R(1.0 / c->grid.n[0]);
+  hipLaunchKernelGGL(fill_q<R>, dim3(blocks), dim3(kBlock), 0, c->stream, static_cast<R*>(mu[0]),
+                     st, int(N), q);
+  hipLaunchKernelGGL(fill_grad<R>, dim3(blocks), dim3(kBlock), 0, c->stream,
+                     static_cast<R*>(dQdF), N, int(N), R(0.5 / (c->p.gamma * c->grid.n[0])));
+  LBM_HIP(c, hipGetLastError(), "adjoint initialisation");
+  int cur = 0;
+  for (int64_t sgi = L.n_ckpt - 1; sgi >= 0; --sgi) {
+    const int64_t s0 = sgi * K, e = std::min(s0 + K, n_steps), len = e - s0;
+    LBM_HIP(c, hipMemcpyAsync(seg, ckpt + size_t(sgi) * state_bytes, state_bytes,
+                              hipMemcpyDeviceToDevice, c->stream),
+            "segment copy");
+    for (int64_t i = 1; i < len; ++i)
+      LBM_HIP(c, launch_glbe_step<R>(c->ga, cargs<R>(c), seg + size_t(i - 1) * state_bytes,
+                                     seg + size_t(i) * state_bytes, c->force(), c->field(), false,
+                                     nullptr, nullptr, c->stream),
+              "segment recompute");
+    for (int64_t n = e; n >= s0 + 1; --n) {
+      LBM_HIP(c, launch_adjoint<R>(c->ga, cargs<R>(c), seg + size_t(n - 1 - s0) * state_bytes,
+                                   c->force(), c->field(), mu[cur], mu[cur ^ 1], dQdF, N, 1,
+                                   nullptr, R(0), R(0), false, nullptr, c->stream),
+              "adjoint launch");
+      cur ^= 1;
+    }
+  }
+  LBM_HIP(c, hipStreamSynchronize(c->stream), "sync");
+  return LBM_OK;
+}
+
+}  // namespace
+
+template hipError_t launch_adjoint<double>(const GridArgs&, const CollideArgs<double>&, const void*,
+                                           const void*, bool, const void*, void*, void*, int64_t,
+                                           int, const double*, double, double, bool, double*,
+                                           hipStream_t);
+template hipError_t launch_adjoint<float>(const GridArgs&, const CollideArgs<float>&, const void*,
+                                          const void*, bool, const void*, void*, void*, int64_t,
+                                          int, const double*, float, float, bool, double*,
+                                          hipStream_t);
+
+}  // namespace lbm
+
+using namespace lbm;
+
+extern "C" {
+
+lbm_status lbm_adjoint_workspace_bytes(const lbm_ctx* cc, int32_t mode, int64_t n_steps,
+                                       int64_t ckpt_every, size_t* bytes) {
+  lbm_ctx* c = const_cast<lbm_ctx*>(cc);
+  const lbm_status s = adj_common_checks(c);
+  if (s != LBM_OK) return s;
+  if (!bytes) return fail(c, LBM_EINVAL, "bytes is NULL");
+  if (mode != 0 && mode != 1) return fail(c, LBM_EINVAL, "mode must be 0 (steady) or 1 (unrolled)");
+  if (mode == 1 && (n_steps < 1 || ckpt_every < 1))
+    return fail(c, LBM_EINVAL, "unrolled adjoint needs n_steps >= 1 and ckpt_every >= 1");
+  *bytes = adj_layout(c, mode, n_steps, ckpt_every).total;
+  return LBM_OK;
+}
+
+lbm_status lbm_adjoint_steady(lbm_ctx* c, void* adj_ws, size_t adj_ws_bytes, double tol,
+                              int64_t max_iter, void* dQdF, int64_t* iters,
+                              double* final_change) {
+  const lbm_status s = adj_common_checks(c);
+  if (s != LBM_OK) return s;
+  if (!dQdF || !iters || !final_change || !(tol > 0.0) || max_iter < 1)
+    return fail(c, LBM_EINVAL, "bad arguments");
+  if (!adj_ws || reinterpret_cast<uintptr_t>(adj_ws) % 256 != 0 ||
+      adj_ws_bytes < adj_layout(c, 0, 0, 1).total)
+    return fail(c, LBM_ENOWS, "adjoint workspace missing, misaligned or too small");
+  char* ws = static_cast<char*>(adj_ws);
+  if (c->p.storage == LBM_F64) return steady_impl<double>(c, ws, tol, max_iter, dQdF, iters, final_change);
+  return steady_impl<float>(c, ws, tol, max_iter, dQdF, iters, final_change);
+}
+
+lbm_status lbm_adjoint_unrolled(lbm_ctx* c, void* adj_ws, size_t adj_ws_bytes, int64_t n_steps,
+                                int64_t ckpt_every, void* dQdF) {
+  const lbm_status s = adj_common_checks(c);
+  if (s != LBM_OK) return s;
+  if (!dQdF || n_steps < 1 || ckpt_every < 1) return fail(c, LBM_EINVAL, "bad arguments");
+  if (!adj_ws || reinterpret_cast<uintptr_t>(adj_ws) % 256 != 0 ||
+      adj_ws_bytes < adj_layout(c, 1, n_steps, ckpt_every).total)
+    return fail(c, LBM_ENOWS, "adjoint workspace missing, misaligned or too small");
+  char* ws = static_cast<char*>(adj_ws);
+  if (c->p.storage == LBM_F64) return unrolled_impl<double>(c, ws, n_steps, ckpt_every, dQdF);
+  return unrolled_impl<float>(c, ws, n_steps, ckpt_every, dQdF);
+}
+
+}  // extern "C"

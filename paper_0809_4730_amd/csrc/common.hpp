@@ -1,0 +1,161 @@
+// Shared device/host definitions for the gfx950 kernels: kernel argument
+// blocks, exact fast division, XCD-aware block numbering, storage-type
+// conversion and FP64 block reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "lattice.hpp"
+
+namespace lbm {
+
+constexpr int kBlock = 256;   // threads per workgroup (4 wave64)
+constexpr int kXcd = 8;       // XCDs on MI355X; workgroups are dealt round-robin
+constexpr int kRecordDoubles = 8;
+constexpr int kPartials = 6;  // du2, u2, mass, flow, nonfinite, spare
+
+// q = floor(n / d) for n < 2^32 via one 64x64 high multiply:
+// M = ceil(2^64 / d) gives n*M/2^64 = n/d + e with 0 <= e < n/2^64 < 1/d.
+struct FastDiv {
+  uint64_t M;
+  uint32_t d;
+  uint32_t pad;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  f.pad = 0;
+  f.M = (d <= 1) ? 0ull : (~0ull) / d + 1ull;
+  return f;
+}
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
+  return f.d == 1 ? n : static_cast<uint32_t>(__umul64hi(static_cast<uint64_t>(n), f.M));
+}
+
+struct GridArgs {
+  int32_t nx, ny, nz;
+  int32_t wall_x, wall_y, wall_z;
+  int32_t N;               // nodes
+  int32_t nblocks;         // logical workgroups covering N
+  int32_t blocks_per_xcd;  // launched grid = kXcd * blocks_per_xcd
+  int32_t pad;
+  int64_t stride;          // elements between direction planes (N rounded up to 64)
+  FastDiv div_nx, div_nxny;
+};
+
+// Workgroup b of the launch runs on XCD (b mod 8); give each XCD one
+// contiguous range of logical blocks so that the neighbouring rows it pulls
+// from sit in its own L2.
+__device__ __forceinline__ int logical_block(const GridArgs& g) {
+  const int b = blockIdx.x;
+  return (b & (kXcd - 1)) * g.blocks_per_xcd + (b >> 3);
+}
+
+// Collision constants for compute type R (host-prepared).
+template <typename R>
+struct CollideArgs {
+  R rho0;
+  R inv_gamma;     // 1/gamma: nonlinear equilibrium terms, linear source terms
+  R inv_gamma2;    // 1/gamma^2: F.u source terms
+  R half_inv_gamma;  // 1/(2 gamma): half-force in j
+  R A[Q19];        // s_k / |T_k|^2
+  R B[Q19];        // (1 - s_k/2) / |T_k|^2
+  R F[3];          // uniform force (force_mode = UNIFORM)
+};
+
+// Induction-LKE constants (Sec. 4, 4.1).
+template <typename R>
+struct MagArgs {
+  R omega;       // 1 / tau_m*
+  R adv;         // chi / (gamma_m theta_m)
+  R a_coef;      // -1 / (mu chi tau_m* theta_m)
+  R kappa;       // 2 / (mu gamma_m tau_m* theta_m)
+  R Bw[3];       // wall / applied field
+  R w_rest, w_axis;
+};
+
+// ------------------------------------------------------------- storage ----
+struct bf16_t {
+  uint16_t bits;
+};
+
+template <typename S>
+struct Storage;
+
+template <>
+struct Storage<double> {
+  using R = double;
+  __device__ __forceinline__ static R ld(const double* p) { return *p; }
+  __device__ __forceinline__ static void st(double* p, R v) { *p = v; }
+};
+
+template <>
+struct Storage<float> {
+  using R = float;
+  __device__ __forceinline__ static R ld(const float* p) { return *p; }
+  __device__ __forceinline__ static void st(float* p, R v) { *p = v; }
+};
+
+template <>
+struct Storage<bf16_t> {
+  using R = float;
+  __device__ __forceinline__ static R ld(const bf16_t* p) {
+    return __uint_as_float(static_cast<uint32_t>(p->bits) << 16);
+  }
+  // round to nearest, ties to even; NaN stays NaN
+  __device__ __forceinline__ static void st(bf16_t* p, R v) {
+    uint32_t u = __float_as_uint(v);
+    uint16_t h;
+    if ((u & 0x7fffffffu) > 0x7f800000u) {
+      h = static_cast<uint16_t>((u >> 16) | 0x40u);
+    } else {
+      u += 0x7fffu + ((u >> 16) & 1u);
+      h = static_cast<uint16_t>(u >> 16);
+    }
+    p->bits = h;
+  }
+};
+
+template <>
+struct Storage<_Float16> {
+  using R = float;
+  __device__ __forceinline__ static R ld(const _Float16* p) { return static_cast<float>(*p); }
+  __device__ __forceinline__ static void st(_Float16* p, R v) { *p = static_cast<_Float16>(v); }
+};
+
+// ------------------------------------------------------------ reductions --
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum K doubles over the workgroup; thread 0 receives the totals in v.
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K]) {
+  __shared__ double red[kBlock / 64][K];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[wave][k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < kBlock / 64; ++w) s += red[w][k];
+      v[k] = s;
+    }
+  }
+}
+
+}  // namespace lbm

@@ -1,0 +1,78 @@
+// Host-side context of the C ABI, shared by the forward (lbm_capi.hip) and
+// adjoint (adjoint.hip) entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lbm_capi.h"
+#include "launch.hpp"
+
+namespace lbm {
+
+inline size_t storage_bytes(int storage) {
+  switch (storage) {
+    case LBM_F64: return 8;
+    case LBM_F32: return 4;
+    case LBM_BF16: return 2;
+    case LBM_F16: return 2;
+    default: return 0;
+  }
+}
+
+inline size_t compute_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
+
+struct Layout {
+  int64_t N = 0, stride = 0;
+  int32_t nblocks = 0;
+  size_t f[2] = {0, 0}, g[2] = {0, 0}, force = 0, usnap = 0, partials = 0, ring = 0, rec = 0;
+  size_t total = 0;
+};
+
+}  // namespace lbm
+
+using lbm::Layout;
+
+struct lbm_ctx {
+  lbm_grid grid;
+  lbm_params p;
+  Layout L;
+  lbm::GridArgs ga;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  int cur = 0;
+  int64_t step = 0;
+  int64_t checks = 0;
+  lbm::CollideArgs<double> cd;
+  lbm::CollideArgs<float> cf;
+  lbm::MagArgs<double> md;
+  lbm::MagArgs<float> mf;
+  std::string err;
+  std::vector<hipEvent_t> events;
+
+  void* f(int i) const { return ws + L.f[i]; }
+  void* g(int i) const { return p.mhd ? static_cast<void*>(ws + L.g[i]) : nullptr; }
+  void* force() const { return p.force_mode == LBM_FORCE_FIELD ? static_cast<void*>(ws + L.force) : nullptr; }
+  double* usnap() const { return reinterpret_cast<double*>(ws + L.usnap); }
+  double* partials() const { return reinterpret_cast<double*>(ws + L.partials); }
+  double* ring() const { return reinterpret_cast<double*>(ws + L.ring); }
+  double* rec() const { return reinterpret_cast<double*>(ws + L.rec); }
+  bool field() const { return p.force_mode == LBM_FORCE_FIELD; }
+  size_t elem() const { return lbm::storage_bytes(p.storage); }
+  size_t celem() const { return lbm::compute_bytes(p.storage); }
+};
+
+namespace lbm {
+// Helpers defined in lbm_capi.hip.
+lbm_status fail(lbm_ctx* c, lbm_status s, const std::string& msg);
+lbm_status hip_fail(lbm_ctx* c, hipError_t e, const char* what);
+lbm_status one_step(lbm_ctx* c, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+}  // namespace lbm
+
+#define LBM_HIP(ctx, call, what)                          \
+  do {                                                    \
+    hipError_t e_ = (call);                               \
+    if (e_ != hipSuccess) return ::lbm::hip_fail(ctx, e_, what); \
+  } while (0)

@@ -1,0 +1,537 @@
+// gfx950 kernels of the preconditioned GLBE time step.
+//
+// glbe_step   fused pull-stream + preconditioned MRT collision with forcing
+//             (Sec. 2 eq. streaming, Sec. 3 eqs. ppostcollision, prelax_term),
+//             one thread per node, structure-of-arrays populations, A/B buffers.
+// mhd_step    the same fused with the D3Q7 vector induction LKE (Sec. 4, 4.1)
+//             and the Lorentz force J x B computed in registers.
+// fields      hydrodynamic (and magnetic) fields of the current state plus the
+//             FP64 mass / flow-rate partial sums.
+// finalize    second pass of the FP64 reductions into one history record.
+//
+// Every population is read once and written once per step; the step is
+// bandwidth-bound, so there is no LDS staging and no MFMA.  Halfway bounce-back
+// needs no solid nodes: a link crossing a wall reads the opposite direction's
+// post-collision value at the same node.
+#include "collide.hpp"
+#include "launch.hpp"
+
+namespace lbm {
+
+// Per-node neighbour offsets for pull streaming.
+struct Nbr {
+  int32_t xm, xp, ym, yp, zm, zp;  // linear offsets to x-1, x+1, ... (periodic wrap applied)
+  bool bxm, bxp, bym, byp, bzm, bzp;  // link to that neighbour crosses a wall
+};
+
+__device__ __forceinline__ Nbr neighbours(const GridArgs& g, uint32_t n) {
+  const uint32_t yz = fdiv(n, g.div_nx);
+  const uint32_t z = fdiv(n, g.div_nxny);
+  const int x = static_cast<int>(n - yz * static_cast<uint32_t>(g.nx));
+  const int y = static_cast<int>(yz - z * static_cast<uint32_t>(g.ny));
+  const int zz = static_cast<int>(z);
+  const int sx = 1, sy = g.nx, sz = g.nx * g.ny;
+  Nbr b;
+  b.xm = (x == 0) ? (g.nx - 1) * sx : -sx;
+  b.xp = (x == g.nx - 1) ? -(g.nx - 1) * sx : sx;
+  b.ym = (y == 0) ? (g.ny - 1) * sy : -sy;
+  b.yp = (y == g.ny - 1) ? -(g.ny - 1) * sy : sy;
+  b.zm = (zz == 0) ? (g.nz - 1) * sz : -sz;
+  b.zp = (zz == g.nz - 1) ? -(g.nz - 1) * sz : sz;
+  b.bxm = g.wall_x && x == 0;
+  b.bxp = g.wall_x && x == g.nx - 1;
+  b.bym = g.wall_y && y == 0;
+  b.byp = g.wall_y && y == g.ny - 1;
+  b.bzm = g.wall_z && zz == 0;
+  b.bzp = g.wall_z && zz == g.nz - 1;
+  return b;
+}
+
+// Source of f_a(x) = f~_a(x - e_a): returns the element index to read in the
+// plane of direction `plane` (a itself, or its opposite on bounce-back).
+template <int EX, int EY, int EZ>
+__device__ __forceinline__ bool pull_source(const Nbr& b, int32_t& off) {
+  off = (EX > 0 ? b.xm : EX < 0 ? b.xp : 0) + (EY > 0 ? b.ym : EY < 0 ? b.yp : 0) +
+        (EZ > 0 ? b.zm : EZ < 0 ? b.zp : 0);
+  return (EX > 0 && b.bxm) || (EX < 0 && b.bxp) || (EY > 0 && b.bym) || (EY < 0 && b.byp) ||
+         (EZ > 0 && b.bzm) || (EZ < 0 && b.bzp);
+}
+
+template <typename S, int A>
+__device__ __forceinline__ typename Storage<S>::R gather_one(const S* __restrict__ fin,
+                                                             int64_t stride, uint32_t n,
+                                                             const Nbr& b) {
+  int32_t off;
+  const bool bounce = pull_source<EX19[A], EY19[A], EZ19[A]>(b, off);
+  const int64_t idx = bounce ? static_cast<int64_t>(OPP19(A)) * stride + n
+                             : static_cast<int64_t>(A) * stride + static_cast<int64_t>(n) + off;
+  return Storage<S>::ld(fin + idx);
+}
+
+template <typename S, int A = 0>
+__device__ __forceinline__ void gather19(const S* __restrict__ fin, int64_t stride, uint32_t n,
+                                         const Nbr& b, typename Storage<S>::R (&f)[Q19]) {
+  if constexpr (A < Q19) {
+    f[A] = gather_one<S, A>(fin, stride, n, b);
+    gather19<S, A + 1>(fin, stride, n, b, f);
+  }
+}
+
+template <typename S>
+__device__ __forceinline__ void store19(S* __restrict__ fout, int64_t stride, uint32_t n,
+                                        const typename Storage<S>::R (&f)[Q19]) {
+#pragma unroll
+  for (int a = 0; a < Q19; ++a) Storage<S>::st(fout + static_cast<int64_t>(a) * stride + n, f[a]);
+}
+
+// Anti-bounce-back gather of the magnetic populations g_{a j} (j outermost).
+template <typename R, int A>
+__device__ __forceinline__ void gather_g_dir(const R* __restrict__ gin, int64_t stride, uint32_t n,
+                                             const Nbr& b, const MagArgs<R>& m, R (&g)[3][Q7]) {
+  int32_t off;
+  const bool bounce = pull_source<EX7[A], EY7[A], EZ7[A]>(b, off);
+  const R w = (A == 0) ? m.w_rest : m.w_axis;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int64_t base = static_cast<int64_t>(j * Q7) * stride;
+    if (bounce) {
+      g[j][A] = R(2) * w * m.Bw[j] - gin[base + static_cast<int64_t>(OPP7(A)) * stride + n];
+    } else {
+      g[j][A] = gin[base + static_cast<int64_t>(A) * stride + static_cast<int64_t>(n) + off];
+    }
+  }
+}
+
+template <typename R, int A = 0>
+__device__ __forceinline__ void gather_g(const R* __restrict__ gin, int64_t stride, uint32_t n,
+                                         const Nbr& b, const MagArgs<R>& m, R (&g)[3][Q7]) {
+  if constexpr (A < Q7) {
+    gather_g_dir<R, A>(gin, stride, n, b, m, g);
+    gather_g<R, A + 1>(gin, stride, n, b, m, g);
+  }
+}
+
+// Self-consistent velocity, current and Lorentz force at one node.
+// J = a + kappa (u x B) with a = a_coef * eps_ijk Lambda_jk (Lambda_jk = sum e_j g_k)
+// and u = (j_raw + (F_ext + J x B)/(2 gamma))/rho; since (u x B) x B = -|B|^2 u_perp
+// the linear system has the closed form u = (u0 + c (u0.B) B) / (1 + c |B|^2),
+// c = kappa/(2 gamma rho), u0 = (j_raw + (F_ext + a x B)/(2 gamma))/rho.
+template <typename R>
+struct Coupled {
+  R Bx, By, Bz;
+  R Fx, Fy, Fz;  // total force
+};
+
+template <typename R>
+__device__ __forceinline__ Coupled<R> lorentz_solve(const R (&f)[Q19], const R (&g)[3][Q7],
+                                                    R Fex, R Fey, R Fez, const CollideArgs<R>& c,
+                                                    const MagArgs<R>& m) {
+  Coupled<R> o;
+  R B[3], L[3][3];  // L[k][j] = sum_a e_{a k} g_{a j}
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    B[j] = g[j][0] + g[j][1] + g[j][2] + g[j][3] + g[j][4] + g[j][5] + g[j][6];
+    L[0][j] = g[j][1] - g[j][2];
+    L[1][j] = g[j][3] - g[j][4];
+    L[2][j] = g[j][5] - g[j][6];
+  }
+  const R ax = m.a_coef * (L[1][2] - L[2][1]);
+  const R ay = m.a_coef * (L[2][0] - L[0][2]);
+  const R az = m.a_coef * (L[0][1] - L[1][0]);
+  R drho, jrx, jry, jrz;
+  raw_moments<R>(f, drho, jrx, jry, jrz);
+  const R rho = c.rho0 + drho;
+  const R irho = R(1) / rho;
+  const R h = c.half_inv_gamma;
+  const R u0x = (jrx + (Fex + (ay * B[2] - az * B[1])) * h) * irho;
+  const R u0y = (jry + (Fey + (az * B[0] - ax * B[2])) * h) * irho;
+  const R u0z = (jrz + (Fez + (ax * B[1] - ay * B[0])) * h) * irho;
+  const R cc = m.kappa * h * irho;
+  const R BB = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+  const R uB = u0x * B[0] + u0y * B[1] + u0z * B[2];
+  const R den = R(1) / (R(1) + cc * BB);
+  const R ux = (u0x + cc * uB * B[0]) * den;
+  const R uy = (u0y + cc * uB * B[1]) * den;
+  const R uz = (u0z + cc * uB * B[2]) * den;
+  const R Jx = ax + m.kappa * (uy * B[2] - uz * B[1]);
+  const R Jy = ay + m.kappa * (uz * B[0] - ux * B[2]);
+  const R Jz = az + m.kappa * (ux * B[1] - uy * B[0]);
+  o.Bx = B[0];
+  o.By = B[1];
+  o.Bz = B[2];
+  o.Fx = Fex + (Jy * B[2] - Jz * B[1]);
+  o.Fy = Fey + (Jz * B[0] - Jx * B[2]);
+  o.Fz = Fez + (Jx * B[1] - Jy * B[0]);
+  return o;
+}
+
+// g~ = g + (g^eq* - g)/tau_m*, g^eq*_{a j} = W_a [B_j + (e_{a k}/theta)(chi/gamma_m)(u_k B_j - B_k u_j)]
+template <typename R>
+__device__ __forceinline__ void collide_g(R (&g)[3][Q7], R Bx, R By, R Bz, R ux, R uy, R uz,
+                                          const MagArgs<R>& m) {
+  const R B[3] = {Bx, By, Bz};
+  const R u[3] = {ux, uy, uz};
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    g[j][0] += m.omega * (m.w_rest * B[j] - g[j][0]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const R adv = m.adv * (u[k] * B[j] - B[k] * u[j]);
+      const R base = m.w_axis * B[j];
+      const R wadv = m.w_axis * adv;
+      g[j][1 + 2 * k] += m.omega * (base + wadv - g[j][1 + 2 * k]);
+      g[j][2 + 2 * k] += m.omega * (base - wadv - g[j][2 + 2 * k]);
+    }
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void load_force(const GridArgs& g, const CollideArgs<R>& c,
+                                           const R* __restrict__ force, bool field, uint32_t n,
+                                           R& Fx, R& Fy, R& Fz) {
+  if (field) {
+    Fx = force[n];
+    Fy = force[g.stride + n];
+    Fz = force[2 * g.stride + n];
+  } else {
+    Fx = c.F[0];
+    Fy = c.F[1];
+    Fz = c.F[2];
+  }
+}
+
+// Residual / reduction bookkeeping of one node (FP64).
+template <typename R>
+__device__ __forceinline__ void check_node(const GridArgs& g, double* __restrict__ usnap, uint32_t n,
+                                           R drho, R jx, R jy, R jz, R ux, R uy, R uz,
+                                           double (&acc)[kPartials]) {
+  const double u[3] = {static_cast<double>(ux), static_cast<double>(uy), static_cast<double>(uz)};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int64_t i = static_cast<int64_t>(k) * g.stride + n;
+    const double d = u[k] - usnap[i];
+    usnap[i] = u[k];
+    acc[0] += d * d;
+    acc[1] += u[k] * u[k];
+  }
+  acc[2] += static_cast<double>(drho);
+  acc[3] += static_cast<double>(jx);
+  const bool fin = isfinite(static_cast<double>(drho)) && isfinite(static_cast<double>(jx)) &&
+                   isfinite(static_cast<double>(jy)) && isfinite(static_cast<double>(jz));
+  acc[4] += fin ? 0.0 : 1.0;
+}
+
+__device__ __forceinline__ void write_partials(double* __restrict__ partials, int lb,
+                                               double (&acc)[kPartials]) {
+  block_sum<kPartials>(acc);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < kPartials; ++k) partials[static_cast<int64_t>(lb) * kPartials + k] = acc[k];
+  }
+}
+
+// ------------------------------------------------------------------ steps --
+template <typename S, bool CHECK, bool FIELD>
+__global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<typename Storage<S>::R> c,
+                                                    const S* __restrict__ fin, S* __restrict__ fout,
+                                                    const typename Storage<S>::R* __restrict__ force,
+                                                    double* __restrict__ usnap,
+                                                    double* __restrict__ partials) {
+  using R = typename Storage<S>::R;
+  const int lb = logical_block(g);
+  if (lb >= g.nblocks) return;  // padding workgroup of the XCD-balanced launch
+  const uint32_t n = static_cast<uint32_t>(lb) * kBlock + threadIdx.x;
+  double acc[kPartials] = {0, 0, 0, 0, 0, 0};
+  if (n < static_cast<uint32_t>(g.N)) {
+    const Nbr b = neighbours(g, n);
+    R f[Q19];
+    gather19<S>(fin, g.stride, n, b, f);
+    R Fx, Fy, Fz;
+    load_force<R>(g, c, force, FIELD, n, Fx, Fy, Fz);
+    const NodeMacro<R> mac = collide19<R>(f, Fx, Fy, Fz, c);
+    store19<S>(fout, g.stride, n, f);
+    if constexpr (CHECK)
+      check_node<R>(g, usnap, n, mac.drho, mac.jx, mac.jy, mac.jz, mac.ux, mac.uy, mac.uz, acc);
+  }
+  if constexpr (CHECK) write_partials(partials, lb, acc);
+}
+
+template <typename R, bool CHECK, bool FIELD>
+__global__ __launch_bounds__(kBlock) void mhd_step(GridArgs g, CollideArgs<R> c, MagArgs<R> m,
+                                                   const R* __restrict__ fin, R* __restrict__ fout,
+                                                   const R* __restrict__ gin, R* __restrict__ gout,
+                                                   const R* __restrict__ force,
+                                                   double* __restrict__ usnap,
+                                                   double* __restrict__ partials) {
+  const int lb = logical_block(g);
+  if (lb >= g.nblocks) return;
+  const uint32_t n = static_cast<uint32_t>(lb) * kBlock + threadIdx.x;
+  double acc[kPartials] = {0, 0, 0, 0, 0, 0};
+  if (n < static_cast<uint32_t>(g.N)) {
+    const Nbr b = neighbours(g, n);
+    R f[Q19];
+    gather19<R>(fin, g.stride, n, b, f);
+    R gg[3][Q7];
+    gather_g<R>(gin, g.stride, n, b, m, gg);
+    R Fx, Fy, Fz;
+    load_force<R>(g, c, force, FIELD, n, Fx, Fy, Fz);
+    const Coupled<R> cp = lorentz_solve<R>(f, gg, Fx, Fy, Fz, c, m);
+    const NodeMacro<R> mac = collide19<R>(f, cp.Fx, cp.Fy, cp.Fz, c);
+    collide_g<R>(gg, cp.Bx, cp.By, cp.Bz, mac.ux, mac.uy, mac.uz, m);
+    store19<R>(fout, g.stride, n, f);
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int a = 0; a < Q7; ++a)
+        gout[static_cast<int64_t>(j * Q7 + a) * g.stride + n] = gg[j][a];
+    if constexpr (CHECK)
+      check_node<R>(g, usnap, n, mac.drho, mac.jx, mac.jy, mac.jz, mac.ux, mac.uy, mac.uz, acc);
+  }
+  if constexpr (CHECK) write_partials(partials, lb, acc);
+}
+
+// ----------------------------------------------------------------- fields --
+// Fields of the streamed current state (no collision).  Writes rho, u (and B)
+// when the pointers are non-null, and always the mass / flow partials.
+template <typename S, typename O, bool MHD>
+__global__ __launch_bounds__(kBlock) void fields_kernel(
+    GridArgs g, CollideArgs<typename Storage<S>::R> c, MagArgs<typename Storage<S>::R> m,
+    const S* __restrict__ fin, const typename Storage<S>::R* __restrict__ gin,
+    const typename Storage<S>::R* __restrict__ force, int field, O* __restrict__ rho_out,
+    O* __restrict__ u_out, O* __restrict__ B_out, int64_t out_stride, double* __restrict__ partials) {
+  using R = typename Storage<S>::R;
+  const int lb = logical_block(g);
+  if (lb >= g.nblocks) return;
+  const uint32_t n = static_cast<uint32_t>(lb) * kBlock + threadIdx.x;
+  double acc[kPartials] = {0, 0, 0, 0, 0, 0};
+  if (n < static_cast<uint32_t>(g.N)) {
+    const Nbr b = neighbours(g, n);
+    R f[Q19];
+    gather19<S>(fin, g.stride, n, b, f);
+    R Fx, Fy, Fz;
+    load_force<R>(g, c, force, field != 0, n, Fx, Fy, Fz);
+    R Bx = 0, By = 0, Bz = 0;
+    if constexpr (MHD) {
+      R gg[3][Q7];
+      gather_g<R>(gin, g.stride, n, b, m, gg);
+      const Coupled<R> cp = lorentz_solve<R>(f, gg, Fx, Fy, Fz, c, m);
+      Fx = cp.Fx;
+      Fy = cp.Fy;
+      Fz = cp.Fz;
+      Bx = cp.Bx;
+      By = cp.By;
+      Bz = cp.Bz;
+    }
+    R drho, jx, jy, jz;
+    raw_moments<R>(f, drho, jx, jy, jz);
+    jx += Fx * c.half_inv_gamma;
+    jy += Fy * c.half_inv_gamma;
+    jz += Fz * c.half_inv_gamma;
+    const R rho = c.rho0 + drho;
+    if (rho_out) rho_out[n] = static_cast<O>(rho);
+    if (u_out) {
+      u_out[n] = static_cast<O>(jx / rho);
+      u_out[out_stride + n] = static_cast<O>(jy / rho);
+      u_out[2 * out_stride + n] = static_cast<O>(jz / rho);
+    }
+    if (MHD && B_out) {
+      B_out[n] = static_cast<O>(Bx);
+      B_out[out_stride + n] = static_cast<O>(By);
+      B_out[2 * out_stride + n] = static_cast<O>(Bz);
+    }
+    acc[2] = static_cast<double>(drho);
+    acc[3] = static_cast<double>(jx);
+  }
+  write_partials(partials, lb, acc);
+}
+
+// ---------------------------------------------------------------- finalize --
+// One workgroup: sum the per-workgroup partials in a fixed order and write one
+// history record {step, residual, du2, u2, mass, flow, nonfinite, 0}.
+__global__ __launch_bounds__(kBlock) void finalize_kernel(const double* __restrict__ partials,
+                                                          int nblocks, double step, double inv_nx,
+                                                          double* __restrict__ record) {
+  double acc[kPartials] = {0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nblocks; b += kBlock) {
+#pragma unroll
+    for (int k = 0; k < kPartials; ++k) acc[k] += partials[static_cast<int64_t>(b) * kPartials + k];
+  }
+  block_sum<kPartials>(acc);
+  if (threadIdx.x == 0) {
+    const double du2 = acc[0], u2 = acc[1];
+    double r;
+    if (u2 > 0.0)
+      r = sqrt(du2 / u2);
+    else
+      r = (du2 == 0.0) ? 0.0 : INFINITY;
+    record[0] = step;
+    record[1] = r;
+    record[2] = du2;
+    record[3] = u2;
+    record[4] = acc[2];
+    record[5] = acc[3] * inv_nx;
+    record[6] = acc[4];
+    record[7] = 0.0;
+  }
+}
+
+// -------------------------------------------------------------------- init --
+template <typename S>
+__global__ __launch_bounds__(kBlock) void fill_zero(S* __restrict__ p, int64_t count) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < count) Storage<S>::st(p + i, typename Storage<S>::R(0));
+}
+
+__global__ __launch_bounds__(kBlock) void fill_zero_f64(double* __restrict__ p, int64_t count) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < count) p[i] = 0.0;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void init_g(R* __restrict__ gout, int64_t stride, int N,
+                                                 MagArgs<R> m) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= N) return;
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int a = 0; a < Q7; ++a)
+      gout[static_cast<int64_t>(j * Q7 + a) * stride + i] = (a == 0 ? m.w_rest : m.w_axis) * m.Bw[j];
+}
+
+// ------------------------------------------------------------- launchers --
+static inline dim3 step_grid(const GridArgs& g) { return dim3(kXcd * g.blocks_per_xcd); }
+
+template <typename S>
+hipError_t launch_glbe_step(const GridArgs& g, const CollideArgs<typename Storage<S>::R>& c,
+                            const void* fin, void* fout, const void* force, bool field, bool check,
+                            double* usnap, double* partials, hipStream_t st) {
+  using R = typename Storage<S>::R;
+  const S* a = static_cast<const S*>(fin);
+  S* b = static_cast<S*>(fout);
+  const R* F = static_cast<const R*>(force);
+  if (check) {
+    if (field)
+      glbe_step<S, true, true><<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
+    else
+      glbe_step<S, true, false><<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
+  } else {
+    if (field)
+      glbe_step<S, false, true><<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
+    else
+      glbe_step<S, false, false><<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_glbe_step<double>(const GridArgs&, const CollideArgs<double>&, const void*,
+                                             void*, const void*, bool, bool, double*, double*,
+                                             hipStream_t);
+template hipError_t launch_glbe_step<float>(const GridArgs&, const CollideArgs<float>&, const void*,
+                                            void*, const void*, bool, bool, double*, double*,
+                                            hipStream_t);
+template hipError_t launch_glbe_step<bf16_t>(const GridArgs&, const CollideArgs<float>&, const void*,
+                                             void*, const void*, bool, bool, double*, double*,
+                                             hipStream_t);
+template hipError_t launch_glbe_step<_Float16>(const GridArgs&, const CollideArgs<float>&,
+                                               const void*, void*, const void*, bool, bool, double*,
+                                               double*, hipStream_t);
+
+template <typename R>
+hipError_t launch_mhd_step(const GridArgs& g, const CollideArgs<R>& c, const MagArgs<R>& m,
+                           const void* fin, void* fout, const void* gin, void* gout,
+                           const void* force, bool field, bool check, double* usnap,
+                           double* partials, hipStream_t st) {
+  const R* a = static_cast<const R*>(fin);
+  R* b = static_cast<R*>(fout);
+  const R* ga = static_cast<const R*>(gin);
+  R* gb = static_cast<R*>(gout);
+  const R* F = static_cast<const R*>(force);
+  if (check) {
+    if (field)
+      mhd_step<R, true, true><<<step_grid(g), kBlock, 0, st>>>(g, c, m, a, b, ga, gb, F, usnap, partials);
+    else
+      mhd_step<R, true, false><<<step_grid(g), kBlock, 0, st>>>(g, c, m, a, b, ga, gb, F, usnap, partials);
+  } else {
+    if (field)
+      mhd_step<R, false, true><<<step_grid(g), kBlock, 0, st>>>(g, c, m, a, b, ga, gb, F, usnap, partials);
+    else
+      mhd_step<R, false, false><<<step_grid(g), kBlock, 0, st>>>(g, c, m, a, b, ga, gb, F, usnap, partials);
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_mhd_step<double>(const GridArgs&, const CollideArgs<double>&,
+                                            const MagArgs<double>&, const void*, void*, const void*,
+                                            void*, const void*, bool, bool, double*, double*,
+                                            hipStream_t);
+template hipError_t launch_mhd_step<float>(const GridArgs&, const CollideArgs<float>&,
+                                           const MagArgs<float>&, const void*, void*, const void*,
+                                           void*, const void*, bool, bool, double*, double*,
+                                           hipStream_t);
+
+template <typename S>
+hipError_t launch_fields(const GridArgs& g, const CollideArgs<typename Storage<S>::R>& c,
+                         const MagArgs<typename Storage<S>::R>& m, bool mhd, const void* fin,
+                         const void* gin, const void* force, bool field, int out_dtype, void* rho,
+                         void* u, void* B, int64_t out_stride, double* partials, hipStream_t st) {
+  using R = typename Storage<S>::R;
+  const S* a = static_cast<const S*>(fin);
+  const R* ga = static_cast<const R*>(gin);
+  const R* F = static_cast<const R*>(force);
+  const int fl = field ? 1 : 0;
+  if (out_dtype == 0) {
+    double *r = static_cast<double*>(rho), *uu = static_cast<double*>(u), *bb = static_cast<double*>(B);
+    if (mhd)
+      fields_kernel<S, double, true><<<step_grid(g), kBlock, 0, st>>>(g, c, m, a, ga, F, fl, r, uu, bb, out_stride, partials);
+    else
+      fields_kernel<S, double, false><<<step_grid(g), kBlock, 0, st>>>(g, c, m, a, ga, F, fl, r, uu, bb, out_stride, partials);
+  } else {
+    float *r = static_cast<float*>(rho), *uu = static_cast<float*>(u), *bb = static_cast<float*>(B);
+    if (mhd)
+      fields_kernel<S, float, true><<<step_grid(g), kBlock, 0, st>>>(g, c, m, a, ga, F, fl, r, uu, bb, out_stride, partials);
+    else
+      fields_kernel<S, float, false><<<step_grid(g), kBlock, 0, st>>>(g, c, m, a, ga, F, fl, r, uu, bb, out_stride, partials);
+  }
+  return hipGetLastError();
+}
+
+#define LBM_INST_FIELDS(S)                                                                        \
+  template hipError_t launch_fields<S>(const GridArgs&, const CollideArgs<Storage<S>::R>&,       \
+                                       const MagArgs<Storage<S>::R>&, bool, const void*,          \
+                                       const void*, const void*, bool, int, void*, void*, void*, \
+                                       int64_t, double*, hipStream_t);
+LBM_INST_FIELDS(double)
+LBM_INST_FIELDS(float)
+LBM_INST_FIELDS(bf16_t)
+LBM_INST_FIELDS(_Float16)
+#undef LBM_INST_FIELDS
+
+hipError_t launch_finalize(const double* partials, int nblocks, double step, double inv_nx,
+                           double* record, hipStream_t st) {
+  finalize_kernel<<<1, kBlock, 0, st>>>(partials, nblocks, step, inv_nx, record);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_fill_zero(void* p, int64_t count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const int64_t blocks = (count + kBlock - 1) / kBlock;
+  fill_zero<S><<<dim3(static_cast<uint32_t>(blocks)), kBlock, 0, st>>>(static_cast<S*>(p), count);
+  return hipGetLastError();
+}
+template hipError_t launch_fill_zero<double>(void*, int64_t, hipStream_t);
+template hipError_t launch_fill_zero<float>(void*, int64_t, hipStream_t);
+template hipError_t launch_fill_zero<bf16_t>(void*, int64_t, hipStream_t);
+template hipError_t launch_fill_zero<_Float16>(void*, int64_t, hipStream_t);
+
+template <typename R>
+hipError_t launch_init_g(void* gout, int64_t stride, int N, const MagArgs<R>& m, hipStream_t st) {
+  const int64_t blocks = (static_cast<int64_t>(N) + kBlock - 1) / kBlock;
+  init_g<R><<<dim3(static_cast<uint32_t>(blocks)), kBlock, 0, st>>>(static_cast<R*>(gout), stride, N, m);
+  return hipGetLastError();
+}
+template hipError_t launch_init_g<double>(void*, int64_t, int, const MagArgs<double>&, hipStream_t);
+template hipError_t launch_init_g<float>(void*, int64_t, int, const MagArgs<float>&, hipStream_t);
+
+}  // namespace lbm

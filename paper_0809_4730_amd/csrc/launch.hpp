@@ -1,0 +1,45 @@
+// Host-side launchers of the gfx950 kernels (defined in kernels.hip and
+// adjoint.hip); used by the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace lbm {
+
+template <typename S>
+hipError_t launch_glbe_step(const GridArgs& g, const CollideArgs<typename Storage<S>::R>& c,
+                            const void* fin, void* fout, const void* force, bool field, bool check,
+                            double* usnap, double* partials, hipStream_t st);
+
+template <typename R>
+hipError_t launch_mhd_step(const GridArgs& g, const CollideArgs<R>& c, const MagArgs<R>& m,
+                           const void* fin, void* fout, const void* gin, void* gout,
+                           const void* force, bool field, bool check, double* usnap,
+                           double* partials, hipStream_t st);
+
+template <typename S>
+hipError_t launch_fields(const GridArgs& g, const CollideArgs<typename Storage<S>::R>& c,
+                         const MagArgs<typename Storage<S>::R>& m, bool mhd, const void* fin,
+                         const void* gin, const void* force, bool field, int out_dtype, void* rho,
+                         void* u, void* B, int64_t out_stride, double* partials, hipStream_t st);
+
+hipError_t launch_finalize(const double* partials, int nblocks, double step, double inv_nx,
+                           double* record, hipStream_t st);
+
+template <typename S>
+hipError_t launch_fill_zero(void* p, int64_t count, hipStream_t st);
+
+template <typename R>
+hipError_t launch_init_g(void* gout, int64_t stride, int N, const MagArgs<R>& m, hipStream_t st);
+
+// ---------------------------------------------------------------- adjoint --
+// One transposed step of the linearised map (adjoint.hip).
+template <typename R>
+hipError_t launch_adjoint(const GridArgs& g, const CollideArgs<R>& c, const void* state,
+                          const void* force, bool field, const void* mu_in, void* mu_out,
+                          void* grad, int64_t grad_stride, int grad_mode, const double* shift,
+                          R q_scale, R grad_direct, bool check, double* partials, hipStream_t st);
+
+}  // namespace lbm

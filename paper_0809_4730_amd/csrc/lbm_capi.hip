@@ -1,0 +1,571 @@
+// Host side of the C ABI declared in include/lbm_capi.h: validation, workspace
+// layout inside caller-owned device memory, the time-step loop on the
+// caller's stream, and the residual history.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm_capi.h"
+#include "ctx.hpp"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool is_conserved(int k) { return k == 0 || k == 3 || k == 5 || k == 7; }
+
+std::string validate(const lbm_grid* grid, const lbm_params* p) {
+  if (!grid || !p) return "grid and params must be non-null";
+  int64_t N = 1;
+  for (int a = 0; a < 3; ++a) {
+    if (grid->n[a] < 1) return "grid dimensions must be >= 1";
+    if (grid->bc[a] != LBM_PERIODIC && grid->bc[a] != LBM_WALL) return "bc must be LBM_PERIODIC or LBM_WALL";
+    N *= grid->n[a];
+  }
+  if (N >= (int64_t(1) << 31)) return "grid has 2^31 or more nodes";
+  if (storage_bytes(p->storage) == 0) return "storage must be LBM_F64, LBM_F32, LBM_BF16 or LBM_F16";
+  if (!(p->gamma > 0.0 && p->gamma <= 1.0)) return "gamma must lie in (0, 1]";
+  for (int k = 0; k < 19; ++k)
+    if (!is_conserved(k) && !(p->s[k] > 0.0 && p->s[k] < 2.0)) {
+      char buf[96];
+      std::snprintf(buf, sizeof buf, "rate s[%d] = %g outside (0, 2)", k, p->s[k]);
+      return buf;
+    }
+  if (!(p->rho0 > 0.0)) return "rho0 must be positive";
+  if (p->force_mode != LBM_FORCE_UNIFORM && p->force_mode != LBM_FORCE_FIELD)
+    return "force_mode must be LBM_FORCE_UNIFORM or LBM_FORCE_FIELD";
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(p->force_const[a])) return "force_const must be finite";
+  if (p->mhd != 0 && p->mhd != 1) return "mhd must be 0 or 1";
+  if (p->mhd) {
+    if (p->storage != LBM_F64 && p->storage != LBM_F32) return "mhd needs LBM_F64 or LBM_F32 storage";
+    if (!(p->gamma_m > 0.0 && p->gamma_m <= 1.0)) return "gamma_m must lie in (0, 1]";
+    if (!(p->chi > 0.0)) return "chi must be positive";
+    if (!(p->eta > 0.0)) return "eta must be positive";
+    if (!(p->mu > 0.0)) return "mu must be positive";
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(p->B0[a])) return "B0 must be finite";
+  }
+  if (p->check_every < 1) return "check_every must be >= 1";
+  if (p->history_len < 1) return "history_len must be >= 1";
+  return "";
+}
+
+Layout make_layout(const lbm_grid* grid, const lbm_params* p) {
+  Layout L;
+  L.N = int64_t(grid->n[0]) * grid->n[1] * grid->n[2];
+  L.stride = (L.N + 63) / 64 * 64;
+  L.nblocks = static_cast<int32_t>((L.N + kBlock - 1) / kBlock);
+  const size_t es = storage_bytes(p->storage), cs = compute_bytes(p->storage);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  L.f[0] = take(19 * L.stride * es);
+  L.f[1] = take(19 * L.stride * es);
+  if (p->mhd) {
+    L.g[0] = take(21 * L.stride * cs);
+    L.g[1] = take(21 * L.stride * cs);
+  }
+  if (p->force_mode == LBM_FORCE_FIELD) L.force = take(3 * L.stride * cs);
+  L.usnap = take(3 * L.stride * sizeof(double));
+  L.partials = take(size_t(L.nblocks) * kPartials * sizeof(double));
+  L.ring = take(size_t(p->history_len) * kRecordDoubles * sizeof(double));
+  L.rec = take(kRecordDoubles * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+namespace lbm {
+
+lbm_status fail(lbm_ctx* c, lbm_status s, const std::string& msg) {
+  if (c) c->err = msg; else g_create_error = msg;
+  return s;
+}
+
+lbm_status hip_fail(lbm_ctx* c, hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(c, LBM_EHIP, m);
+}
+
+
+template <typename R>
+CollideArgs<R> collide_args(const lbm_params& p) {
+  CollideArgs<R> c;
+  c.rho0 = R(p.rho0);
+  c.inv_gamma = R(1.0 / p.gamma);
+  c.inv_gamma2 = R(1.0 / (p.gamma * p.gamma));
+  c.half_inv_gamma = R(0.5 / p.gamma);
+  for (int k = 0; k < 19; ++k) {
+    c.A[k] = R(p.s[k] / NORM19[k]);
+    c.B[k] = R((1.0 - 0.5 * p.s[k]) / NORM19[k]);
+  }
+  for (int a = 0; a < 3; ++a) c.F[a] = R(p.force_const[a]);
+  return c;
+}
+
+template <typename R>
+MagArgs<R> mag_args(const lbm_params& p) {
+  MagArgs<R> m{};
+  if (!p.mhd) {
+    m.w_rest = R(W7_REST);
+    m.w_axis = R(W7_AXIS);
+    return m;
+  }
+  const double tau = p.eta / (p.gamma_m * THETA_M) + 0.5;
+  m.omega = R(1.0 / tau);
+  m.adv = R(p.chi / (p.gamma_m * THETA_M));
+  m.a_coef = R(-1.0 / (p.mu * p.chi * tau * THETA_M));
+  m.kappa = R(2.0 / (p.mu * p.gamma_m * tau * THETA_M));
+  for (int a = 0; a < 3; ++a) m.Bw[a] = R(p.B0[a]);
+  m.w_rest = R(W7_REST);
+  m.w_axis = R(W7_AXIS);
+  return m;
+}
+
+hipError_t launch_step_kernel(lbm_ctx* c, bool check) {
+  const void* fin = c->f(c->cur);
+  void* fout = c->f(c->cur ^ 1);
+  const bool fld = c->field();
+  if (c->p.mhd) {
+    if (c->p.storage == LBM_F64)
+      return launch_mhd_step<double>(c->ga, c->cd, c->md, fin, fout, c->g(c->cur), c->g(c->cur ^ 1),
+                                     c->force(), fld, check, c->usnap(), c->partials(), c->stream);
+    return launch_mhd_step<float>(c->ga, c->cf, c->mf, fin, fout, c->g(c->cur), c->g(c->cur ^ 1),
+                                  c->force(), fld, check, c->usnap(), c->partials(), c->stream);
+  }
+  switch (c->p.storage) {
+    case LBM_F64:
+      return launch_glbe_step<double>(c->ga, c->cd, fin, fout, c->force(), fld, check, c->usnap(),
+                                      c->partials(), c->stream);
+    case LBM_F32:
+      return launch_glbe_step<float>(c->ga, c->cf, fin, fout, c->force(), fld, check, c->usnap(),
+                                     c->partials(), c->stream);
+    case LBM_BF16:
+      return launch_glbe_step<bf16_t>(c->ga, c->cf, fin, fout, c->force(), fld, check, c->usnap(),
+                                      c->partials(), c->stream);
+    default:
+      return launch_glbe_step<_Float16>(c->ga, c->cf, fin, fout, c->force(), fld, check,
+                                        c->usnap(), c->partials(), c->stream);
+  }
+}
+
+// Enqueue one step (and its history record when due).
+lbm_status one_step(lbm_ctx* c, hipEvent_t ev0, hipEvent_t ev1) {
+  const int64_t next = c->step + 1;
+  const bool check = (next % c->p.check_every) == 0;
+  if (ev0) LBM_HIP(c, hipEventRecord(ev0, c->stream), "hipEventRecord");
+  LBM_HIP(c, launch_step_kernel(c, check), "step kernel launch");
+  if (ev1) LBM_HIP(c, hipEventRecord(ev1, c->stream), "hipEventRecord");
+  c->cur ^= 1;
+  c->step = next;
+  if (check) {
+    double* rec = c->ring() + (c->checks % c->p.history_len) * kRecordDoubles;
+    LBM_HIP(c, launch_finalize(c->partials(), c->L.nblocks, double(next), 1.0 / c->grid.n[0], rec,
+                               c->stream),
+            "finalize launch");
+    ++c->checks;
+  }
+  return LBM_OK;
+}
+
+template <typename S>
+hipError_t fields_dispatch(lbm_ctx* c, int out_dtype, void* rho, void* u, void* B) {
+  using R = typename Storage<S>::R;
+  const CollideArgs<R>* ca;
+  const MagArgs<R>* ma;
+  if constexpr (sizeof(R) == 8) {
+    ca = &c->cd;
+    ma = &c->md;
+  } else {
+    ca = &c->cf;
+    ma = &c->mf;
+  }
+  return launch_fields<S>(c->ga, *ca, *ma, c->p.mhd != 0, c->f(c->cur), c->g(c->cur), c->force(),
+                          c->field(), out_dtype, rho, u, B, c->L.N, c->partials(), c->stream);
+}
+
+hipError_t launch_fields_any(lbm_ctx* c, int out_dtype, void* rho, void* u, void* B) {
+  switch (c->p.storage) {
+    case LBM_F64: return fields_dispatch<double>(c, out_dtype, rho, u, B);
+    case LBM_F32: return fields_dispatch<float>(c, out_dtype, rho, u, B);
+    case LBM_BF16: return fields_dispatch<bf16_t>(c, out_dtype, rho, u, B);
+    default: return fields_dispatch<_Float16>(c, out_dtype, rho, u, B);
+  }
+}
+
+hipError_t zero_storage(lbm_ctx* c, void* p, int64_t count) {
+  switch (c->p.storage) {
+    case LBM_F64: return launch_fill_zero<double>(p, count, c->stream);
+    case LBM_F32: return launch_fill_zero<float>(p, count, c->stream);
+    case LBM_BF16: return launch_fill_zero<bf16_t>(p, count, c->stream);
+    default: return launch_fill_zero<_Float16>(p, count, c->stream);
+  }
+}
+
+lbm_status copy_force_in(lbm_ctx* c, const void* force) {
+  const size_t cs = c->celem();
+  LBM_HIP(c, hipMemcpy2DAsync(c->force(), c->L.stride * cs, force, c->L.N * cs, c->L.N * cs, 3,
+                              hipMemcpyDeviceToDevice, c->stream),
+          "force copy");
+  return LBM_OK;
+}
+
+lbm_status read_records(lbm_ctx* c, int64_t first, int64_t count, std::vector<double>& out) {
+  // records first .. first+count-1 (global indices), all still inside the ring
+  out.assign(size_t(count) * kRecordDoubles, 0.0);
+  const int64_t len = c->p.history_len;
+  std::vector<double> ring(size_t(len) * kRecordDoubles);
+  LBM_HIP(c, hipMemcpyAsync(ring.data(), c->ring(), ring.size() * sizeof(double),
+                            hipMemcpyDeviceToHost, c->stream),
+          "history copy");
+  LBM_HIP(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  for (int64_t i = 0; i < count; ++i) {
+    const int64_t slot = (first + i) % len;
+    std::memcpy(&out[size_t(i) * kRecordDoubles], &ring[size_t(slot) * kRecordDoubles],
+                kRecordDoubles * sizeof(double));
+  }
+  return LBM_OK;
+}
+
+}  // namespace lbm
+
+extern "C" {
+
+lbm_status lbm_default_rates(double nu, double gamma, int32_t mode, double Lambda, double s_out[19]) {
+  if (!s_out) return fail(nullptr, LBM_EINVAL, "s_out is NULL");
+  if (!(nu > 0.0)) return fail(nullptr, LBM_EINVAL, "nu must be positive");
+  if (!(gamma > 0.0 && gamma <= 1.0)) return fail(nullptr, LBM_EINVAL, "gamma must lie in (0, 1]");
+  if (mode != 0 && mode != 1) return fail(nullptr, LBM_EINVAL, "mode must be 0 or 1");
+  if (mode == 1 && !(Lambda > 0.0)) return fail(nullptr, LBM_EINVAL, "Lambda must be positive");
+  for (int k = 0; k < 19; ++k) s_out[k] = 1.0;
+  const double s_nu = 1.0 / (3.0 * nu / gamma + 0.5);
+  for (int k : {9, 11, 13, 14, 15}) s_out[k] = s_nu;
+  s_out[1] = 1.19;
+  for (int k : {2, 10, 12}) s_out[k] = 1.4;
+  if (mode == 0) {
+    for (int k : {4, 6, 8}) s_out[k] = 1.2;
+    for (int k : {16, 17, 18}) s_out[k] = 1.98;
+  } else {
+    const double s_q = 1.0 / (Lambda * gamma / (3.0 * nu) + 0.5);
+    for (int k : {4, 6, 8, 16, 17, 18}) s_out[k] = s_q;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_lattice_velocities(int32_t q, int32_t* e_out) {
+  if (!e_out) return fail(nullptr, LBM_EINVAL, "e_out is NULL");
+  if (q == 19) {
+    for (int a = 0; a < 19; ++a) {
+      e_out[3 * a] = EX19[a];
+      e_out[3 * a + 1] = EY19[a];
+      e_out[3 * a + 2] = EZ19[a];
+    }
+    return LBM_OK;
+  }
+  if (q == 7) {
+    for (int a = 0; a < 7; ++a) {
+      e_out[3 * a] = EX7[a];
+      e_out[3 * a + 1] = EY7[a];
+      e_out[3 * a + 2] = EZ7[a];
+    }
+    return LBM_OK;
+  }
+  return fail(nullptr, LBM_EINVAL, "q must be 19 or 7");
+}
+
+lbm_status lbm_workspace_bytes(const lbm_grid* grid, const lbm_params* params, size_t* bytes) {
+  if (!bytes) return fail(nullptr, LBM_EINVAL, "bytes is NULL");
+  const std::string v = validate(grid, params);
+  if (!v.empty()) return fail(nullptr, LBM_EINVAL, v);
+  *bytes = make_layout(grid, params).total;
+  return LBM_OK;
+}
+
+lbm_status lbm_create(const lbm_grid* grid, const lbm_params* params, const void* force,
+                      void* workspace, size_t workspace_bytes, void* hip_stream, lbm_ctx** out) {
+  if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  const std::string v = validate(grid, params);
+  if (!v.empty()) return fail(nullptr, LBM_EINVAL, v);
+  if (params->force_mode == LBM_FORCE_FIELD && !force)
+    return fail(nullptr, LBM_EINVAL, "force_mode = FIELD needs a force pointer");
+  const Layout L = make_layout(grid, params);
+  if (!workspace) return fail(nullptr, LBM_ENOWS, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+    return fail(nullptr, LBM_ENOWS, "workspace must be 256-byte aligned");
+  if (workspace_bytes < L.total) return fail(nullptr, LBM_ENOWS, "workspace too small");
+
+  lbm_ctx* c = new lbm_ctx();
+  c->grid = *grid;
+  c->p = *params;
+  c->L = L;
+  c->ws = static_cast<char*>(workspace);
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  GridArgs& g = c->ga;
+  g.nx = grid->n[0];
+  g.ny = grid->n[1];
+  g.nz = grid->n[2];
+  g.wall_x = grid->bc[0] == LBM_WALL;
+  g.wall_y = grid->bc[1] == LBM_WALL;
+  g.wall_z = grid->bc[2] == LBM_WALL;
+  g.N = static_cast<int32_t>(L.N);
+  g.nblocks = L.nblocks;
+  g.blocks_per_xcd = (L.nblocks + kXcd - 1) / kXcd;
+  g.pad = 0;
+  g.stride = L.stride;
+  g.div_nx = make_fastdiv(static_cast<uint32_t>(g.nx));
+  g.div_nxny = make_fastdiv(static_cast<uint32_t>(g.nx * g.ny));
+  c->cd = collide_args<double>(c->p);
+  c->cf = collide_args<float>(c->p);
+  c->md = mag_args<double>(c->p);
+  c->mf = mag_args<float>(c->p);
+
+  hipError_t e = zero_storage(c, c->f(0), 19 * L.stride);
+  if (e == hipSuccess) e = zero_storage(c, c->f(1), 19 * L.stride);
+  if (e == hipSuccess) e = launch_fill_zero<double>(c->usnap(), 3 * L.stride, c->stream);
+  if (e == hipSuccess) e = launch_fill_zero<double>(c->ring(), int64_t(params->history_len) * kRecordDoubles, c->stream);
+  if (e == hipSuccess && params->mhd) {
+    if (params->storage == LBM_F64) {
+      e = launch_init_g<double>(c->g(0), L.stride, g.N, c->md, c->stream);
+      if (e == hipSuccess) e = launch_init_g<double>(c->g(1), L.stride, g.N, c->md, c->stream);
+    } else {
+      e = launch_init_g<float>(c->g(0), L.stride, g.N, c->mf, c->stream);
+      if (e == hipSuccess) e = launch_init_g<float>(c->g(1), L.stride, g.N, c->mf, c->stream);
+    }
+  }
+  if (e != hipSuccess) {
+    g_create_error = std::string("initialisation: ") + hipGetErrorString(e);
+    delete c;
+    return LBM_EHIP;
+  }
+  if (c->field()) {
+    if (copy_force_in(c, force) != LBM_OK) {
+      g_create_error = c->err;
+      delete c;
+      return LBM_EHIP;
+    }
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* ctx) {
+  if (!ctx) return;
+  for (hipEvent_t ev : ctx->events) (void)hipEventDestroy(ev);
+  delete ctx;
+}
+
+lbm_status lbm_set_force(lbm_ctx* c, const void* force) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (!c->field()) return fail(c, LBM_ESTATE, "context was created with a uniform force");
+  if (!force) return fail(c, LBM_EINVAL, "force is NULL");
+  return copy_force_in(c, force);
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t n) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (n < 0) return fail(c, LBM_EINVAL, "n must be >= 0");
+  for (int64_t i = 0; i < n; ++i) {
+    const lbm_status s = one_step(c);
+    if (s != LBM_OK) return s;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_step_timed(lbm_ctx* c, int64_t n, double* mean_kernel_us, double* wall_ms) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (n < 1 || !mean_kernel_us || !wall_ms) return fail(c, LBM_EINVAL, "need n >= 1 and outputs");
+  constexpr int kPool = 512;
+  while (c->events.size() < 2 * kPool + 2) {
+    hipEvent_t ev;
+    LBM_HIP(c, hipEventCreate(&ev), "hipEventCreate");
+    c->events.push_back(ev);
+  }
+  hipEvent_t wall0 = c->events[2 * kPool], wall1 = c->events[2 * kPool + 1];
+  double total_ms = 0.0;
+  LBM_HIP(c, hipEventRecord(wall0, c->stream), "hipEventRecord");
+  int64_t done = 0;
+  while (done < n) {
+    const int64_t chunk = std::min<int64_t>(kPool, n - done);
+    for (int64_t i = 0; i < chunk; ++i) {
+      const lbm_status s = one_step(c, c->events[2 * i], c->events[2 * i + 1]);
+      if (s != LBM_OK) return s;
+    }
+    LBM_HIP(c, hipEventSynchronize(c->events[2 * (chunk - 1) + 1]), "hipEventSynchronize");
+    for (int64_t i = 0; i < chunk; ++i) {
+      float ms = 0.0f;
+      LBM_HIP(c, hipEventElapsedTime(&ms, c->events[2 * i], c->events[2 * i + 1]), "hipEventElapsedTime");
+      total_ms += ms;
+    }
+    done += chunk;
+  }
+  LBM_HIP(c, hipEventRecord(wall1, c->stream), "hipEventRecord");
+  LBM_HIP(c, hipEventSynchronize(wall1), "hipEventSynchronize");
+  float wms = 0.0f;
+  LBM_HIP(c, hipEventElapsedTime(&wms, wall0, wall1), "hipEventElapsedTime");
+  *mean_kernel_us = 1000.0 * total_ms / double(n);
+  *wall_ms = wms;
+  return LBM_OK;
+}
+
+lbm_status lbm_residual(lbm_ctx* c, double* residual, int64_t* at_step) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (c->checks == 0) return fail(c, LBM_ESTATE, "no residual check has run yet");
+  std::vector<double> r;
+  const lbm_status s = read_records(c, c->checks - 1, 1, r);
+  if (s != LBM_OK) return s;
+  if (residual) *residual = r[1];
+  if (at_step) *at_step = static_cast<int64_t>(r[0]);
+  if (r[6] > 0.0) return fail(c, LBM_EUNSTABLE, "non-finite values at the last check");
+  return LBM_OK;
+}
+
+lbm_status lbm_history(lbm_ctx* c, lbm_record* out, int64_t max_records, int64_t* n_out) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (!out || !n_out || max_records < 0) return fail(c, LBM_EINVAL, "bad output arguments");
+  const int64_t avail = std::min<int64_t>(c->checks, c->p.history_len);
+  const int64_t cnt = std::min(avail, max_records);
+  std::vector<double> r;
+  const lbm_status s = read_records(c, c->checks - cnt, cnt, r);
+  if (s != LBM_OK) return s;
+  std::memcpy(out, r.data(), size_t(cnt) * sizeof(lbm_record));
+  *n_out = cnt;
+  return LBM_OK;
+}
+
+lbm_status lbm_run_to_residual(lbm_ctx* c, double tol, int64_t max_steps, int64_t poll_every,
+                               int64_t* steps_to_tol, double* final_residual) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (!(tol > 0.0) || max_steps < 0 || poll_every < 1 || !steps_to_tol || !final_residual)
+    return fail(c, LBM_EINVAL, "bad arguments");
+  const int64_t ce = c->p.check_every;
+  const int64_t cap = int64_t(c->p.history_len) * ce;
+  int64_t chunk = std::max<int64_t>(ce, poll_every / ce * ce);
+  chunk = std::min(chunk, cap);
+  *steps_to_tol = -1;
+  *final_residual = NAN;
+  double rmin = INFINITY;
+  int64_t taken = 0;
+  std::vector<double> r;
+  while (taken < max_steps) {
+    const int64_t todo = std::min(chunk, max_steps - taken);
+    const int64_t first = c->checks;
+    lbm_status s = lbm_step(c, todo);
+    if (s != LBM_OK) return s;
+    taken += todo;
+    const int64_t cnt = c->checks - first;
+    if (cnt == 0) continue;
+    s = read_records(c, first, cnt, r);
+    if (s != LBM_OK) return s;
+    for (int64_t i = 0; i < cnt; ++i) {
+      const double* rec = &r[size_t(i) * kRecordDoubles];
+      *final_residual = rec[1];
+      if (rec[6] > 0.0 || std::isnan(rec[1]))
+        return fail(c, LBM_EUNSTABLE, "non-finite values during the march");
+      if (first + i >= 1) {  // the first record compares against zero velocity
+        rmin = std::min(rmin, rec[1]);
+        if (rec[1] > 1e-2 && rec[1] > 1e3 * rmin)
+          return fail(c, LBM_EUNSTABLE, "residual grew 1e3-fold over its minimum");
+      }
+      if (first + i >= 1 && rec[1] < tol) {
+        *steps_to_tol = static_cast<int64_t>(rec[0]);
+        return LBM_OK;
+      }
+    }
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_reductions(lbm_ctx* c, double* mass_drift, double* flow_rate) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (!mass_drift || !flow_rate) return fail(c, LBM_EINVAL, "outputs are NULL");
+  LBM_HIP(c, launch_fields_any(c, 0, nullptr, nullptr, nullptr), "fields launch");
+  LBM_HIP(c, launch_finalize(c->partials(), c->L.nblocks, double(c->step), 1.0 / c->grid.n[0],
+                             c->rec(), c->stream),
+          "finalize launch");
+  double rec[kRecordDoubles];
+  LBM_HIP(c, hipMemcpyAsync(rec, c->rec(), sizeof rec, hipMemcpyDeviceToHost, c->stream), "copy");
+  LBM_HIP(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  *mass_drift = rec[4];
+  *flow_rate = rec[5];
+  return LBM_OK;
+}
+
+lbm_status lbm_moments(lbm_ctx* c, int32_t out_dtype, void* rho, void* u, void* B) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (out_dtype != LBM_F64 && out_dtype != LBM_F32) return fail(c, LBM_EINVAL, "out_dtype must be F64 or F32");
+  if (B && !c->p.mhd) return fail(c, LBM_EINVAL, "B requested without mhd");
+  LBM_HIP(c, launch_fields_any(c, out_dtype == LBM_F64 ? 0 : 1, rho, u, B), "fields launch");
+  return LBM_OK;
+}
+
+lbm_status lbm_state_bytes(const lbm_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return fail(nullptr, LBM_EINVAL, "NULL argument");
+  *bytes = 19 * c->L.N * c->elem() + (c->p.mhd ? 21 * c->L.N * c->celem() : 0);
+  return LBM_OK;
+}
+
+lbm_status lbm_get_state(lbm_ctx* c, void* dst) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (!dst) return fail(c, LBM_EINVAL, "dst is NULL");
+  const size_t es = c->elem(), N = size_t(c->L.N), st = size_t(c->L.stride);
+  LBM_HIP(c, hipMemcpy2DAsync(dst, N * es, c->f(c->cur), st * es, N * es, 19, hipMemcpyDeviceToDevice,
+                              c->stream),
+          "state copy");
+  if (c->p.mhd) {
+    const size_t cs = c->celem();
+    char* gdst = static_cast<char*>(dst) + 19 * N * es;
+    LBM_HIP(c, hipMemcpy2DAsync(gdst, N * cs, c->g(c->cur), st * cs, N * cs, 21,
+                                hipMemcpyDeviceToDevice, c->stream),
+            "state copy");
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_set_state(lbm_ctx* c, const void* src, int64_t step) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (!src || step < 0) return fail(c, LBM_EINVAL, "src is NULL or step < 0");
+  const size_t es = c->elem(), N = size_t(c->L.N), st = size_t(c->L.stride);
+  LBM_HIP(c, hipMemcpy2DAsync(c->f(c->cur), st * es, src, N * es, N * es, 19, hipMemcpyDeviceToDevice,
+                              c->stream),
+          "state copy");
+  if (c->p.mhd) {
+    const size_t cs = c->celem();
+    const char* gsrc = static_cast<const char*>(src) + 19 * N * es;
+    LBM_HIP(c, hipMemcpy2DAsync(c->g(c->cur), st * cs, gsrc, N * cs, N * cs, 21,
+                                hipMemcpyDeviceToDevice, c->stream),
+            "state copy");
+  }
+  LBM_HIP(c, launch_fill_zero<double>(c->usnap(), 3 * c->L.stride, c->stream), "fill");
+  c->step = step;
+  c->checks = 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_step(const lbm_ctx* c, int64_t* step) {
+  if (!c || !step) return fail(nullptr, LBM_EINVAL, "NULL argument");
+  *step = c->step;
+  return LBM_OK;
+}
+
+const char* lbm_last_error(const lbm_ctx* c) {
+  return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

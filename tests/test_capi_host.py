@@ -1,0 +1,146 @@
+"""Host-side checks of the C ABI: the library builds and loads, exports every
+entry point the header declares, and its validation and host helpers agree
+with the paper (no kernel is launched here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import glbe
+from oracle.lattice import E19, E7
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm_capi.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_0809_4730_amd as pkg
+    if not os.path.exists(pkg.library_path()):
+        from paper_0809_4730_amd import build
+        build.build()
+    return pkg.load_library()
+
+
+def _declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_named_calls():
+    names = _declared_symbols()
+    for n in ("lbm_create", "lbm_step", "lbm_residual", "lbm_moments", "lbm_destroy",
+              "lbm_reductions", "lbm_adjoint_steady", "lbm_adjoint_unrolled"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared_symbols():
+        assert hasattr(lib, name), name
+
+
+def test_library_has_gfx950_code_only():
+    import paper_0809_4730_amd as pkg
+    blob = open(pkg.library_path(), "rb").read()
+    assert b"gfx950" in blob
+    for other in (b"gfx942", b"gfx90a", b"gfx1100"):
+        assert other not in blob
+
+
+@pytest.mark.parametrize("nu,gamma", [(0.1, 1.0), (0.131, 0.05), (0.004, 0.05)])
+def test_default_rates_match_oracle(lib, nu, gamma):
+    import paper_0809_4730_amd as pkg
+    assert np.allclose(pkg.default_rates(nu, gamma), glbe.rates(nu, gamma), rtol=1e-15)
+    assert np.allclose(pkg.default_rates(nu, gamma, "lambda", 0.3),
+                       glbe.rates(nu, gamma, "lambda", 0.3), rtol=1e-15)
+
+
+def test_lattice_velocities(lib):
+    import paper_0809_4730_amd as pkg
+    e19 = pkg.lattice_velocities(19)
+    assert sorted(map(tuple, e19)) == sorted(map(tuple, E19))
+    # opposite pairs are adjacent (the kernels rely on it)
+    for a in range(1, 19, 2):
+        assert tuple(e19[a]) == tuple(-e19[a + 1])
+    e7 = pkg.lattice_velocities(7)
+    assert sorted(map(tuple, e7)) == sorted(map(tuple, E7))
+
+
+def _grid_params(pkg, **kw):
+    g = pkg._Grid()
+    for a, n in enumerate(kw.get("n", (8, 8, 8))):
+        g.n[a] = n
+        g.bc[a] = kw.get("bc", (0, 0, 1))[a]
+    p = pkg._Params()
+    p.storage = kw.get("storage", pkg.F32)
+    p.gamma = kw.get("gamma", 0.5)
+    for k, v in enumerate(glbe.rates(0.1, 0.5)):
+        p.s[k] = v
+    p.rho0 = 1.0
+    p.force_mode = 0
+    p.check_every = 10
+    p.history_len = 16
+    p.mhd = kw.get("mhd", 0)
+    p.gamma_m, p.chi, p.eta, p.mu = 0.1, 0.01, 0.025, 1.0
+    return g, p
+
+
+@pytest.mark.parametrize("bad", [
+    dict(gamma=0.0), dict(gamma=1.5), dict(n=(0, 4, 4)), dict(storage=7),
+    dict(mhd=1, storage=2), dict(n=(2048, 2048, 1024)),
+])
+def test_validation_rejects(lib, bad):
+    import paper_0809_4730_amd as pkg
+    g, p = _grid_params(pkg, **bad)
+    nbytes = ctypes.c_size_t()
+    st = lib.lbm_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nbytes))
+    assert st == -1
+    assert lib.lbm_last_error(None)
+
+
+def test_rate_outside_interval_rejected(lib):
+    import paper_0809_4730_amd as pkg
+    g, p = _grid_params(pkg)
+    p.s[9] = 2.0
+    nbytes = ctypes.c_size_t()
+    assert lib.lbm_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nbytes)) == -1
+    assert b"s[9]" in lib.lbm_last_error(None)
+    p.s[9] = 1.0
+    p.s[3] = 5.0   # conserved moment: ignored
+    assert lib.lbm_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nbytes)) == 0
+
+
+def test_workspace_size_and_create_checks(lib):
+    import paper_0809_4730_amd as pkg
+    g, p = _grid_params(pkg, n=(64, 64, 64))
+    nbytes = ctypes.c_size_t()
+    assert lib.lbm_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nbytes)) == 0
+    N = 64 ** 3
+    assert nbytes.value >= 2 * 19 * N * 4 + 3 * N * 8
+    assert nbytes.value < 2 * 19 * N * 4 + 3 * N * 8 + (1 << 20)
+    ctx = ctypes.c_void_p()
+    # NULL workspace and misaligned workspace are rejected before any device call
+    st = lib.lbm_create(ctypes.byref(g), ctypes.byref(p), None, None, nbytes.value, None,
+                        ctypes.byref(ctx))
+    assert st == -2 and not ctx.value
+    st = lib.lbm_create(ctypes.byref(g), ctypes.byref(p), None, 0x1001, nbytes.value, None,
+                        ctypes.byref(ctx))
+    assert st == -2
+    st = lib.lbm_create(ctypes.byref(g), ctypes.byref(p), None, 0x10000, nbytes.value - 1, None,
+                        ctypes.byref(ctx))
+    assert st == -2
+    p.force_mode = 1
+    st = lib.lbm_create(ctypes.byref(g), ctypes.byref(p), None, 0x10000, nbytes.value, None,
+                        ctypes.byref(ctx))
+    assert st == -1
+
+
+def test_product_path_refuses_missing_library(monkeypatch, tmp_path):
+    import paper_0809_4730_amd as pkg
+    monkeypatch.setattr(pkg, "_LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(pkg, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        pkg.load_library()

@@ -1,0 +1,120 @@
+"""GPU parity of the coupled GLBE + D3Q7 induction LKE step (Sec. 4, 4.1).
+
+FP64 storage matches the oracle to 1e-12 relative; FP32 to FP32 rounding; the
+Hartmann workload (32x32x128, FP32, gamma = gamma_m = 0.1) reaches the textbook
+profiles within the discretisation error of the oracle at the same resolution.
+"""
+import numpy as np
+import pytest
+
+from oracle import glbe, mhd
+from oracle.lattice import W7
+from paper_0809_4730_amd import inputs
+from tests.gpu_util import announce, from_gpu_f, from_gpu_g, rel, to_gpu_f, to_gpu_g
+
+pytestmark = pytest.mark.gpu
+PER, WALL = "periodic", "wall"
+
+
+def _mhd_sim(shape, bc, gamma, s, storage, F, p):
+    import paper_0809_4730_amd as pkg
+    return pkg.Simulation(shape, bc, gamma, s, storage=storage, force=tuple(F), mhd=p)
+
+
+def _random_g(shape, seed, B0, amp=1e-4):
+    nx, ny, nz = shape
+    g = mhd.initial_g(shape, B0)
+    g += inputs.random_deviations(shape, seed=seed, amp=amp, q=21).reshape(3, 7, nz, ny, nx)
+    return g
+
+
+@pytest.mark.parametrize("shape,bc", [((6, 8, 5), (PER, WALL, PER)),
+                                      ((5, 6, 7), (WALL, WALL, WALL)),
+                                      ((8, 4, 4), (PER, PER, PER))])
+@pytest.mark.parametrize("nsteps", [1, 40])
+def test_mhd_fp64_matches_oracle(shape, bc, nsteps):
+    import torch
+    announce("mhd fp64 %s %s n=%d" % (shape, bc, nsteps))
+    gamma, gm = 0.2, 0.3
+    B0 = np.array([0.01, 0.03, -0.02])
+    p = dict(gamma_m=gm, chi=0.05, eta=0.02, B0=tuple(B0))
+    s = glbe.rates(0.05, gamma)
+    F = np.array([1e-5, 2e-6, -3e-6])
+    f0 = inputs.random_deviations(shape, seed=11, amp=1e-3)
+    g0 = _random_g(shape, 12, B0)
+    sim = _mhd_sim(shape, bc, gamma, s, "f64", F, p)
+    sim.set_state(to_gpu_f(f0, torch.float64), to_gpu_g(g0, torch.float64))
+    sim.step(nsteps)
+    fg, gg = sim.get_state()
+    fo, go = f0, g0
+    pp = dict(gamma=gamma, s=s, gamma_m=gm, chi=p["chi"], eta=p["eta"], B_wall=B0)
+    Ff = inputs.uniform_force(shape, F)
+    for _ in range(nsteps):
+        fo, go, u, B = mhd.step(fo, go, Ff, pp, bc)
+    assert rel(from_gpu_f(fg), fo) < 1e-12
+    assert rel(from_gpu_g(gg), go) < 1e-13
+    rho, ug, Bg = sim.moments("f64")
+    # fields of the streamed current state, with the self-consistent Lorentz force
+    f_s = glbe.stream(fo, bc)
+    g_s = mhd.stream_g(go, bc, B0)
+    rho_o, u_o, B_o, J_o, F_o = mhd.coupled_fields(f_s, g_s, Ff, gamma, gm, p["chi"], p["eta"])
+    assert rel(ug.cpu().numpy(), u_o) < 1e-11
+    assert rel(Bg.cpu().numpy(), B_o) < 1e-14
+
+
+def test_mhd_fp32_single_step():
+    import torch
+    shape, bc = (6, 8, 5), (PER, WALL, PER)
+    gamma, gm = 0.1, 0.1
+    B0 = np.array([0.0, 0.03, 0.0])
+    p = dict(gamma_m=gm, chi=0.01, eta=0.025, B0=tuple(B0))
+    s = glbe.rates(0.1, gamma)
+    F = np.array([1e-5, 0.0, 0.0])
+    f0 = inputs.random_deviations(shape, seed=13, amp=1e-3).astype(np.float32).astype(np.float64)
+    g0 = _random_g(shape, 14, B0).astype(np.float32).astype(np.float64)
+    sim = _mhd_sim(shape, bc, gamma, s, "f32", F, p)
+    sim.set_state(to_gpu_f(f0, torch.float32), to_gpu_g(g0, torch.float32))
+    sim.step(1)
+    fg, gg = sim.get_state()
+    pp = dict(gamma=gamma, s=s, gamma_m=gm, chi=p["chi"], eta=p["eta"], B_wall=B0)
+    fo, go, _, _ = mhd.step(f0, g0, inputs.uniform_force(shape, F), pp, bc)
+    assert rel(from_gpu_f(fg), fo) < 2e-6
+    assert rel(from_gpu_g(gg), go) < 1e-6
+
+
+@pytest.mark.parametrize("Ha", [5.0, 10.0, 20.0])
+@pytest.mark.parametrize("Pm", [0.01, 0.1])
+def test_hartmann_workload(Ha, Pm):
+    """32x32x128, walls normal to y (the applied-field direction), FP32,
+    gamma = gamma_m = 0.1, to residual 1e-8; compared with the oracle on the
+    same y-resolution (1x32x1 by homogeneity) and the closed forms."""
+    cfg = inputs.HARTMANN
+    announce("hartmann Ha=%g Pm=%g" % (Ha, Pm))
+    ny = cfg["shape"][1]
+    B0, chi = inputs.hartmann_parameters(Ha, Pm, ny, cfg["nu"], cfg["eta"])
+    p = dict(gamma_m=cfg["gamma_m"], chi=chi, eta=cfg["eta"], B0=(0.0, B0, 0.0))
+    s = glbe.rates(cfg["nu"], cfg["gamma"])
+    sim = _mhd_sim(cfg["shape"], cfg["bc"], cfg["gamma"], s, "f32", cfg["F"], p)
+    steps, r = sim.run_to_residual(cfg["tol"], 200000, poll_every=500)
+    assert steps > 0, r
+    _, u, B = sim.moments("f64")
+    ug = u[0].cpu().numpy()
+    bg = B[0].cpu().numpy()
+    assert np.ptp(ug, axis=(0, 2)).max() < 1e-6 * np.abs(ug).max()
+    ug, bg = ug[0, :, 0], bg[0, :, 0]
+    L = ny / 2
+    y = np.arange(ny) + 0.5 - L
+    F = cfg["F"][0]
+    uex = F * L * L / (cfg["nu"] * Ha) * (np.cosh(Ha) - np.cosh(Ha * y / L)) / np.sinh(Ha)
+    bex = chi * F * L / B0 * (np.sinh(Ha * y / L) / np.sinh(Ha) - y / L)
+    fl = mhd.MHDFlow((1, ny, 1), cfg["bc"], np.array(cfg["F"]), cfg["gamma"], s, cfg["gamma_m"],
+                     chi, cfg["eta"], np.array([0.0, B0, 0.0]))
+    assert fl.run_to(1e-10, 200000)
+    uo, bo = fl.u[0][0, :, 0], fl.B[0][0, :, 0]
+    assert rel(ug, uo) < 2e-5
+    assert rel(bg, bo) < 2e-4
+    # paper rates at gamma = 0.1 put the bounce-back slip at Lambda ~ 1, and the
+    # Ha = 20 layer (L/Ha = 0.8 cells) is under-resolved: oracle errors are
+    # 0.9 / 3.5 / 13 % in u and 1.2 / 2.4 / 5.5 % in b for Ha = 5 / 10 / 20
+    tol = {5.0: 0.015, 10.0: 0.05, 20.0: 0.15}[Ha]
+    assert rel(uo, uex) < tol and rel(bo, bex) < tol
