@@ -48,7 +48,11 @@ def algorithmic_bytes_per_node(storage_bytes, force_field, check_every, mhd=Fals
     return b
 
 
-def make_sim(shape, storage, gamma, nu=0.131, F0=1e-5, bc=("periodic", "wall", "wall")):
+NO_CHECK = 1 << 30   # check_every that never fires: a march of the plain step kernel only
+
+
+def make_sim(shape, storage, gamma, nu=0.131, F0=1e-5, bc=("periodic", "wall", "wall"),
+             check_every=10):
     import torch
 
     import paper_0809_4730_amd as pkg
@@ -56,11 +60,12 @@ def make_sim(shape, storage, gamma, nu=0.131, F0=1e-5, bc=("periodic", "wall", "
     dt = torch.float64 if storage == "f64" else torch.float32
     F = torch.tensor(inputs.duct_force(shape, F0), dtype=dt, device="cuda")
     s = pkg.default_rates(nu, gamma)
-    return pkg.Simulation(shape, bc, gamma, s, storage=storage, force=F)
+    return pkg.Simulation(shape, bc, gamma, s, storage=storage, force=F, check_every=check_every)
 
 
-def measure(sim, steps, warmup):
-    """(MLUPS, wall seconds of the plain timed region, mean kernel us, event wall ms)."""
+def timed_region(sim, steps, warmup):
+    """(MLUPS, wall seconds) of `steps` full steps (residual checks included),
+    bracketed by device synchronisations."""
     import torch
     sim.step(warmup)
     torch.cuda.synchronize()
@@ -68,8 +73,52 @@ def measure(sim, steps, warmup):
     sim.step(steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    mean_us, ev_ms = sim.step_timed(steps)
-    return sim.N * steps / wall / 1e6, wall, mean_us, ev_ms
+    return sim.N * steps / wall / 1e6, wall
+
+
+def kernel_time_us(sim, launches, warmup=20):
+    """Mean duration of the step kernel: HIP events on the library's stream
+    around `launches` back-to-back launches (sim built with NO_CHECK, so every
+    launch is the same kernel)."""
+    import torch
+    sim.step(warmup)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sim.step(launches)
+    e1.record()
+    e1.synchronize()
+    return 1000.0 * e0.elapsed_time(e1) / launches
+
+
+def measure(shape, storage, gamma, steps, warmup):
+    """(MLUPS with checks, wall s, mean plain-kernel us)."""
+    import torch
+    sim = make_sim(shape, storage, gamma)
+    mlups, wall = timed_region(sim, steps, warmup)
+    del sim
+    sim = make_sim(shape, storage, gamma, check_every=NO_CHECK)
+    us = kernel_time_us(sim, steps)
+    del sim
+    torch.cuda.empty_cache()
+    return mlups, wall, us
+
+
+def copy_bandwidth_GBs(nbytes=4 << 30, reps=10):
+    """Device-to-device copy (read + write) bandwidth of a plain copy kernel."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
 
 
 def traffic_from_profiles(kernel_tag, khash):
@@ -138,9 +187,12 @@ def extras(args):
     out = {}
     # time to residual 1e-8 on the 64^3 duct: gamma sweep vs plain gamma = 1 (FP64 and FP32)
     tt = []
-    tt.append(time_to_residual((64, 64, 64), "f64", 1.0, 1e-8, 400000))
     for g in (1.0, 0.5, 0.1, 0.05):
-        tt.append(time_to_residual((64, 64, 64), "f32", g, 1e-8, 400000))
+        tt.append(time_to_residual((64, 64, 64), "f64", g, 1e-8, 400000))
+    for g in (1.0, 0.5, 0.1, 0.05):
+        e = time_to_residual((64, 64, 64), "f32", g, 1e-7, 400000)
+        e["note"] = "FP32 storage stalls near 6e-8 at this Mach number; tol 1e-7"
+        tt.append(e)
     out["time_to_residual_duct64"] = tt
     ref = tt[0]
     if ref["steps"] > 0:
@@ -151,16 +203,15 @@ def extras(args):
     # 256^3 throughput per storage type (kernel roofline at HBM scale)
     big = []
     for st, nb in (("f32", 4), ("bf16", 2), ("f16", 2), ("f64", 8)):
-        sim = make_sim((256, 256, 256), st, 1.0)
-        mlups, wall, us, _ = measure(sim, args.big_steps, 20)
-        bpn = algorithmic_bytes_per_node(nb, True, 10)
+        mlups, wall, us = measure((256, 256, 256), st, 1.0, args.big_steps, 10)
+        bpn = algorithmic_bytes_per_node(nb, True, NO_CHECK)
         gbs = bpn * 256 ** 3 / (us * 1e-6) / 1e9
-        big.append({"storage": st, "MLUPS": round(mlups, 1), "kernel_us": round(us, 2),
+        big.append({"storage": st, "MLUPS_with_checks": round(mlups, 1), "kernel_us": round(us, 2),
+                    "kernel_MLUPS": round(256 ** 3 / us, 1),
                     "alg_bytes_per_node": bpn, "achieved_GBs": round(gbs, 1),
                     "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)})
-        del sim
-        torch.cuda.empty_cache()
     out["duct256_throughput"] = big
+    out["hbm_copy_GBs"] = round(copy_bandwidth_GBs(), 1)
     # coupled MHD step on the Hartmann workload
     cfg = inputs.HARTMANN
     B0, chi = inputs.hartmann_parameters(10.0, 0.01, cfg["shape"][1], cfg["nu"], cfg["eta"])
@@ -171,16 +222,17 @@ def extras(args):
         return pkg.Simulation(cfg["shape"], cfg["bc"], g, pkg.default_rates(cfg["nu"], g),
                               storage="f32", force=cfg["F"], mhd=mp2)
     sim = hart()
-    mlups, wall, us, _ = measure(sim, 1000, 100)
+    mlups, wall = timed_region(sim, 1000, 100)
+    us = 1e6 * wall / 1000
     bpn = algorithmic_bytes_per_node(4, False, 10, mhd=True)
     out["hartmann_mhd_step"] = {"shape": cfg["shape"], "MLUPS": round(mlups, 1),
                                 "kernel_us": round(us, 2), "alg_bytes_per_node": bpn,
                                 "achieved_GBs": round(bpn * sim.N / (us * 1e-6) / 1e9, 1)}
     ttm = []
     for g in (1.0, 0.1):
-        ttm.append(time_to_residual(None, "f32", g, 1e-8, 400000,
+        ttm.append(time_to_residual(None, "f32", g, 2e-7, 400000,
                                     mhd=lambda g=g: hart(g, g)))
-    out["time_to_residual_hartmann_Ha10"] = ttm
+    out["time_to_residual_hartmann_Ha10_f32_tol2e-7"] = ttm
     return out
 
 
@@ -207,10 +259,9 @@ def main():
     pkg.load_library()
 
     shape, gamma, storage = (64, 64, 64), 0.1, "f32"
-    sim = make_sim(shape, storage, gamma)
-    mlups, wall, mean_us, ev_ms = measure(sim, args.steps, args.warmup)
-    N = sim.N
-    bpn = algorithmic_bytes_per_node(4, True, 10)
+    mlups, wall, mean_us = measure(shape, storage, gamma, args.steps, args.warmup)
+    N = shape[0] * shape[1] * shape[2]
+    bpn = algorithmic_bytes_per_node(4, True, NO_CHECK)
     achieved = bpn * N / (mean_us * 1e-6) / 1e9
     khash = kernel_hash()
     traffic = traffic_from_profiles("glbe_step_f32_duct64", khash)
@@ -233,12 +284,10 @@ def main():
                    "grid": list(shape), "gamma": gamma, "storage": storage},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "glbe_step<float>",
+                     "traffic": traffic, "kernel": "glbe_step<float, check=false, field=true>",
                      "alg_bytes_per_node": bpn, "mean_kernel_us": round(mean_us, 3),
                      "kernel_hash": khash},
     }
-    del sim
-    torch.cuda.empty_cache()
     if args.copy_probe:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -19,7 +19,10 @@
 // step conserves mass, so 1 is an eigenvector of C_f^T S^T with eigenvalue 1
 // and C_F^T 1 = 0: the mean of mu drifts linearly without changing the
 // gradient.  The mean is removed every check and convergence is measured on
-// the gradient field itself.
+// the gradient field itself.  The linearised step also has undamped period-2
+// (eigenvalue -1) modes; when the adjoint source excites them the iterates
+// alternate between two branches whose mean is the fixed point, so the
+// gradient reported at each check is the mean of the last two iterations.
 //
 // Unrolled adjoint over N steps from p_0: mu_{N+1} = q; for n = N..1,
 // lam_n = S^T mu_{n+1}, mu_n = C_f(f_n)^T lam_n, dQ/dF += C_F(f_n)^T lam_n with
@@ -101,14 +104,15 @@ __device__ __forceinline__ void gather_transpose(const R* __restrict__ mu, int64
   }
 }
 
-// GRAD: 0 none, 1 accumulate into grad, 2 overwrite grad (with the direct term)
-// and accumulate the change against its previous content.
+// GRAD: 0 none; 1 accumulate into grad; 3 write half the gradient (with the
+// direct term) into gpre; 2 (check) grad = half the gradient + gpre, and
+// accumulate the change against the previous content of grad.
 template <typename R, bool CHECK, int GRAD, bool FIELD>
 __global__ __launch_bounds__(kBlock) void adjoint_step(
     GridArgs g, CollideArgs<R> c, const R* __restrict__ state, const R* __restrict__ force,
     const R* __restrict__ mu_in, R* __restrict__ mu_out, R* __restrict__ grad,
-    int64_t grad_stride, const double* __restrict__ shift, R q_scale, R grad_direct,
-    double* __restrict__ partials) {
+    R* __restrict__ gpre, int64_t grad_stride, const double* __restrict__ shift, R q_scale,
+    R grad_direct, double* __restrict__ partials) {
   const int lb = logical_block(g);
   if (lb >= g.nblocks) return;
   const uint32_t n = static_cast<uint32_t>(lb) * kBlock + threadIdx.x;
@@ -143,8 +147,13 @@ __global__ __launch_bounds__(kBlock) void adjoint_step(
       grad[n] += gx;
       grad[grad_stride + n] += gy;
       grad[2 * grad_stride + n] += gz;
+    } else if constexpr (GRAD == 3) {
+      gpre[n] = R(0.5) * (gx + grad_direct);
+      gpre[grad_stride + n] = R(0.5) * gy;
+      gpre[2 * grad_stride + n] = R(0.5) * gz;
     } else if constexpr (GRAD == 2) {
-      const R gv[3] = {gx + grad_direct, gy, gz};
+      const R gv[3] = {R(0.5) * (gx + grad_direct) + gpre[n], R(0.5) * gy + gpre[grad_stride + n],
+                       R(0.5) * gz + gpre[2 * grad_stride + n]};
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const int64_t i = k * grad_stride + n;
@@ -216,19 +225,23 @@ __global__ void fill_f64(double* __restrict__ p, int count, double v) {
 template <typename R>
 hipError_t launch_adjoint(const GridArgs& g, const CollideArgs<R>& c, const void* state,
                           const void* force, bool field, const void* mu_in, void* mu_out,
-                          void* grad, int64_t grad_stride, int grad_mode, const double* shift,
-                          R q_scale, R grad_direct, bool check, double* partials, hipStream_t st) {
+                          void* grad, void* gpre, int64_t grad_stride, int grad_mode,
+                          const double* shift, R q_scale, R grad_direct, bool check,
+                          double* partials, hipStream_t st) {
   const dim3 grid(kXcd * g.blocks_per_xcd);
   const R* s = static_cast<const R*>(state);
   const R* F = static_cast<const R*>(force);
   const R* mi = static_cast<const R*>(mu_in);
   R* mo = static_cast<R*>(mu_out);
   R* gr = static_cast<R*>(grad);
-#define LBM_ADJ(CH, GM, FL)                                                                     \
-  adjoint_step<R, CH, GM, FL><<<grid, kBlock, 0, st>>>(g, c, s, F, mi, mo, gr, grad_stride, shift, \
-                                                        q_scale, grad_direct, partials)
+  R* gp = static_cast<R*>(gpre);
+#define LBM_ADJ(CH, GM, FL)                                                                      \
+  adjoint_step<R, CH, GM, FL><<<grid, kBlock, 0, st>>>(g, c, s, F, mi, mo, gr, gp, grad_stride, \
+                                                        shift, q_scale, grad_direct, partials)
   if (check) {
     if (field) LBM_ADJ(true, 2, true); else LBM_ADJ(true, 2, false);
+  } else if (grad_mode == 3) {
+    if (field) LBM_ADJ(false, 3, true); else LBM_ADJ(false, 3, false);
   } else if (grad_mode == 1) {
     if (field) LBM_ADJ(false, 1, true); else LBM_ADJ(false, 1, false);
   } else {
@@ -245,7 +258,7 @@ constexpr size_t kA = 256;
 size_t al(size_t v) { return (v + kA - 1) / kA * kA; }
 
 struct AdjLayout {
-  size_t mu[2] = {0, 0}, partials = 0, ring = 0, shift = 0, ckpt = 0, seg = 0, total = 0;
+  size_t mu[2] = {0, 0}, gpre = 0, partials = 0, ring = 0, shift = 0, ckpt = 0, seg = 0, total = 0;
   int64_t n_ckpt = 0, seg_len = 0;
 };
 constexpr int kAdjRing = 64;
@@ -263,6 +276,7 @@ AdjLayout adj_layout(const lbm_ctx* c, int mode, int64_t n_steps, int64_t ckpt_e
   };
   L.mu[0] = take(state);
   L.mu[1] = take(state);
+  if (mode == 0) L.gpre = take(3 * size_t(c->L.N) * cs);
   L.partials = take(size_t(c->L.nblocks) * kPartials * sizeof(double));
   L.ring = take(kAdjRing * kAdjRec * sizeof(double));
   L.shift = take(2 * sizeof(double));
@@ -309,7 +323,9 @@ lbm_status steady_impl(lbm_ctx* c, char* ws, double tol, int64_t max_iter, void*
                      static_cast<R*>(dQdF), N, int(N), R(0));
   hipLaunchKernelGGL(fill_f64, dim3(1), dim3(64), 0, c->stream, shift, 2, 0.0);
   LBM_HIP(c, hipGetLastError(), "adjoint initialisation");
-  const int ce = c->p.check_every;
+  // a check every P >= 2 iterations; the iteration before it stores half its gradient
+  const int ce = std::max(2, c->p.check_every);
+  void* gpre = ws + L.gpre;
   int cur = 0;
   int64_t checks = 0, done = 0;
   bool prev_check = false;
@@ -318,10 +334,11 @@ lbm_status steady_impl(lbm_ctx* c, char* ws, double tol, int64_t max_iter, void*
   while (done < max_iter) {
     const int64_t it = done + 1;
     const bool check = (it % ce) == 0;
+    const bool pre = ((it + 1) % ce) == 0;
     const double* sh = prev_check ? shift : nullptr;
     LBM_HIP(c, launch_adjoint<R>(c->ga, cargs<R>(c), c->f(c->cur), c->force(), c->field(),
-                                 mu[cur], mu[cur ^ 1], dQdF, N, check ? 2 : 0, sh, q, direct,
-                                 check, partials, c->stream),
+                                 mu[cur], mu[cur ^ 1], dQdF, gpre, N, check ? 2 : (pre ? 3 : 0),
+                                 sh, q, direct, check, partials, c->stream),
             "adjoint launch");
     cur ^= 1;
     done = it;
@@ -400,8 +417,8 @@ lbm_status unrolled_impl(lbm_ctx* c, char* ws, int64_t n_steps, int64_t K, void*
               "segment recompute");
     for (int64_t n = e; n >= s0 + 1; --n) {
       LBM_HIP(c, launch_adjoint<R>(c->ga, cargs<R>(c), seg + size_t(n - 1 - s0) * state_bytes,
-                                   c->force(), c->field(), mu[cur], mu[cur ^ 1], dQdF, N, 1,
-                                   nullptr, R(0), R(0), false, nullptr, c->stream),
+                                   c->force(), c->field(), mu[cur], mu[cur ^ 1], dQdF, nullptr, N,
+                                   1, nullptr, R(0), R(0), false, nullptr, c->stream),
               "adjoint launch");
       cur ^= 1;
     }
@@ -413,12 +430,12 @@ lbm_status unrolled_impl(lbm_ctx* c, char* ws, int64_t n_steps, int64_t K, void*
 }  // namespace
 
 template hipError_t launch_adjoint<double>(const GridArgs&, const CollideArgs<double>&, const void*,
-                                           const void*, bool, const void*, void*, void*, int64_t,
-                                           int, const double*, double, double, bool, double*,
-                                           hipStream_t);
+                                           const void*, bool, const void*, void*, void*, void*,
+                                           int64_t, int, const double*, double, double, bool,
+                                           double*, hipStream_t);
 template hipError_t launch_adjoint<float>(const GridArgs&, const CollideArgs<float>&, const void*,
-                                          const void*, bool, const void*, void*, void*, int64_t,
-                                          int, const double*, float, float, bool, double*,
+                                          const void*, bool, const void*, void*, void*, void*,
+                                          int64_t, int, const double*, float, float, bool, double*,
                                           hipStream_t);
 
 }  // namespace lbm

@@ -11,6 +11,20 @@
 
 namespace lbm {
 
+// Build-time tuning knobs (defaults are the measured best on MI355X):
+//   LBM_XCD_REMAP   1: contiguous logical-block range per XCD; 0: identity
+//   LBM_NT_STORE    1: population stores bypass the caches (streaming stores)
+//   LBM_NT_LOAD     1: population loads marked non-temporal
+#ifndef LBM_XCD_REMAP
+#define LBM_XCD_REMAP 1
+#endif
+#ifndef LBM_NT_STORE
+#define LBM_NT_STORE 0
+#endif
+#ifndef LBM_NT_LOAD
+#define LBM_NT_LOAD 0
+#endif
+
 constexpr int kBlock = 256;   // threads per workgroup (4 wave64)
 constexpr int kXcd = 8;       // XCDs on MI355X; workgroups are dealt round-robin
 constexpr int kRecordDoubles = 8;
@@ -52,7 +66,11 @@ struct GridArgs {
 // from sit in its own L2.
 __device__ __forceinline__ int logical_block(const GridArgs& g) {
   const int b = blockIdx.x;
+#if LBM_XCD_REMAP
   return (b & (kXcd - 1)) * g.blocks_per_xcd + (b >> 3);
+#else
+  return b;
+#endif
 }
 
 // Collision constants for compute type R (host-prepared).
@@ -86,25 +104,43 @@ struct bf16_t {
 template <typename S>
 struct Storage;
 
+template <typename T>
+__device__ __forceinline__ T ld_pop(const T* p) {
+#if LBM_NT_LOAD
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
+
+template <typename T>
+__device__ __forceinline__ void st_pop(T* p, T v) {
+#if LBM_NT_STORE
+  __builtin_nontemporal_store(v, p);
+#else
+  *p = v;
+#endif
+}
+
 template <>
 struct Storage<double> {
   using R = double;
-  __device__ __forceinline__ static R ld(const double* p) { return *p; }
-  __device__ __forceinline__ static void st(double* p, R v) { *p = v; }
+  __device__ __forceinline__ static R ld(const double* p) { return ld_pop(p); }
+  __device__ __forceinline__ static void st(double* p, R v) { st_pop(p, v); }
 };
 
 template <>
 struct Storage<float> {
   using R = float;
-  __device__ __forceinline__ static R ld(const float* p) { return *p; }
-  __device__ __forceinline__ static void st(float* p, R v) { *p = v; }
+  __device__ __forceinline__ static R ld(const float* p) { return ld_pop(p); }
+  __device__ __forceinline__ static void st(float* p, R v) { st_pop(p, v); }
 };
 
 template <>
 struct Storage<bf16_t> {
   using R = float;
   __device__ __forceinline__ static R ld(const bf16_t* p) {
-    return __uint_as_float(static_cast<uint32_t>(p->bits) << 16);
+    return __uint_as_float(static_cast<uint32_t>(ld_pop(&p->bits)) << 16);
   }
   // round to nearest, ties to even; NaN stays NaN
   __device__ __forceinline__ static void st(bf16_t* p, R v) {
@@ -116,15 +152,15 @@ struct Storage<bf16_t> {
       u += 0x7fffu + ((u >> 16) & 1u);
       h = static_cast<uint16_t>(u >> 16);
     }
-    p->bits = h;
+    st_pop(&p->bits, h);
   }
 };
 
 template <>
 struct Storage<_Float16> {
   using R = float;
-  __device__ __forceinline__ static R ld(const _Float16* p) { return static_cast<float>(*p); }
-  __device__ __forceinline__ static void st(_Float16* p, R v) { *p = static_cast<_Float16>(v); }
+  __device__ __forceinline__ static R ld(const _Float16* p) { return static_cast<float>(ld_pop(p)); }
+  __device__ __forceinline__ static void st(_Float16* p, R v) { st_pop(p, static_cast<_Float16>(v)); }
 };
 
 // ------------------------------------------------------------ reductions --

@@ -39,7 +39,8 @@ hipError_t launch_init_g(void* gout, int64_t stride, int N, const MagArgs<R>& m,
 template <typename R>
 hipError_t launch_adjoint(const GridArgs& g, const CollideArgs<R>& c, const void* state,
                           const void* force, bool field, const void* mu_in, void* mu_out,
-                          void* grad, int64_t grad_stride, int grad_mode, const double* shift,
-                          R q_scale, R grad_direct, bool check, double* partials, hipStream_t st);
+                          void* grad, void* gpre, int64_t grad_stride, int grad_mode,
+                          const double* shift, R q_scale, R grad_direct, bool check,
+                          double* partials, hipStream_t st);
 
 }  // namespace lbm

@@ -84,10 +84,17 @@ def test_steady_adjoint_duct_vs_finite_differences(storage, tol):
     v = np.zeros_like(F)
     v[0] = 1e-5 * (np.cos(np.pi * z / nz)[:, None] * (1 + 0.2 * np.sin(2 * np.pi * y / ny))[None, :])[:, :, None]
     v[1] = 3e-6 * np.sin(np.pi * y / ny)[None, :, None]
-    sim = _sim(shape, bc, gamma, s, storage, F)
-    assert sim.run_to_residual(1e-10 if storage == "f64" else 1e-8, 400000)[0] > 0
+    ref = _sim(shape, bc, gamma, s, "f64", F)
+    assert ref.run_to_residual(1e-10, 400000)[0] > 0
+    if storage == "f64":
+        sim = ref
+    else:
+        # FP32 storage cannot reach 1e-10 (its rounding floor is ~1e-7): march the
+        # same number of steps as FP64 plus margin, then iterate the FP32 adjoint
+        sim = _sim(shape, bc, gamma, s, storage, F)
+        sim.step(ref.t + 2000)
     grad, iters, change = sim.adjoint_steady(tol=1e-10 if storage == "f64" else 1e-6,
-                                             max_iter=400000)
+                                             max_iter=2 * ref.t + 20000)
     d = float((grad.double().cpu().numpy() * v).sum())
     eps = 1e-2
     q = []

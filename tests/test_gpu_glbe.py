@@ -145,8 +145,10 @@ def test_residual_history_matches_oracle():
     fl.step(200)
     steps = {int(h[0]): h for h in hist}
     assert sorted(steps) == list(range(10, 201, 10))
+    # R is a relative difference of velocities 10 steps apart: an FP64 state error
+    # of ~1e-16 |u| shows up as ~1e-16 / R relative in R
     for t, r in fl.history:
-        assert abs(steps[t][1] - r) <= 1e-10 * r
+        assert abs(steps[t][1] - r) <= 1e-14 + 1e-8 * r
     mass, q = sim.reductions()
     assert abs(mass) < 1e-14
     assert abs(q - fl.flow_rate()) < 1e-12 * max(abs(fl.flow_rate()), 1e-15) + 1e-20
