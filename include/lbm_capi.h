@@ -92,6 +92,10 @@ typedef struct {
   double B0[3];           /* applied field: initial state and wall value */
   int32_t check_every;    /* residual / reductions every this many steps (10) */
   int32_t history_len;    /* entries of the device residual history ring (>= 1) */
+  int32_t source_mode;    /* 0: preconditioned sources S^* = P_S S^ (Sec. 3, eq.
+                             precondsourceterm); 1: the naive S^/gamma for every
+                             moment (Sec. 3.1, eq. precondsourceincorrect), kept
+                             only to exhibit its spurious steady-state error */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx;
@@ -187,7 +191,8 @@ lbm_status lbm_moments(lbm_ctx* ctx, int32_t out_dtype, void* rho, void* u, void
 
 /* Number of bytes of the state blob: populations [19][N] in the storage type,
  * followed (mhd) by the magnetic populations [3][7][N] (field component
- * outermost) in the compute type. */
+ * outermost) in the compute type, held as deviations g_{a j} - W_a B0_j from the
+ * applied field's rest equilibrium (so that FP32 keeps the small induced field). */
 lbm_status lbm_state_bytes(const lbm_ctx* ctx, size_t* bytes);
 
 /* Copy the state blob to / from caller device memory, and read / set the step

@@ -153,19 +153,27 @@ def velocity_source(F, u):
 
 
 # -------------------------------------------------------------- collision ---
-def collide(d, F, gamma, s, rho0=1.0):
+def collide(d, F, gamma, s, rho0=1.0, source="precond"):
     """One preconditioned GLBE collision with forcing (Sec. 3, eq. prelax_term).
 
     d:  (19, ...) pre-collision deviations f - w rho0.
     F:  (3, ...) force.
     s:  (19,) rates s*_k.
+    source: "precond" uses S^* = P_S S^ (eq. precondsourceterm); "naive" uses
+        S^/gamma for every moment, i.e. S* = S/gamma in velocity space
+        (eq. precondsourceincorrect), the form Sec. 3.1 warns against.
     Returns the post-collision deviations f~ - w rho0.
     """
     drho, rho, j, u = fields(d, F, gamma, rho0)
     m_dev = np.tensordot(T19, d, axes=(1, 0))          # T f - T w rho0
     neq = m_dev - meq_star_dev(drho, rho, j, gamma)    # f^ - f^eq*
-    S_star = source_precond_diag(gamma).reshape((Q19,) + (1,) * (d.ndim - 1)) \
-        * source_moments(F, u)
+    if source == "precond":
+        P = source_precond_diag(gamma)
+    elif source == "naive":
+        P = np.full(Q19, 1.0 / gamma)
+    else:
+        raise ValueError(source)
+    S_star = P.reshape((Q19,) + (1,) * (d.ndim - 1)) * source_moments(F, u)
     sk = np.asarray(s, dtype=float).reshape((Q19,) + (1,) * (d.ndim - 1))
     dm = -sk * neq + (1.0 - 0.5 * sk) * S_star
     return d + np.tensordot(T19_INV, dm, axes=(1, 0))
@@ -202,12 +210,12 @@ def stream(post, bc, e=E19, opp=OPP19):
 
 
 # ------------------------------------------------------------------- step ---
-def step(post, F, gamma, s, bc, rho0=1.0):
+def step(post, F, gamma, s, bc, rho0=1.0, source="precond"):
     """One time step: stream, then collide.  Returns (new_post, u) where u is the
     velocity of the collision just performed (physical, with F/(2 gamma))."""
     f = stream(post, bc)
     _, _, _, u = fields(f, F, gamma, rho0)
-    return collide(f, F, gamma, s, rho0), u
+    return collide(f, F, gamma, s, rho0, source), u
 
 
 def flow_rate(post, F, gamma, bc, rho0=1.0):
@@ -268,8 +276,10 @@ class Flow:
     velocity of that step's collision.
     """
 
-    def __init__(self, shape_xyz, bc, F, gamma, s, rho0=1.0, dtype=np.float64, post=None):
+    def __init__(self, shape_xyz, bc, F, gamma, s, rho0=1.0, dtype=np.float64, post=None,
+                 source="precond"):
         nx, ny, nz = shape_xyz
+        self.source = source
         self.bc = tuple(bc)
         self.gamma = gamma
         self.s = np.asarray(s, dtype=float)
@@ -286,7 +296,8 @@ class Flow:
 
     def step(self, n=1, check_every=10):
         for _ in range(n):
-            self.post, u = step(self.post, self.F, self.gamma, self.s, self.bc, self.rho0)
+            self.post, u = step(self.post, self.F, self.gamma, self.s, self.bc, self.rho0,
+                                self.source)
             self.t += 1
             if self.t % check_every == 0:
                 if self.u_snap is not None:

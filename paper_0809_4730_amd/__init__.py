@@ -52,6 +52,7 @@ class _Params(ctypes.Structure):
         ("B0", ctypes.c_double * 3),
         ("check_every", ctypes.c_int32),
         ("history_len", ctypes.c_int32),
+        ("source_mode", ctypes.c_int32),
     ]
 
 
@@ -158,10 +159,12 @@ class Simulation:
     force: a 3-vector (uniform) or a device tensor (3, nz, ny, nx) in the compute
     dtype (float64 for f64 storage, float32 otherwise).
     mhd: None or dict(gamma_m=, chi=, eta=, B0=(..), mu=1.0).
+    source: "precond" (P_S, the paper's form) or "naive" (S/gamma, its negative control).
     """
 
     def __init__(self, shape, bc, gamma, s, storage="f32", force=(0.0, 0.0, 0.0), rho0=1.0,
-                 mhd=None, check_every=10, history_len=4096, device="cuda", stream=None):
+                 mhd=None, check_every=10, history_len=4096, device="cuda", stream=None,
+                 source="precond"):
         torch = _torch()
         self._lib = load_library()
         self.device = torch.device(device)
@@ -205,6 +208,7 @@ class Simulation:
                 p.B0[a] = float(mhd["B0"][a])
         p.check_every = check_every
         p.history_len = history_len
+        p.source_mode = {"precond": 0, "naive": 1}[source]
         self._params = p
         self.gamma = gamma
         nbytes = ctypes.c_size_t()
@@ -307,7 +311,8 @@ class Simulation:
     # ------------------------------------------------------------- state
     def get_state(self):
         """Populations (19, nz, ny, nx) in the storage dtype, plus (mhd) the
-        magnetic populations (3, 7, nz, ny, nx); deviations from the rest state."""
+        magnetic populations (3, 7, nz, ny, nx); both as deviations from the rest
+        state (f - w rho0, g - W B0)."""
         torch = _torch()
         nx, ny, nz = self.shape
         f = torch.empty((19, nz, ny, nx), dtype=_state_torch_dtype(self.storage), device=self.device)

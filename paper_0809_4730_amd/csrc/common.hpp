@@ -11,16 +11,9 @@
 
 namespace lbm {
 
-// Build-time tuning knobs (defaults are the measured best on MI355X):
-//   LBM_XCD_REMAP   1: contiguous logical-block range per XCD; 0: identity
-//   LBM_NT_STORE    1: population stores bypass the caches (streaming stores)
-//   LBM_NT_LOAD     1: population loads marked non-temporal
-#ifndef LBM_XCD_REMAP
-#define LBM_XCD_REMAP 1
-#endif
-#ifndef LBM_NT_STORE
-#define LBM_NT_STORE 0
-#endif
+// Build-time knob: LBM_NT_LOAD 1 marks population loads non-temporal (measured
+// slower for FP32, so off).  Streaming stores and the XCD block mapping are
+// chosen at run time (GridArgs::xcd_chunk, the NT template flag of the step).
 #ifndef LBM_NT_LOAD
 #define LBM_NT_LOAD 0
 #endif
@@ -55,22 +48,23 @@ struct GridArgs {
   int32_t wall_x, wall_y, wall_z;
   int32_t N;               // nodes
   int32_t nblocks;         // logical workgroups covering N
-  int32_t blocks_per_xcd;  // launched grid = kXcd * blocks_per_xcd
-  int32_t pad;
+  int32_t blocks_per_xcd;  // launched grid = kXcd * blocks_per_xcd (a multiple of xcd_chunk)
+  int32_t xcd_chunk;       // consecutive logical blocks an XCD takes at a time
   int64_t stride;          // elements between direction planes (N rounded up to 64)
   FastDiv div_nx, div_nxny;
 };
 
-// Workgroup b of the launch runs on XCD (b mod 8); give each XCD one
-// contiguous range of logical blocks so that the neighbouring rows it pulls
-// from sit in its own L2.
+// Workgroup b of the launch runs on XCD (b mod 8) as that XCD's (b / 8)-th
+// workgroup.  XCDs take chunks of xcd_chunk consecutive logical blocks in turn:
+// chunk = blocks_per_xcd gives each XCD one contiguous slab (neighbour rows stay
+// in its L2: best when the lattice lives in the caches), chunk = 1 interleaves
+// single blocks (all XCDs stream the same DRAM pages: best from HBM).
 __device__ __forceinline__ int logical_block(const GridArgs& g) {
   const int b = blockIdx.x;
-#if LBM_XCD_REMAP
-  return (b & (kXcd - 1)) * g.blocks_per_xcd + (b >> 3);
-#else
-  return b;
-#endif
+  const int xcd = b & (kXcd - 1);
+  const int i = b >> 3;
+  const int C = g.xcd_chunk;
+  return ((i / C) * kXcd + xcd) * C + (i % C);
 }
 
 // Collision constants for compute type R (host-prepared).
@@ -78,7 +72,7 @@ template <typename R>
 struct CollideArgs {
   R rho0;
   R inv_gamma;     // 1/gamma: nonlinear equilibrium terms, linear source terms
-  R inv_gamma2;    // 1/gamma^2: F.u source terms
+  R inv_gamma2;    // 1/gamma^2: F.u source terms (1/gamma for the naive source form)
   R half_inv_gamma;  // 1/(2 gamma): half-force in j
   R A[Q19];        // s_k / |T_k|^2
   R B[Q19];        // (1 - s_k/2) / |T_k|^2
@@ -92,7 +86,7 @@ struct MagArgs {
   R adv;         // chi / (gamma_m theta_m)
   R a_coef;      // -1 / (mu chi tau_m* theta_m)
   R kappa;       // 2 / (mu gamma_m tau_m* theta_m)
-  R Bw[3];       // wall / applied field
+  R B0[3];       // applied field: initial state and wall value
   R w_rest, w_axis;
 };
 
@@ -113,27 +107,28 @@ __device__ __forceinline__ T ld_pop(const T* p) {
 #endif
 }
 
-template <typename T>
+template <bool NT, typename T>
 __device__ __forceinline__ void st_pop(T* p, T v) {
-#if LBM_NT_STORE
-  __builtin_nontemporal_store(v, p);
-#else
-  *p = v;
-#endif
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
 }
 
 template <>
 struct Storage<double> {
   using R = double;
   __device__ __forceinline__ static R ld(const double* p) { return ld_pop(p); }
-  __device__ __forceinline__ static void st(double* p, R v) { st_pop(p, v); }
+  template <bool NT = false>
+  __device__ __forceinline__ static void st(double* p, R v) { st_pop<NT>(p, v); }
 };
 
 template <>
 struct Storage<float> {
   using R = float;
   __device__ __forceinline__ static R ld(const float* p) { return ld_pop(p); }
-  __device__ __forceinline__ static void st(float* p, R v) { st_pop(p, v); }
+  template <bool NT = false>
+  __device__ __forceinline__ static void st(float* p, R v) { st_pop<NT>(p, v); }
 };
 
 template <>
@@ -143,6 +138,7 @@ struct Storage<bf16_t> {
     return __uint_as_float(static_cast<uint32_t>(ld_pop(&p->bits)) << 16);
   }
   // round to nearest, ties to even; NaN stays NaN
+  template <bool NT = false>
   __device__ __forceinline__ static void st(bf16_t* p, R v) {
     uint32_t u = __float_as_uint(v);
     uint16_t h;
@@ -152,7 +148,7 @@ struct Storage<bf16_t> {
       u += 0x7fffu + ((u >> 16) & 1u);
       h = static_cast<uint16_t>(u >> 16);
     }
-    st_pop(&p->bits, h);
+    st_pop<NT>(&p->bits, h);
   }
 };
 
@@ -160,7 +156,10 @@ template <>
 struct Storage<_Float16> {
   using R = float;
   __device__ __forceinline__ static R ld(const _Float16* p) { return static_cast<float>(ld_pop(p)); }
-  __device__ __forceinline__ static void st(_Float16* p, R v) { st_pop(p, static_cast<_Float16>(v)); }
+  template <bool NT = false>
+  __device__ __forceinline__ static void st(_Float16* p, R v) {
+    st_pop<NT>(p, static_cast<_Float16>(v));
+  }
 };
 
 // ------------------------------------------------------------ reductions --

@@ -43,6 +43,7 @@ struct lbm_ctx {
   hipStream_t stream = nullptr;
   char* ws = nullptr;
   int cur = 0;
+  bool nt_store = false;  // streaming (cache-bypassing) population stores
   int64_t step = 0;
   int64_t checks = 0;
   lbm::CollideArgs<double> cd;
@@ -69,6 +70,7 @@ namespace lbm {
 lbm_status fail(lbm_ctx* c, lbm_status s, const std::string& msg);
 lbm_status hip_fail(lbm_ctx* c, hipError_t e, const char* what);
 lbm_status one_step(lbm_ctx* c, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+void choose_launch_shape(lbm_ctx* c);
 }  // namespace lbm
 
 #define LBM_HIP(ctx, call, what)                          \

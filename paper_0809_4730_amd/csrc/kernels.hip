@@ -77,25 +77,28 @@ __device__ __forceinline__ void gather19(const S* __restrict__ fin, int64_t stri
   }
 }
 
-template <typename S>
+template <typename S, bool NT = false>
 __device__ __forceinline__ void store19(S* __restrict__ fout, int64_t stride, uint32_t n,
                                         const typename Storage<S>::R (&f)[Q19]) {
 #pragma unroll
-  for (int a = 0; a < Q19; ++a) Storage<S>::st(fout + static_cast<int64_t>(a) * stride + n, f[a]);
+  for (int a = 0; a < Q19; ++a)
+    Storage<S>::template st<NT>(fout + static_cast<int64_t>(a) * stride + n, f[a]);
 }
 
-// Anti-bounce-back gather of the magnetic populations g_{a j} (j outermost).
+// Gather of the magnetic populations, stored as deviations from the applied
+// field's equilibrium, d_{a j} = g_{a j} - W_a B0_j (j outermost).  At a wall,
+// anti-bounce-back g_a = -g~_opp(a) + 2 W_a B0 (insulating wall, B = B0 there)
+// reads d_a = -d~_opp(a) in deviation form.
 template <typename R, int A>
 __device__ __forceinline__ void gather_g_dir(const R* __restrict__ gin, int64_t stride, uint32_t n,
-                                             const Nbr& b, const MagArgs<R>& m, R (&g)[3][Q7]) {
+                                             const Nbr& b, R (&g)[3][Q7]) {
   int32_t off;
   const bool bounce = pull_source<EX7[A], EY7[A], EZ7[A]>(b, off);
-  const R w = (A == 0) ? m.w_rest : m.w_axis;
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     const int64_t base = static_cast<int64_t>(j * Q7) * stride;
     if (bounce) {
-      g[j][A] = R(2) * w * m.Bw[j] - gin[base + static_cast<int64_t>(OPP7(A)) * stride + n];
+      g[j][A] = -gin[base + static_cast<int64_t>(OPP7(A)) * stride + n];
     } else {
       g[j][A] = gin[base + static_cast<int64_t>(A) * stride + static_cast<int64_t>(n) + off];
     }
@@ -104,10 +107,10 @@ __device__ __forceinline__ void gather_g_dir(const R* __restrict__ gin, int64_t 
 
 template <typename R, int A = 0>
 __device__ __forceinline__ void gather_g(const R* __restrict__ gin, int64_t stride, uint32_t n,
-                                         const Nbr& b, const MagArgs<R>& m, R (&g)[3][Q7]) {
+                                         const Nbr& b, R (&g)[3][Q7]) {
   if constexpr (A < Q7) {
-    gather_g_dir<R, A>(gin, stride, n, b, m, g);
-    gather_g<R, A + 1>(gin, stride, n, b, m, g);
+    gather_g_dir<R, A>(gin, stride, n, b, g);
+    gather_g<R, A + 1>(gin, stride, n, b, g);
   }
 }
 
@@ -118,7 +121,8 @@ __device__ __forceinline__ void gather_g(const R* __restrict__ gin, int64_t stri
 // c = kappa/(2 gamma rho), u0 = (j_raw + (F_ext + a x B)/(2 gamma))/rho.
 template <typename R>
 struct Coupled {
-  R Bx, By, Bz;
+  R Bx, By, Bz;  // full field B0 + b
+  R bx, by, bz;  // induced part b = sum_a d_a
   R Fx, Fy, Fz;  // total force
 };
 
@@ -127,10 +131,13 @@ __device__ __forceinline__ Coupled<R> lorentz_solve(const R (&f)[Q19], const R (
                                                     R Fex, R Fey, R Fez, const CollideArgs<R>& c,
                                                     const MagArgs<R>& m) {
   Coupled<R> o;
-  R B[3], L[3][3];  // L[k][j] = sum_a e_{a k} g_{a j}
+  // g holds deviations d = g - W B0: sum_a d_a = b = B - B0, and the W B0 part
+  // has no first moment, so L is taken from d directly.
+  R B[3], bb[3], L[3][3];  // L[k][j] = sum_a e_{a k} g_{a j}
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    B[j] = g[j][0] + g[j][1] + g[j][2] + g[j][3] + g[j][4] + g[j][5] + g[j][6];
+    bb[j] = g[j][0] + g[j][1] + g[j][2] + g[j][3] + g[j][4] + g[j][5] + g[j][6];
+    B[j] = m.B0[j] + bb[j];
     L[0][j] = g[j][1] - g[j][2];
     L[1][j] = g[j][3] - g[j][4];
     L[2][j] = g[j][5] - g[j][6];
@@ -159,25 +166,31 @@ __device__ __forceinline__ Coupled<R> lorentz_solve(const R (&f)[Q19], const R (
   o.Bx = B[0];
   o.By = B[1];
   o.Bz = B[2];
+  o.bx = bb[0];
+  o.by = bb[1];
+  o.bz = bb[2];
   o.Fx = Fex + (Jy * B[2] - Jz * B[1]);
   o.Fy = Fey + (Jz * B[0] - Jx * B[2]);
   o.Fz = Fez + (Jx * B[1] - Jy * B[0]);
   return o;
 }
 
-// g~ = g + (g^eq* - g)/tau_m*, g^eq*_{a j} = W_a [B_j + (e_{a k}/theta)(chi/gamma_m)(u_k B_j - B_k u_j)]
+// g~ = g + (g^eq* - g)/tau_m*, g^eq*_{a j} = W_a [B_j + (e_{a k}/theta)(chi/gamma_m)(u_k B_j - B_k u_j)],
+// on deviations d = g - W B0: d~ = d + (g^eq* - W B0 - d)/tau_m*, where
+// g^eq* - W B0 = W_a [b_j + (e_{a k}/theta)(chi/gamma_m)(u_k B_j - B_k u_j)].
 template <typename R>
-__device__ __forceinline__ void collide_g(R (&g)[3][Q7], R Bx, R By, R Bz, R ux, R uy, R uz,
+__device__ __forceinline__ void collide_g(R (&g)[3][Q7], const Coupled<R>& cp, R ux, R uy, R uz,
                                           const MagArgs<R>& m) {
-  const R B[3] = {Bx, By, Bz};
+  const R B[3] = {cp.Bx, cp.By, cp.Bz};
+  const R b[3] = {cp.bx, cp.by, cp.bz};
   const R u[3] = {ux, uy, uz};
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    g[j][0] += m.omega * (m.w_rest * B[j] - g[j][0]);
+    g[j][0] += m.omega * (m.w_rest * b[j] - g[j][0]);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const R adv = m.adv * (u[k] * B[j] - B[k] * u[j]);
-      const R base = m.w_axis * B[j];
+      const R base = m.w_axis * b[j];
       const R wadv = m.w_axis * adv;
       g[j][1 + 2 * k] += m.omega * (base + wadv - g[j][1 + 2 * k]);
       g[j][2 + 2 * k] += m.omega * (base - wadv - g[j][2 + 2 * k]);
@@ -231,7 +244,7 @@ __device__ __forceinline__ void write_partials(double* __restrict__ partials, in
 }
 
 // ------------------------------------------------------------------ steps --
-template <typename S, bool CHECK, bool FIELD>
+template <typename S, bool CHECK, bool FIELD, bool NT>
 __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<typename Storage<S>::R> c,
                                                     const S* __restrict__ fin, S* __restrict__ fout,
                                                     const typename Storage<S>::R* __restrict__ force,
@@ -249,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<type
     R Fx, Fy, Fz;
     load_force<R>(g, c, force, FIELD, n, Fx, Fy, Fz);
     const NodeMacro<R> mac = collide19<R>(f, Fx, Fy, Fz, c);
-    store19<S>(fout, g.stride, n, f);
+    store19<S, NT>(fout, g.stride, n, f);
     if constexpr (CHECK)
       check_node<R>(g, usnap, n, mac.drho, mac.jx, mac.jy, mac.jz, mac.ux, mac.uy, mac.uz, acc);
   }
@@ -272,12 +285,12 @@ __global__ __launch_bounds__(kBlock) void mhd_step(GridArgs g, CollideArgs<R> c,
     R f[Q19];
     gather19<R>(fin, g.stride, n, b, f);
     R gg[3][Q7];
-    gather_g<R>(gin, g.stride, n, b, m, gg);
+    gather_g<R>(gin, g.stride, n, b, gg);
     R Fx, Fy, Fz;
     load_force<R>(g, c, force, FIELD, n, Fx, Fy, Fz);
     const Coupled<R> cp = lorentz_solve<R>(f, gg, Fx, Fy, Fz, c, m);
     const NodeMacro<R> mac = collide19<R>(f, cp.Fx, cp.Fy, cp.Fz, c);
-    collide_g<R>(gg, cp.Bx, cp.By, cp.Bz, mac.ux, mac.uy, mac.uz, m);
+    collide_g<R>(gg, cp, mac.ux, mac.uy, mac.uz, m);
     store19<R>(fout, g.stride, n, f);
 #pragma unroll
     for (int j = 0; j < 3; ++j)
@@ -313,7 +326,7 @@ __global__ __launch_bounds__(kBlock) void fields_kernel(
     R Bx = 0, By = 0, Bz = 0;
     if constexpr (MHD) {
       R gg[3][Q7];
-      gather_g<R>(gin, g.stride, n, b, m, gg);
+      gather_g<R>(gin, g.stride, n, b, gg);
       const Coupled<R> cp = lorentz_solve<R>(f, gg, Fx, Fy, Fz, c, m);
       Fx = cp.Fx;
       Fy = cp.Fy;
@@ -387,55 +400,45 @@ __global__ __launch_bounds__(kBlock) void fill_zero_f64(double* __restrict__ p, 
   if (i < count) p[i] = 0.0;
 }
 
-template <typename R>
-__global__ __launch_bounds__(kBlock) void init_g(R* __restrict__ gout, int64_t stride, int N,
-                                                 MagArgs<R> m) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  if (i >= N) return;
-#pragma unroll
-  for (int j = 0; j < 3; ++j)
-#pragma unroll
-    for (int a = 0; a < Q7; ++a)
-      gout[static_cast<int64_t>(j * Q7 + a) * stride + i] = (a == 0 ? m.w_rest : m.w_axis) * m.Bw[j];
-}
-
 // ------------------------------------------------------------- launchers --
 static inline dim3 step_grid(const GridArgs& g) { return dim3(kXcd * g.blocks_per_xcd); }
 
 template <typename S>
 hipError_t launch_glbe_step(const GridArgs& g, const CollideArgs<typename Storage<S>::R>& c,
                             const void* fin, void* fout, const void* force, bool field, bool check,
-                            double* usnap, double* partials, hipStream_t st) {
+                            bool nt, double* usnap, double* partials, hipStream_t st) {
   using R = typename Storage<S>::R;
   const S* a = static_cast<const S*>(fin);
   S* b = static_cast<S*>(fout);
   const R* F = static_cast<const R*>(force);
-  if (check) {
-    if (field)
-      glbe_step<S, true, true><<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
-    else
-      glbe_step<S, true, false><<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
+#define LBM_STEP(CH, FL, NTS) \
+  glbe_step<S, CH, FL, NTS><<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials)
+  if (nt) {
+    if (check) {
+      if (field) LBM_STEP(true, true, true); else LBM_STEP(true, false, true);
+    } else {
+      if (field) LBM_STEP(false, true, true); else LBM_STEP(false, false, true);
+    }
   } else {
-    if (field)
-      glbe_step<S, false, true><<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
-    else
-      glbe_step<S, false, false><<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
+    if (check) {
+      if (field) LBM_STEP(true, true, false); else LBM_STEP(true, false, false);
+    } else {
+      if (field) LBM_STEP(false, true, false); else LBM_STEP(false, false, false);
+    }
   }
+#undef LBM_STEP
   return hipGetLastError();
 }
 
-template hipError_t launch_glbe_step<double>(const GridArgs&, const CollideArgs<double>&, const void*,
-                                             void*, const void*, bool, bool, double*, double*,
-                                             hipStream_t);
-template hipError_t launch_glbe_step<float>(const GridArgs&, const CollideArgs<float>&, const void*,
-                                            void*, const void*, bool, bool, double*, double*,
-                                            hipStream_t);
-template hipError_t launch_glbe_step<bf16_t>(const GridArgs&, const CollideArgs<float>&, const void*,
-                                             void*, const void*, bool, bool, double*, double*,
-                                             hipStream_t);
-template hipError_t launch_glbe_step<_Float16>(const GridArgs&, const CollideArgs<float>&,
-                                               const void*, void*, const void*, bool, bool, double*,
-                                               double*, hipStream_t);
+#define LBM_INST_STEP(S)                                                                          \
+  template hipError_t launch_glbe_step<S>(const GridArgs&, const CollideArgs<Storage<S>::R>&,      \
+                                          const void*, void*, const void*, bool, bool, bool,       \
+                                          double*, double*, hipStream_t);
+LBM_INST_STEP(double)
+LBM_INST_STEP(float)
+LBM_INST_STEP(bf16_t)
+LBM_INST_STEP(_Float16)
+#undef LBM_INST_STEP
 
 template <typename R>
 hipError_t launch_mhd_step(const GridArgs& g, const CollideArgs<R>& c, const MagArgs<R>& m,
@@ -525,13 +528,6 @@ template hipError_t launch_fill_zero<float>(void*, int64_t, hipStream_t);
 template hipError_t launch_fill_zero<bf16_t>(void*, int64_t, hipStream_t);
 template hipError_t launch_fill_zero<_Float16>(void*, int64_t, hipStream_t);
 
-template <typename R>
-hipError_t launch_init_g(void* gout, int64_t stride, int N, const MagArgs<R>& m, hipStream_t st) {
-  const int64_t blocks = (static_cast<int64_t>(N) + kBlock - 1) / kBlock;
-  init_g<R><<<dim3(static_cast<uint32_t>(blocks)), kBlock, 0, st>>>(static_cast<R*>(gout), stride, N, m);
-  return hipGetLastError();
-}
-template hipError_t launch_init_g<double>(void*, int64_t, int, const MagArgs<double>&, hipStream_t);
-template hipError_t launch_init_g<float>(void*, int64_t, int, const MagArgs<float>&, hipStream_t);
+
 
 }  // namespace lbm

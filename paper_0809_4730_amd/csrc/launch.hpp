@@ -11,7 +11,7 @@ namespace lbm {
 template <typename S>
 hipError_t launch_glbe_step(const GridArgs& g, const CollideArgs<typename Storage<S>::R>& c,
                             const void* fin, void* fout, const void* force, bool field, bool check,
-                            double* usnap, double* partials, hipStream_t st);
+                            bool nt, double* usnap, double* partials, hipStream_t st);
 
 template <typename R>
 hipError_t launch_mhd_step(const GridArgs& g, const CollideArgs<R>& c, const MagArgs<R>& m,
@@ -31,8 +31,6 @@ hipError_t launch_finalize(const double* partials, int nblocks, double step, dou
 template <typename S>
 hipError_t launch_fill_zero(void* p, int64_t count, hipStream_t st);
 
-template <typename R>
-hipError_t launch_init_g(void* gout, int64_t stride, int N, const MagArgs<R>& m, hipStream_t st);
 
 // ---------------------------------------------------------------- adjoint --
 // One transposed step of the linearised map (adjoint.hip).

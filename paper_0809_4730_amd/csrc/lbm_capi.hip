@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -59,6 +60,7 @@ std::string validate(const lbm_grid* grid, const lbm_params* p) {
   }
   if (p->check_every < 1) return "check_every must be >= 1";
   if (p->history_len < 1) return "history_len must be >= 1";
+  if (p->source_mode != 0 && p->source_mode != 1) return "source_mode must be 0 or 1";
   return "";
 }
 
@@ -109,7 +111,8 @@ CollideArgs<R> collide_args(const lbm_params& p) {
   CollideArgs<R> c;
   c.rho0 = R(p.rho0);
   c.inv_gamma = R(1.0 / p.gamma);
-  c.inv_gamma2 = R(1.0 / (p.gamma * p.gamma));
+  // the F.u source moments carry 1/gamma^2 (P_S); the naive form uses 1/gamma
+  c.inv_gamma2 = R(p.source_mode == 1 ? 1.0 / p.gamma : 1.0 / (p.gamma * p.gamma));
   c.half_inv_gamma = R(0.5 / p.gamma);
   for (int k = 0; k < 19; ++k) {
     c.A[k] = R(p.s[k] / NORM19[k]);
@@ -132,7 +135,7 @@ MagArgs<R> mag_args(const lbm_params& p) {
   m.adv = R(p.chi / (p.gamma_m * THETA_M));
   m.a_coef = R(-1.0 / (p.mu * p.chi * tau * THETA_M));
   m.kappa = R(2.0 / (p.mu * p.gamma_m * tau * THETA_M));
-  for (int a = 0; a < 3; ++a) m.Bw[a] = R(p.B0[a]);
+  for (int a = 0; a < 3; ++a) m.B0[a] = R(p.B0[a]);
   m.w_rest = R(W7_REST);
   m.w_axis = R(W7_AXIS);
   return m;
@@ -151,18 +154,42 @@ hipError_t launch_step_kernel(lbm_ctx* c, bool check) {
   }
   switch (c->p.storage) {
     case LBM_F64:
-      return launch_glbe_step<double>(c->ga, c->cd, fin, fout, c->force(), fld, check, c->usnap(),
-                                      c->partials(), c->stream);
+      return launch_glbe_step<double>(c->ga, c->cd, fin, fout, c->force(), fld, check, c->nt_store,
+                                      c->usnap(), c->partials(), c->stream);
     case LBM_F32:
-      return launch_glbe_step<float>(c->ga, c->cf, fin, fout, c->force(), fld, check, c->usnap(),
-                                     c->partials(), c->stream);
+      return launch_glbe_step<float>(c->ga, c->cf, fin, fout, c->force(), fld, check, c->nt_store,
+                                     c->usnap(), c->partials(), c->stream);
     case LBM_BF16:
-      return launch_glbe_step<bf16_t>(c->ga, c->cf, fin, fout, c->force(), fld, check, c->usnap(),
-                                      c->partials(), c->stream);
+      return launch_glbe_step<bf16_t>(c->ga, c->cf, fin, fout, c->force(), fld, check, c->nt_store,
+                                      c->usnap(), c->partials(), c->stream);
     default:
       return launch_glbe_step<_Float16>(c->ga, c->cf, fin, fout, c->force(), fld, check,
-                                        c->usnap(), c->partials(), c->stream);
+                                        c->nt_store, c->usnap(), c->partials(), c->stream);
   }
+}
+
+// Launch shape.  When both population buffers fit the 256 MB last-level cache
+// (MALL) the lattice is cache-resident: each XCD sweeps one contiguous slab so
+// that pulled neighbour rows hit its own L2, and stores stay cacheable.  Larger
+// lattices stream from HBM: stores bypass the caches.  LBM_XCD_CHUNK and
+// LBM_NT_STORE in the environment override the choice (tuning sweeps).
+void choose_launch_shape(lbm_ctx* c) {
+  constexpr double kMallBytes = 256.0 * 1024 * 1024;
+  const double pop_bytes =
+      2.0 * double(c->L.stride) * (19.0 * storage_bytes(c->p.storage) +
+                                   (c->p.mhd ? 21.0 * compute_bytes(c->p.storage) : 0.0));
+  const bool hbm = pop_bytes > kMallBytes;
+  const int bpx0 = (c->L.nblocks + kXcd - 1) / kXcd;
+  int chunk = bpx0;
+  c->nt_store = hbm;
+  if (const char* e = std::getenv("LBM_XCD_CHUNK")) {
+    const int v = std::atoi(e);
+    if (v > 0) chunk = v;
+  }
+  if (const char* e = std::getenv("LBM_NT_STORE")) c->nt_store = std::atoi(e) != 0;
+  chunk = std::max(1, std::min(chunk, bpx0));
+  c->ga.xcd_chunk = chunk;
+  c->ga.blocks_per_xcd = (bpx0 + chunk - 1) / chunk * chunk;
 }
 
 // Enqueue one step (and its history record when due).
@@ -326,8 +353,7 @@ lbm_status lbm_create(const lbm_grid* grid, const lbm_params* params, const void
   g.wall_z = grid->bc[2] == LBM_WALL;
   g.N = static_cast<int32_t>(L.N);
   g.nblocks = L.nblocks;
-  g.blocks_per_xcd = (L.nblocks + kXcd - 1) / kXcd;
-  g.pad = 0;
+  choose_launch_shape(c);
   g.stride = L.stride;
   g.div_nx = make_fastdiv(static_cast<uint32_t>(g.nx));
   g.div_nxny = make_fastdiv(static_cast<uint32_t>(g.nx * g.ny));
@@ -341,13 +367,11 @@ lbm_status lbm_create(const lbm_grid* grid, const lbm_params* params, const void
   if (e == hipSuccess) e = launch_fill_zero<double>(c->usnap(), 3 * L.stride, c->stream);
   if (e == hipSuccess) e = launch_fill_zero<double>(c->ring(), int64_t(params->history_len) * kRecordDoubles, c->stream);
   if (e == hipSuccess && params->mhd) {
-    if (params->storage == LBM_F64) {
-      e = launch_init_g<double>(c->g(0), L.stride, g.N, c->md, c->stream);
-      if (e == hipSuccess) e = launch_init_g<double>(c->g(1), L.stride, g.N, c->md, c->stream);
-    } else {
-      e = launch_init_g<float>(c->g(0), L.stride, g.N, c->mf, c->stream);
-      if (e == hipSuccess) e = launch_init_g<float>(c->g(1), L.stride, g.N, c->mf, c->stream);
-    }
+    // magnetic populations are stored as deviations from W_a B0: zero at rest
+    const size_t cs = compute_bytes(params->storage);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i)
+      e = (cs == 8) ? launch_fill_zero<double>(c->g(i), 21 * L.stride, c->stream)
+                    : launch_fill_zero<float>(c->g(i), 21 * L.stride, c->stream);
   }
   if (e != hipSuccess) {
     g_create_error = std::string("initialisation: ") + hipGetErrorString(e);

@@ -34,18 +34,29 @@ def from_gpu_f(t):
     return out
 
 
-def to_gpu_g(g, torch_dtype, device="cuda"):
+def _rest_g(g_shape, B0):
+    from oracle.lattice import W7
+    rest = np.zeros(g_shape)
+    for j in range(3):
+        for a in range(7):
+            rest[j, a] = W7[a] * B0[j]
+    return rest
+
+
+def to_gpu_g(g, torch_dtype, B0, device="cuda"):
+    """Oracle magnetic populations -> library state (deviations from W B0)."""
     import torch
     _, p7 = perms()
-    return torch.tensor(np.ascontiguousarray(g[:, p7]), dtype=torch.float64, device=device).to(torch_dtype)
+    dev = g - _rest_g(g.shape, B0)
+    return torch.tensor(np.ascontiguousarray(dev[:, p7]), dtype=torch.float64, device=device).to(torch_dtype)
 
 
-def from_gpu_g(t):
+def from_gpu_g(t, B0):
     _, p7 = perms()
     arr = t.to(__import__("torch").float64).cpu().numpy()
     out = np.empty_like(arr)
     out[:, p7] = arr
-    return out
+    return out + _rest_g(out.shape, B0)
 
 
 def rel(a, b):

@@ -43,7 +43,7 @@ def test_mhd_fp64_matches_oracle(shape, bc, nsteps):
     f0 = inputs.random_deviations(shape, seed=11, amp=1e-3)
     g0 = _random_g(shape, 12, B0)
     sim = _mhd_sim(shape, bc, gamma, s, "f64", F, p)
-    sim.set_state(to_gpu_f(f0, torch.float64), to_gpu_g(g0, torch.float64))
+    sim.set_state(to_gpu_f(f0, torch.float64), to_gpu_g(g0, torch.float64, B0))
     sim.step(nsteps)
     fg, gg = sim.get_state()
     fo, go = f0, g0
@@ -52,7 +52,7 @@ def test_mhd_fp64_matches_oracle(shape, bc, nsteps):
     for _ in range(nsteps):
         fo, go, u, B = mhd.step(fo, go, Ff, pp, bc)
     assert rel(from_gpu_f(fg), fo) < 1e-12
-    assert rel(from_gpu_g(gg), go) < 1e-13
+    assert rel(from_gpu_g(gg, B0), go) < 1e-13
     rho, ug, Bg = sim.moments("f64")
     # fields of the streamed current state, with the self-consistent Lorentz force
     f_s = glbe.stream(fo, bc)
@@ -71,15 +71,22 @@ def test_mhd_fp32_single_step():
     s = glbe.rates(0.1, gamma)
     F = np.array([1e-5, 0.0, 0.0])
     f0 = inputs.random_deviations(shape, seed=13, amp=1e-3).astype(np.float32).astype(np.float64)
-    g0 = _random_g(shape, 14, B0).astype(np.float32).astype(np.float64)
+    nx, ny, nz = shape
+    # FP32 stores g - W B0: give both sides deviations that FP32 holds exactly
+    dev = inputs.random_deviations(shape, seed=14, amp=1e-4, q=21).astype(np.float32)
+    g0 = mhd.initial_g(shape, B0) + dev.astype(np.float64).reshape(3, 7, nz, ny, nx)
     sim = _mhd_sim(shape, bc, gamma, s, "f32", F, p)
-    sim.set_state(to_gpu_f(f0, torch.float32), to_gpu_g(g0, torch.float32))
+    sim.set_state(to_gpu_f(f0, torch.float32), to_gpu_g(g0, torch.float32, B0))
     sim.step(1)
     fg, gg = sim.get_state()
     pp = dict(gamma=gamma, s=s, gamma_m=gm, chi=p["chi"], eta=p["eta"], B_wall=B0)
     fo, go, _, _ = mhd.step(f0, g0, inputs.uniform_force(shape, F), pp, bc)
     assert rel(from_gpu_f(fg), fo) < 2e-6
-    assert rel(from_gpu_g(gg), go) < 1e-6
+    assert rel(from_gpu_g(gg, B0), go) < 1e-6
+    # the deviation from W B0 (what FP32 stores) is itself accurate
+    from tests.gpu_util import _rest_g
+    rest = _rest_g(go.shape, B0)
+    assert rel(from_gpu_g(gg, B0) - rest, go - rest) < 1e-5
 
 
 @pytest.mark.parametrize("Ha", [5.0, 10.0, 20.0])
