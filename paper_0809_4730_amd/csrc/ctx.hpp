@@ -27,7 +27,9 @@ inline size_t compute_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
 struct Layout {
   int64_t N = 0, stride = 0;
   int32_t nblocks = 0;
-  size_t f[2] = {0, 0}, g[2] = {0, 0}, force = 0, usnap = 0, partials = 0, ring = 0, rec = 0;
+  size_t f[2] = {0, 0}, g[2] = {0, 0}, force = 0, usnap = 0, partials = 0, fpartials = 0, ring = 0,
+         rec = 0;
+  int32_t pslots = 1;  // slots of the per-check partials ring
   size_t total = 0;
 };
 
@@ -45,7 +47,9 @@ struct lbm_ctx {
   int cur = 0;
   bool nt_store = false;  // streaming (cache-bypassing) population stores
   int64_t step = 0;
-  int64_t checks = 0;
+  int64_t checks = 0;            // residual checks launched since the last reset
+  int64_t finalized = 0;         // checks whose history records have been written
+  int64_t first_check_step = 0;  // step number of check 0
   lbm::CollideArgs<double> cd;
   lbm::CollideArgs<float> cf;
   lbm::MagArgs<double> md;
@@ -56,8 +60,9 @@ struct lbm_ctx {
   void* f(int i) const { return ws + L.f[i]; }
   void* g(int i) const { return p.mhd ? static_cast<void*>(ws + L.g[i]) : nullptr; }
   void* force() const { return p.force_mode == LBM_FORCE_FIELD ? static_cast<void*>(ws + L.force) : nullptr; }
-  double* usnap() const { return reinterpret_cast<double*>(ws + L.usnap); }
+  void* usnap() const { return ws + L.usnap; }
   double* partials() const { return reinterpret_cast<double*>(ws + L.partials); }
+  double* fpartials() const { return reinterpret_cast<double*>(ws + L.fpartials); }
   double* ring() const { return reinterpret_cast<double*>(ws + L.ring); }
   double* rec() const { return reinterpret_cast<double*>(ws + L.rec); }
   bool field() const { return p.force_mode == LBM_FORCE_FIELD; }
@@ -71,6 +76,8 @@ lbm_status fail(lbm_ctx* c, lbm_status s, const std::string& msg);
 lbm_status hip_fail(lbm_ctx* c, hipError_t e, const char* what);
 lbm_status one_step(lbm_ctx* c, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void choose_launch_shape(lbm_ctx* c);
+lbm_status flush_checks(lbm_ctx* c);
+void reset_checks(lbm_ctx* c, int64_t step);
 }  // namespace lbm
 
 #define LBM_HIP(ctx, call, what)                          \

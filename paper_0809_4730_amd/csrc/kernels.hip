@@ -213,19 +213,22 @@ __device__ __forceinline__ void load_force(const GridArgs& g, const CollideArgs<
   }
 }
 
-// Residual / reduction bookkeeping of one node (FP64).
+// Residual / reduction bookkeeping of one node, accumulated in FP64.  The
+// velocity snapshot is kept in the compute type R: u is an R value, so the
+// FP64 difference of two snapshots is exact.
 template <typename R>
-__device__ __forceinline__ void check_node(const GridArgs& g, double* __restrict__ usnap, uint32_t n,
+__device__ __forceinline__ void check_node(const GridArgs& g, R* __restrict__ usnap, uint32_t n,
                                            R drho, R jx, R jy, R jz, R ux, R uy, R uz,
                                            double (&acc)[kPartials]) {
-  const double u[3] = {static_cast<double>(ux), static_cast<double>(uy), static_cast<double>(uz)};
+  const R ur[3] = {ux, uy, uz};
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const int64_t i = static_cast<int64_t>(k) * g.stride + n;
-    const double d = u[k] - usnap[i];
-    usnap[i] = u[k];
+    const double uk = static_cast<double>(ur[k]);
+    const double d = uk - static_cast<double>(usnap[i]);
+    usnap[i] = ur[k];
     acc[0] += d * d;
-    acc[1] += u[k] * u[k];
+    acc[1] += uk * uk;
   }
   acc[2] += static_cast<double>(drho);
   acc[3] += static_cast<double>(jx);
@@ -248,7 +251,7 @@ template <typename S, bool CHECK, bool FIELD, bool NT>
 __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<typename Storage<S>::R> c,
                                                     const S* __restrict__ fin, S* __restrict__ fout,
                                                     const typename Storage<S>::R* __restrict__ force,
-                                                    double* __restrict__ usnap,
+                                                    typename Storage<S>::R* __restrict__ usnap,
                                                     double* __restrict__ partials) {
   using R = typename Storage<S>::R;
   const int lb = logical_block(g);
@@ -274,7 +277,7 @@ __global__ __launch_bounds__(kBlock) void mhd_step(GridArgs g, CollideArgs<R> c,
                                                    const R* __restrict__ fin, R* __restrict__ fout,
                                                    const R* __restrict__ gin, R* __restrict__ gout,
                                                    const R* __restrict__ force,
-                                                   double* __restrict__ usnap,
+                                                   R* __restrict__ usnap,
                                                    double* __restrict__ partials) {
   const int lb = logical_block(g);
   if (lb >= g.nblocks) return;
@@ -359,25 +362,31 @@ __global__ __launch_bounds__(kBlock) void fields_kernel(
 }
 
 // ---------------------------------------------------------------- finalize --
-// One workgroup: sum the per-workgroup partials in a fixed order and write one
-// history record {step, residual, du2, u2, mass, flow, nonfinite, 0}.
+// One workgroup per pending check: sum that check's per-workgroup partials in
+// a fixed order and write its history record {step, residual, du2, u2, mass,
+// flow, nonfinite, 0}.  Checks are check_every steps apart.
 __global__ __launch_bounds__(kBlock) void finalize_kernel(const double* __restrict__ partials,
-                                                          int nblocks, double step, double inv_nx,
-                                                          double* __restrict__ record) {
+                                                          int nblocks, int pslots, int64_t first,
+                                                          double step0, double dstep,
+                                                          double inv_nx, double* __restrict__ ring,
+                                                          int history_len) {
+  const int64_t k = first + blockIdx.x;
+  const double* p = partials + (k % pslots) * int64_t(nblocks) * kPartials;
   double acc[kPartials] = {0, 0, 0, 0, 0, 0};
   for (int b = threadIdx.x; b < nblocks; b += kBlock) {
 #pragma unroll
-    for (int k = 0; k < kPartials; ++k) acc[k] += partials[static_cast<int64_t>(b) * kPartials + k];
+    for (int q = 0; q < kPartials; ++q) acc[q] += p[static_cast<int64_t>(b) * kPartials + q];
   }
   block_sum<kPartials>(acc);
   if (threadIdx.x == 0) {
+    double* record = ring + (k % history_len) * kRecordDoubles;
     const double du2 = acc[0], u2 = acc[1];
     double r;
     if (u2 > 0.0)
       r = sqrt(du2 / u2);
     else
       r = (du2 == 0.0) ? 0.0 : INFINITY;
-    record[0] = step;
+    record[0] = step0 + dstep * double(blockIdx.x);
     record[1] = r;
     record[2] = du2;
     record[3] = u2;
@@ -406,8 +415,9 @@ static inline dim3 step_grid(const GridArgs& g) { return dim3(kXcd * g.blocks_pe
 template <typename S>
 hipError_t launch_glbe_step(const GridArgs& g, const CollideArgs<typename Storage<S>::R>& c,
                             const void* fin, void* fout, const void* force, bool field, bool check,
-                            bool nt, double* usnap, double* partials, hipStream_t st) {
+                            bool nt, void* usnap_v, double* partials, hipStream_t st) {
   using R = typename Storage<S>::R;
+  R* usnap = static_cast<R*>(usnap_v);
   const S* a = static_cast<const S*>(fin);
   S* b = static_cast<S*>(fout);
   const R* F = static_cast<const R*>(force);
@@ -433,7 +443,7 @@ hipError_t launch_glbe_step(const GridArgs& g, const CollideArgs<typename Storag
 #define LBM_INST_STEP(S)                                                                          \
   template hipError_t launch_glbe_step<S>(const GridArgs&, const CollideArgs<Storage<S>::R>&,      \
                                           const void*, void*, const void*, bool, bool, bool,       \
-                                          double*, double*, hipStream_t);
+                                          void*, double*, hipStream_t);
 LBM_INST_STEP(double)
 LBM_INST_STEP(float)
 LBM_INST_STEP(bf16_t)
@@ -443,8 +453,9 @@ LBM_INST_STEP(_Float16)
 template <typename R>
 hipError_t launch_mhd_step(const GridArgs& g, const CollideArgs<R>& c, const MagArgs<R>& m,
                            const void* fin, void* fout, const void* gin, void* gout,
-                           const void* force, bool field, bool check, double* usnap,
+                           const void* force, bool field, bool check, void* usnap_v,
                            double* partials, hipStream_t st) {
+  R* usnap = static_cast<R*>(usnap_v);
   const R* a = static_cast<const R*>(fin);
   R* b = static_cast<R*>(fout);
   const R* ga = static_cast<const R*>(gin);
@@ -466,11 +477,11 @@ hipError_t launch_mhd_step(const GridArgs& g, const CollideArgs<R>& c, const Mag
 
 template hipError_t launch_mhd_step<double>(const GridArgs&, const CollideArgs<double>&,
                                             const MagArgs<double>&, const void*, void*, const void*,
-                                            void*, const void*, bool, bool, double*, double*,
+                                            void*, const void*, bool, bool, void*, double*,
                                             hipStream_t);
 template hipError_t launch_mhd_step<float>(const GridArgs&, const CollideArgs<float>&,
                                            const MagArgs<float>&, const void*, void*, const void*,
-                                           void*, const void*, bool, bool, double*, double*,
+                                           void*, const void*, bool, bool, void*, double*,
                                            hipStream_t);
 
 template <typename S>
@@ -510,9 +521,12 @@ LBM_INST_FIELDS(bf16_t)
 LBM_INST_FIELDS(_Float16)
 #undef LBM_INST_FIELDS
 
-hipError_t launch_finalize(const double* partials, int nblocks, double step, double inv_nx,
-                           double* record, hipStream_t st) {
-  finalize_kernel<<<1, kBlock, 0, st>>>(partials, nblocks, step, inv_nx, record);
+hipError_t launch_finalize(const double* partials, int nblocks, int pslots, int64_t first,
+                           int count, double step0, double dstep, double inv_nx, double* ring,
+                           int history_len, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  finalize_kernel<<<count, kBlock, 0, st>>>(partials, nblocks, pslots, first, step0, dstep, inv_nx,
+                                            ring, history_len);
   return hipGetLastError();
 }
 

@@ -11,12 +11,12 @@ namespace lbm {
 template <typename S>
 hipError_t launch_glbe_step(const GridArgs& g, const CollideArgs<typename Storage<S>::R>& c,
                             const void* fin, void* fout, const void* force, bool field, bool check,
-                            bool nt, double* usnap, double* partials, hipStream_t st);
+                            bool nt, void* usnap, double* partials, hipStream_t st);
 
 template <typename R>
 hipError_t launch_mhd_step(const GridArgs& g, const CollideArgs<R>& c, const MagArgs<R>& m,
                            const void* fin, void* fout, const void* gin, void* gout,
-                           const void* force, bool field, bool check, double* usnap,
+                           const void* force, bool field, bool check, void* usnap,
                            double* partials, hipStream_t st);
 
 template <typename S>
@@ -25,8 +25,11 @@ hipError_t launch_fields(const GridArgs& g, const CollideArgs<typename Storage<S
                          const void* gin, const void* force, bool field, int out_dtype, void* rho,
                          void* u, void* B, int64_t out_stride, double* partials, hipStream_t st);
 
-hipError_t launch_finalize(const double* partials, int nblocks, double step, double inv_nx,
-                           double* record, hipStream_t st);
+// Reduce `count` pending checks (global indices first .. first+count-1) from the
+// partials ring (pslots slots) into the history ring.
+hipError_t launch_finalize(const double* partials, int nblocks, int pslots, int64_t first,
+                           int count, double step0, double dstep, double inv_nx, double* ring,
+                           int history_len, hipStream_t st);
 
 template <typename S>
 hipError_t launch_fill_zero(void* p, int64_t count, hipStream_t st);
