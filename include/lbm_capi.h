@@ -96,6 +96,13 @@ typedef struct {
                              precondsourceterm); 1: the naive S^/gamma for every
                              moment (Sec. 3.1, eq. precondsourceincorrect), kept
                              only to exhibit its spurious steady-state error */
+  double wall_u[6][3];    /* velocity of each wall face (x-low, x-high, y-low,
+                             y-high, z-low, z-high) for link bounce-back with wall
+                             momentum (the moving lid of Sec. 5's cavity): a link
+                             reflected at a moving face gains 6 w_a rho0 (e_a . u_w);
+                             a link crossing two walls at an edge takes the mean of
+                             the two faces' terms.  Zero for fixed walls; ignored on
+                             periodic axes and by the magnetic populations. */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx;

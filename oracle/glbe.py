@@ -193,10 +193,28 @@ def _outside_masks(shape, e, bc):
     return mask
 
 
-def stream(post, bc, e=E19, opp=OPP19):
+def _crossed_faces(shape, e, bc):
+    """For each of the six faces (x-low, x-high, y-low, y-high, z-low, z-high),
+    the mask of nodes whose link to x - e crosses that wall."""
+    nz, ny, nx = shape
+    coords = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    faces = []
+    for axis_arr, comp, n in ((2, 0, nx), (1, 1, ny), (0, 2, nz)):
+        src = coords[axis_arr] - e[comp]
+        wall = bc[comp] == WALL and e[comp] != 0
+        faces.append(wall & (src < 0))
+        faces.append(wall & (src >= n))
+    return faces
+
+
+def stream(post, bc, e=E19, opp=OPP19, wall_u=None, rho0=1.0):
     """Pull streaming f_a(x) = f~_a(x - e_a), periodic wrap or halfway bounce-back.
 
     post: (Q, nz, ny, nx).  bc: (bcx, bcy, bcz), each PERIODIC or WALL.
+    wall_u: optional (6, 3) velocities of the faces x-low, x-high, y-low, y-high,
+    z-low, z-high.  A link bounced at a moving wall gains 6 w_a rho0 (e_a . u_w)
+    (link bounce-back with wall momentum, Sec. 5, cavity); a link crossing two
+    walls at an edge takes the mean of the two faces' terms (reading).
     """
     out = np.empty_like(post)
     shape = post.shape[1:]
@@ -206,14 +224,23 @@ def stream(post, bc, e=E19, opp=OPP19):
         m = _outside_masks(shape, (ex, ey, ez), bc)
         if m.any():
             out[a][m] = post[opp[a]][m]
+            if wall_u is not None and len(e) == Q19:
+                faces = _crossed_faces(shape, (ex, ey, ez), bc)
+                total = np.zeros(shape)
+                count = np.zeros(shape)
+                for f, mf in enumerate(faces):
+                    term = 6.0 * W19[a] * rho0 * float(np.dot(E19[a], wall_u[f]))
+                    total = total + np.where(mf, term, 0.0)
+                    count = count + mf
+                out[a][m] = out[a][m] + (total / np.maximum(count, 1))[m]
     return out
 
 
 # ------------------------------------------------------------------- step ---
-def step(post, F, gamma, s, bc, rho0=1.0, source="precond"):
+def step(post, F, gamma, s, bc, rho0=1.0, source="precond", wall_u=None):
     """One time step: stream, then collide.  Returns (new_post, u) where u is the
     velocity of the collision just performed (physical, with F/(2 gamma))."""
-    f = stream(post, bc)
+    f = stream(post, bc, wall_u=wall_u, rho0=rho0)
     _, _, _, u = fields(f, F, gamma, rho0)
     return collide(f, F, gamma, s, rho0, source), u
 
@@ -277,9 +304,10 @@ class Flow:
     """
 
     def __init__(self, shape_xyz, bc, F, gamma, s, rho0=1.0, dtype=np.float64, post=None,
-                 source="precond"):
+                 source="precond", wall_u=None):
         nx, ny, nz = shape_xyz
         self.source = source
+        self.wall_u = None if wall_u is None else np.asarray(wall_u, dtype=float)
         self.bc = tuple(bc)
         self.gamma = gamma
         self.s = np.asarray(s, dtype=float)
@@ -297,7 +325,7 @@ class Flow:
     def step(self, n=1, check_every=10):
         for _ in range(n):
             self.post, u = step(self.post, self.F, self.gamma, self.s, self.bc, self.rho0,
-                                self.source)
+                                self.source, self.wall_u)
             self.t += 1
             if self.t % check_every == 0:
                 if self.u_snap is not None:
@@ -313,7 +341,7 @@ class Flow:
         return False
 
     def velocity(self):
-        f = stream(self.post, self.bc)
+        f = stream(self.post, self.bc, wall_u=self.wall_u, rho0=self.rho0)
         return fields(f, self.F, self.gamma, self.rho0)[3]
 
     def flow_rate(self):

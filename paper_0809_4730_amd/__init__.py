@@ -53,6 +53,7 @@ class _Params(ctypes.Structure):
         ("check_every", ctypes.c_int32),
         ("history_len", ctypes.c_int32),
         ("source_mode", ctypes.c_int32),
+        ("wall_u", (ctypes.c_double * 3) * 6),
     ]
 
 
@@ -160,11 +161,12 @@ class Simulation:
     dtype (float64 for f64 storage, float32 otherwise).
     mhd: None or dict(gamma_m=, chi=, eta=, B0=(..), mu=1.0).
     source: "precond" (P_S, the paper's form) or "naive" (S/gamma, its negative control).
+    wall_u: None or (6, 3) face velocities (x-low, x-high, y-low, y-high, z-low, z-high).
     """
 
     def __init__(self, shape, bc, gamma, s, storage="f32", force=(0.0, 0.0, 0.0), rho0=1.0,
                  mhd=None, check_every=10, history_len=4096, device="cuda", stream=None,
-                 source="precond"):
+                 source="precond", wall_u=None):
         torch = _torch()
         self._lib = load_library()
         self.device = torch.device(device)
@@ -209,6 +211,10 @@ class Simulation:
         p.check_every = check_every
         p.history_len = history_len
         p.source_mode = {"precond": 0, "naive": 1}[source]
+        if wall_u is not None:
+            for f in range(6):
+                for a in range(3):
+                    p.wall_u[f][a] = float(wall_u[f][a])
         self._params = p
         self.gamma = gamma
         nbytes = ctypes.c_size_t()

@@ -79,15 +79,30 @@ __device__ __forceinline__ bool adj_link(const AdjNbr& b, int32_t& off) {
          (EZ > 0 && b.bzm) || (EZ < 0 && b.bzp);
 }
 
+// Forward pull of the state (with the constant wall-momentum term of moving
+// walls, which drops out of the transposed streaming).
 template <typename R, int A = 0>
 __device__ __forceinline__ void gather_fwd(const R* __restrict__ p, int64_t st, uint32_t n,
-                                           const AdjNbr& b, R (&f)[Q19]) {
+                                           const AdjNbr& b, const CollideArgs<R>& c,
+                                           R (&f)[Q19]) {
   if constexpr (A < Q19) {
     int32_t off;
     const bool bb = adj_link<EX19[A], EY19[A], EZ19[A]>(b, off);
     const int64_t idx = bb ? int64_t(OPP19(A)) * st + n : int64_t(A) * st + int64_t(n) + off;
-    f[A] = p[idx];
-    gather_fwd<R, A + 1>(p, st, n, b, f);
+    R v = p[idx];
+    if (bb && c.moving) {
+      R sum = R(0);
+      int cnt = 0;
+      if (EX19[A] > 0 && b.bxm) { sum += c.wall[A][0]; ++cnt; }
+      if (EX19[A] < 0 && b.bxp) { sum += c.wall[A][1]; ++cnt; }
+      if (EY19[A] > 0 && b.bym) { sum += c.wall[A][2]; ++cnt; }
+      if (EY19[A] < 0 && b.byp) { sum += c.wall[A][3]; ++cnt; }
+      if (EZ19[A] > 0 && b.bzm) { sum += c.wall[A][4]; ++cnt; }
+      if (EZ19[A] < 0 && b.bzp) { sum += c.wall[A][5]; ++cnt; }
+      v += cnt > 1 ? sum / R(cnt) : sum;
+    }
+    f[A] = v;
+    gather_fwd<R, A + 1>(p, st, n, b, c, f);
   }
 }
 
@@ -121,7 +136,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_step(
     int x, y, z;
     const AdjNbr b = adj_neighbours(g, n, x, y, z);
     R f[Q19];
-    gather_fwd<R>(state, g.stride, n, b, f);
+    gather_fwd<R>(state, g.stride, n, b, c, f);
     const R sh = shift ? R(*shift) : R(0);
     R lam[Q19];
     gather_transpose<R>(mu_in, g.stride, n, b, sh, lam);

@@ -77,6 +77,8 @@ struct CollideArgs {
   R A[Q19];        // s_k / |T_k|^2
   R B[Q19];        // (1 - s_k/2) / |T_k|^2
   R F[3];          // uniform force (force_mode = UNIFORM)
+  R wall[Q19][6];  // 6 w_a rho0 (e_a . u_face) for link bounce-back at moving faces
+  int32_t moving;  // any face moving
 };
 
 // Induction-LKE constants (Sec. 4, 4.1).

@@ -57,23 +57,43 @@ __device__ __forceinline__ bool pull_source(const Nbr& b, int32_t& off) {
          (EZ > 0 && b.bzm) || (EZ < 0 && b.bzp);
 }
 
+// Wall-momentum term of a bounced link of direction A at this node: mean over
+// the crossed moving faces of 6 w_A rho0 (e_A . u_face).
+template <typename R, int A>
+__device__ __forceinline__ R wall_term(const Nbr& b, const CollideArgs<R>& c) {
+  R sum = R(0);
+  int cnt = 0;
+  if (EX19[A] > 0 && b.bxm) { sum += c.wall[A][0]; ++cnt; }
+  if (EX19[A] < 0 && b.bxp) { sum += c.wall[A][1]; ++cnt; }
+  if (EY19[A] > 0 && b.bym) { sum += c.wall[A][2]; ++cnt; }
+  if (EY19[A] < 0 && b.byp) { sum += c.wall[A][3]; ++cnt; }
+  if (EZ19[A] > 0 && b.bzm) { sum += c.wall[A][4]; ++cnt; }
+  if (EZ19[A] < 0 && b.bzp) { sum += c.wall[A][5]; ++cnt; }
+  return cnt > 1 ? sum / R(cnt) : sum;
+}
+
 template <typename S, int A>
-__device__ __forceinline__ typename Storage<S>::R gather_one(const S* __restrict__ fin,
-                                                             int64_t stride, uint32_t n,
-                                                             const Nbr& b) {
+__device__ __forceinline__ typename Storage<S>::R gather_one(
+    const S* __restrict__ fin, int64_t stride, uint32_t n, const Nbr& b,
+    const CollideArgs<typename Storage<S>::R>& c) {
+  using R = typename Storage<S>::R;
   int32_t off;
   const bool bounce = pull_source<EX19[A], EY19[A], EZ19[A]>(b, off);
   const int64_t idx = bounce ? static_cast<int64_t>(OPP19(A)) * stride + n
                              : static_cast<int64_t>(A) * stride + static_cast<int64_t>(n) + off;
-  return Storage<S>::ld(fin + idx);
+  R v = Storage<S>::ld(fin + idx);
+  if (bounce && c.moving) v += wall_term<R, A>(b, c);
+  return v;
 }
 
 template <typename S, int A = 0>
 __device__ __forceinline__ void gather19(const S* __restrict__ fin, int64_t stride, uint32_t n,
-                                         const Nbr& b, typename Storage<S>::R (&f)[Q19]) {
+                                         const Nbr& b,
+                                         const CollideArgs<typename Storage<S>::R>& c,
+                                         typename Storage<S>::R (&f)[Q19]) {
   if constexpr (A < Q19) {
-    f[A] = gather_one<S, A>(fin, stride, n, b);
-    gather19<S, A + 1>(fin, stride, n, b, f);
+    f[A] = gather_one<S, A>(fin, stride, n, b, c);
+    gather19<S, A + 1>(fin, stride, n, b, c, f);
   }
 }
 
@@ -261,7 +281,7 @@ __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<type
   if (n < static_cast<uint32_t>(g.N)) {
     const Nbr b = neighbours(g, n);
     R f[Q19];
-    gather19<S>(fin, g.stride, n, b, f);
+    gather19<S>(fin, g.stride, n, b, c, f);
     R Fx, Fy, Fz;
     load_force<R>(g, c, force, FIELD, n, Fx, Fy, Fz);
     const NodeMacro<R> mac = collide19<R>(f, Fx, Fy, Fz, c);
@@ -286,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void mhd_step(GridArgs g, CollideArgs<R> c,
   if (n < static_cast<uint32_t>(g.N)) {
     const Nbr b = neighbours(g, n);
     R f[Q19];
-    gather19<R>(fin, g.stride, n, b, f);
+    gather19<R>(fin, g.stride, n, b, c, f);
     R gg[3][Q7];
     gather_g<R>(gin, g.stride, n, b, gg);
     R Fx, Fy, Fz;
@@ -323,7 +343,7 @@ __global__ __launch_bounds__(kBlock) void fields_kernel(
   if (n < static_cast<uint32_t>(g.N)) {
     const Nbr b = neighbours(g, n);
     R f[Q19];
-    gather19<S>(fin, g.stride, n, b, f);
+    gather19<S>(fin, g.stride, n, b, c, f);
     R Fx, Fy, Fz;
     load_force<R>(g, c, force, field != 0, n, Fx, Fy, Fz);
     R Bx = 0, By = 0, Bz = 0;

@@ -61,6 +61,9 @@ std::string validate(const lbm_grid* grid, const lbm_params* p) {
   if (p->check_every < 1) return "check_every must be >= 1";
   if (p->history_len < 1) return "history_len must be >= 1";
   if (p->source_mode != 0 && p->source_mode != 1) return "source_mode must be 0 or 1";
+  for (int f = 0; f < 6; ++f)
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(p->wall_u[f][a])) return "wall_u must be finite";
   return "";
 }
 
@@ -125,6 +128,17 @@ CollideArgs<R> collide_args(const lbm_params& p) {
     c.B[k] = R((1.0 - 0.5 * p.s[k]) / NORM19[k]);
   }
   for (int a = 0; a < 3; ++a) c.F[a] = R(p.force_const[a]);
+  // link bounce-back with wall momentum: 6 w_a rho0 (e_a . u_face); w by shell
+  c.moving = 0;
+  for (int a = 0; a < Q19; ++a) {
+    const int e2 = EX19[a] * EX19[a] + EY19[a] * EY19[a] + EZ19[a] * EZ19[a];
+    const double w = e2 == 0 ? 1.0 / 3.0 : (e2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+    for (int f = 0; f < 6; ++f) {
+      const double eu = EX19[a] * p.wall_u[f][0] + EY19[a] * p.wall_u[f][1] + EZ19[a] * p.wall_u[f][2];
+      c.wall[a][f] = R(6.0 * w * p.rho0 * eu);
+      if (eu != 0.0) c.moving = 1;
+    }
+  }
   return c;
 }
 
