@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_0809_4730_amd/csrc/kernels.hip", "paper_0809_4730_amd/csrc/collide.hpp",
-                  "paper_0809_4730_amd/csrc/common.hpp"]
+                  "paper_0809_4730_amd/csrc/common.hpp", "paper_0809_4730_amd/csrc/lbm_capi.hip"]
 
 
 def kernel_hash():
@@ -160,13 +160,13 @@ def cpu_baseline(budget_s=12.0):
                       "cores = BLAS threads" % n}
 
 
-def time_to_residual(shape, storage, gamma, tol, max_steps, mhd=None, **kw):
+def time_to_residual(shape, storage, gamma, tol, max_steps, mhd=None, poll=200, **kw):
     import torch
     sim = make_sim(shape, storage, gamma, **kw) if mhd is None else mhd()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     try:
-        steps, r = sim.run_to_residual(tol, max_steps, poll_every=2000)
+        steps, r = sim.run_to_residual(tol, max_steps, poll_every=poll)
         status = "ok" if steps > 0 else "not reached"
     except Exception as e:  # unstable
         steps, r, status = -1, float("nan"), "error: %s" % e
@@ -233,6 +233,64 @@ def extras(args):
         ttm.append(time_to_residual(None, "f32", g, 2e-7, 400000,
                                     mhd=lambda g=g: hart(g, g)))
     out["time_to_residual_hartmann_Ha10_f32_tol2e-7"] = ttm
+    out["precision_duct64"] = precision_table()
+    out["adjoint"] = adjoint_extras()
+    return out
+
+
+def precision_table():
+    """Velocity error of each storage type against FP64 on the 64^3 duct at the
+    FP64 steady state (residual 1e-8), gamma = 0.1."""
+    import numpy as np
+    import torch
+    ref = make_sim((64, 64, 64), "f64", 0.1)
+    ref.run_to_residual(1e-8, 200000, poll_every=200)
+    n = ref.t
+    _, u64, _ = ref.moments("f64")
+    out = {"steps": n}
+    for st in ("f32", "bf16", "f16"):
+        sim = make_sim((64, 64, 64), st, 0.1)
+        sim.step(n)
+        _, u, _ = sim.moments("f64")
+        err = float(torch.linalg.vector_norm(u - u64) / torch.linalg.vector_norm(u64))
+        mass, _ = sim.reductions()
+        floor = float(sim.history(64)[:, 1].min())
+        out[st] = {"u_rel_L2_vs_f64": err, "mass_drift": mass, "residual_floor": floor}
+    return out
+
+
+def adjoint_extras():
+    """Steady adjoint on the 128^3 duct (FP32) and the checkpointed unrolled
+    adjoint over 2000 steps on 32^3: iteration counts and kernel rates."""
+    import torch
+    from paper_0809_4730_amd import inputs
+    cfg = inputs.ADJOINT
+    out = {}
+    sim = make_sim(cfg["shape"], "f32", 0.1)
+    t0 = time.perf_counter()
+    steps, r = sim.run_to_residual(1e-7, 400000, poll_every=1000)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    grad, iters, change = sim.adjoint_steady(tol=1e-6, max_iter=400000)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    N = sim.N
+    out["steady_128"] = {"gamma": 0.1, "forward_steps_to_1e-7": steps, "forward_s": round(t_fwd, 3),
+                         "adjoint_iters": iters, "adjoint_change": change,
+                         "adjoint_s": round(t_adj, 3),
+                         "adjoint_MLUPS": round(N * iters / t_adj / 1e6, 1),
+                         "grad_norm": float(torch.linalg.vector_norm(grad))}
+    del sim, grad
+    torch.cuda.empty_cache()
+    sim = make_sim(cfg["unrolled_shape"], "f32", cfg["gamma"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = sim.adjoint_unrolled(cfg["unrolled_steps"], cfg["ckpt_every"])
+    torch.cuda.synchronize()
+    out["unrolled_32"] = {"steps": cfg["unrolled_steps"], "ckpt_every": cfg["ckpt_every"],
+                          "wall_s": round(time.perf_counter() - t0, 3),
+                          "grad_norm": float(torch.linalg.vector_norm(g))}
     return out
 
 
@@ -244,6 +302,8 @@ def main():
     ap.add_argument("--big-steps", type=int, default=100)
     ap.add_argument("--extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--grid", type=int, default=64, help="cube edge of the duct (64 = headline)")
+    ap.add_argument("--storage", default="f32", choices=["f32", "f64", "bf16", "f16"])
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -258,13 +318,14 @@ def main():
     import paper_0809_4730_amd as pkg
     pkg.load_library()
 
-    shape, gamma, storage = (64, 64, 64), 0.1, "f32"
+    shape, gamma, storage = (args.grid,) * 3, 0.1, args.storage
     mlups, wall, mean_us = measure(shape, storage, gamma, args.steps, args.warmup)
     N = shape[0] * shape[1] * shape[2]
-    bpn = algorithmic_bytes_per_node(4, True, NO_CHECK)
+    sb = {"f32": 4, "f64": 8, "bf16": 2, "f16": 2}[storage]
+    bpn = algorithmic_bytes_per_node(sb, True, NO_CHECK)
     achieved = bpn * N / (mean_us * 1e-6) / 1e9
     khash = kernel_hash()
-    traffic = traffic_from_profiles("glbe_step_f32_duct64", khash)
+    traffic = traffic_from_profiles("glbe_step_%s_duct%d" % (storage, args.grid), khash)
     line = {
         "metric": "MLUPS, % HBM roofline; wall time to 1e-8 residual, gamma<1 vs plain gamma=1",
         "value": round(mlups, 2),
@@ -276,15 +337,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": storage,
         "data": "synthetic",
-        "config": {"workload": "square duct 64x64x64, D3Q19 preconditioned MRT-GLBE, "
+        "config": {"workload": "square duct %dx%dx%d, D3Q19 preconditioned MRT-GLBE, "
                                "spatially varying force F0=1e-5, nu=0.131, gamma=0.1, "
-                               "FP32 deviation storage, FP64 residual every 10 steps",
+                               "%s deviation storage, FP64 residual every 10 steps"
+                               % (shape + (storage.upper(),)),
                    "grid": list(shape), "gamma": gamma, "storage": storage},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "glbe_step<float, check=false, field=true>",
+                     "traffic": traffic,
+                     "kernel": "glbe_step<%s, check=false, field=true>" % storage,
                      "alg_bytes_per_node": bpn, "mean_kernel_us": round(mean_us, 3),
                      "kernel_hash": khash},
     }
