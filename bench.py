@@ -235,6 +235,51 @@ def extras(args):
     out["time_to_residual_hartmann_Ha10_f32_tol2e-7"] = ttm
     out["precision_duct64"] = precision_table()
     out["adjoint"] = adjoint_extras()
+    out.update(cavity_extras())
+    return out
+
+
+def cavity_extras():
+    """Lid-driven cubic cavity, 64^3 fluid nodes, Re = 100 (U0 = 0.0235,
+    nu = 0.015), FP32: steps and wall time to a residual of 1e-6 for each gamma,
+    without field and with Ha = 45 (B0 parallel to the lid, normal to its motion;
+    eta = 0.015, Pm = 5.625e-7, gamma_m = gamma) on an induction lattice that
+    extends 16 nodes beyond each wall; plus the per-step time of both."""
+    import numpy as np
+
+    import paper_0809_4730_amd as pkg
+    from paper_0809_4730_amd import inputs
+    c = inputs.MHD_CAVITY
+    W, pad, nu = c["W"], c["pad"], c["nu"]
+    walls = ("wall", "wall", "wall")
+    wall_u = np.zeros((6, 3))
+    wall_u[5] = (c["U0"], 0.0, 0.0)
+    B0, chi = inputs.cavity_field(c["Ha"], c["Pm"], W, nu, c["eta"])
+    n = W + 2 * pad
+
+    def plain(g):
+        return pkg.Simulation((W, W, W), walls, g, pkg.default_rates(nu, g), storage="f32",
+                              wall_u=wall_u)
+
+    def magnetic(g):
+        return pkg.Simulation((n, n, n), walls, g, pkg.default_rates(nu, g), storage="f32",
+                              wall_u=wall_u,
+                              mhd=dict(gamma_m=g, chi=chi, eta=c["eta"], B0=(0.0, B0, 0.0),
+                                       pad=(pad, pad, pad)))
+    out = {}
+    for name, make in (("cavity64_Ha0", plain), ("cavity64_Ha45_ext16", magnetic)):
+        rows = []
+        for g in c["gammas"]:
+            rows.append(time_to_residual(None, "f32", g, c["tol"], 400000, mhd=lambda g=g: make(g)))
+        ref = rows[0]
+        for e in rows[1:]:
+            if ref["steps"] > 0 and e["steps"] > 0:
+                e["step_ratio_vs_gamma1"] = round(ref["steps"] / e["steps"], 3)
+                e["speedup_vs_gamma1_wall"] = round(ref["wall_s"] / e["wall_s"], 3)
+        sim = make(0.1)
+        mlups, wall = timed_region(sim, 500, 50)
+        out[name] = {"time_to_residual_tol1e-6": rows, "lattice_nodes": sim.N,
+                     "us_per_step": round(1e6 * wall / 500, 2), "MLUPS": round(mlups, 1)}
     return out
 
 

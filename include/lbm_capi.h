@@ -103,16 +103,27 @@ typedef struct {
                              a link crossing two walls at an edge takes the mean of
                              the two faces' terms.  Zero for fixed walls; ignored on
                              periodic axes and by the magnetic populations. */
+  int32_t mag_pad[3];     /* extended induction lattice (Sec. 5, MHD cavity): with
+                             mhd = 1 and wall axes only, the grid is the induction
+                             lattice and the fluid occupies the box
+                             [mag_pad[a], n[a] - mag_pad[a]) on each axis a.  The
+                             flow has no-slip walls (moving as wall_u says) at the
+                             box faces; the induced field B - B0 is zero at the
+                             lattice faces; outside the box u = 0, rho = rho0, f is
+                             not updated, and the induction populations only
+                             diffuse.  Residual, mass and flow sums cover the box.
+                             All zero: fluid and induction lattices coincide. */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx;
 
 /* One residual-history record (all FP64), written on device every
  * check_every steps.  residual = sqrt(du2 / u2), with du2 = sum |u(t)-u(t-k)|^2
- * and u2 = sum |u(t)|^2 over all nodes and components (u(t-k) = 0 at the
- * first check).  mass = sum (rho - rho0); flow = (1/nx) sum j_x (j includes
- * F/(2 gamma)); nonfinite = count of nodes with a non-finite rho or j.  All of
- * these are taken from the populations entering the collision of `step`. */
+ * and u2 = sum |u(t)|^2 over all fluid nodes and components (u(t-k) = 0 at
+ * the first check).  mass = sum (rho - rho0); flow = (1/nx) sum j_x with nx the
+ * fluid box's x extent (j includes F/(2 gamma)); nonfinite = count of nodes
+ * with a non-finite rho or j.  All of these are taken from the populations
+ * entering the collision of `step`. */
 typedef struct {
   double step, residual, du2, u2, mass, flow, nonfinite, reserved;
 } lbm_record;
@@ -203,7 +214,9 @@ lbm_status lbm_moments(lbm_ctx* ctx, int32_t out_dtype, void* rho, void* u, void
 lbm_status lbm_state_bytes(const lbm_ctx* ctx, size_t* bytes);
 
 /* Copy the state blob to / from caller device memory, and read / set the step
- * counter.  lbm_set_state also clears the residual snapshot and history. */
+ * counter.  lbm_set_state also clears the residual snapshot and history.  With
+ * mag_pad, f outside the fluid box keeps the values last set here (zero
+ * deviations after lbm_create). */
 lbm_status lbm_get_state(lbm_ctx* ctx, void* dst);
 lbm_status lbm_set_state(lbm_ctx* ctx, const void* src, int64_t step);
 lbm_status lbm_get_step(const lbm_ctx* ctx, int64_t* step);

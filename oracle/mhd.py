@@ -25,6 +25,14 @@ Readings (the paper is silent, garbled or inconsistent here):
 * Walls: insulating, induced field zero at the halfway wall, imposed by
   anti-bounce-back g_a(x) = -g~_opp(a)(x) + 2 W_a B_wall (B_wall = B0).
 * mu = 1 (lattice units).
+* Extended magnetic domain (Sec. 5, MHD cavity): the induction lattice covers
+  the fluid box plus ``pad`` nodes on each side of the padded axes.  The paper
+  asks for a zero induced field on the outer boundary and cites an
+  extrapolation scheme for it without giving it; the oracle imposes the same
+  condition (B = B0 at the outer halfway wall) with the anti-bounce-back above.
+  Outside the fluid box u = 0, so the induction lattice only diffuses there; the
+  cavity walls do not act on g.  The fluid lattice has no-slip halfway walls at
+  its own box faces.
 """
 import numpy as np
 
@@ -127,17 +135,33 @@ def collide_g(g, B, u, chi, gamma_m, eta):
     return g - (g - g_eq(B, u, chi, gamma_m)) / tau_m(eta, gamma_m)
 
 
-def step(post_f, post_g, F_ext, p, bc):
+def fluid_box(shape_g, pad):
+    """(z, y, x) slices of the fluid box inside an induction lattice of shape
+    shape_g = (nz, ny, nx) extended by pad = (px, py, pz) nodes per side."""
+    px, py, pz = pad
+    nz, ny, nx = shape_g
+    return (slice(pz, nz - pz), slice(py, ny - py), slice(px, nx - px))
+
+
+def step(post_f, post_g, F_ext, p, bc, wall_u=None, pad=(0, 0, 0)):
     """One coupled step.  p: dict(gamma, s, gamma_m, chi, eta, B_wall, rho0, mu).
 
-    Returns (post_f, post_g, u, B).
+    post_f covers the fluid box, post_g the induction lattice, which is larger
+    by pad nodes per side (pad = 0: the same lattice).  wall_u: face velocities
+    of the fluid box (see glbe.stream).  Returns (post_f, post_g, u, B) with u on
+    the fluid box and B on the induction lattice.
     """
-    f = glbe.stream(post_f, bc)
+    rho0 = p.get("rho0", 1.0)
+    f = glbe.stream(post_f, bc, wall_u=wall_u, rho0=rho0)
     g = stream_g(post_g, bc, p["B_wall"])
-    rho, u, B, J, F = coupled_fields(f, g, F_ext, p["gamma"], p["gamma_m"], p["chi"],
-                                     p["eta"], p.get("mu", 1.0), p.get("rho0", 1.0))
-    new_f = glbe.collide(f, F, p["gamma"], p["s"], p.get("rho0", 1.0))
-    new_g = collide_g(g, B, u, p["chi"], p["gamma_m"], p["eta"])
+    box = fluid_box(g.shape[2:], pad)
+    rho, u, Bf, J, F = coupled_fields(f, g[(slice(None), slice(None)) + box], F_ext, p["gamma"],
+                                      p["gamma_m"], p["chi"], p["eta"], p.get("mu", 1.0), rho0)
+    new_f = glbe.collide(f, F, p["gamma"], p["s"], rho0)
+    B = g.sum(axis=1)
+    u_all = np.zeros_like(B)
+    u_all[(slice(None),) + box] = u
+    new_g = collide_g(g, B, u_all, p["chi"], p["gamma_m"], p["eta"])
     return new_f, new_g, u, B
 
 
@@ -155,8 +179,16 @@ class MHDFlow:
     """Time march of the coupled GLBE + vector LKE to steady state."""
 
     def __init__(self, shape_xyz, bc, F_ext, gamma, s, gamma_m, chi, eta, B0,
-                 rho0=1.0, mu=1.0, dtype=np.float64):
-        nx, ny, nz = shape_xyz
+                 rho0=1.0, mu=1.0, dtype=np.float64, wall_u=None, pad=(0, 0, 0)):
+        """shape_xyz: the induction lattice; the fluid box is smaller by pad
+        nodes per side (pad only on wall axes)."""
+        self.pad = tuple(int(v) for v in pad)
+        for a in range(3):
+            if self.pad[a] and bc[a] != WALL:
+                raise ValueError("pad only on wall axes")
+        self.shape_g = tuple(shape_xyz)
+        nx, ny, nz = (shape_xyz[a] - 2 * self.pad[a] for a in range(3))
+        self.wall_u = None if wall_u is None else np.asarray(wall_u, dtype=float)
         self.bc = tuple(bc)
         F_ext = np.asarray(F_ext)
         if F_ext.ndim == 1:
@@ -165,7 +197,7 @@ class MHDFlow:
         self.p = dict(gamma=gamma, s=np.asarray(s, dtype=float), gamma_m=gamma_m, chi=chi,
                       eta=eta, B_wall=np.asarray(B0, dtype=float), rho0=rho0, mu=mu)
         self.post_f = np.zeros((19, nz, ny, nx), dtype=dtype)
-        self.post_g = initial_g(shape_xyz, B0, dtype)
+        self.post_g = initial_g(self.shape_g, B0, dtype)
         self.t = 0
         self.u_snap = None
         self.history = []
@@ -174,7 +206,8 @@ class MHDFlow:
 
     def step(self, n=1, check_every=10):
         for _ in range(n):
-            self.post_f, self.post_g, u, B = step(self.post_f, self.post_g, self.F, self.p, self.bc)
+            self.post_f, self.post_g, u, B = step(self.post_f, self.post_g, self.F, self.p, self.bc,
+                                                  self.wall_u, self.pad)
             self.u, self.B = u, B
             self.t += 1
             if self.t % check_every == 0:

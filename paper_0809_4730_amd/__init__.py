@@ -54,6 +54,7 @@ class _Params(ctypes.Structure):
         ("history_len", ctypes.c_int32),
         ("source_mode", ctypes.c_int32),
         ("wall_u", (ctypes.c_double * 3) * 6),
+        ("mag_pad", ctypes.c_int32 * 3),
     ]
 
 
@@ -77,6 +78,10 @@ def load_library():
     if not os.path.exists(_LIB_PATH):
         raise RuntimeError("liblbm.so is not built (expected at %s); run "
                            "paper_0809_4730_amd.build.build()" % _LIB_PATH)
+    # torch first: it ships its own HIP runtime, and liblbm.so must bind to that
+    # one.  Loaded the other way round the process maps two HIP/HSA runtimes and
+    # the second one finds no device.
+    _torch()
     lib = ctypes.CDLL(_LIB_PATH)
     c_int32, c_int64, c_double, c_size_t, c_void_p = (ctypes.c_int32, ctypes.c_int64,
                                                       ctypes.c_double, ctypes.c_size_t,
@@ -159,7 +164,9 @@ class Simulation:
     s: 19 preconditioned rates (default_rates).  storage: "f64", "f32", "bf16", "f16".
     force: a 3-vector (uniform) or a device tensor (3, nz, ny, nx) in the compute
     dtype (float64 for f64 storage, float32 otherwise).
-    mhd: None or dict(gamma_m=, chi=, eta=, B0=(..), mu=1.0).
+    mhd: None or dict(gamma_m=, chi=, eta=, B0=(..), mu=1.0, pad=(0, 0, 0)); pad > 0
+         extends the induction lattice beyond the fluid box (shape is then the
+         induction lattice, the fluid box is pad nodes in from each wall face).
     source: "precond" (P_S, the paper's form) or "naive" (S/gamma, its negative control).
     wall_u: None or (6, 3) face velocities (x-low, x-high, y-low, y-high, z-low, z-high).
     """
@@ -208,6 +215,7 @@ class Simulation:
             p.mu = mhd.get("mu", 1.0)
             for a in range(3):
                 p.B0[a] = float(mhd["B0"][a])
+                p.mag_pad[a] = int(mhd.get("pad", (0, 0, 0))[a])
         p.check_every = check_every
         p.history_len = history_len
         p.source_mode = {"precond": 0, "naive": 1}[source]

@@ -52,6 +52,11 @@ struct GridArgs {
   int32_t xcd_chunk;       // consecutive logical blocks an XCD takes at a time
   int64_t stride;          // elements between direction planes (N rounded up to 64)
   FastDiv div_nx, div_nxny;
+  // Fluid box [flo, fhi) per axis (x, y, z).  The whole lattice, unless the
+  // induction lattice extends beyond the fluid; its faces are then no-slip
+  // walls of the flow, while the induction lattice's walls stay at the lattice
+  // faces.
+  int32_t flo[3], fhi[3];
 };
 
 // Workgroup b of the launch runs on XCD (b mod 8) as that XCD's (b / 8)-th

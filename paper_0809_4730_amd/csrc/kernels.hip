@@ -24,27 +24,57 @@ struct Nbr {
   bool bxm, bxp, bym, byp, bzm, bzp;  // link to that neighbour crosses a wall
 };
 
-__device__ __forceinline__ Nbr neighbours(const GridArgs& g, uint32_t n) {
+struct Coord {
+  int x, y, z;
+};
+
+__device__ __forceinline__ Coord coords(const GridArgs& g, uint32_t n) {
   const uint32_t yz = fdiv(n, g.div_nx);
   const uint32_t z = fdiv(n, g.div_nxny);
-  const int x = static_cast<int>(n - yz * static_cast<uint32_t>(g.nx));
-  const int y = static_cast<int>(yz - z * static_cast<uint32_t>(g.ny));
-  const int zz = static_cast<int>(z);
+  Coord q;
+  q.x = static_cast<int>(n - yz * static_cast<uint32_t>(g.nx));
+  q.y = static_cast<int>(yz - z * static_cast<uint32_t>(g.ny));
+  q.z = static_cast<int>(z);
+  return q;
+}
+
+// Offsets with periodic wrap, and the walls at the lattice faces.
+__device__ __forceinline__ Nbr neighbours_at(const GridArgs& g, const Coord& q) {
   const int sx = 1, sy = g.nx, sz = g.nx * g.ny;
   Nbr b;
-  b.xm = (x == 0) ? (g.nx - 1) * sx : -sx;
-  b.xp = (x == g.nx - 1) ? -(g.nx - 1) * sx : sx;
-  b.ym = (y == 0) ? (g.ny - 1) * sy : -sy;
-  b.yp = (y == g.ny - 1) ? -(g.ny - 1) * sy : sy;
-  b.zm = (zz == 0) ? (g.nz - 1) * sz : -sz;
-  b.zp = (zz == g.nz - 1) ? -(g.nz - 1) * sz : sz;
-  b.bxm = g.wall_x && x == 0;
-  b.bxp = g.wall_x && x == g.nx - 1;
-  b.bym = g.wall_y && y == 0;
-  b.byp = g.wall_y && y == g.ny - 1;
-  b.bzm = g.wall_z && zz == 0;
-  b.bzp = g.wall_z && zz == g.nz - 1;
+  b.xm = (q.x == 0) ? (g.nx - 1) * sx : -sx;
+  b.xp = (q.x == g.nx - 1) ? -(g.nx - 1) * sx : sx;
+  b.ym = (q.y == 0) ? (g.ny - 1) * sy : -sy;
+  b.yp = (q.y == g.ny - 1) ? -(g.ny - 1) * sy : sy;
+  b.zm = (q.z == 0) ? (g.nz - 1) * sz : -sz;
+  b.zp = (q.z == g.nz - 1) ? -(g.nz - 1) * sz : sz;
+  b.bxm = g.wall_x && q.x == 0;
+  b.bxp = g.wall_x && q.x == g.nx - 1;
+  b.bym = g.wall_y && q.y == 0;
+  b.byp = g.wall_y && q.y == g.ny - 1;
+  b.bzm = g.wall_z && q.z == 0;
+  b.bzp = g.wall_z && q.z == g.nz - 1;
   return b;
+}
+
+__device__ __forceinline__ Nbr neighbours(const GridArgs& g, uint32_t n) {
+  return neighbours_at(g, coords(g, n));
+}
+
+// The same node seen by the flow: walls at the fluid box faces.
+__device__ __forceinline__ Nbr box_walls(const GridArgs& g, const Coord& q, Nbr b) {
+  b.bxm = g.wall_x && q.x == g.flo[0];
+  b.bxp = g.wall_x && q.x == g.fhi[0] - 1;
+  b.bym = g.wall_y && q.y == g.flo[1];
+  b.byp = g.wall_y && q.y == g.fhi[1] - 1;
+  b.bzm = g.wall_z && q.z == g.flo[2];
+  b.bzp = g.wall_z && q.z == g.fhi[2] - 1;
+  return b;
+}
+
+__device__ __forceinline__ bool in_box(const GridArgs& g, const Coord& q) {
+  return q.x >= g.flo[0] && q.x < g.fhi[0] && q.y >= g.flo[1] && q.y < g.fhi[1] &&
+         q.z >= g.flo[2] && q.z < g.fhi[2];
 }
 
 // Source of f_a(x) = f~_a(x - e_a): returns the element index to read in the
@@ -72,7 +102,9 @@ __device__ __forceinline__ R wall_term(const Nbr& b, const CollideArgs<R>& c) {
   return cnt > 1 ? sum / R(cnt) : sum;
 }
 
-template <typename S, int A>
+// MOVING = false compiles the wall-momentum term out (the plain step); with
+// MOVING = true it is added on bounced links when c.moving is set.
+template <typename S, int A, bool MOVING>
 __device__ __forceinline__ typename Storage<S>::R gather_one(
     const S* __restrict__ fin, int64_t stride, uint32_t n, const Nbr& b,
     const CollideArgs<typename Storage<S>::R>& c) {
@@ -82,18 +114,20 @@ __device__ __forceinline__ typename Storage<S>::R gather_one(
   const int64_t idx = bounce ? static_cast<int64_t>(OPP19(A)) * stride + n
                              : static_cast<int64_t>(A) * stride + static_cast<int64_t>(n) + off;
   R v = Storage<S>::ld(fin + idx);
-  if (bounce && c.moving) v += wall_term<R, A>(b, c);
+  if constexpr (MOVING) {
+    if (bounce && c.moving) v += wall_term<R, A>(b, c);
+  }
   return v;
 }
 
-template <typename S, int A = 0>
+template <typename S, bool MOVING, int A = 0>
 __device__ __forceinline__ void gather19(const S* __restrict__ fin, int64_t stride, uint32_t n,
                                          const Nbr& b,
                                          const CollideArgs<typename Storage<S>::R>& c,
                                          typename Storage<S>::R (&f)[Q19]) {
   if constexpr (A < Q19) {
-    f[A] = gather_one<S, A>(fin, stride, n, b, c);
-    gather19<S, A + 1>(fin, stride, n, b, c, f);
+    f[A] = gather_one<S, A, MOVING>(fin, stride, n, b, c);
+    gather19<S, MOVING, A + 1>(fin, stride, n, b, c, f);
   }
 }
 
@@ -195,6 +229,24 @@ __device__ __forceinline__ Coupled<R> lorentz_solve(const R (&f)[Q19], const R (
   return o;
 }
 
+// Outside the fluid box: the field alone (u = 0, no force).
+template <typename R>
+__device__ __forceinline__ Coupled<R> field_only(const R (&g)[3][Q7], const MagArgs<R>& m) {
+  Coupled<R> o;
+  R bb[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+    bb[j] = g[j][0] + g[j][1] + g[j][2] + g[j][3] + g[j][4] + g[j][5] + g[j][6];
+  o.bx = bb[0];
+  o.by = bb[1];
+  o.bz = bb[2];
+  o.Bx = m.B0[0] + bb[0];
+  o.By = m.B0[1] + bb[1];
+  o.Bz = m.B0[2] + bb[2];
+  o.Fx = o.Fy = o.Fz = R(0);
+  return o;
+}
+
 // g~ = g + (g^eq* - g)/tau_m*, g^eq*_{a j} = W_a [B_j + (e_{a k}/theta)(chi/gamma_m)(u_k B_j - B_k u_j)],
 // on deviations d = g - W B0: d~ = d + (g^eq* - W B0 - d)/tau_m*, where
 // g^eq* - W B0 = W_a [b_j + (e_{a k}/theta)(chi/gamma_m)(u_k B_j - B_k u_j)].
@@ -267,7 +319,7 @@ __device__ __forceinline__ void write_partials(double* __restrict__ partials, in
 }
 
 // ------------------------------------------------------------------ steps --
-template <typename S, bool CHECK, bool FIELD, bool NT>
+template <typename S, bool CHECK, bool FIELD, bool NT, bool MOVING>
 __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<typename Storage<S>::R> c,
                                                     const S* __restrict__ fin, S* __restrict__ fout,
                                                     const typename Storage<S>::R* __restrict__ force,
@@ -281,7 +333,7 @@ __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<type
   if (n < static_cast<uint32_t>(g.N)) {
     const Nbr b = neighbours(g, n);
     R f[Q19];
-    gather19<S>(fin, g.stride, n, b, c, f);
+    gather19<S, MOVING>(fin, g.stride, n, b, c, f);
     R Fx, Fy, Fz;
     load_force<R>(g, c, force, FIELD, n, Fx, Fy, Fz);
     const NodeMacro<R> mac = collide19<R>(f, Fx, Fy, Fz, c);
@@ -292,7 +344,9 @@ __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<type
   if constexpr (CHECK) write_partials(partials, lb, acc);
 }
 
-template <typename R, bool CHECK, bool FIELD>
+// EXT: the induction lattice extends beyond the fluid box; nodes outside it
+// relax g with u = 0 and leave f untouched.
+template <typename R, bool CHECK, bool FIELD, bool MOVING, bool EXT>
 __global__ __launch_bounds__(kBlock) void mhd_step(GridArgs g, CollideArgs<R> c, MagArgs<R> m,
                                                    const R* __restrict__ fin, R* __restrict__ fout,
                                                    const R* __restrict__ gin, R* __restrict__ gout,
@@ -304,24 +358,33 @@ __global__ __launch_bounds__(kBlock) void mhd_step(GridArgs g, CollideArgs<R> c,
   const uint32_t n = static_cast<uint32_t>(lb) * kBlock + threadIdx.x;
   double acc[kPartials] = {0, 0, 0, 0, 0, 0};
   if (n < static_cast<uint32_t>(g.N)) {
-    const Nbr b = neighbours(g, n);
-    R f[Q19];
-    gather19<R>(fin, g.stride, n, b, c, f);
+    const Coord q = coords(g, n);
+    const Nbr b = neighbours_at(g, q);
     R gg[3][Q7];
     gather_g<R>(gin, g.stride, n, b, gg);
-    R Fx, Fy, Fz;
-    load_force<R>(g, c, force, FIELD, n, Fx, Fy, Fz);
-    const Coupled<R> cp = lorentz_solve<R>(f, gg, Fx, Fy, Fz, c, m);
-    const NodeMacro<R> mac = collide19<R>(f, cp.Fx, cp.Fy, cp.Fz, c);
-    collide_g<R>(gg, cp, mac.ux, mac.uy, mac.uz, m);
-    store19<R>(fout, g.stride, n, f);
+    bool fluid = true;
+    if constexpr (EXT) fluid = in_box(g, q);
+    if (fluid) {
+      const Nbr bf = EXT ? box_walls(g, q, b) : b;
+      R f[Q19];
+      gather19<R, MOVING>(fin, g.stride, n, bf, c, f);
+      R Fx, Fy, Fz;
+      load_force<R>(g, c, force, FIELD, n, Fx, Fy, Fz);
+      const Coupled<R> cp = lorentz_solve<R>(f, gg, Fx, Fy, Fz, c, m);
+      const NodeMacro<R> mac = collide19<R>(f, cp.Fx, cp.Fy, cp.Fz, c);
+      collide_g<R>(gg, cp, mac.ux, mac.uy, mac.uz, m);
+      store19<R>(fout, g.stride, n, f);
+      if constexpr (CHECK)
+        check_node<R>(g, usnap, n, mac.drho, mac.jx, mac.jy, mac.jz, mac.ux, mac.uy, mac.uz, acc);
+    } else {
+      const Coupled<R> cp = field_only<R>(gg, m);
+      collide_g<R>(gg, cp, R(0), R(0), R(0), m);
+    }
 #pragma unroll
     for (int j = 0; j < 3; ++j)
 #pragma unroll
       for (int a = 0; a < Q7; ++a)
         gout[static_cast<int64_t>(j * Q7 + a) * g.stride + n] = gg[j][a];
-    if constexpr (CHECK)
-      check_node<R>(g, usnap, n, mac.drho, mac.jx, mac.jy, mac.jz, mac.ux, mac.uy, mac.uz, acc);
   }
   if constexpr (CHECK) write_partials(partials, lb, acc);
 }
@@ -341,42 +404,63 @@ __global__ __launch_bounds__(kBlock) void fields_kernel(
   const uint32_t n = static_cast<uint32_t>(lb) * kBlock + threadIdx.x;
   double acc[kPartials] = {0, 0, 0, 0, 0, 0};
   if (n < static_cast<uint32_t>(g.N)) {
-    const Nbr b = neighbours(g, n);
-    R f[Q19];
-    gather19<S>(fin, g.stride, n, b, c, f);
-    R Fx, Fy, Fz;
-    load_force<R>(g, c, force, field != 0, n, Fx, Fy, Fz);
-    R Bx = 0, By = 0, Bz = 0;
-    if constexpr (MHD) {
-      R gg[3][Q7];
-      gather_g<R>(gin, g.stride, n, b, gg);
-      const Coupled<R> cp = lorentz_solve<R>(f, gg, Fx, Fy, Fz, c, m);
-      Fx = cp.Fx;
-      Fy = cp.Fy;
-      Fz = cp.Fz;
-      Bx = cp.Bx;
-      By = cp.By;
-      Bz = cp.Bz;
+    const Coord q = coords(g, n);
+    const Nbr b = neighbours_at(g, q);
+    if (MHD && !in_box(g, q)) {  // induction lattice outside the fluid box
+      if constexpr (MHD) {
+        R gg[3][Q7];
+        gather_g<R>(gin, g.stride, n, b, gg);
+        const Coupled<R> cp = field_only<R>(gg, m);
+        if (rho_out) rho_out[n] = static_cast<O>(c.rho0);
+        if (u_out) {
+          u_out[n] = O(0);
+          u_out[out_stride + n] = O(0);
+          u_out[2 * out_stride + n] = O(0);
+        }
+        if (B_out) {
+          B_out[n] = static_cast<O>(cp.Bx);
+          B_out[out_stride + n] = static_cast<O>(cp.By);
+          B_out[2 * out_stride + n] = static_cast<O>(cp.Bz);
+        }
+      }
+    } else {
+      const Nbr bf = box_walls(g, q, b);
+      R f[Q19];
+      gather19<S, true>(fin, g.stride, n, bf, c, f);
+      R Fx, Fy, Fz;
+      load_force<R>(g, c, force, field != 0, n, Fx, Fy, Fz);
+      R Bx = 0, By = 0, Bz = 0;
+      if constexpr (MHD) {
+        R gg[3][Q7];
+        gather_g<R>(gin, g.stride, n, b, gg);
+        const Coupled<R> cp = lorentz_solve<R>(f, gg, Fx, Fy, Fz, c, m);
+        Fx = cp.Fx;
+        Fy = cp.Fy;
+        Fz = cp.Fz;
+        Bx = cp.Bx;
+        By = cp.By;
+        Bz = cp.Bz;
+      }
+      R drho, jx, jy, jz;
+      raw_moments<R>(f, drho, jx, jy, jz);
+      jx += Fx * c.half_inv_gamma;
+      jy += Fy * c.half_inv_gamma;
+      jz += Fz * c.half_inv_gamma;
+      const R rho = c.rho0 + drho;
+      if (rho_out) rho_out[n] = static_cast<O>(rho);
+      if (u_out) {
+        u_out[n] = static_cast<O>(jx / rho);
+        u_out[out_stride + n] = static_cast<O>(jy / rho);
+        u_out[2 * out_stride + n] = static_cast<O>(jz / rho);
+      }
+      if (MHD && B_out) {
+        B_out[n] = static_cast<O>(Bx);
+        B_out[out_stride + n] = static_cast<O>(By);
+        B_out[2 * out_stride + n] = static_cast<O>(Bz);
+      }
+      acc[2] = static_cast<double>(drho);
+      acc[3] = static_cast<double>(jx);
     }
-    R drho, jx, jy, jz;
-    raw_moments<R>(f, drho, jx, jy, jz);
-    jx += Fx * c.half_inv_gamma;
-    jy += Fy * c.half_inv_gamma;
-    jz += Fz * c.half_inv_gamma;
-    const R rho = c.rho0 + drho;
-    if (rho_out) rho_out[n] = static_cast<O>(rho);
-    if (u_out) {
-      u_out[n] = static_cast<O>(jx / rho);
-      u_out[out_stride + n] = static_cast<O>(jy / rho);
-      u_out[2 * out_stride + n] = static_cast<O>(jz / rho);
-    }
-    if (MHD && B_out) {
-      B_out[n] = static_cast<O>(Bx);
-      B_out[out_stride + n] = static_cast<O>(By);
-      B_out[2 * out_stride + n] = static_cast<O>(Bz);
-    }
-    acc[2] = static_cast<double>(drho);
-    acc[3] = static_cast<double>(jx);
   }
   write_partials(partials, lb, acc);
 }
@@ -442,8 +526,16 @@ hipError_t launch_glbe_step(const GridArgs& g, const CollideArgs<typename Storag
   S* b = static_cast<S*>(fout);
   const R* F = static_cast<const R*>(force);
 #define LBM_STEP(CH, FL, NTS) \
-  glbe_step<S, CH, FL, NTS><<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials)
-  if (nt) {
+  glbe_step<S, CH, FL, NTS, false><<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials)
+#define LBM_STEP_MOVING(CH, FL) \
+  glbe_step<S, CH, FL, false, true><<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials)
+  if (c.moving) {  // moving walls: small problems, regular stores
+    if (check) {
+      if (field) LBM_STEP_MOVING(true, true); else LBM_STEP_MOVING(true, false);
+    } else {
+      if (field) LBM_STEP_MOVING(false, true); else LBM_STEP_MOVING(false, false);
+    }
+  } else if (nt) {
     if (check) {
       if (field) LBM_STEP(true, true, true); else LBM_STEP(true, false, true);
     } else {
@@ -457,6 +549,7 @@ hipError_t launch_glbe_step(const GridArgs& g, const CollideArgs<typename Storag
     }
   }
 #undef LBM_STEP
+#undef LBM_STEP_MOVING
   return hipGetLastError();
 }
 
@@ -481,17 +574,24 @@ hipError_t launch_mhd_step(const GridArgs& g, const CollideArgs<R>& c, const Mag
   const R* ga = static_cast<const R*>(gin);
   R* gb = static_cast<R*>(gout);
   const R* F = static_cast<const R*>(force);
-  if (check) {
-    if (field)
-      mhd_step<R, true, true><<<step_grid(g), kBlock, 0, st>>>(g, c, m, a, b, ga, gb, F, usnap, partials);
-    else
-      mhd_step<R, true, false><<<step_grid(g), kBlock, 0, st>>>(g, c, m, a, b, ga, gb, F, usnap, partials);
-  } else {
-    if (field)
-      mhd_step<R, false, true><<<step_grid(g), kBlock, 0, st>>>(g, c, m, a, b, ga, gb, F, usnap, partials);
-    else
-      mhd_step<R, false, false><<<step_grid(g), kBlock, 0, st>>>(g, c, m, a, b, ga, gb, F, usnap, partials);
+  const bool ext = g.flo[0] > 0 || g.flo[1] > 0 || g.flo[2] > 0;
+#define LBM_MHD(CH, FL, MV, EX) \
+  mhd_step<R, CH, FL, MV, EX><<<step_grid(g), kBlock, 0, st>>>(g, c, m, a, b, ga, gb, F, usnap, partials)
+#define LBM_MHD_MV(CH, FL)                         \
+  if (ext) {                                       \
+    if (c.moving) LBM_MHD(CH, FL, true, true);     \
+    else LBM_MHD(CH, FL, false, true);             \
+  } else {                                         \
+    if (c.moving) LBM_MHD(CH, FL, true, false);    \
+    else LBM_MHD(CH, FL, false, false);            \
   }
+  if (check) {
+    if (field) { LBM_MHD_MV(true, true); } else { LBM_MHD_MV(true, false); }
+  } else {
+    if (field) { LBM_MHD_MV(false, true); } else { LBM_MHD_MV(false, false); }
+  }
+#undef LBM_MHD_MV
+#undef LBM_MHD
   return hipGetLastError();
 }
 

@@ -64,6 +64,14 @@ std::string validate(const lbm_grid* grid, const lbm_params* p) {
   for (int f = 0; f < 6; ++f)
     for (int a = 0; a < 3; ++a)
       if (!std::isfinite(p->wall_u[f][a])) return "wall_u must be finite";
+  for (int a = 0; a < 3; ++a) {
+    if (p->mag_pad[a] < 0) return "mag_pad must be >= 0";
+    if (p->mag_pad[a] == 0) continue;
+    if (!p->mhd) return "mag_pad needs mhd = 1";
+    if (grid->bc[a] != LBM_WALL) return "mag_pad only on wall axes";
+    if (int64_t(grid->n[a]) - 2 * int64_t(p->mag_pad[a]) < 1)
+      return "mag_pad leaves no fluid nodes";
+  }
   return "";
 }
 
@@ -223,7 +231,7 @@ lbm_status flush_checks(lbm_ctx* c) {
   if (count <= 0) return LBM_OK;
   const double step0 = double(c->first_check_step + c->finalized * c->p.check_every);
   LBM_HIP(c, launch_finalize(c->partials(), c->L.nblocks, c->L.pslots, c->finalized, int(count),
-                             step0, double(c->p.check_every), 1.0 / c->grid.n[0], c->ring(),
+                             step0, double(c->p.check_every), 1.0 / (c->grid.n[0] - 2 * c->p.mag_pad[0]), c->ring(),
                              c->p.history_len, c->stream),
           "finalize launch");
   c->finalized = c->checks;
@@ -403,6 +411,10 @@ lbm_status lbm_create(const lbm_grid* grid, const lbm_params* params, const void
   g.stride = L.stride;
   g.div_nx = make_fastdiv(static_cast<uint32_t>(g.nx));
   g.div_nxny = make_fastdiv(static_cast<uint32_t>(g.nx * g.ny));
+  for (int a = 0; a < 3; ++a) {
+    g.flo[a] = params->mag_pad[a];
+    g.fhi[a] = grid->n[a] - params->mag_pad[a];
+  }
   c->cd = collide_args<double>(c->p);
   c->cf = collide_args<float>(c->p);
   c->md = mag_args<double>(c->p);
@@ -571,7 +583,7 @@ lbm_status lbm_reductions(lbm_ctx* c, double* mass_drift, double* flow_rate) {
   if (!mass_drift || !flow_rate) return fail(c, LBM_EINVAL, "outputs are NULL");
   LBM_HIP(c, launch_fields_any(c, 0, nullptr, nullptr, nullptr), "fields launch");
   LBM_HIP(c, launch_finalize(c->fpartials(), c->L.nblocks, 1, 0, 1, double(c->step), 0.0,
-                             1.0 / c->grid.n[0], c->rec(), 1, c->stream),
+                             1.0 / (c->grid.n[0] - 2 * c->p.mag_pad[0]), c->rec(), 1, c->stream),
           "finalize launch");
   double rec[kRecordDoubles];
   LBM_HIP(c, hipMemcpyAsync(rec, c->rec(), sizeof rec, hipMemcpyDeviceToHost, c->stream), "copy");
@@ -619,6 +631,12 @@ lbm_status lbm_set_state(lbm_ctx* c, const void* src, int64_t step) {
   LBM_HIP(c, hipMemcpy2DAsync(c->f(c->cur), st * es, src, N * es, N * es, 19, hipMemcpyDeviceToDevice,
                               c->stream),
           "state copy");
+  // With an extended induction lattice the step never writes f outside the
+  // fluid box: give both buffers the same values there.
+  if (c->p.mag_pad[0] || c->p.mag_pad[1] || c->p.mag_pad[2])
+    LBM_HIP(c, hipMemcpy2DAsync(c->f(1 - c->cur), st * es, src, N * es, N * es, 19,
+                                hipMemcpyDeviceToDevice, c->stream),
+            "state copy");
   if (c->p.mhd) {
     const size_t cs = c->celem();
     const char* gsrc = static_cast<const char*>(src) + 19 * N * es;

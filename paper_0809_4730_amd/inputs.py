@@ -68,6 +68,12 @@ def hartmann_parameters(Ha, Pm, ny, nu=0.1, eta=0.025, rho=1.0, mu=1.0):
     return B0, chi
 
 
+def cavity_field(Ha, Pm, W, nu, eta, rho=1.0, mu=1.0):
+    """(B0, chi) for Hartmann number Ha = B0 W / sqrt(mu eta rho nu) on a cavity
+    of side W and effective magnetic Prandtl number Pm = chi nu / eta."""
+    return Ha * np.sqrt(mu * eta * rho * nu) / W, Pm * eta / nu
+
+
 # Workload presets (sizes and parameters of the configurations measured).
 POISEUILLE = dict(shape=(8, 8, 32), bc=("periodic", "periodic", "wall"), F=(1e-6, 0.0, 0.0),
                   nu=0.1, gammas=(1.0, 0.1), tol=1e-10)
@@ -80,3 +86,5 @@ DUCT256 = dict(shape=(256, 256, 256), bc=("periodic", "wall", "wall"), F0=1e-5, 
                gamma=1.0)
 ADJOINT = dict(shape=(128, 128, 128), bc=("periodic", "wall", "wall"), F0=1e-5, nu=0.131,
                gamma=1.0, unrolled_shape=(32, 32, 32), unrolled_steps=2000, ckpt_every=45)
+MHD_CAVITY = dict(W=64, U0=0.0235, nu=0.015, eta=0.015, Ha=45.0, Pm=5.625e-7, pad=16,
+                  gammas=(1.0, 0.5, 0.1), tol=1e-6)

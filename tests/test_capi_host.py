@@ -146,3 +146,37 @@ def test_product_path_refuses_missing_library(monkeypatch, tmp_path):
     monkeypatch.setattr(pkg, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         pkg.load_library()
+
+
+def test_library_binds_to_torch_hip_runtime():
+    """Loading liblbm.so maps exactly one HIP runtime (torch's), whatever was
+    imported first; two runtimes in one process leave the second without a device."""
+    import subprocess
+    import sys
+    code = ("import paper_0809_4730_amd as p; p.load_library(); "
+            "m = open('/proc/self/maps').read(); "
+            "print(len({l.split()[-1] for l in m.splitlines() if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+@pytest.mark.parametrize("pad,mhd,bc,msg", [
+    ((0, 2, 0), 0, (0, 1, 0), b"needs mhd"),
+    ((2, 0, 0), 1, (0, 1, 0), b"wall axes"),
+    ((0, 4, 0), 1, (0, 1, 0), b"no fluid"),
+    ((0, -1, 0), 1, (0, 1, 0), b">= 0"),
+])
+def test_mag_pad_validation(lib, pad, mhd, bc, msg):
+    import paper_0809_4730_amd as pkg
+    g, p = _grid_params(pkg, n=(8, 8, 8), bc=bc, mhd=mhd, storage=pkg.F64)
+    for a in range(3):
+        p.mag_pad[a] = pad[a]
+    nbytes = ctypes.c_size_t()
+    assert lib.lbm_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nbytes)) == -1
+    assert msg in lib.lbm_last_error(None)
+    p.mag_pad[0], p.mag_pad[1], p.mag_pad[2] = 0, 3, 0
+    p.mhd = 1
+    g.bc[1] = 1
+    assert lib.lbm_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nbytes)) == 0

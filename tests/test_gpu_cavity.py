@@ -1,0 +1,151 @@
+"""GPU parity of the extended induction lattice and the MHD lid-driven cavity
+(Sec. 5): the coupled step with the fluid box inside a larger induction lattice
+against the oracle, the extended-domain Hartmann closed form, and the cavity
+workload's flattening by the field."""
+import numpy as np
+import pytest
+
+from oracle import glbe, mhd
+from paper_0809_4730_amd import inputs
+from tests.gpu_util import announce, from_gpu_f, from_gpu_g, rel, to_gpu_f, to_gpu_g
+
+pytestmark = pytest.mark.gpu
+PER, WALL = "periodic", "wall"
+
+
+def _box(shape, pad):
+    nx, ny, nz = shape
+    px, py, pz = pad
+    return (slice(pz, nz - pz), slice(py, ny - py), slice(px, nx - px))
+
+
+@pytest.mark.parametrize("shape,bc,pad", [((10, 12, 9), (WALL, WALL, WALL), (2, 3, 1)),
+                                          ((6, 14, 5), (PER, WALL, PER), (0, 4, 0))])
+@pytest.mark.parametrize("nsteps", [1, 25])
+def test_extended_domain_fp64_matches_oracle(shape, bc, pad, nsteps):
+    import torch
+    import paper_0809_4730_amd as pkg
+    announce("extended domain fp64 %s pad %s n=%d" % (shape, pad, nsteps))
+    gamma, gm = 0.3, 0.4
+    B0 = np.array([0.004, 0.02, -0.01])
+    p = dict(gamma_m=gm, chi=0.05, eta=0.03, B0=tuple(B0), pad=pad)
+    s = glbe.rates(0.04, gamma)
+    F = np.array([2e-6, -1e-6, 3e-6])
+    wall_u = np.zeros((6, 3))
+    wall_u[5] = (0.02, 0.005, 0.0)     # lid: z-high face
+    wall_u[2] = (0.0, 0.0, -0.01)      # y-low face
+    nx, ny, nz = shape
+    box = _box(shape, pad)
+    f_full = inputs.random_deviations(shape, seed=21, amp=1e-3)
+    g0 = mhd.initial_g(shape, B0)
+    g0 += inputs.random_deviations(shape, seed=22, amp=1e-4, q=21).reshape(3, 7, nz, ny, nx)
+    sim = pkg.Simulation(shape, bc, gamma, s, storage="f64", force=tuple(F), mhd=p,
+                         wall_u=wall_u)
+    sim.set_state(to_gpu_f(f_full, torch.float64), to_gpu_g(g0, torch.float64, B0))
+    sim.step(nsteps)
+    fg, gg = sim.get_state()
+    fo = np.ascontiguousarray(f_full[(slice(None),) + box])
+    go = g0
+    fshape = fo.shape[1:]
+    Ff = np.broadcast_to(F.reshape(3, 1, 1, 1), (3,) + fshape)
+    pp = dict(gamma=gamma, s=s, gamma_m=gm, chi=p["chi"], eta=p["eta"], B_wall=B0)
+    for _ in range(nsteps):
+        fo, go, u, B = mhd.step(fo, go, Ff, pp, bc, wall_u, pad)
+    f_lib = from_gpu_f(fg)
+    assert rel(f_lib[(slice(None),) + box], fo) < 1e-12
+    # outside the box f is never touched
+    outside = np.ones((nz, ny, nx), bool)
+    outside[box] = False
+    assert np.array_equal(f_lib[:, outside], f_full[:, outside])
+    assert rel(from_gpu_g(gg, B0), go) < 1e-13
+    rho, ug, Bg = sim.moments("f64")
+    f_s = glbe.stream(fo, bc, wall_u=wall_u)
+    g_s = mhd.stream_g(go, bc, B0)
+    _, u_o, _, _, _ = mhd.coupled_fields(f_s, g_s[(slice(None), slice(None)) + box], Ff, gamma,
+                                         gm, p["chi"], p["eta"])
+    ug = ug.cpu().numpy()
+    assert rel(ug[(slice(None),) + box], u_o) < 1e-11
+    assert np.all(ug[:, outside] == 0.0)
+    assert np.all(rho.cpu().numpy()[outside] == 1.0)
+    assert rel(Bg.cpu().numpy(), g_s.sum(axis=1)) < 1e-14
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-11), ("f32", 2e-7)])
+def test_extended_hartmann_closed_form(storage, tol):
+    """Hartmann channel (walls normal to y, 2L fluid nodes) with the induction
+    lattice d = L nodes beyond each wall: the return current through the outer
+    layer scales the flow by 1 / (1 - (L/(L+d))(1 - tanh(Ha)/Ha)) against the
+    conducting-wall limit; second-order error at L = 16 is about 0.13%."""
+    import paper_0809_4730_amd as pkg
+    L, d, Ha, chi, nu, eta, F = 16, 16, 5.0, 0.0025, 0.1, 0.025, 1e-5
+    gamma = gm = 0.1
+    B0 = Ha * np.sqrt(eta * nu) / L
+    shape = (4, 2 * L + 2 * d, 4)
+    announce("extended hartmann %s" % storage)
+    sim = pkg.Simulation(shape, (PER, WALL, PER), gamma, glbe.rates(nu, gamma, "lambda", 3 / 16),
+                         storage=storage, force=(F, 0.0, 0.0),
+                         mhd=dict(gamma_m=gm, chi=chi, eta=eta, B0=(0.0, B0, 0.0), pad=(0, d, 0)))
+    steps, r = sim.run_to_residual(tol, 100000, poll_every=500)
+    assert steps > 0, r
+    if storage == "f32":
+        sim.step(2000)
+    _, u, B = sim.moments("f64")
+    u = u.cpu().numpy()[0, 0, :, 0]
+    bx = B.cpu().numpy()[0, 0, :, 0]
+    T = np.tanh(Ha)
+    U = F * L * L / (nu * Ha * Ha) / (1 - (L / (L + d)) * (1 - T / Ha))
+    yy = np.arange(2 * L + 2 * d) + 0.5 - L - d
+    fl = np.abs(yy) < L
+    uex = np.where(fl, U * (1 - np.cosh(Ha * yy / L) / np.cosh(Ha)), 0.0)
+    C = B0 * 2 * L * U * (1 - T / Ha) / (2 * (L + d))
+
+    def b_in(z):
+        return (d * C + C * (z + L)
+                - B0 * U * ((z + L) - (L / Ha) * (np.sinh(Ha * z / L) + np.sinh(Ha)) / np.cosh(Ha))) / eta
+
+    bex = chi * np.where(yy > L, b_in(L) + (yy - L) * C / eta,
+                         np.where(yy < -L, b_in(-L) + (yy + L) * C / eta, b_in(yy)))
+    eu = np.sqrt(np.mean((u[fl] - uex[fl]) ** 2)) / uex.max()
+    eb = np.sqrt(np.mean((bx - bex) ** 2)) / np.abs(bex).max()
+    announce("extended hartmann %s: steps %d eu %.3g eb %.3g" % (storage, steps, eu, eb))
+    assert eu < 0.002 and eb < 0.002
+    assert np.all(u[~fl] == 0.0)
+
+
+def test_mhd_cavity_field_flattens_the_flow():
+    """MHD lid-driven cavity (Sec. 5): 64^3 fluid, Re = 100 (U0 = 0.0235,
+    nu = 0.015), B0 parallel to the lid and normal to its motion, Ha = 45
+    (eta = 0.015, Pm = 5.625e-7), induction lattice 8 nodes beyond each wall,
+    FP32, gamma = gamma_m = 0.1.  The centreline profile u(z) at x = y = W/2 is
+    flattened by the field: its return flow is weaker than without field."""
+    import paper_0809_4730_amd as pkg
+    c = inputs.MHD_CAVITY
+    W, pad = c["W"], 8
+    nu, U0, gamma = c["nu"], c["U0"], 0.1
+    s = glbe.rates(nu, gamma)
+    wall_u = np.zeros((6, 3))
+    wall_u[5] = (U0, 0.0, 0.0)
+    announce("cavity Ha=0")
+    plain = pkg.Simulation((W, W, W), (WALL, WALL, WALL), gamma, s, storage="f32", wall_u=wall_u)
+    n0, _ = plain.run_to_residual(1e-6, 60000, poll_every=500)
+    assert n0 > 0
+    _, u0, _ = plain.moments("f64")
+    prof0 = u0.cpu().numpy()[0, :, W // 2, W // 2]
+    B0, chi = inputs.cavity_field(c["Ha"], c["Pm"], W, nu, c["eta"])
+    n = W + 2 * pad
+    announce("cavity Ha=%g B0=%.4g" % (c["Ha"], B0))
+    mag = pkg.Simulation((n, n, n), (WALL, WALL, WALL), gamma, s, storage="f32", wall_u=wall_u,
+                         mhd=dict(gamma_m=gamma, chi=chi, eta=c["eta"], B0=(0.0, B0, 0.0),
+                                  pad=(pad, pad, pad)))
+    n1, _ = mag.run_to_residual(1e-6, 60000, poll_every=500)
+    assert n1 > 0
+    _, u1, Bf = mag.moments("f64")
+    prof1 = u1.cpu().numpy()[0, pad:pad + W, pad + W // 2, pad + W // 2]
+    announce("cavity steps %d / %d; return flow %.4g -> %.4g" % (n0, n1, prof0.min(), prof1.min()))
+    assert np.isfinite(prof1).all()
+    assert prof1[-1] > 0.5 * U0 and prof0[-1] > 0.5 * U0   # driven by the lid
+    assert prof1.min() < 0 and prof0.min() < 0               # recirculation
+    assert abs(prof1.min()) < 0.8 * abs(prof0.min())          # flattened
+    # the induced field is of order chi Rm: tiny against B0
+    b = Bf.cpu().numpy() - np.array([0.0, B0, 0.0]).reshape(3, 1, 1, 1)
+    assert np.abs(b).max() < 1e-3 * B0

@@ -185,6 +185,57 @@ def test_hartmann_steady_state_independent_of_preconditioning():
     assert np.max(np.abs(b1 - b2)) / np.max(np.abs(b1)) < 1e-3
 
 
+def _hartmann_extended(L, d, Ha=5.0, chi=0.0025, gamma=0.1, gamma_m=0.1, nu=0.1, eta=0.025,
+                       F=1e-5, tol=1e-11):
+    """Hartmann channel whose induction lattice extends d nodes beyond each wall
+    (zero induced field at the outer boundary, u = 0 outside the fluid).
+
+    Closed form (derived for this pin): outside the fluid the steady induction
+    equation reduces to b'' = 0, so b is linear there and vanishes at the outer
+    boundary; with the flux eta b' + B0 u = C continuous across the wall the
+    current that returns through the outer layer gives
+        u = U (1 - cosh(Ha y/L)/cosh Ha),
+        U = (F L^2 / (nu Ha^2)) / (1 - (L/(L+d)) (1 - tanh(Ha)/Ha)),
+        C = B0 Q / (2 (L + d)),  Q = 2 L U (1 - tanh(Ha)/Ha),
+    and b/chi = [d C + C (y+L) - B0 U ((y+L) - (L/Ha)(sinh(Ha y/L) + sinh Ha)/cosh Ha)]/eta
+    inside, continued linearly with slope C/eta outside.  d = 0 is the
+    insulating-wall profile; d -> inf the perfectly conducting one."""
+    B0 = Ha * np.sqrt(eta * nu) / L
+    s = glbe.rates(nu, gamma, "lambda", 3 / 16)
+    fl = mhd.MHDFlow((1, 2 * L + 2 * d, 1), (PER, WALL, PER), np.array([F, 0, 0]), gamma, s,
+                     gamma_m, chi, eta, np.array([0, B0, 0]), pad=(0, d, 0))
+    ok = fl.run_to(tol, 60000)
+    T = np.tanh(Ha)
+    U = F * L * L / (nu * Ha * Ha) / (1 - (L / (L + d)) * (1 - T / Ha))
+    y = np.arange(2 * L) + 0.5 - L
+    uex = U * (1 - np.cosh(Ha * y / L) / np.cosh(Ha))
+    C = B0 * 2 * L * U * (1 - T / Ha) / (2 * (L + d))
+
+    def b_in(z):
+        return (d * C + C * (z + L)
+                - B0 * U * ((z + L) - (L / Ha) * (np.sinh(Ha * z / L) + np.sinh(Ha)) / np.cosh(Ha))) / eta
+
+    yy = np.arange(2 * L + 2 * d) + 0.5 - L - d
+    b = np.where(yy > L, b_in(L) + (yy - L) * C / eta,
+                 np.where(yy < -L, b_in(-L) + (yy + L) * C / eta, b_in(yy)))
+    u = fl.u[0][0, :, 0]
+    bb = fl.B[0][0, :, 0]
+    eu = np.sqrt(np.mean((u - uex) ** 2)) / np.max(uex)
+    eb = np.sqrt(np.mean((bb - chi * b) ** 2)) / np.max(np.abs(chi * b))
+    return ok, eu, eb
+
+
+def test_hartmann_extended_magnetic_domain_closed_form():
+    """Extended induction lattice (Sec. 5, MHD cavity): the return current through
+    the outer layer lowers the flow by the factor in the closed form; the error
+    against it is second order."""
+    ok1, eu1, eb1 = _hartmann_extended(8, 8)
+    ok2, eu2, eb2 = _hartmann_extended(16, 16)
+    assert ok1 and ok2
+    assert eu2 < 0.002 and eb2 < 0.002, (eu2, eb2)
+    assert 3.5 < eu1 / eu2 < 4.5 and 3.5 < eb1 / eb2 < 4.5, (eu1, eu2, eb1, eb2)
+
+
 def test_printed_current_contraction_is_unstable(monkeypatch):
     """Planted mistake (on the oracle): contracting as printed flips the sign of
     J; the Lorentz force then feeds the flow and the march diverges."""
