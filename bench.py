@@ -24,7 +24,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_0809_4730_amd/csrc/kernels.hip", "paper_0809_4730_amd/csrc/collide.hpp",
-                  "paper_0809_4730_amd/csrc/common.hpp", "paper_0809_4730_amd/csrc/lbm_capi.hip"]
+                  "paper_0809_4730_amd/csrc/common.hpp", "paper_0809_4730_amd/csrc/stream.hpp",
+                  "paper_0809_4730_amd/csrc/lattice.hpp", "paper_0809_4730_amd/csrc/lbm_capi.hip"]
 
 
 def kernel_hash():
@@ -236,6 +237,46 @@ def extras(args):
     out["precision_duct64"] = precision_table()
     out["adjoint"] = adjoint_extras()
     out.update(cavity_extras())
+    out["d2q9"] = d2q9_extras()
+    return out
+
+
+def d2q9_extras():
+    """Two-dimensional variants: plain D2Q9 step throughput at 4096^2 per
+    storage type (uniform force, periodic x, walls in y), the coupled
+    D2Q9 + D2Q5 step at 2048^2 (FP32), and 2D Hartmann (Ha = 10, Pm = 0.01,
+    2L = 128) steps to a residual of 2e-7 at gamma = gamma_m = 1 and 0.1."""
+    import paper_0809_4730_amd as pkg
+    from paper_0809_4730_amd import inputs
+    nu = 0.1
+    bc = ("periodic", "wall", "periodic")
+    out = {"step_4096x4096": []}
+    for st, nb in (("f32", 4), ("bf16", 2), ("f16", 2), ("f64", 8)):
+        sim = pkg.Simulation((4096, 4096, 1), bc, 0.1, pkg.default_rates_d2q9(nu, 0.1),
+                             storage=st, force=(1e-7, 0.0), check_every=NO_CHECK, lattice="d2q9")
+        us = kernel_time_us(sim, 200)
+        bpn = 2 * 9 * nb
+        out["step_4096x4096"].append({"storage": st, "kernel_us": round(us, 2),
+                                      "kernel_MLUPS": round(sim.N / us, 1),
+                                      "alg_bytes_per_node": bpn,
+                                      "achieved_GBs": round(bpn * sim.N / (us * 1e-6) / 1e9, 1)})
+        sim.close()
+    L, Ha, Pm, eta, F = 64, 10.0, 0.01, 0.025, 1e-5
+    B0, chi = inputs.hartmann_parameters(Ha, Pm, 2 * L, nu, eta)
+
+    def hart(g, n=(4, 2 * L, 1), ce=10):
+        return pkg.Simulation(n, bc, g, pkg.default_rates_d2q9(nu, g, "lambda", 3 / 16),
+                              storage="f32", force=(F, 0.0), check_every=ce, lattice="d2q9",
+                              mhd=dict(gamma_m=g, chi=chi, eta=eta, B0=(0.0, B0)))
+    sim = hart(0.1, (2048, 2048, 1), NO_CHECK)
+    us = kernel_time_us(sim, 200)
+    bpn = 2 * (9 + 10) * 4
+    out["mhd_step_2048x2048_f32"] = {"kernel_us": round(us, 2), "kernel_MLUPS": round(sim.N / us, 1),
+                                     "alg_bytes_per_node": bpn,
+                                     "achieved_GBs": round(bpn * sim.N / (us * 1e-6) / 1e9, 1)}
+    sim.close()
+    out["hartmann2d_Ha10_tol2e-7"] = [
+        time_to_residual(None, "f32", g, 2e-7, 400000, mhd=lambda g=g: hart(g)) for g in (1.0, 0.1)]
     return out
 
 

@@ -70,6 +70,10 @@ typedef enum { LBM_PERIODIC = 0, LBM_WALL = 1 } lbm_bc;
 
 typedef enum { LBM_FORCE_UNIFORM = 0, LBM_FORCE_FIELD = 1 } lbm_force_mode;
 
+/* Velocity sets: D3Q19 flow with D3Q7 induction, or the two-dimensional D2Q9
+ * flow with D2Q5 induction (Sec. 2 eq. velocityd2q9, Sec. 4 eq. velocityd2q5). */
+typedef enum { LBM_D3Q19 = 0, LBM_D2Q9 = 1 } lbm_lattice;
+
 typedef struct {
   int32_t n[3];   /* nx, ny, nz >= 1; N = nx*ny*nz < 2^31 */
   int32_t bc[3];  /* lbm_bc per axis */
@@ -113,6 +117,16 @@ typedef struct {
                              not updated, and the induction populations only
                              diffuse.  Residual, mass and flow sums cover the box.
                              All zero: fluid and induction lattices coincide. */
+  int32_t lattice;        /* lbm_lattice.  LBM_D2Q9: n[2] must be 1 (bc[2] is
+                             ignored); s[0..8] are the rates in D2Q9 moment order
+                             (rho, e, e2, j_x, q_x, j_y, q_y, p_xx, p_xy; conserved
+                             0, 3, 5 ignored; lbm_default_rates_d2q9 fills them);
+                             forces and B0 use their x and y components (B0[2]
+                             and force_const[2] must be 0); wall_u and mag_pad
+                             must be zero; no adjoint.  Force fields, u and B
+                             keep their [3][N] layout (z components unused on
+                             input, zero on output); the state blob holds f as
+                             [9][N] and (mhd) g as [2][5][N]. */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx;
@@ -137,7 +151,16 @@ typedef struct {
 lbm_status lbm_default_rates(double nu, double gamma, int32_t mode, double Lambda,
                              double s_out[19]);
 
-/* Velocity set in the library's direction order: q = 19 (D3Q19, flow) or q = 7
+/* Fill s_out[9] with the preconditioned D2Q9 rates of Sec. 3 (moment order
+ * rho, e, e2, j_x, q_x, j_y, q_y, p_xx, p_xy): p_xx, p_xy: 1/s = 3 nu/gamma + 1/2;
+ * s_e = 1.63, s_e2 = 1.14; mode 0: s_q = 1.92; mode 1: s_q from
+ * (3 nu/gamma)(1/s_q - 1/2) = Lambda.  Conserved entries are set to 1.
+ * Errors as lbm_default_rates. */
+lbm_status lbm_default_rates_d2q9(double nu, double gamma, int32_t mode, double Lambda,
+                                  double s_out[9]);
+
+/* Velocity set in the library's direction order: q = 19 (D3Q19, flow), q = 9
+ * (D2Q9, flow), q = 5 (D2Q5, induction; both with e_z = 0) or q = 7
  * (D3Q7, induction); writes q*3 integers (ex, ey, ez per direction) to e_out
  * (host memory).  Errors: LBM_EINVAL for another q or a NULL pointer. */
 lbm_status lbm_lattice_velocities(int32_t q, int32_t* e_out);

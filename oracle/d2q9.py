@@ -123,6 +123,16 @@ def meq_star(rho, j, gamma):
     return np.stack([np.broadcast_to(v, np.shape(rho)) for v in out])
 
 
+def meq_star_dev(drho, rho, j, gamma):
+    """meq*(rho, j) - T w rho0 written out (T w rho0 = rho0 (1, -2, 1, 0, ...), the
+    printed list at rest), so that deviations keep full precision."""
+    jx, jy = j
+    jj = (jx * jx + jy * jy) / (gamma * rho)
+    out = [drho, -2.0 * drho + 3.0 * jj, drho - 3.0 * jj, jx, -jx, jy, -jy,
+           (jx * jx - jy * jy) / (gamma * rho), jx * jy / (gamma * rho)]
+    return np.stack([np.broadcast_to(v, np.shape(drho)) for v in out])
+
+
 def source_moments(F, u):
     """Moments of the source term at gamma = 1 (the D2Q9 list of Sec. 3 with gamma = 1)."""
     Fx, Fy = F
@@ -161,10 +171,10 @@ def velocity_equilibrium(rho, u):
 # ------------------------------------------------------------- collision ---
 def collide(d, F, gamma, s, rho0=1.0):
     """One preconditioned D2Q9 collision with forcing (Sec. 3, eq. prelax_term):
-    m~ = m - s (m - meq*) + (1 - s/2) P_S S^.  d: deviations f - w rho0."""
+    m~ = m - s (m - meq*) + (1 - s/2) P_S S^.  d: deviations f - w rho0; both m
+    and meq* are taken relative to the rest state (T d and meq*_dev)."""
     drho, rho, j, u = fields(d, F, gamma, rho0)
-    m = np.tensordot(T9, d + W9.reshape((Q9,) + (1,) * (d.ndim - 1)) * rho0, axes=(1, 0))
-    neq = m - meq_star(rho, j, gamma)
+    neq = np.tensordot(T9, d, axes=(1, 0)) - meq_star_dev(drho, rho, j, gamma)
     sk = np.asarray(s, dtype=float).reshape((Q9,) + (1,) * (d.ndim - 1))
     S = source_precond_diag(gamma).reshape(sk.shape) * source_moments(F, u)
     dm = -sk * neq + (1.0 - 0.5 * sk) * S

@@ -55,6 +55,7 @@ class _Params(ctypes.Structure):
         ("source_mode", ctypes.c_int32),
         ("wall_u", (ctypes.c_double * 3) * 6),
         ("mag_pad", ctypes.c_int32 * 3),
+        ("lattice", ctypes.c_int32),
     ]
 
 
@@ -89,6 +90,7 @@ def load_library():
     P = ctypes.POINTER
     sig = {
         "lbm_default_rates": [c_double, c_double, c_int32, c_double, P(c_double)],
+        "lbm_default_rates_d2q9": [c_double, c_double, c_int32, c_double, P(c_double)],
         "lbm_lattice_velocities": [c_int32, P(c_int32)],
         "lbm_workspace_bytes": [P(_Grid), P(_Params), P(c_size_t)],
         "lbm_create": [P(_Grid), P(_Params), c_void_p, c_void_p, c_size_t, c_void_p, P(c_void_p)],
@@ -135,6 +137,14 @@ def default_rates(nu, gamma, mode="paper", Lambda=1.0):
     return np.array(list(out))
 
 
+def default_rates_d2q9(nu, gamma, mode="paper", Lambda=1.0):
+    """Preconditioned D2Q9 rates (see lbm_default_rates_d2q9)."""
+    lib = load_library()
+    out = (ctypes.c_double * 9)()
+    _check(lib.lbm_default_rates_d2q9(nu, gamma, 0 if mode == "paper" else 1, Lambda, out))
+    return np.array(list(out))
+
+
 def lattice_velocities(q=19):
     lib = load_library()
     out = (ctypes.c_int32 * (3 * q))()
@@ -173,13 +183,15 @@ class Simulation:
 
     def __init__(self, shape, bc, gamma, s, storage="f32", force=(0.0, 0.0, 0.0), rho0=1.0,
                  mhd=None, check_every=10, history_len=4096, device="cuda", stream=None,
-                 source="precond", wall_u=None):
+                 source="precond", wall_u=None, lattice="d3q19"):
         torch = _torch()
         self._lib = load_library()
         self.device = torch.device(device)
         if self.device.index is None:
             self.device = torch.device(self.device.type, torch.cuda.current_device())
         self.shape = tuple(int(v) for v in shape)
+        self.lattice = {"d3q19": 0, "d2q9": 1}[lattice]
+        self.q, self.qg = (9, (2, 5)) if self.lattice == 1 else (19, (3, 7))
         self.storage = _DTYPES[storage] if isinstance(storage, str) else int(storage)
         self._grid = _Grid()
         for a in range(3):
@@ -187,9 +199,10 @@ class Simulation:
             b = bc[a]
             self._grid.bc[a] = (WALL if b in ("wall", WALL) else PERIODIC)
         p = _Params()
+        p.lattice = self.lattice
         p.storage = self.storage
         p.gamma = gamma
-        for k in range(19):
+        for k in range(len(s)):
             p.s[k] = float(s[k])
         p.rho0 = rho0
         self._force_tensor = None
@@ -205,7 +218,7 @@ class Simulation:
             self._force_tensor = force.contiguous()
         else:
             p.force_mode = 0
-            for a in range(3):
+            for a in range(len(force)):
                 p.force_const[a] = float(force[a])
         if mhd:
             p.mhd = 1
@@ -213,8 +226,9 @@ class Simulation:
             p.chi = mhd["chi"]
             p.eta = mhd["eta"]
             p.mu = mhd.get("mu", 1.0)
-            for a in range(3):
+            for a in range(len(mhd["B0"])):
                 p.B0[a] = float(mhd["B0"][a])
+            for a in range(3):
                 p.mag_pad[a] = int(mhd.get("pad", (0, 0, 0))[a])
         p.check_every = check_every
         p.history_len = history_len
@@ -324,19 +338,21 @@ class Simulation:
 
     # ------------------------------------------------------------- state
     def get_state(self):
-        """Populations (19, nz, ny, nx) in the storage dtype, plus (mhd) the
-        magnetic populations (3, 7, nz, ny, nx); both as deviations from the rest
-        state (f - w rho0, g - W B0)."""
+        """Populations (q, nz, ny, nx) in the storage dtype (q = 19, or 9 for
+        D2Q9), plus (mhd) the magnetic populations (3, 7, nz, ny, nx) (D2Q5:
+        (2, 5, ...)); both as deviations from the rest state (f - w rho0,
+        g - W B0)."""
         torch = _torch()
         nx, ny, nz = self.shape
-        f = torch.empty((19, nz, ny, nx), dtype=_state_torch_dtype(self.storage), device=self.device)
+        q, (gj, ga) = self.q, self.qg
+        f = torch.empty((q, nz, ny, nx), dtype=_state_torch_dtype(self.storage), device=self.device)
         if self._params.mhd:
-            blob = torch.empty(19 * self.N * f.element_size() + 21 * self.N * f.element_size(),
+            blob = torch.empty((q + gj * ga) * self.N * f.element_size(),
                                dtype=torch.uint8, device=self.device)
             self._c(self._lib.lbm_get_state(self._ctx, blob.data_ptr()))
-            nf = 19 * self.N * f.element_size()
-            f = blob[:nf].view(f.dtype).reshape(19, nz, ny, nx)
-            g = blob[nf:].view(f.dtype).reshape(3, 7, nz, ny, nx)
+            nf = q * self.N * f.element_size()
+            f = blob[:nf].view(f.dtype).reshape(q, nz, ny, nx)
+            g = blob[nf:].view(f.dtype).reshape(gj, ga, nz, ny, nx)
             return f, g
         self._c(self._lib.lbm_get_state(self._ctx, f.data_ptr()))
         return f

@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_step(
   const int lb = logical_block(g);
   if (lb >= g.nblocks) return;
   const uint32_t n = static_cast<uint32_t>(lb) * kBlock + threadIdx.x;
-  double acc[kPartials] = {0, 0, 0, 0, 0, 0};
+  double acc[kPartials] = {};
   if (n < static_cast<uint32_t>(g.N)) {
     int x, y, z;
     const AdjNbr b = adj_neighbours(g, n, x, y, z);
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(kBlock) void finalize_adjoint_kernel(const double* 
                                                                   int nblocks, double inv_count,
                                                                   double* __restrict__ record,
                                                                   double* __restrict__ shift) {
-  double acc[kPartials] = {0, 0, 0, 0, 0, 0};
+  double acc[kPartials] = {};
   for (int b = threadIdx.x; b < nblocks; b += kBlock) {
 #pragma unroll
     for (int k = 0; k < kPartials; ++k) acc[k] += partials[int64_t(b) * kPartials + k];
@@ -308,6 +308,7 @@ AdjLayout adj_layout(const lbm_ctx* c, int mode, int64_t n_steps, int64_t ckpt_e
 lbm_status adj_common_checks(lbm_ctx* c) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (c->p.mhd) return fail(c, LBM_EUNSUPPORTED, "the adjoint covers the GLBE step without mhd");
+  if (c->p.lattice != LBM_D3Q19) return fail(c, LBM_EUNSUPPORTED, "the adjoint covers D3Q19 only");
   if (c->p.storage != LBM_F64 && c->p.storage != LBM_F32)
     return fail(c, LBM_EUNSUPPORTED, "the adjoint needs LBM_F64 or LBM_F32 storage");
   return LBM_OK;

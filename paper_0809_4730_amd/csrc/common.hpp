@@ -21,7 +21,7 @@ namespace lbm {
 constexpr int kBlock = 256;   // threads per workgroup (4 wave64)
 constexpr int kXcd = 8;       // XCDs on MI355X; workgroups are dealt round-robin
 constexpr int kRecordDoubles = 8;
-constexpr int kPartials = 6;  // du2, u2, mass, flow, nonfinite, spare
+constexpr int kPartials = 5;  // du2, u2, mass, flow, nonfinite
 
 // q = floor(n / d) for n < 2^32 via one 64x64 high multiply:
 // M = ceil(2^64 / d) gives n*M/2^64 = n/d + e with 0 <= e < n/2^64 < 1/d.
@@ -144,18 +144,10 @@ struct Storage<bf16_t> {
   __device__ __forceinline__ static R ld(const bf16_t* p) {
     return __uint_as_float(static_cast<uint32_t>(ld_pop(&p->bits)) << 16);
   }
-  // round to nearest, ties to even; NaN stays NaN
+  // round to nearest, ties to even, NaN stays NaN: one v_cvt_pk_bf16_f32 on gfx950
   template <bool NT = false>
   __device__ __forceinline__ static void st(bf16_t* p, R v) {
-    uint32_t u = __float_as_uint(v);
-    uint16_t h;
-    if ((u & 0x7fffffffu) > 0x7f800000u) {
-      h = static_cast<uint16_t>((u >> 16) | 0x40u);
-    } else {
-      u += 0x7fffu + ((u >> 16) & 1u);
-      h = static_cast<uint16_t>(u >> 16);
-    }
-    st_pop<NT>(&p->bits, h);
+    st_pop<NT>(&p->bits, __builtin_bit_cast(uint16_t, static_cast<__bf16>(v)));
   }
 };
 
@@ -170,10 +162,34 @@ struct Storage<_Float16> {
 };
 
 // ------------------------------------------------------------ reductions --
+// v from the lane CTRL selects (DPP row shift right within rows of 16 lanes);
+// lanes whose source lies outside the row read 0.
+template <int CTRL>
+__device__ __forceinline__ double dpp_row_shr(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(u), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(u >> 32), CTRL, 0xf, 0xf, true);
+  return __builtin_bit_cast(double, (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) |
+                                        static_cast<uint32_t>(lo));
+}
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readlane(static_cast<int>(u), lane);
+  const uint32_t hi = __builtin_amdgcn_readlane(static_cast<int>(u >> 32), lane);
+  return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+// Sum over the 64 lanes of a wave (all lanes active), returned to every lane.
+// Inclusive prefix sums within each row of 16 lanes by row shifts of 1, 2, 4
+// and 8 (register moves, no LDS), then the four row totals from lanes 15, 31,
+// 47, 63 in a fixed order.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += dpp_row_shr<0x111>(v);
+  v += dpp_row_shr<0x112>(v);
+  v += dpp_row_shr<0x114>(v);
+  v += dpp_row_shr<0x118>(v);
+  return (lane_value(v, 15) + lane_value(v, 31)) + (lane_value(v, 47) + lane_value(v, 63));
 }
 
 // Sum K doubles over the workgroup; thread 0 receives the totals in v.

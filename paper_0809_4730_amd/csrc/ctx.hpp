@@ -24,6 +24,11 @@ inline size_t storage_bytes(int storage) {
 
 inline size_t compute_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
 
+// Population planes of the flow (19 for D3Q19, 9 for D2Q9) and of the
+// induction lattice (3 x 7 for D3Q7, 2 x 5 for D2Q5).
+inline int flow_planes(const lbm_params& p) { return p.lattice == LBM_D2Q9 ? 9 : 19; }
+inline int mag_planes(const lbm_params& p) { return p.lattice == LBM_D2Q9 ? 10 : 21; }
+
 struct Layout {
   int64_t N = 0, stride = 0;
   int32_t nblocks = 0;
@@ -68,6 +73,8 @@ struct lbm_ctx {
   bool field() const { return p.force_mode == LBM_FORCE_FIELD; }
   size_t elem() const { return lbm::storage_bytes(p.storage); }
   size_t celem() const { return lbm::compute_bytes(p.storage); }
+  int qf() const { return lbm::flow_planes(p); }
+  int qg() const { return lbm::mag_planes(p); }
 };
 
 namespace lbm {

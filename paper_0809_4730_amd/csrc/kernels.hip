@@ -15,77 +15,9 @@
 // post-collision value at the same node.
 #include "collide.hpp"
 #include "launch.hpp"
+#include "stream.hpp"
 
 namespace lbm {
-
-// Per-node neighbour offsets for pull streaming.
-struct Nbr {
-  int32_t xm, xp, ym, yp, zm, zp;  // linear offsets to x-1, x+1, ... (periodic wrap applied)
-  bool bxm, bxp, bym, byp, bzm, bzp;  // link to that neighbour crosses a wall
-};
-
-struct Coord {
-  int x, y, z;
-};
-
-__device__ __forceinline__ Coord coords(const GridArgs& g, uint32_t n) {
-  const uint32_t yz = fdiv(n, g.div_nx);
-  const uint32_t z = fdiv(n, g.div_nxny);
-  Coord q;
-  q.x = static_cast<int>(n - yz * static_cast<uint32_t>(g.nx));
-  q.y = static_cast<int>(yz - z * static_cast<uint32_t>(g.ny));
-  q.z = static_cast<int>(z);
-  return q;
-}
-
-// Offsets with periodic wrap, and the walls at the lattice faces.
-__device__ __forceinline__ Nbr neighbours_at(const GridArgs& g, const Coord& q) {
-  const int sx = 1, sy = g.nx, sz = g.nx * g.ny;
-  Nbr b;
-  b.xm = (q.x == 0) ? (g.nx - 1) * sx : -sx;
-  b.xp = (q.x == g.nx - 1) ? -(g.nx - 1) * sx : sx;
-  b.ym = (q.y == 0) ? (g.ny - 1) * sy : -sy;
-  b.yp = (q.y == g.ny - 1) ? -(g.ny - 1) * sy : sy;
-  b.zm = (q.z == 0) ? (g.nz - 1) * sz : -sz;
-  b.zp = (q.z == g.nz - 1) ? -(g.nz - 1) * sz : sz;
-  b.bxm = g.wall_x && q.x == 0;
-  b.bxp = g.wall_x && q.x == g.nx - 1;
-  b.bym = g.wall_y && q.y == 0;
-  b.byp = g.wall_y && q.y == g.ny - 1;
-  b.bzm = g.wall_z && q.z == 0;
-  b.bzp = g.wall_z && q.z == g.nz - 1;
-  return b;
-}
-
-__device__ __forceinline__ Nbr neighbours(const GridArgs& g, uint32_t n) {
-  return neighbours_at(g, coords(g, n));
-}
-
-// The same node seen by the flow: walls at the fluid box faces.
-__device__ __forceinline__ Nbr box_walls(const GridArgs& g, const Coord& q, Nbr b) {
-  b.bxm = g.wall_x && q.x == g.flo[0];
-  b.bxp = g.wall_x && q.x == g.fhi[0] - 1;
-  b.bym = g.wall_y && q.y == g.flo[1];
-  b.byp = g.wall_y && q.y == g.fhi[1] - 1;
-  b.bzm = g.wall_z && q.z == g.flo[2];
-  b.bzp = g.wall_z && q.z == g.fhi[2] - 1;
-  return b;
-}
-
-__device__ __forceinline__ bool in_box(const GridArgs& g, const Coord& q) {
-  return q.x >= g.flo[0] && q.x < g.fhi[0] && q.y >= g.flo[1] && q.y < g.fhi[1] &&
-         q.z >= g.flo[2] && q.z < g.fhi[2];
-}
-
-// Source of f_a(x) = f~_a(x - e_a): returns the element index to read in the
-// plane of direction `plane` (a itself, or its opposite on bounce-back).
-template <int EX, int EY, int EZ>
-__device__ __forceinline__ bool pull_source(const Nbr& b, int32_t& off) {
-  off = (EX > 0 ? b.xm : EX < 0 ? b.xp : 0) + (EY > 0 ? b.ym : EY < 0 ? b.yp : 0) +
-        (EZ > 0 ? b.zm : EZ < 0 ? b.zp : 0);
-  return (EX > 0 && b.bxm) || (EX < 0 && b.bxp) || (EY > 0 && b.bym) || (EY < 0 && b.byp) ||
-         (EZ > 0 && b.bzm) || (EZ < 0 && b.bzp);
-}
 
 // Wall-momentum term of a bounced link of direction A at this node: mean over
 // the crossed moving faces of 6 w_A rho0 (e_A . u_face).
@@ -285,39 +217,6 @@ __device__ __forceinline__ void load_force(const GridArgs& g, const CollideArgs<
   }
 }
 
-// Residual / reduction bookkeeping of one node, accumulated in FP64.  The
-// velocity snapshot is kept in the compute type R: u is an R value, so the
-// FP64 difference of two snapshots is exact.
-template <typename R>
-__device__ __forceinline__ void check_node(const GridArgs& g, R* __restrict__ usnap, uint32_t n,
-                                           R drho, R jx, R jy, R jz, R ux, R uy, R uz,
-                                           double (&acc)[kPartials]) {
-  const R ur[3] = {ux, uy, uz};
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const int64_t i = static_cast<int64_t>(k) * g.stride + n;
-    const double uk = static_cast<double>(ur[k]);
-    const double d = uk - static_cast<double>(usnap[i]);
-    usnap[i] = ur[k];
-    acc[0] += d * d;
-    acc[1] += uk * uk;
-  }
-  acc[2] += static_cast<double>(drho);
-  acc[3] += static_cast<double>(jx);
-  const bool fin = isfinite(static_cast<double>(drho)) && isfinite(static_cast<double>(jx)) &&
-                   isfinite(static_cast<double>(jy)) && isfinite(static_cast<double>(jz));
-  acc[4] += fin ? 0.0 : 1.0;
-}
-
-__device__ __forceinline__ void write_partials(double* __restrict__ partials, int lb,
-                                               double (&acc)[kPartials]) {
-  block_sum<kPartials>(acc);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < kPartials; ++k) partials[static_cast<int64_t>(lb) * kPartials + k] = acc[k];
-  }
-}
-
 // ------------------------------------------------------------------ steps --
 template <typename S, bool CHECK, bool FIELD, bool NT, bool MOVING>
 __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<typename Storage<S>::R> c,
@@ -329,7 +228,7 @@ __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<type
   const int lb = logical_block(g);
   if (lb >= g.nblocks) return;  // padding workgroup of the XCD-balanced launch
   const uint32_t n = static_cast<uint32_t>(lb) * kBlock + threadIdx.x;
-  double acc[kPartials] = {0, 0, 0, 0, 0, 0};
+  double acc[kPartials] = {};
   if (n < static_cast<uint32_t>(g.N)) {
     const Nbr b = neighbours(g, n);
     R f[Q19];
@@ -356,7 +255,7 @@ __global__ __launch_bounds__(kBlock) void mhd_step(GridArgs g, CollideArgs<R> c,
   const int lb = logical_block(g);
   if (lb >= g.nblocks) return;
   const uint32_t n = static_cast<uint32_t>(lb) * kBlock + threadIdx.x;
-  double acc[kPartials] = {0, 0, 0, 0, 0, 0};
+  double acc[kPartials] = {};
   if (n < static_cast<uint32_t>(g.N)) {
     const Coord q = coords(g, n);
     const Nbr b = neighbours_at(g, q);
@@ -402,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void fields_kernel(
   const int lb = logical_block(g);
   if (lb >= g.nblocks) return;
   const uint32_t n = static_cast<uint32_t>(lb) * kBlock + threadIdx.x;
-  double acc[kPartials] = {0, 0, 0, 0, 0, 0};
+  double acc[kPartials] = {};
   if (n < static_cast<uint32_t>(g.N)) {
     const Coord q = coords(g, n);
     const Nbr b = neighbours_at(g, q);
@@ -476,7 +375,7 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(const double* __restri
                                                           int history_len) {
   const int64_t k = first + blockIdx.x;
   const double* p = partials + (k % pslots) * int64_t(nblocks) * kPartials;
-  double acc[kPartials] = {0, 0, 0, 0, 0, 0};
+  double acc[kPartials] = {};
   for (int b = threadIdx.x; b < nblocks; b += kBlock) {
 #pragma unroll
     for (int q = 0; q < kPartials; ++q) acc[q] += p[static_cast<int64_t>(b) * kPartials + q];
@@ -514,8 +413,6 @@ __global__ __launch_bounds__(kBlock) void fill_zero_f64(double* __restrict__ p, 
 }
 
 // ------------------------------------------------------------- launchers --
-static inline dim3 step_grid(const GridArgs& g) { return dim3(kXcd * g.blocks_per_xcd); }
-
 template <typename S>
 hipError_t launch_glbe_step(const GridArgs& g, const CollideArgs<typename Storage<S>::R>& c,
                             const void* fin, void* fout, const void* force, bool field, bool check,

@@ -25,6 +25,25 @@ hipError_t launch_fields(const GridArgs& g, const CollideArgs<typename Storage<S
                          const void* gin, const void* force, bool field, int out_dtype, void* rho,
                          void* u, void* B, int64_t out_stride, double* partials, hipStream_t st);
 
+// Two-dimensional variants (kernels2d.hip): D2Q9 flow, D2Q5 induction, same
+// argument conventions as above (nz = 1).
+template <typename S>
+hipError_t launch_glbe2_step(const GridArgs& g, const CollideArgs<typename Storage<S>::R>& c,
+                             const void* fin, void* fout, const void* force, bool field, bool check,
+                             bool nt, void* usnap, double* partials, hipStream_t st);
+
+template <typename R>
+hipError_t launch_mhd2_step(const GridArgs& g, const CollideArgs<R>& c, const MagArgs<R>& m,
+                            const void* fin, void* fout, const void* gin, void* gout,
+                            const void* force, bool field, bool check, void* usnap,
+                            double* partials, hipStream_t st);
+
+template <typename S>
+hipError_t launch_fields2(const GridArgs& g, const CollideArgs<typename Storage<S>::R>& c,
+                          const MagArgs<typename Storage<S>::R>& m, bool mhd, const void* fin,
+                          const void* gin, const void* force, bool field, int out_dtype, void* rho,
+                          void* u, void* B, int64_t out_stride, double* partials, hipStream_t st);
+
 // Reduce `count` pending checks (global indices first .. first+count-1) from the
 // partials ring (pslots slots) into the history ring.
 hipError_t launch_finalize(const double* partials, int nblocks, int pslots, int64_t first,

@@ -36,9 +36,11 @@ std::string validate(const lbm_grid* grid, const lbm_params* p) {
   }
   if (N >= (int64_t(1) << 31)) return "grid has 2^31 or more nodes";
   if (storage_bytes(p->storage) == 0) return "storage must be LBM_F64, LBM_F32, LBM_BF16 or LBM_F16";
+  if (p->lattice != LBM_D3Q19 && p->lattice != LBM_D2Q9) return "lattice must be LBM_D3Q19 or LBM_D2Q9";
   if (!(p->gamma > 0.0 && p->gamma <= 1.0)) return "gamma must lie in (0, 1]";
-  for (int k = 0; k < 19; ++k)
-    if (!is_conserved(k) && !(p->s[k] > 0.0 && p->s[k] < 2.0)) {
+  const bool d2 = p->lattice == LBM_D2Q9;
+  for (int k = 0; k < (d2 ? 9 : 19); ++k)
+    if (!(d2 ? (k == 0 || k == 3 || k == 5) : is_conserved(k)) && !(p->s[k] > 0.0 && p->s[k] < 2.0)) {
       char buf[96];
       std::snprintf(buf, sizeof buf, "rate s[%d] = %g outside (0, 2)", k, p->s[k]);
       return buf;
@@ -64,6 +66,15 @@ std::string validate(const lbm_grid* grid, const lbm_params* p) {
   for (int f = 0; f < 6; ++f)
     for (int a = 0; a < 3; ++a)
       if (!std::isfinite(p->wall_u[f][a])) return "wall_u must be finite";
+  if (p->lattice == LBM_D2Q9) {
+    if (grid->n[2] != 1) return "LBM_D2Q9 needs n[2] = 1";
+    if (p->force_const[2] != 0.0 || p->B0[2] != 0.0) return "LBM_D2Q9: force_const[2] and B0[2] must be 0";
+    for (int f = 0; f < 6; ++f)
+      for (int a = 0; a < 3; ++a)
+        if (p->wall_u[f][a] != 0.0) return "LBM_D2Q9 has no moving walls";
+    for (int a = 0; a < 3; ++a)
+      if (p->mag_pad[a] != 0) return "LBM_D2Q9 has no extended induction lattice";
+  }
   for (int a = 0; a < 3; ++a) {
     if (p->mag_pad[a] < 0) return "mag_pad must be >= 0";
     if (p->mag_pad[a] == 0) continue;
@@ -87,11 +98,12 @@ Layout make_layout(const lbm_grid* grid, const lbm_params* p) {
     off = align_up(off + bytes);
     return at;
   };
-  L.f[0] = take(19 * L.stride * es);
-  L.f[1] = take(19 * L.stride * es);
+  const int qf = flow_planes(*p), qg = mag_planes(*p);
+  L.f[0] = take(qf * L.stride * es);
+  L.f[1] = take(qf * L.stride * es);
   if (p->mhd) {
-    L.g[0] = take(21 * L.stride * cs);
-    L.g[1] = take(21 * L.stride * cs);
+    L.g[0] = take(qg * L.stride * cs);
+    L.g[1] = take(qg * L.stride * cs);
   }
   if (p->force_mode == LBM_FORCE_FIELD) L.force = take(3 * L.stride * cs);
   L.usnap = take(3 * L.stride * cs);
@@ -131,9 +143,12 @@ CollideArgs<R> collide_args(const lbm_params& p) {
   // the F.u source moments carry 1/gamma^2 (P_S); the naive form uses 1/gamma
   c.inv_gamma2 = R(p.source_mode == 1 ? 1.0 / p.gamma : 1.0 / (p.gamma * p.gamma));
   c.half_inv_gamma = R(0.5 / p.gamma);
+  const bool d2 = p.lattice == LBM_D2Q9;
   for (int k = 0; k < 19; ++k) {
-    c.A[k] = R(p.s[k] / NORM19[k]);
-    c.B[k] = R((1.0 - 0.5 * p.s[k]) / NORM19[k]);
+    const double norm = d2 ? (k < Q9 ? NORM9[k] : 1.0) : NORM19[k];
+    const double s = (d2 && k >= Q9) ? 1.0 : p.s[k];
+    c.A[k] = R(s / norm);
+    c.B[k] = R((1.0 - 0.5 * s) / norm);
   }
   for (int a = 0; a < 3; ++a) c.F[a] = R(p.force_const[a]);
   // link bounce-back with wall momentum: 6 w_a rho0 (e_a . u_face); w by shell
@@ -158,14 +173,17 @@ MagArgs<R> mag_args(const lbm_params& p) {
     m.w_axis = R(W7_AXIS);
     return m;
   }
-  const double tau = p.eta / (p.gamma_m * THETA_M) + 0.5;
+  // theta_m = 1/N_m and the weights: N_m = 4 (D3Q7) or 3 (D2Q5), Sec. 4
+  const bool d2 = p.lattice == LBM_D2Q9;
+  const double theta = d2 ? THETA_M2 : THETA_M;
+  const double tau = p.eta / (p.gamma_m * theta) + 0.5;
   m.omega = R(1.0 / tau);
-  m.adv = R(p.chi / (p.gamma_m * THETA_M));
-  m.a_coef = R(-1.0 / (p.mu * p.chi * tau * THETA_M));
-  m.kappa = R(2.0 / (p.mu * p.gamma_m * tau * THETA_M));
+  m.adv = R(p.chi / (p.gamma_m * theta));
+  m.a_coef = R(-1.0 / (p.mu * p.chi * tau * theta));
+  m.kappa = R(2.0 / (p.mu * p.gamma_m * tau * theta));
   for (int a = 0; a < 3; ++a) m.B0[a] = R(p.B0[a]);
-  m.w_rest = R(W7_REST);
-  m.w_axis = R(W7_AXIS);
+  m.w_rest = R(d2 ? W5_REST : W7_REST);
+  m.w_axis = R(d2 ? W5_AXIS : W7_AXIS);
   return m;
 }
 
@@ -174,6 +192,30 @@ hipError_t launch_step_kernel(lbm_ctx* c, bool check) {
   const void* fin = c->f(c->cur);
   void* fout = c->f(c->cur ^ 1);
   const bool fld = c->field();
+  if (c->p.lattice == LBM_D2Q9) {
+    if (c->p.mhd) {
+      if (c->p.storage == LBM_F64)
+        return launch_mhd2_step<double>(c->ga, c->cd, c->md, fin, fout, c->g(c->cur),
+                                        c->g(c->cur ^ 1), c->force(), fld, check, c->usnap(),
+                                        partials, c->stream);
+      return launch_mhd2_step<float>(c->ga, c->cf, c->mf, fin, fout, c->g(c->cur), c->g(c->cur ^ 1),
+                                     c->force(), fld, check, c->usnap(), partials, c->stream);
+    }
+    switch (c->p.storage) {
+      case LBM_F64:
+        return launch_glbe2_step<double>(c->ga, c->cd, fin, fout, c->force(), fld, check,
+                                         c->nt_store, c->usnap(), partials, c->stream);
+      case LBM_F32:
+        return launch_glbe2_step<float>(c->ga, c->cf, fin, fout, c->force(), fld, check,
+                                        c->nt_store, c->usnap(), partials, c->stream);
+      case LBM_BF16:
+        return launch_glbe2_step<bf16_t>(c->ga, c->cf, fin, fout, c->force(), fld, check,
+                                         c->nt_store, c->usnap(), partials, c->stream);
+      default:
+        return launch_glbe2_step<_Float16>(c->ga, c->cf, fin, fout, c->force(), fld, check,
+                                           c->nt_store, c->usnap(), partials, c->stream);
+    }
+  }
   if (c->p.mhd) {
     if (c->p.storage == LBM_F64)
       return launch_mhd_step<double>(c->ga, c->cd, c->md, fin, fout, c->g(c->cur), c->g(c->cur ^ 1),
@@ -209,8 +251,8 @@ hipError_t launch_step_kernel(lbm_ctx* c, bool check) {
 void choose_launch_shape(lbm_ctx* c) {
   constexpr double kMallBytes = 256.0 * 1024 * 1024;
   const double pop_bytes =
-      2.0 * double(c->L.stride) * (19.0 * storage_bytes(c->p.storage) +
-                                   (c->p.mhd ? 21.0 * compute_bytes(c->p.storage) : 0.0));
+      2.0 * double(c->L.stride) * (c->qf() * double(storage_bytes(c->p.storage)) +
+                                   (c->p.mhd ? c->qg() * double(compute_bytes(c->p.storage)) : 0.0));
   const int bpx0 = (c->L.nblocks + kXcd - 1) / kXcd;
   int chunk = pop_bytes > 2.0 * kMallBytes ? 2 : bpx0;
   c->nt_store = pop_bytes > kMallBytes;
@@ -275,6 +317,9 @@ hipError_t fields_dispatch(lbm_ctx* c, int out_dtype, void* rho, void* u, void* 
     ca = &c->cf;
     ma = &c->mf;
   }
+  if (c->p.lattice == LBM_D2Q9)
+    return launch_fields2<S>(c->ga, *ca, *ma, c->p.mhd != 0, c->f(c->cur), c->g(c->cur), c->force(),
+                             c->field(), out_dtype, rho, u, B, c->L.N, c->fpartials(), c->stream);
   return launch_fields<S>(c->ga, *ca, *ma, c->p.mhd != 0, c->f(c->cur), c->g(c->cur), c->force(),
                           c->field(), out_dtype, rho, u, B, c->L.N, c->fpartials(), c->stream);
 }
@@ -349,6 +394,21 @@ lbm_status lbm_default_rates(double nu, double gamma, int32_t mode, double Lambd
   return LBM_OK;
 }
 
+lbm_status lbm_default_rates_d2q9(double nu, double gamma, int32_t mode, double Lambda,
+                                  double s_out[9]) {
+  if (!s_out) return fail(nullptr, LBM_EINVAL, "s_out is NULL");
+  if (!(nu > 0.0)) return fail(nullptr, LBM_EINVAL, "nu must be positive");
+  if (!(gamma > 0.0 && gamma <= 1.0)) return fail(nullptr, LBM_EINVAL, "gamma must lie in (0, 1]");
+  if (mode != 0 && mode != 1) return fail(nullptr, LBM_EINVAL, "mode must be 0 or 1");
+  if (mode == 1 && !(Lambda > 0.0)) return fail(nullptr, LBM_EINVAL, "Lambda must be positive");
+  for (int k = 0; k < 9; ++k) s_out[k] = 1.0;
+  s_out[7] = s_out[8] = 1.0 / (3.0 * nu / gamma + 0.5);
+  s_out[1] = 1.63;
+  s_out[2] = 1.14;
+  s_out[4] = s_out[6] = mode == 0 ? 1.92 : 1.0 / (Lambda * gamma / (3.0 * nu) + 0.5);
+  return LBM_OK;
+}
+
 lbm_status lbm_lattice_velocities(int32_t q, int32_t* e_out) {
   if (!e_out) return fail(nullptr, LBM_EINVAL, "e_out is NULL");
   if (q == 19) {
@@ -367,7 +427,15 @@ lbm_status lbm_lattice_velocities(int32_t q, int32_t* e_out) {
     }
     return LBM_OK;
   }
-  return fail(nullptr, LBM_EINVAL, "q must be 19 or 7");
+  if (q == 9 || q == 5) {
+    for (int a = 0; a < q; ++a) {
+      e_out[3 * a] = q == 9 ? EX9[a] : EX5[a];
+      e_out[3 * a + 1] = q == 9 ? EY9[a] : EY5[a];
+      e_out[3 * a + 2] = 0;
+    }
+    return LBM_OK;
+  }
+  return fail(nullptr, LBM_EINVAL, "q must be 19, 7, 9 or 5");
 }
 
 lbm_status lbm_workspace_bytes(const lbm_grid* grid, const lbm_params* params, size_t* bytes) {
@@ -420,8 +488,8 @@ lbm_status lbm_create(const lbm_grid* grid, const lbm_params* params, const void
   c->md = mag_args<double>(c->p);
   c->mf = mag_args<float>(c->p);
 
-  hipError_t e = zero_storage(c, c->f(0), 19 * L.stride);
-  if (e == hipSuccess) e = zero_storage(c, c->f(1), 19 * L.stride);
+  hipError_t e = zero_storage(c, c->f(0), int64_t(c->qf()) * L.stride);
+  if (e == hipSuccess) e = zero_storage(c, c->f(1), int64_t(c->qf()) * L.stride);
   if (e == hipSuccess)
     e = (compute_bytes(params->storage) == 8)
             ? launch_fill_zero<double>(c->usnap(), 3 * L.stride, c->stream)
@@ -432,8 +500,8 @@ lbm_status lbm_create(const lbm_grid* grid, const lbm_params* params, const void
     // magnetic populations are stored as deviations from W_a B0: zero at rest
     const size_t cs = compute_bytes(params->storage);
     for (int i = 0; i < 2 && e == hipSuccess; ++i)
-      e = (cs == 8) ? launch_fill_zero<double>(c->g(i), 21 * L.stride, c->stream)
-                    : launch_fill_zero<float>(c->g(i), 21 * L.stride, c->stream);
+      e = (cs == 8) ? launch_fill_zero<double>(c->g(i), int64_t(c->qg()) * L.stride, c->stream)
+                    : launch_fill_zero<float>(c->g(i), int64_t(c->qg()) * L.stride, c->stream);
   }
   if (e != hipSuccess) {
     g_create_error = std::string("initialisation: ") + hipGetErrorString(e);
@@ -603,7 +671,7 @@ lbm_status lbm_moments(lbm_ctx* c, int32_t out_dtype, void* rho, void* u, void* 
 
 lbm_status lbm_state_bytes(const lbm_ctx* c, size_t* bytes) {
   if (!c || !bytes) return fail(nullptr, LBM_EINVAL, "NULL argument");
-  *bytes = 19 * c->L.N * c->elem() + (c->p.mhd ? 21 * c->L.N * c->celem() : 0);
+  *bytes = c->qf() * c->L.N * c->elem() + (c->p.mhd ? c->qg() * c->L.N * c->celem() : 0);
   return LBM_OK;
 }
 
@@ -611,13 +679,13 @@ lbm_status lbm_get_state(lbm_ctx* c, void* dst) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (!dst) return fail(c, LBM_EINVAL, "dst is NULL");
   const size_t es = c->elem(), N = size_t(c->L.N), st = size_t(c->L.stride);
-  LBM_HIP(c, hipMemcpy2DAsync(dst, N * es, c->f(c->cur), st * es, N * es, 19, hipMemcpyDeviceToDevice,
+  LBM_HIP(c, hipMemcpy2DAsync(dst, N * es, c->f(c->cur), st * es, N * es, c->qf(), hipMemcpyDeviceToDevice,
                               c->stream),
           "state copy");
   if (c->p.mhd) {
     const size_t cs = c->celem();
-    char* gdst = static_cast<char*>(dst) + 19 * N * es;
-    LBM_HIP(c, hipMemcpy2DAsync(gdst, N * cs, c->g(c->cur), st * cs, N * cs, 21,
+    char* gdst = static_cast<char*>(dst) + c->qf() * N * es;
+    LBM_HIP(c, hipMemcpy2DAsync(gdst, N * cs, c->g(c->cur), st * cs, N * cs, c->qg(),
                                 hipMemcpyDeviceToDevice, c->stream),
             "state copy");
   }
@@ -628,19 +696,19 @@ lbm_status lbm_set_state(lbm_ctx* c, const void* src, int64_t step) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (!src || step < 0) return fail(c, LBM_EINVAL, "src is NULL or step < 0");
   const size_t es = c->elem(), N = size_t(c->L.N), st = size_t(c->L.stride);
-  LBM_HIP(c, hipMemcpy2DAsync(c->f(c->cur), st * es, src, N * es, N * es, 19, hipMemcpyDeviceToDevice,
+  LBM_HIP(c, hipMemcpy2DAsync(c->f(c->cur), st * es, src, N * es, N * es, c->qf(), hipMemcpyDeviceToDevice,
                               c->stream),
           "state copy");
   // With an extended induction lattice the step never writes f outside the
   // fluid box: give both buffers the same values there.
   if (c->p.mag_pad[0] || c->p.mag_pad[1] || c->p.mag_pad[2])
-    LBM_HIP(c, hipMemcpy2DAsync(c->f(1 - c->cur), st * es, src, N * es, N * es, 19,
+    LBM_HIP(c, hipMemcpy2DAsync(c->f(1 - c->cur), st * es, src, N * es, N * es, c->qf(),
                                 hipMemcpyDeviceToDevice, c->stream),
             "state copy");
   if (c->p.mhd) {
     const size_t cs = c->celem();
-    const char* gsrc = static_cast<const char*>(src) + 19 * N * es;
-    LBM_HIP(c, hipMemcpy2DAsync(c->g(c->cur), st * cs, gsrc, N * cs, N * cs, 21,
+    const char* gsrc = static_cast<const char*>(src) + c->qf() * N * es;
+    LBM_HIP(c, hipMemcpy2DAsync(c->g(c->cur), st * cs, gsrc, N * cs, N * cs, c->qg(),
                                 hipMemcpyDeviceToDevice, c->stream),
             "state copy");
   }

@@ -180,3 +180,48 @@ def test_mag_pad_validation(lib, pad, mhd, bc, msg):
     p.mhd = 1
     g.bc[1] = 1
     assert lib.lbm_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nbytes)) == 0
+
+
+@pytest.mark.parametrize("change,msg", [
+    (dict(n=(8, 8, 2)), b"n[2] = 1"),
+    (dict(B0z=0.1), b"B0[2]"),
+    (dict(wall=True), b"moving walls"),
+    (dict(lattice=2), b"lattice must be"),
+])
+def test_d2q9_validation(lib, change, msg):
+    import paper_0809_4730_amd as pkg
+    g, p = _grid_params(pkg, n=change.get("n", (8, 8, 1)), bc=(0, 1, 0), mhd=1, storage=pkg.F64)
+    p.lattice = change.get("lattice", 1)
+    for k, v in enumerate(pkg.default_rates_d2q9(0.1, 0.5)):
+        p.s[k] = v
+    for k in range(9, 19):
+        p.s[k] = 5.0  # beyond the nine D2Q9 rates: ignored
+    p.B0[2] = change.get("B0z", 0.0)
+    if change.get("wall"):
+        p.wall_u[3][0] = 0.01
+    nbytes = ctypes.c_size_t()
+    assert lib.lbm_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nbytes)) == -1
+    assert msg in lib.lbm_last_error(None)
+
+
+def test_d2q9_workspace_and_rates(lib):
+    import paper_0809_4730_amd as pkg
+    from oracle import d2q9
+    g, p = _grid_params(pkg, n=(64, 32, 1), bc=(0, 1, 0), storage=pkg.F32)
+    p.lattice = 1
+    for k, v in enumerate(pkg.default_rates_d2q9(0.1, 0.5)):
+        p.s[k] = v
+    nbytes = ctypes.c_size_t()
+    assert lib.lbm_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nbytes)) == 0
+    N = 64 * 32
+    assert nbytes.value >= 2 * 9 * N * 4 + 3 * N * 4
+    assert nbytes.value < 2 * 19 * N * 4
+    assert np.allclose(pkg.default_rates_d2q9(0.05, 0.2), d2q9.rates(0.05, 0.2), rtol=1e-15)
+    assert np.allclose(pkg.default_rates_d2q9(0.05, 0.2, "lambda", 0.25),
+                       d2q9.rates(0.05, 0.2, "lambda", 0.25), rtol=1e-15)
+    e9 = pkg.lattice_velocities(9)
+    assert sorted(map(tuple, e9[:, :2])) == sorted(map(tuple, d2q9.E9)) and not e9[:, 2].any()
+    e5 = pkg.lattice_velocities(5)
+    assert sorted(map(tuple, e5[:, :2])) == sorted(map(tuple, d2q9.E5))
+    for a in range(1, 9, 2):
+        assert tuple(e9[a]) == tuple(-e9[a + 1])

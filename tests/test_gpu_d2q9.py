@@ -1,0 +1,225 @@
+"""GPU parity of the two-dimensional variants (D2Q9 flow, D2Q5 induction)
+against the 2D oracle: single and repeated steps in FP64 (1e-12), FP32 and
+16-bit storage, fields, residual history, and the Poiseuille and Hartmann
+workloads against their closed forms."""
+import numpy as np
+import pytest
+
+from oracle import d2q9 as d
+from paper_0809_4730_amd import inputs
+from tests.gpu_util import announce, rel
+
+pytestmark = pytest.mark.gpu
+PER, WALL = "periodic", "wall"
+
+
+def _perm(q):
+    import paper_0809_4730_amd as pkg
+    e_lib = pkg.lattice_velocities(q)[:, :2]
+    e_or = d.E9 if q == 9 else d.E5
+    idx = {tuple(v): a for a, v in enumerate(e_or)}
+    return np.array([idx[tuple(v)] for v in e_lib])
+
+
+def _to_f(f, dtype):
+    """Oracle (9, ny, nx) -> library state (9, 1, ny, nx)."""
+    import torch
+    p = _perm(9)
+    return torch.tensor(np.ascontiguousarray(f[p][:, None]), dtype=torch.float64,
+                        device="cuda").to(dtype)
+
+
+def _from_f(t):
+    import torch
+    p = _perm(9)
+    a = t.to(torch.float64).cpu().numpy()[:, 0]
+    out = np.empty_like(a)
+    out[p] = a
+    return out
+
+
+def _rest_g(shape, B0):
+    nx, ny = shape
+    return d.initial_g((nx, ny), B0)
+
+
+def _to_g(g, dtype, B0):
+    import torch
+    p = _perm(5)
+    dev = g - _rest_g((g.shape[3], g.shape[2]), B0)
+    return torch.tensor(np.ascontiguousarray(dev[:, p][:, :, None]), dtype=torch.float64,
+                        device="cuda").to(dtype)
+
+
+def _from_g(t, B0):
+    import torch
+    p = _perm(5)
+    a = t.to(torch.float64).cpu().numpy()[:, :, 0]
+    out = np.empty_like(a)
+    out[:, p] = a
+    return out + _rest_g((a.shape[3], a.shape[2]), B0)
+
+
+def _sim(shape, bc, gamma, s, storage, force, mhd=None):
+    import paper_0809_4730_amd as pkg
+    nx, ny = shape
+    return pkg.Simulation((nx, ny, 1), (bc[0], bc[1], PER), gamma, s, storage=storage, force=force,
+                          mhd=mhd, lattice="d2q9")
+
+
+def _field_force(shape, seed, amp=1e-5):
+    nx, ny = shape
+    return amp * np.random.default_rng(seed).uniform(-1, 1, (2, ny, nx))
+
+
+def _lib_force(F, dtype):
+    import torch
+    F3 = np.concatenate([F, np.zeros_like(F[:1])])[:, None]
+    return torch.tensor(F3, dtype=dtype, device="cuda")
+
+
+GRIDS = [((7, 9), (PER, WALL)), ((5, 6), (WALL, WALL)), ((8, 4), (PER, PER)), ((300, 5), (PER, WALL))]
+
+
+@pytest.mark.parametrize("shape,bc", GRIDS)
+@pytest.mark.parametrize("nsteps", [1, 40])
+def test_d2q9_fp64_matches_oracle(shape, bc, nsteps):
+    import torch
+    announce("d2q9 fp64 %s %s n=%d" % (shape, bc, nsteps))
+    gamma = 0.3
+    s = d.rates(0.05, gamma)
+    nx, ny = shape
+    f0 = inputs.random_deviations((nx, ny, 1), seed=31, amp=1e-3, q=9)[:, 0]
+    F = _field_force(shape, 32)
+    sim = _sim(shape, bc, gamma, s, "f64", _lib_force(F, torch.float64))
+    sim.set_state(_to_f(f0, torch.float64))
+    sim.step(nsteps)
+    fo = f0
+    for _ in range(nsteps):
+        fo, u = d.step(fo, F, gamma, s, bc)
+    assert rel(_from_f(sim.get_state()), fo) < 1e-12
+    rho, ug, _ = sim.moments("f64")
+    fs = d.stream(fo, bc)
+    _, rho_o, _, u_o = d.fields(fs, F, gamma)
+    ug = ug.cpu().numpy()[:, 0]
+    assert rel(ug[:2], u_o) < 1e-11
+    assert np.all(ug[2] == 0.0)
+    assert rel(rho.cpu().numpy()[0], rho_o) < 1e-14
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 2e-6), ("bf16", 1e-2), ("f16", 2e-3)])
+def test_d2q9_reduced_precision_single_step(storage, tol):
+    import torch
+    shape, bc = (33, 17), (PER, WALL)
+    gamma = 0.2
+    s = d.rates(0.04, gamma)
+    nx, ny = shape
+    f0 = inputs.random_deviations((nx, ny, 1), seed=41, amp=1e-3, q=9)[:, 0]
+    dt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[storage]
+    f0 = _from_f(_to_f(f0, dt))  # values the storage holds exactly
+    F = (2e-5, -1e-5)
+    sim = _sim(shape, bc, gamma, s, storage, F)
+    sim.set_state(_to_f(f0, dt))
+    sim.step(1)
+    fo, _ = d.step(f0, np.broadcast_to(np.array(F).reshape(2, 1, 1), (2, ny, nx)), gamma, s, bc)
+    assert rel(_from_f(sim.get_state()), fo) < tol
+
+
+def test_d2q9_residual_history_matches_oracle():
+    import torch
+    shape, bc = (16, 24), (PER, WALL)
+    gamma, nu = 0.5, 0.1
+    s = d.rates(nu, gamma)
+    sim = _sim(shape, bc, gamma, s, "f64", (1e-5, 0.0))
+    sim.step(200)
+    h = sim.history(64)
+    fl = d.Flow2D(shape, bc, (1e-5, 0.0), gamma, s)
+    fl.step(200)
+    ref = np.array([r for _, r in fl.history])
+    # the library also records the first check (against a zero snapshot: 1)
+    assert h[0, 1] == 1.0
+    got = h[1:, 1]
+    assert len(got) == len(ref)
+    assert np.all(np.abs(got - ref) <= 1e-14 + 1e-8 * ref)
+    mass, flow = sim.reductions()
+    assert abs(mass) < 1e-12
+
+
+def test_d2q9_poiseuille_workload_fp32():
+    """Plane Poiseuille, 4 x 64, FP32 storage, gamma = 0.1, Lambda = 3/16: the
+    steady profile is the parabola to FP32 accuracy."""
+    nu, gamma, F, H = 0.1, 0.1, 1e-6, 64
+    import paper_0809_4730_amd as pkg
+    s = pkg.default_rates_d2q9(nu, gamma, "lambda", 3 / 16)
+    assert np.allclose(s, d.rates(nu, gamma, "lambda", 3 / 16), rtol=1e-15)
+    sim = _sim((4, H), (PER, WALL), gamma, s, "f32", (F, 0.0))
+    steps, r = sim.run_to_residual(2e-7, 200000, poll_every=500)
+    assert steps > 0
+    sim.step(2000)
+    _, u, _ = sim.moments("f64")
+    u = u.cpu().numpy()[0, 0, :, 0]
+    y = np.arange(H) + 0.5
+    exact = F * y * (H - y) / (2 * nu)
+    assert np.max(np.abs(u - exact)) / exact.max() < 1e-4
+
+
+@pytest.mark.parametrize("shape,bc", [((6, 10), (PER, WALL)), ((5, 7), (WALL, WALL))])
+@pytest.mark.parametrize("nsteps", [1, 40])
+def test_d2q5_mhd_fp64_matches_oracle(shape, bc, nsteps):
+    import torch
+    announce("d2q5 mhd fp64 %s %s n=%d" % (shape, bc, nsteps))
+    gamma, gm = 0.2, 0.3
+    B0 = np.array([0.01, 0.03])
+    p = dict(gamma_m=gm, chi=0.05, eta=0.02, B0=tuple(B0))
+    s = d.rates(0.05, gamma)
+    nx, ny = shape
+    F = np.array([1e-5, -2e-6])
+    f0 = inputs.random_deviations((nx, ny, 1), seed=51, amp=1e-3, q=9)[:, 0]
+    g0 = d.initial_g(shape, B0) + inputs.random_deviations((nx, ny, 1), seed=52, amp=1e-4,
+                                                            q=10).reshape(2, 5, ny, nx)
+    sim = _sim(shape, bc, gamma, s, "f64", tuple(F), mhd=p)
+    sim.set_state(_to_f(f0, torch.float64), _to_g(g0, torch.float64, B0))
+    sim.step(nsteps)
+    fg, gg = sim.get_state()
+    pp = dict(gamma=gamma, s=s, gamma_m=gm, chi=p["chi"], eta=p["eta"], B_wall=B0)
+    Ff = np.broadcast_to(F.reshape(2, 1, 1), (2, ny, nx))
+    fo, go = f0, g0
+    for _ in range(nsteps):
+        fo, go, u, B = d.mhd_step(fo, go, Ff, pp, bc)
+    assert rel(_from_f(fg), fo) < 1e-12
+    assert rel(_from_g(gg, B0), go) < 1e-13
+    _, ug, Bg = sim.moments("f64")
+    fs, gs = d.stream(fo, bc), d.stream_g(go, bc, B0)
+    _, u_o, B_o, _, _ = d.coupled_fields(fs, gs, Ff, gamma, gm, p["chi"], p["eta"])
+    assert rel(ug.cpu().numpy()[:2, 0], u_o) < 1e-11
+    assert rel(Bg.cpu().numpy()[:2, 0], B_o) < 1e-14
+    assert np.all(Bg.cpu().numpy()[2] == 0.0)
+
+
+def test_d2q5_hartmann_fp32_closed_form():
+    """2D Hartmann flow (Ha = 10, Pm = 0.01, 2L = 32 between walls normal to y),
+    FP32, gamma = gamma_m = 0.1: u and b_x against the insulating-wall profiles."""
+    L, Ha, Pm, nu, eta, F = 16, 10.0, 0.01, 0.1, 0.025, 1e-5
+    B0, chi = inputs.hartmann_parameters(Ha, Pm, 2 * L, nu, eta)
+    import paper_0809_4730_amd as pkg
+    s = pkg.default_rates_d2q9(nu, 0.1, "lambda", 3 / 16)
+    sim = _sim((4, 2 * L), (PER, WALL), 0.1, s, "f32", (F, 0.0),
+               mhd=dict(gamma_m=0.1, chi=chi, eta=eta, B0=(0.0, B0)))
+    steps, _ = sim.run_to_residual(2e-7, 200000, poll_every=500)
+    assert steps > 0
+    sim.step(2000)
+    _, u, B = sim.moments("f64")
+    u = u.cpu().numpy()[0, 0, :, 0]
+    b = B.cpu().numpy()[0, 0, :, 0]
+    y = np.arange(2 * L) + 0.5 - L
+    uex = F * L * L / (nu * Ha) * (np.cosh(Ha) - np.cosh(Ha * y / L)) / np.sinh(Ha)
+    bex = chi * F * L / B0 * (np.sinh(Ha * y / L) / np.sinh(Ha) - y / L)
+    eu = np.sqrt(np.mean((u - uex) ** 2)) / uex.max()
+    eb = np.sqrt(np.mean((b - bex) ** 2)) / np.abs(bex).max()
+    announce("d2q5 hartmann: steps %d eu %.3g eb %.3g" % (steps, eu, eb))
+    # the oracle at the same resolution carries the same discretisation error
+    # (2.3% and 1.5% here); the FP32 library must agree with it closely
+    fl = d.MHDFlow2D((1, 2 * L), (PER, WALL), (F, 0.0), 0.1, s, 0.1, chi, eta, (0.0, B0))
+    assert fl.run_to(1e-10, 60000)
+    assert rel(u, fl.u[0][:, 0]) < 1e-4 and rel(b, fl.B[0][:, 0]) < 1e-3
+    assert eu < 0.03 and eb < 0.025

@@ -113,6 +113,8 @@ def test_oracle_equilibrium_function(seed):
     ej = e @ j
     feq = d.W9[:, None] * (rho + 3 * ej + (4.5 * ej ** 2 - 1.5 * (j * j).sum(0)) / (g * rho))
     assert np.allclose(d.meq_star(rho, j, g), d.T9 @ feq, rtol=0, atol=1e-13)
+    dev = d.meq_star_dev(rho - 1.0, rho, j, g)
+    assert np.allclose(dev + (d.T9 @ d.W9)[:, None], d.T9 @ feq, rtol=0, atol=1e-13)
 
 
 # ----------------------------------------------------------- sources
