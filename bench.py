@@ -238,7 +238,29 @@ def extras(args):
     out["adjoint"] = adjoint_extras()
     out.update(cavity_extras())
     out["d2q9"] = d2q9_extras()
+    out["stability_envelope"] = stability_extras()
     return out
+
+
+def stability_extras():
+    """Stability map (Sec. 5): gamma_min for 3 viscosities x 4 velocities on
+    4x4x64 FP64 channels (20,000 steps per march): sequential bisection (one
+    lattice per launch, 9 marches per point) against the batched k-section (all
+    points and 15 gammas per round in one launch per step, 2 rounds)."""
+    import torch
+
+    from paper_0809_4730_amd import stability
+    nus, us = (0.002, 0.02, 0.1), (0.005, 0.02, 0.05, 0.08)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq = stability.envelope(nus, us, lo=1e-3, hi=1.0, iters=7, max_steps=20000)
+    t_seq = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    bat = stability.envelope_batched(nus, us, per_round=15, rounds=2, max_steps=20000)
+    t_bat = time.perf_counter() - t0
+    return {"sequential_s": round(t_seq, 3), "batched_s": round(t_bat, 3),
+            "points": [{"nu": a["nu"], "u_max": a["u_max"], "gamma_min_bisection": round(a["gamma_min"], 5),
+                        "gamma_min_batched": round(b["gamma_min"], 5)} for a, b in zip(seq, bat)]}
 
 
 def d2q9_extras():

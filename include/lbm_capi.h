@@ -276,6 +276,46 @@ lbm_status lbm_adjoint_unrolled(lbm_ctx* ctx, void* adj_ws, size_t adj_ws_bytes,
  * lbm_create on this thread.  Never NULL. */
 const char* lbm_last_error(const lbm_ctx* ctx);
 
+/* ------------------------------------------------------------- batches --
+ * Many independent small lattices marched together, one launch per step: the
+ * stability map of Sec. 5 classifies many (viscosity, velocity, gamma) points
+ * on small Poiseuille lattices.  All members share the grid (no induction);
+ * each has its own gamma, rates and uniform force. */
+typedef struct {
+  double gamma;     /* 0 < gamma <= 1 */
+  double s[19];     /* D3Q19 rates as in lbm_params */
+  double force[3];  /* uniform force */
+} lbm_member;
+
+typedef struct {
+  int32_t verdict;   /* 0: undecided after max_steps; 1: residual below tol;
+                        2: unstable (non-finite values, or the residual above
+                        1e-2 and 1e3 times its running minimum) */
+  int32_t reserved;
+  int64_t step;      /* step of the verdict (-1 when undecided) */
+  double residual;   /* last residual computed (NaN before the first check) */
+} lbm_member_result;
+
+/* Device workspace bytes for `count` members on `grid` with storage type
+ * `storage` (each member's nodes rounded up to whole 256-node workgroups).
+ * Errors: LBM_EINVAL for a bad grid or storage, count < 1, or 2^31 or more
+ * padded nodes. */
+lbm_status lbm_batch_workspace_bytes(const lbm_grid* grid, int32_t storage, int32_t count,
+                                     size_t* bytes);
+
+/* March all members from rest (deviations zero) on `stream` until each is
+ * decided or max_steps is reached, with the residual every check_every steps
+ * (the rules of lbm_run_to_residual, per member); the host polls the verdicts
+ * every poll_every steps and stops early once all are decided.  members and
+ * results are host arrays of `count`; workspace is caller device memory
+ * (256-byte aligned, lbm_batch_workspace_bytes).  Blocks the calling thread
+ * until the march ends.  Errors: LBM_EINVAL (arguments, with the member
+ * index), LBM_ENOWS (workspace), LBM_EHIP. */
+lbm_status lbm_batch_run(const lbm_grid* grid, int32_t storage, double rho0, int32_t count,
+                         const lbm_member* members, void* workspace, size_t workspace_bytes,
+                         void* stream, double tol, int64_t max_steps, int32_t check_every,
+                         int64_t poll_every, lbm_member_result* results);
+
 #ifdef __cplusplus
 }
 #endif

@@ -59,6 +59,16 @@ class _Params(ctypes.Structure):
     ]
 
 
+class _Member(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("s", ctypes.c_double * 19),
+                ("force", ctypes.c_double * 3)]
+
+
+class _MemberResult(ctypes.Structure):
+    _fields_ = [("verdict", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("step", ctypes.c_int64), ("residual", ctypes.c_double)]
+
+
 class _Record(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in
                 ("step", "residual", "du2", "u2", "mass", "flow", "nonfinite", "reserved")]
@@ -91,6 +101,9 @@ def load_library():
     sig = {
         "lbm_default_rates": [c_double, c_double, c_int32, c_double, P(c_double)],
         "lbm_default_rates_d2q9": [c_double, c_double, c_int32, c_double, P(c_double)],
+        "lbm_batch_workspace_bytes": [P(_Grid), c_int32, c_int32, P(c_size_t)],
+        "lbm_batch_run": [P(_Grid), c_int32, c_double, c_int32, P(_Member), c_void_p, c_size_t,
+                          c_void_p, c_double, c_int64, c_int32, c_int64, P(_MemberResult)],
         "lbm_lattice_velocities": [c_int32, P(c_int32)],
         "lbm_workspace_bytes": [P(_Grid), P(_Params), P(c_size_t)],
         "lbm_create": [P(_Grid), P(_Params), c_void_p, c_void_p, c_size_t, c_void_p, P(c_void_p)],
@@ -150,6 +163,45 @@ def lattice_velocities(q=19):
     out = (ctypes.c_int32 * (3 * q))()
     _check(lib.lbm_lattice_velocities(q, out))
     return np.array(list(out), dtype=np.int64).reshape(q, 3)
+
+
+VERDICTS = {0: "undecided", 1: "converged", 2: "unstable"}
+
+
+def batch_run(shape, bc, members, storage="f64", rho0=1.0, tol=1e-9, max_steps=20000,
+              check_every=10, poll_every=1000, device="cuda", stream=None):
+    """March independent lattices of one grid together (lbm_batch_run).
+
+    members: sequence of (gamma, rates[19], force[3]).  Returns a list of
+    (verdict, step, last residual), verdict one of VERDICTS' values."""
+    torch = _torch()
+    lib = load_library()
+    g = _Grid()
+    for a in range(3):
+        g.n[a] = int(shape[a])
+        g.bc[a] = WALL if bc[a] in ("wall", WALL) else PERIODIC
+    st = _DTYPES[storage] if isinstance(storage, str) else int(storage)
+    count = len(members)
+    arr = (_Member * count)()
+    for i, (gamma, s, force) in enumerate(members):
+        arr[i].gamma = float(gamma)
+        for k in range(19):
+            arr[i].s[k] = float(s[k])
+        for a in range(3):
+            arr[i].force[a] = float(force[a])
+    nbytes = ctypes.c_size_t()
+    _check(lib.lbm_batch_workspace_bytes(ctypes.byref(g), st, count, ctypes.byref(nbytes)))
+    dev = torch.device(device)
+    raw = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=dev)
+    ptr = raw.data_ptr() + (-raw.data_ptr()) % 256
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    res = (_MemberResult * count)()
+    _check(lib.lbm_batch_run(ctypes.byref(g), st, float(rho0), count, arr, ptr, nbytes.value,
+                             stream.cuda_stream, float(tol), int(max_steps), int(check_every),
+                             int(poll_every), res))
+    del raw
+    return [(VERDICTS[r.verdict], r.step, r.residual) for r in res]
 
 
 def _torch():

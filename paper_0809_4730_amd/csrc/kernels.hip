@@ -19,58 +19,6 @@
 
 namespace lbm {
 
-// Wall-momentum term of a bounced link of direction A at this node: mean over
-// the crossed moving faces of 6 w_A rho0 (e_A . u_face).
-template <typename R, int A>
-__device__ __forceinline__ R wall_term(const Nbr& b, const CollideArgs<R>& c) {
-  R sum = R(0);
-  int cnt = 0;
-  if (EX19[A] > 0 && b.bxm) { sum += c.wall[A][0]; ++cnt; }
-  if (EX19[A] < 0 && b.bxp) { sum += c.wall[A][1]; ++cnt; }
-  if (EY19[A] > 0 && b.bym) { sum += c.wall[A][2]; ++cnt; }
-  if (EY19[A] < 0 && b.byp) { sum += c.wall[A][3]; ++cnt; }
-  if (EZ19[A] > 0 && b.bzm) { sum += c.wall[A][4]; ++cnt; }
-  if (EZ19[A] < 0 && b.bzp) { sum += c.wall[A][5]; ++cnt; }
-  return cnt > 1 ? sum / R(cnt) : sum;
-}
-
-// MOVING = false compiles the wall-momentum term out (the plain step); with
-// MOVING = true it is added on bounced links when c.moving is set.
-template <typename S, int A, bool MOVING>
-__device__ __forceinline__ typename Storage<S>::R gather_one(
-    const S* __restrict__ fin, int64_t stride, uint32_t n, const Nbr& b,
-    const CollideArgs<typename Storage<S>::R>& c) {
-  using R = typename Storage<S>::R;
-  int32_t off;
-  const bool bounce = pull_source<EX19[A], EY19[A], EZ19[A]>(b, off);
-  const int64_t idx = bounce ? static_cast<int64_t>(OPP19(A)) * stride + n
-                             : static_cast<int64_t>(A) * stride + static_cast<int64_t>(n) + off;
-  R v = Storage<S>::ld(fin + idx);
-  if constexpr (MOVING) {
-    if (bounce && c.moving) v += wall_term<R, A>(b, c);
-  }
-  return v;
-}
-
-template <typename S, bool MOVING, int A = 0>
-__device__ __forceinline__ void gather19(const S* __restrict__ fin, int64_t stride, uint32_t n,
-                                         const Nbr& b,
-                                         const CollideArgs<typename Storage<S>::R>& c,
-                                         typename Storage<S>::R (&f)[Q19]) {
-  if constexpr (A < Q19) {
-    f[A] = gather_one<S, A, MOVING>(fin, stride, n, b, c);
-    gather19<S, MOVING, A + 1>(fin, stride, n, b, c, f);
-  }
-}
-
-template <typename S, bool NT = false>
-__device__ __forceinline__ void store19(S* __restrict__ fout, int64_t stride, uint32_t n,
-                                        const typename Storage<S>::R (&f)[Q19]) {
-#pragma unroll
-  for (int a = 0; a < Q19; ++a)
-    Storage<S>::template st<NT>(fout + static_cast<int64_t>(a) * stride + n, f[a]);
-}
-
 // Gather of the magnetic populations, stored as deviations from the applied
 // field's equilibrium, d_{a j} = g_{a j} - W_a B0_j (j outermost).  At a wall,
 // anti-bounce-back g_a = -g~_opp(a) + 2 W_a B0 (insulating wall, B = B0 there)

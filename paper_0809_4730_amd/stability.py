@@ -13,7 +13,9 @@ set is gamma >= gamma_min.
 """
 import math
 
-from . import LbmError, Simulation, default_rates
+import numpy as np
+
+from . import LbmError, Simulation, batch_run, default_rates
 
 STABLE, UNSTABLE = "stable", "unstable"
 
@@ -76,4 +78,67 @@ def envelope(nus, u_maxes, **kw):
         for um in u_maxes:
             g, n = gamma_min(nu, um, **kw)
             out.append({"nu": nu, "u_max": um, "gamma_min": g, "runs": n})
+    return out
+
+
+# ------------------------------------------------------------ batched ----
+def march_batch(points, H=64, width=4, max_steps=20000, tol=1e-9, storage="f64",
+                rates_mode="paper"):
+    """Verdicts for many (nu, u_max, gamma) points in one batched march (one
+    launch per step for all points).  Returns [(STABLE | UNSTABLE, step)]."""
+    members = [(g, default_rates(nu, g, rates_mode), (poiseuille_force(nu, um, H), 0.0, 0.0))
+               for nu, um, g in points]
+    out = batch_run((width, width, H), ("periodic", "periodic", "wall"), members,
+                    storage=storage, tol=tol, max_steps=max_steps)
+    return [(UNSTABLE if v == "unstable" else STABLE, step) for v, step, _ in out]
+
+
+def envelope_batched(nus, u_maxes, lo=1e-3, hi=1.0, per_round=15, rounds=2, **kw):
+    """gamma_min for every (nu, u_max) by k-section in log(gamma): each round
+    evaluates per_round gammas inside every point's bracket, all points and
+    gammas in one batched march.  The first round also covers lo and hi.  After
+    r rounds the bracket is (hi/lo)^(1/(per_round+1)^r) wide.  Returns the same
+    records as envelope()."""
+    keys = [(nu, um) for nu in nus for um in u_maxes]
+    brk = {k: (np.log(lo), np.log(hi)) for k in keys}
+    state = {k: None for k in keys}  # None: open; math.inf: hi unstable; lo: lo stable
+    runs = {k: 0 for k in keys}
+    for r in range(rounds):
+        pts, owner = [], []
+        for k in keys:
+            if state[k] is not None:
+                continue
+            a, b = brk[k]
+            if r == 0:
+                grid = np.linspace(a, b, per_round + 2)
+            else:
+                grid = np.linspace(a, b, per_round + 2)[1:-1]
+            for x in grid:
+                pts.append((k[0], k[1], float(np.exp(x))))
+                owner.append((k, x))
+        if not pts:
+            break
+        verdicts = march_batch(pts, **kw)
+        by_key = {}
+        for (k, x), (v, _) in zip(owner, verdicts):
+            by_key.setdefault(k, []).append((x, v))
+            runs[k] += 1
+        for k, lst in by_key.items():
+            a, b = brk[k]
+            if r == 0:
+                if lst[-1][1] == UNSTABLE:      # hi itself unstable
+                    state[k] = math.inf
+                    continue
+                if lst[0][1] == STABLE:         # lo already stable
+                    state[k] = lo
+                    continue
+            lst = [(a, UNSTABLE)] + lst + [(b, STABLE)] if r > 0 else lst
+            unstable = [x for x, v in lst if v == UNSTABLE]
+            a_new = max(unstable)
+            b_new = min(x for x, v in lst if v == STABLE and x > a_new)
+            brk[k] = (a_new, b_new)
+    out = []
+    for k in keys:
+        g = state[k] if state[k] is not None else float(np.exp(brk[k][1]))
+        out.append({"nu": k[0], "u_max": k[1], "gamma_min": g, "runs": runs[k]})
     return out

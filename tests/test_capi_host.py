@@ -225,3 +225,31 @@ def test_d2q9_workspace_and_rates(lib):
     assert sorted(map(tuple, e5[:, :2])) == sorted(map(tuple, d2q9.E5))
     for a in range(1, 9, 2):
         assert tuple(e9[a]) == tuple(-e9[a + 1])
+
+
+def test_batch_workspace_and_validation(lib):
+    import paper_0809_4730_amd as pkg
+    g = pkg._Grid()
+    for a in range(3):
+        g.n[a] = (4, 4, 64)[a]
+        g.bc[a] = (0, 0, 1)[a]
+    nbytes = ctypes.c_size_t()
+    assert lib.lbm_batch_workspace_bytes(ctypes.byref(g), pkg.F64, 10, ctypes.byref(nbytes)) == 0
+    # two population buffers and the snapshot per member (1024 nodes: 4 whole workgroups)
+    assert nbytes.value >= 10 * 1024 * (2 * 19 * 8 + 3 * 8)
+    assert lib.lbm_batch_workspace_bytes(ctypes.byref(g), 9, 10, ctypes.byref(nbytes)) == -1
+    assert lib.lbm_batch_workspace_bytes(ctypes.byref(g), pkg.F64, 0, ctypes.byref(nbytes)) == -1
+    members = (pkg._Member * 2)()
+    for i in range(2):
+        members[i].gamma = 0.5
+        for k, v in enumerate(glbe.rates(0.1, 0.5)):
+            members[i].s[k] = v
+    members[1].s[9] = 2.5
+    res = (pkg._MemberResult * 2)()
+    st = lib.lbm_batch_run(ctypes.byref(g), pkg.F64, 1.0, 2, members, None, 0, None, 1e-9, 100, 10,
+                           100, res)
+    assert st == -1 and b"member 1" in lib.lbm_last_error(None)
+    members[1].s[9] = 1.0
+    st = lib.lbm_batch_run(ctypes.byref(g), pkg.F64, 1.0, 2, members, None, 0, None, 1e-9, 100, 10,
+                           100, res)
+    assert st == -2  # no workspace: rejected before any device call

@@ -85,3 +85,31 @@ def test_envelope_rises_with_viscosity():
     g_hi, _ = stability.gamma_min(0.1, 0.05, lo=1e-3, hi=1.0, iters=6, max_steps=4000)
     announce("gamma_min(u_max=0.05): nu=0.002 -> %.4g, nu=0.1 -> %.4g" % (g_lo, g_hi))
     assert g_hi > 1.5 * g_lo
+
+
+POINTS = [(0.02, 0.05, 1.0), (0.02, 0.05, 1e-3), (0.02, 0.05, 0.05), (0.02, 0.05, 0.02),
+          (0.1, 0.02, 0.5), (0.1, 0.08, 0.03), (0.002, 0.005, 0.01), (0.002, 0.08, 0.02)]
+
+
+def test_batched_verdicts_match_single_lattice_marches():
+    """Members of one batched march reach the verdicts of separate marches of
+    the same lattices (and a converged member at the same step)."""
+    got = stability.march_batch(POINTS, max_steps=4000, tol=1e-9)
+    announce("batched verdicts: %s" % got)
+    for (nu, um, g), (v, step) in zip(POINTS, got):
+        vs, ts = stability.march(nu, um, g, max_steps=4000, tol=1e-9)
+        assert v == vs, (nu, um, g, v, vs)
+        if v == stability.UNSTABLE:
+            assert step <= ts
+    assert {v for v, _ in got} == {stability.STABLE, stability.UNSTABLE}
+
+
+def test_batched_envelope_matches_bisection():
+    nus, us = (0.02, 0.1), (0.02, 0.05)
+    env_b = stability.envelope_batched(nus, us, per_round=15, rounds=2, max_steps=4000)
+    announce("batched envelope: %s" % [(e["nu"], e["u_max"], round(e["gamma_min"], 5)) for e in env_b])
+    res_b = 1e3 ** (1.0 / 16 ** 2)
+    res_s = 1e3 ** (2.0 ** -7)
+    for e in env_b:
+        g, _ = stability.gamma_min(e["nu"], e["u_max"], lo=1e-3, hi=1.0, iters=7, max_steps=4000)
+        assert g / (res_b * res_s) <= e["gamma_min"] <= g * res_b * res_s, (e, g)
