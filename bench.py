@@ -161,9 +161,11 @@ def cpu_baseline(budget_s=12.0):
                       "cores = BLAS threads" % n}
 
 
-def time_to_residual(shape, storage, gamma, tol, max_steps, mhd=None, poll=200, **kw):
+def time_to_residual(shape, storage, gamma, tol, max_steps, make=None, poll=200, **kw):
+    """Steps and wall time to a residual below tol; `make` builds the simulation
+    (default: the duct of make_sim)."""
     import torch
-    sim = make_sim(shape, storage, gamma, **kw) if mhd is None else mhd()
+    sim = make_sim(shape, storage, gamma, **kw) if make is None else make()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     try:
@@ -195,6 +197,18 @@ def extras(args):
         e["note"] = "FP32 storage stalls near 6e-8 at this Mach number; tol 1e-7"
         tt.append(e)
     out["time_to_residual_duct64"] = tt
+    # plane Poiseuille 8x8x32 (uniform force) to 1e-10, FP64
+    pc = inputs.POISEUILLE
+
+    def pois(g):
+        return pkg.Simulation(pc["shape"], pc["bc"], g, pkg.default_rates(pc["nu"], g),
+                              storage="f64", force=pc["F"])
+    tp = [time_to_residual(None, "f64", g, 1e-10, 400000, make=lambda g=g: pois(g))
+          for g in (1.0, 0.5, 0.1, 0.05)]
+    for e in tp[1:]:
+        if tp[0]["steps"] > 0 and e["steps"] > 0:
+            e["step_ratio_vs_gamma1"] = round(tp[0]["steps"] / e["steps"], 3)
+    out["time_to_residual_poiseuille8x8x32_tol1e-10"] = tp
     ref = tt[0]
     if ref["steps"] > 0:
         for e in tt[1:]:
@@ -230,9 +244,10 @@ def extras(args):
                                 "kernel_us": round(us, 2), "alg_bytes_per_node": bpn,
                                 "achieved_GBs": round(bpn * sim.N / (us * 1e-6) / 1e9, 1)}
     ttm = []
-    for g in (1.0, 0.1):
-        ttm.append(time_to_residual(None, "f32", g, 2e-7, 400000,
-                                    mhd=lambda g=g: hart(g, g)))
+    for g, gm in ((1.0, 1.0), (0.1, 0.1), (0.1, 1.0), (1.0, 0.1), (0.1, 0.3), (0.3, 0.1)):
+        e = time_to_residual(None, "f32", g, 2e-7, 400000, make=lambda g=g, gm=gm: hart(g, gm))
+        e["gamma_m"] = gm
+        ttm.append(e)
     out["time_to_residual_hartmann_Ha10_f32_tol2e-7"] = ttm
     out["precision_duct64"] = precision_table()
     out["adjoint"] = adjoint_extras()
@@ -298,7 +313,7 @@ def d2q9_extras():
                                      "achieved_GBs": round(bpn * sim.N / (us * 1e-6) / 1e9, 1)}
     sim.close()
     out["hartmann2d_Ha10_tol2e-7"] = [
-        time_to_residual(None, "f32", g, 2e-7, 400000, mhd=lambda g=g: hart(g)) for g in (1.0, 0.1)]
+        time_to_residual(None, "f32", g, 2e-7, 400000, make=lambda g=g: hart(g)) for g in (1.0, 0.1)]
     return out
 
 
@@ -333,7 +348,7 @@ def cavity_extras():
     for name, make in (("cavity64_Ha0", plain), ("cavity64_Ha45_ext16", magnetic)):
         rows = []
         for g in c["gammas"]:
-            rows.append(time_to_residual(None, "f32", g, c["tol"], 400000, mhd=lambda g=g: make(g)))
+            rows.append(time_to_residual(None, "f32", g, c["tol"], 400000, make=lambda g=g: make(g)))
         ref = rows[0]
         for e in rows[1:]:
             if ref["steps"] > 0 and e["steps"] > 0:

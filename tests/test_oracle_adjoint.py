@@ -86,3 +86,24 @@ def test_unrolled_gradient_matches_directional_and_fd():
     qp = glbe.Flow(shape, BC, F + eps * v, g, s).step(n).flow_rate()
     qm = glbe.Flow(shape, BC, F - eps * v, g, s).step(n).flow_rate()
     assert abs((qp - qm) / (2 * eps) - d) < 1e-6 * abs(d)
+
+
+def test_newton_fixed_point_matches_time_march(steady):
+    """The steady state as a fixed point f = Phi(f): Newton's method with the
+    dense Jacobian (complex step) and the mass row bordering the singular
+    I - J_f, started from rest, reaches the time-marched state."""
+    g, s, fl = steady["gamma"], steady["s"], steady["fl"]
+    f = np.zeros_like(fl.post)
+    n = f.size
+    for _ in range(4):
+        phi, _ = glbe.step(f, fl.F, g, s, BC)
+        Jf, _ = adjoint.step_jacobians(f, fl.F, g, s, BC)
+        A = np.zeros((n + 1, n + 1))
+        A[:n, :n] = np.eye(n) - Jf
+        A[:n, n] = 1.0
+        A[n, :n] = 1.0
+        d = np.linalg.solve(A, np.concatenate([(phi - f).ravel(), [0.0]]))[:n]
+        f = f + d.reshape(f.shape)
+    phi, _ = glbe.step(f, fl.F, g, s, BC)
+    assert np.max(np.abs(phi - f)) < 1e-15 * np.max(np.abs(f)) + 1e-20
+    assert np.max(np.abs(f - fl.post)) < 1e-9 * np.max(np.abs(fl.post))
