@@ -16,7 +16,12 @@
  *     Lorentz force J x B enters the GLBE force (Sec. 4, Sec. 4.1);
  *   * the steady-state residual ||u(t) - u(t-10)||_2 (Sec. 5), relative, in FP64;
  *   * FP64 global mass and flow-rate reductions;
- *   * a discrete adjoint of the step for d(steady flow rate)/d(force field).
+ *   * a discrete adjoint of the step for d(steady flow rate)/d(force field);
+ *   * the two-dimensional variants (D2Q9 flow, D2Q5 induction; Sec. 2-4);
+ *   * moving walls and an induction lattice extending beyond the fluid box
+ *     (the MHD lid-driven cavity of Sec. 5);
+ *   * batched marches of many small independent lattices with per-lattice
+ *     stability verdicts (the stability map of Sec. 5).
  *
  * Conventions (all entry points):
  *   - Every function returns an lbm_status; no exception crosses the ABI.
@@ -30,9 +35,9 @@
  *   - Grid layout: nodes are indexed (x, y, z) with x the unit-stride axis,
  *     linear index n = x + nx*(y + ny*z), N = nx*ny*nz.  Population arrays
  *     exchanged through the ABI are structure-of-arrays [q][N] (direction
- *     outermost, unpadded).  Every node is a fluid node: walls sit half a
- *     link outside the first and last node of a wall axis (halfway
- *     bounce-back, Sec. 5).
+ *     outermost, unpadded).  Every node is a fluid node (unless mag_pad
+ *     extends the induction lattice): walls sit half a link outside the first
+ *     and last node of a wall axis (halfway bounce-back, Sec. 5).
  *   - State: the stored populations are the post-collision values of the last
  *     completed step, held as deviations from the rest state,
  *     f~_alpha - w_alpha rho0.  The hydrodynamic fields "at the current time"

@@ -37,92 +37,29 @@
 
 #include "collide.hpp"
 #include "ctx.hpp"
+#include "stream.hpp"
 
 namespace lbm {
 
 // ---------------------------------------------------------------- kernels --
-struct AdjNbr {
-  int32_t xm, xp, ym, yp, zm, zp;
-  bool bxm, bxp, bym, byp, bzm, bzp;
-};
-
-__device__ __forceinline__ AdjNbr adj_neighbours(const GridArgs& g, uint32_t n, int& x, int& y,
-                                                 int& z) {
-  const uint32_t yz = fdiv(n, g.div_nx);
-  const uint32_t zz = fdiv(n, g.div_nxny);
-  x = static_cast<int>(n - yz * static_cast<uint32_t>(g.nx));
-  y = static_cast<int>(yz - zz * static_cast<uint32_t>(g.ny));
-  z = static_cast<int>(zz);
-  const int sy = g.nx, sz = g.nx * g.ny;
-  AdjNbr b;
-  b.xm = (x == 0) ? (g.nx - 1) : -1;
-  b.xp = (x == g.nx - 1) ? -(g.nx - 1) : 1;
-  b.ym = (y == 0) ? (g.ny - 1) * sy : -sy;
-  b.yp = (y == g.ny - 1) ? -(g.ny - 1) * sy : sy;
-  b.zm = (z == 0) ? (g.nz - 1) * sz : -sz;
-  b.zp = (z == g.nz - 1) ? -(g.nz - 1) * sz : sz;
-  b.bxm = g.wall_x && x == 0;
-  b.bxp = g.wall_x && x == g.nx - 1;
-  b.bym = g.wall_y && y == 0;
-  b.byp = g.wall_y && y == g.ny - 1;
-  b.bzm = g.wall_z && z == 0;
-  b.bzp = g.wall_z && z == g.nz - 1;
-  return b;
-}
-
-// Offset to x - e (forward pull source) and whether that link crosses a wall.
-template <int EX, int EY, int EZ>
-__device__ __forceinline__ bool adj_link(const AdjNbr& b, int32_t& off) {
-  off = (EX > 0 ? b.xm : EX < 0 ? b.xp : 0) + (EY > 0 ? b.ym : EY < 0 ? b.yp : 0) +
-        (EZ > 0 ? b.zm : EZ < 0 ? b.zp : 0);
-  return (EX > 0 && b.bxm) || (EX < 0 && b.bxp) || (EY > 0 && b.bym) || (EY < 0 && b.byp) ||
-         (EZ > 0 && b.bzm) || (EZ < 0 && b.bzp);
-}
-
-// Forward pull of the state (with the constant wall-momentum term of moving
-// walls, which drops out of the transposed streaming).
-template <typename R, int A = 0>
-__device__ __forceinline__ void gather_fwd(const R* __restrict__ p, int64_t st, uint32_t n,
-                                           const AdjNbr& b, const CollideArgs<R>& c,
-                                           R (&f)[Q19]) {
-  if constexpr (A < Q19) {
-    int32_t off;
-    const bool bb = adj_link<EX19[A], EY19[A], EZ19[A]>(b, off);
-    const int64_t idx = bb ? int64_t(OPP19(A)) * st + n : int64_t(A) * st + int64_t(n) + off;
-    R v = p[idx];
-    if (bb && c.moving) {
-      R sum = R(0);
-      int cnt = 0;
-      if (EX19[A] > 0 && b.bxm) { sum += c.wall[A][0]; ++cnt; }
-      if (EX19[A] < 0 && b.bxp) { sum += c.wall[A][1]; ++cnt; }
-      if (EY19[A] > 0 && b.bym) { sum += c.wall[A][2]; ++cnt; }
-      if (EY19[A] < 0 && b.byp) { sum += c.wall[A][3]; ++cnt; }
-      if (EZ19[A] > 0 && b.bzm) { sum += c.wall[A][4]; ++cnt; }
-      if (EZ19[A] < 0 && b.bzp) { sum += c.wall[A][5]; ++cnt; }
-      v += cnt > 1 ? sum / R(cnt) : sum;
-    }
-    f[A] = v;
-    gather_fwd<R, A + 1>(p, st, n, b, c, f);
-  }
-}
-
-// lam_b(x) = mu_b(x + e_b), or mu_opp(b)(x) if that link crosses a wall.
-template <typename R, int A = 0>
+// lam_a(x) = mu_a(x + e_a), or mu_opp(a)(x) if that link crosses a wall: the
+// forward pull read along -e_a, with the same pair-relative offsets.
+template <typename R, bool WIDE, int A = 0>
 __device__ __forceinline__ void gather_transpose(const R* __restrict__ mu, int64_t st, uint32_t n,
-                                                 const AdjNbr& b, R shift, R (&lam)[Q19]) {
+                                                 const Nbr& b, R shift, R (&lam)[Q19]) {
   if constexpr (A < Q19) {
     int32_t off;
-    const bool bb = adj_link<-EX19[A], -EY19[A], -EZ19[A]>(b, off);
-    const int64_t idx = bb ? int64_t(OPP19(A)) * st + n : int64_t(A) * st + int64_t(n) + off;
-    lam[A] = mu[idx] - shift;
-    gather_transpose<R, A + 1>(mu, st, n, b, shift, lam);
+    const bool bb = pull_source<-EX19[A], -EY19[A], -EZ19[A]>(b, off);
+    const R* base = mu + static_cast<int64_t>(pair_plane<A>()) * st;
+    lam[A] = *elem<WIDE>(base, pull_offset<A>(bb, off, n, static_cast<uint32_t>(st))) - shift;
+    gather_transpose<R, WIDE, A + 1>(mu, st, n, b, shift, lam);
   }
 }
 
 // GRAD: 0 none; 1 accumulate into grad; 3 write half the gradient (with the
 // direct term) into gpre; 2 (check) grad = half the gradient + gpre, and
 // accumulate the change against the previous content of grad.
-template <typename R, bool CHECK, int GRAD, bool FIELD>
+template <typename R, bool CHECK, int GRAD, bool FIELD, bool WIDE>
 __global__ __launch_bounds__(kBlock) void adjoint_step(
     GridArgs g, CollideArgs<R> c, const R* __restrict__ state, const R* __restrict__ force,
     const R* __restrict__ mu_in, R* __restrict__ mu_out, R* __restrict__ grad,
@@ -133,18 +70,19 @@ __global__ __launch_bounds__(kBlock) void adjoint_step(
   const uint32_t n = static_cast<uint32_t>(lb) * kBlock + threadIdx.x;
   double acc[kPartials] = {};
   if (n < static_cast<uint32_t>(g.N)) {
-    int x, y, z;
-    const AdjNbr b = adj_neighbours(g, n, x, y, z);
+    const Nbr b = neighbours(g, n);
     R f[Q19];
-    gather_fwd<R>(state, g.stride, n, b, c, f);
+    // forward pull of the state; the constant wall-momentum term of moving
+    // walls drops out of the transposed streaming
+    gather19<R, true, WIDE>(state, g.stride, n, b, c, f);
     const R sh = shift ? R(*shift) : R(0);
     R lam[Q19];
-    gather_transpose<R>(mu_in, g.stride, n, b, sh, lam);
+    gather_transpose<R, WIDE>(mu_in, g.stride, n, b, sh, lam);
     R Fx, Fy, Fz;
     if (FIELD) {
-      Fx = force[n];
-      Fy = force[g.stride + n];
-      Fz = force[2 * g.stride + n];
+      Fx = *elem<WIDE>(force, n);
+      Fy = *elem<WIDE>(force + g.stride, n);
+      Fz = *elem<WIDE>(force + 2 * g.stride, n);
     } else {
       Fx = c.F[0];
       Fy = c.F[1];
@@ -155,25 +93,27 @@ __global__ __launch_bounds__(kBlock) void adjoint_step(
 #pragma unroll
     for (int a = 0; a < Q19; ++a) {
       const R v = nu[a] + q_scale * R(EX19[a]);
-      mu_out[int64_t(a) * g.stride + n] = v;
+      *elem<WIDE>(mu_out + int64_t(a) * g.stride, n) = v;
       if (CHECK) acc[2] += static_cast<double>(v);
     }
     if constexpr (GRAD == 1) {
-      grad[n] += gx;
-      grad[grad_stride + n] += gy;
-      grad[2 * grad_stride + n] += gz;
+      *elem<WIDE>(grad, n) += gx;
+      *elem<WIDE>(grad + grad_stride, n) += gy;
+      *elem<WIDE>(grad + 2 * grad_stride, n) += gz;
     } else if constexpr (GRAD == 3) {
-      gpre[n] = R(0.5) * (gx + grad_direct);
-      gpre[grad_stride + n] = R(0.5) * gy;
-      gpre[2 * grad_stride + n] = R(0.5) * gz;
+      *elem<WIDE>(gpre, n) = R(0.5) * (gx + grad_direct);
+      *elem<WIDE>(gpre + grad_stride, n) = R(0.5) * gy;
+      *elem<WIDE>(gpre + 2 * grad_stride, n) = R(0.5) * gz;
     } else if constexpr (GRAD == 2) {
-      const R gv[3] = {R(0.5) * (gx + grad_direct) + gpre[n], R(0.5) * gy + gpre[grad_stride + n],
-                       R(0.5) * gz + gpre[2 * grad_stride + n]};
+      const R gv[3] = {R(0.5) * (gx + grad_direct) + *elem<WIDE>(gpre, n),
+                       R(0.5) * gy + *elem<WIDE>(gpre + grad_stride, n),
+                       R(0.5) * gz + *elem<WIDE>(gpre + 2 * grad_stride, n)};
+      R* gk[3] = {elem<WIDE>(grad, n), elem<WIDE>(grad + grad_stride, n),
+                  elem<WIDE>(grad + 2 * grad_stride, n)};
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const int64_t i = k * grad_stride + n;
-        const double d = static_cast<double>(gv[k]) - static_cast<double>(grad[i]);
-        grad[i] = gv[k];
+        const double d = static_cast<double>(gv[k]) - static_cast<double>(*gk[k]);
+        *gk[k] = gv[k];
         acc[0] += d * d;
         acc[1] += static_cast<double>(gv[k]) * static_cast<double>(gv[k]);
       }
@@ -250,20 +190,31 @@ hipError_t launch_adjoint(const GridArgs& g, const CollideArgs<R>& c, const void
   R* mo = static_cast<R*>(mu_out);
   R* gr = static_cast<R*>(grad);
   R* gp = static_cast<R*>(gpre);
-#define LBM_ADJ(CH, GM, FL)                                                                      \
-  adjoint_step<R, CH, GM, FL><<<grid, kBlock, 0, st>>>(g, c, s, F, mi, mo, gr, gp, grad_stride, \
-                                                        shift, q_scale, grad_direct, partials)
-  if (check) {
-    if (field) LBM_ADJ(true, 2, true); else LBM_ADJ(true, 2, false);
-  } else if (grad_mode == 3) {
-    if (field) LBM_ADJ(false, 3, true); else LBM_ADJ(false, 3, false);
-  } else if (grad_mode == 1) {
-    if (field) LBM_ADJ(false, 1, true); else LBM_ADJ(false, 1, false);
-  } else {
-    if (field) LBM_ADJ(false, 0, true); else LBM_ADJ(false, 0, false);
-  }
-#undef LBM_ADJ
-  return hipGetLastError();
+  // check iterations use GRAD mode 2; the others the requested mode
+  const int gm = check ? 2 : grad_mode;
+  return with_flag(field, [&](auto FL) {
+    return with_flag(wide_offsets(g, sizeof(R)), [&](auto W) {
+      constexpr bool fl = decltype(FL)::value, w = decltype(W)::value;
+      switch (gm) {
+        case 2:
+          adjoint_step<R, true, 2, fl, w><<<grid, kBlock, 0, st>>>(g, c, s, F, mi, mo, gr, gp, grad_stride,
+                                                                   shift, q_scale, grad_direct, partials);
+          break;
+        case 3:
+          adjoint_step<R, false, 3, fl, w><<<grid, kBlock, 0, st>>>(g, c, s, F, mi, mo, gr, gp, grad_stride,
+                                                                    shift, q_scale, grad_direct, partials);
+          break;
+        case 1:
+          adjoint_step<R, false, 1, fl, w><<<grid, kBlock, 0, st>>>(g, c, s, F, mi, mo, gr, gp, grad_stride,
+                                                                    shift, q_scale, grad_direct, partials);
+          break;
+        default:
+          adjoint_step<R, false, 0, fl, w><<<grid, kBlock, 0, st>>>(g, c, s, F, mi, mo, gr, gp, grad_stride,
+                                                                    shift, q_scale, grad_direct, partials);
+      }
+      return hipGetLastError();
+    });
+  });
 }
 
 // ------------------------------------------------------------------ host ---

@@ -32,7 +32,7 @@ struct BatchArgs {
   int32_t blocks_per_member;  // workgroups per member
 };
 
-template <typename S, bool CHECK>
+template <typename S, bool CHECK, bool WIDE>
 __global__ __launch_bounds__(kBlock) void batch_step(GridArgs g, BatchArgs ba,
                                                      const CollideArgs<typename Storage<S>::R>* __restrict__ args,
                                                      const int32_t* __restrict__ verdict,
@@ -52,11 +52,11 @@ __global__ __launch_bounds__(kBlock) void batch_step(GridArgs g, BatchArgs ba,
     const Nbr b = neighbours(g, local);  // offsets within the member's lattice
     const uint32_t n = base + local;
     R f[Q19];
-    gather19<S, false>(fin, g.stride, n, b, c, f);
+    gather19<S, false, WIDE>(fin, g.stride, n, b, c, f);
     const NodeMacro<R> mac = collide19<R>(f, c.F[0], c.F[1], c.F[2], c);
-    store19<S, false>(fout, g.stride, n, f);
+    store19<S, false, WIDE>(fout, g.stride, n, f);
     if constexpr (CHECK)
-      check_node<R>(g, usnap, n, mac.drho, mac.jx, mac.jy, mac.jz, mac.ux, mac.uy, mac.uz, acc);
+      check_node<R, WIDE>(g, usnap, n, mac.drho, mac.jx, mac.jy, mac.jz, mac.ux, mac.uy, mac.uz, acc);
   }
   if constexpr (CHECK) write_partials(partials, lb, acc);
 }
@@ -236,17 +236,20 @@ lbm_status batch_run(const lbm_grid* grid, int32_t storage, double rho0, int32_t
                           hipMemcpyHostToDevice, st), "status copy");
 
   const dim3 grid_dim(kXcd * g.blocks_per_xcd), check_dim((count + kBlock - 1) / kBlock);
+  const bool wide = wide_offsets(g, sizeof(R));
   int cur = 0;
   int64_t checks = 0;
   for (int64_t step = 1; step <= max_steps; ++step) {
     const bool check = step % check_every == 0;
-    if (check)
-      batch_step<S, true><<<grid_dim, kBlock, 0, st>>>(g, ba, dargs, dverdict, f[cur], f[cur ^ 1],
-                                                       usnap, partials);
-    else
-      batch_step<S, false><<<grid_dim, kBlock, 0, st>>>(g, ba, dargs, dverdict, f[cur], f[cur ^ 1],
-                                                        usnap, partials);
-    LBM_BHIP(hipGetLastError(), "batch step launch");
+    LBM_BHIP(with_flag(check, [&](auto CH) {
+               return with_flag(wide, [&](auto W) {
+                 batch_step<S, decltype(CH)::value, decltype(W)::value>
+                     <<<grid_dim, kBlock, 0, st>>>(g, ba, dargs, dverdict, f[cur], f[cur ^ 1], usnap,
+                                                   partials);
+                 return hipGetLastError();
+               });
+             }),
+             "batch step launch");
     if (check) {
       batch_check<<<check_dim, kBlock, 0, st>>>(ba, partials, checks, step, tol, dverdict, dvstep,
                                                 drmin, drlast);

@@ -18,7 +18,13 @@ namespace lbm {
 #define LBM_NT_LOAD 0
 #endif
 
-constexpr int kBlock = 256;   // threads per workgroup (4 wave64)
+// Build-time knob: LBM_BLOCK threads per workgroup (a multiple of 64).
+#ifndef LBM_BLOCK
+#define LBM_BLOCK 256
+#endif
+
+constexpr int kBlock = LBM_BLOCK;  // threads per workgroup (4 wave64 by default)
+static_assert(kBlock % 64 == 0 && kBlock <= 1024, "LBM_BLOCK must be a multiple of 64, at most 1024");
 constexpr int kXcd = 8;       // XCDs on MI355X; workgroups are dealt round-robin
 constexpr int kRecordDoubles = 8;
 constexpr int kPartials = 5;  // du2, u2, mass, flow, nonfinite

@@ -23,28 +23,26 @@ namespace lbm {
 // field's equilibrium, d_{a j} = g_{a j} - W_a B0_j (j outermost).  At a wall,
 // anti-bounce-back g_a = -g~_opp(a) + 2 W_a B0 (insulating wall, B = B0 there)
 // reads d_a = -d~_opp(a) in deviation form.
-template <typename R, int A>
+template <typename R, int A, bool WIDE>
 __device__ __forceinline__ void gather_g_dir(const R* __restrict__ gin, int64_t stride, uint32_t n,
                                              const Nbr& b, R (&g)[3][Q7]) {
   int32_t off;
   const bool bounce = pull_source<EX7[A], EY7[A], EZ7[A]>(b, off);
+  const uint32_t i = pull_offset<A>(bounce, off, n, static_cast<uint32_t>(stride));
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    const int64_t base = static_cast<int64_t>(j * Q7) * stride;
-    if (bounce) {
-      g[j][A] = -gin[base + static_cast<int64_t>(OPP7(A)) * stride + n];
-    } else {
-      g[j][A] = gin[base + static_cast<int64_t>(A) * stride + static_cast<int64_t>(n) + off];
-    }
+    const R* base = gin + static_cast<int64_t>(j * Q7 + pair_plane<A>()) * stride;
+    const R v = *elem<WIDE>(base, i);
+    g[j][A] = bounce ? -v : v;
   }
 }
 
-template <typename R, int A = 0>
+template <typename R, bool WIDE, int A = 0>
 __device__ __forceinline__ void gather_g(const R* __restrict__ gin, int64_t stride, uint32_t n,
                                          const Nbr& b, R (&g)[3][Q7]) {
   if constexpr (A < Q7) {
-    gather_g_dir<R, A>(gin, stride, n, b, g);
-    gather_g<R, A + 1>(gin, stride, n, b, g);
+    gather_g_dir<R, A, WIDE>(gin, stride, n, b, g);
+    gather_g<R, WIDE, A + 1>(gin, stride, n, b, g);
   }
 }
 
@@ -150,14 +148,14 @@ __device__ __forceinline__ void collide_g(R (&g)[3][Q7], const Coupled<R>& cp, R
   }
 }
 
-template <typename R>
+template <typename R, bool WIDE>
 __device__ __forceinline__ void load_force(const GridArgs& g, const CollideArgs<R>& c,
                                            const R* __restrict__ force, bool field, uint32_t n,
                                            R& Fx, R& Fy, R& Fz) {
   if (field) {
-    Fx = force[n];
-    Fy = force[g.stride + n];
-    Fz = force[2 * g.stride + n];
+    Fx = *elem<WIDE>(force, n);
+    Fy = *elem<WIDE>(force + g.stride, n);
+    Fz = *elem<WIDE>(force + 2 * g.stride, n);
   } else {
     Fx = c.F[0];
     Fy = c.F[1];
@@ -166,7 +164,7 @@ __device__ __forceinline__ void load_force(const GridArgs& g, const CollideArgs<
 }
 
 // ------------------------------------------------------------------ steps --
-template <typename S, bool CHECK, bool FIELD, bool NT, bool MOVING>
+template <typename S, bool CHECK, bool FIELD, bool NT, bool MOVING, bool WIDE>
 __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<typename Storage<S>::R> c,
                                                     const S* __restrict__ fin, S* __restrict__ fout,
                                                     const typename Storage<S>::R* __restrict__ force,
@@ -180,20 +178,20 @@ __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<type
   if (n < static_cast<uint32_t>(g.N)) {
     const Nbr b = neighbours(g, n);
     R f[Q19];
-    gather19<S, MOVING>(fin, g.stride, n, b, c, f);
+    gather19<S, MOVING, WIDE>(fin, g.stride, n, b, c, f);
     R Fx, Fy, Fz;
-    load_force<R>(g, c, force, FIELD, n, Fx, Fy, Fz);
+    load_force<R, WIDE>(g, c, force, FIELD, n, Fx, Fy, Fz);
     const NodeMacro<R> mac = collide19<R>(f, Fx, Fy, Fz, c);
-    store19<S, NT>(fout, g.stride, n, f);
+    store19<S, NT, WIDE>(fout, g.stride, n, f);
     if constexpr (CHECK)
-      check_node<R>(g, usnap, n, mac.drho, mac.jx, mac.jy, mac.jz, mac.ux, mac.uy, mac.uz, acc);
+      check_node<R, WIDE>(g, usnap, n, mac.drho, mac.jx, mac.jy, mac.jz, mac.ux, mac.uy, mac.uz, acc);
   }
   if constexpr (CHECK) write_partials(partials, lb, acc);
 }
 
 // EXT: the induction lattice extends beyond the fluid box; nodes outside it
 // relax g with u = 0 and leave f untouched.
-template <typename R, bool CHECK, bool FIELD, bool MOVING, bool EXT>
+template <typename R, bool CHECK, bool FIELD, bool MOVING, bool EXT, bool WIDE>
 __global__ __launch_bounds__(kBlock) void mhd_step(GridArgs g, CollideArgs<R> c, MagArgs<R> m,
                                                    const R* __restrict__ fin, R* __restrict__ fout,
                                                    const R* __restrict__ gin, R* __restrict__ gout,
@@ -208,21 +206,21 @@ __global__ __launch_bounds__(kBlock) void mhd_step(GridArgs g, CollideArgs<R> c,
     const Coord q = coords(g, n);
     const Nbr b = neighbours_at(g, q);
     R gg[3][Q7];
-    gather_g<R>(gin, g.stride, n, b, gg);
+    gather_g<R, WIDE>(gin, g.stride, n, b, gg);
     bool fluid = true;
     if constexpr (EXT) fluid = in_box(g, q);
     if (fluid) {
       const Nbr bf = EXT ? box_walls(g, q, b) : b;
       R f[Q19];
-      gather19<R, MOVING>(fin, g.stride, n, bf, c, f);
+      gather19<R, MOVING, WIDE>(fin, g.stride, n, bf, c, f);
       R Fx, Fy, Fz;
-      load_force<R>(g, c, force, FIELD, n, Fx, Fy, Fz);
+      load_force<R, WIDE>(g, c, force, FIELD, n, Fx, Fy, Fz);
       const Coupled<R> cp = lorentz_solve<R>(f, gg, Fx, Fy, Fz, c, m);
       const NodeMacro<R> mac = collide19<R>(f, cp.Fx, cp.Fy, cp.Fz, c);
       collide_g<R>(gg, cp, mac.ux, mac.uy, mac.uz, m);
-      store19<R>(fout, g.stride, n, f);
+      store19<R, false, WIDE>(fout, g.stride, n, f);
       if constexpr (CHECK)
-        check_node<R>(g, usnap, n, mac.drho, mac.jx, mac.jy, mac.jz, mac.ux, mac.uy, mac.uz, acc);
+        check_node<R, WIDE>(g, usnap, n, mac.drho, mac.jx, mac.jy, mac.jz, mac.ux, mac.uy, mac.uz, acc);
     } else {
       const Coupled<R> cp = field_only<R>(gg, m);
       collide_g<R>(gg, cp, R(0), R(0), R(0), m);
@@ -231,7 +229,7 @@ __global__ __launch_bounds__(kBlock) void mhd_step(GridArgs g, CollideArgs<R> c,
     for (int j = 0; j < 3; ++j)
 #pragma unroll
       for (int a = 0; a < Q7; ++a)
-        gout[static_cast<int64_t>(j * Q7 + a) * g.stride + n] = gg[j][a];
+        *elem<WIDE>(gout + static_cast<int64_t>(j * Q7 + a) * g.stride, n) = gg[j][a];
   }
   if constexpr (CHECK) write_partials(partials, lb, acc);
 }
@@ -256,7 +254,7 @@ __global__ __launch_bounds__(kBlock) void fields_kernel(
     if (MHD && !in_box(g, q)) {  // induction lattice outside the fluid box
       if constexpr (MHD) {
         R gg[3][Q7];
-        gather_g<R>(gin, g.stride, n, b, gg);
+        gather_g<R, true>(gin, g.stride, n, b, gg);
         const Coupled<R> cp = field_only<R>(gg, m);
         if (rho_out) rho_out[n] = static_cast<O>(c.rho0);
         if (u_out) {
@@ -273,13 +271,13 @@ __global__ __launch_bounds__(kBlock) void fields_kernel(
     } else {
       const Nbr bf = box_walls(g, q, b);
       R f[Q19];
-      gather19<S, true>(fin, g.stride, n, bf, c, f);
+      gather19<S, true, true>(fin, g.stride, n, bf, c, f);
       R Fx, Fy, Fz;
-      load_force<R>(g, c, force, field != 0, n, Fx, Fy, Fz);
+      load_force<R, true>(g, c, force, field != 0, n, Fx, Fy, Fz);
       R Bx = 0, By = 0, Bz = 0;
       if constexpr (MHD) {
         R gg[3][Q7];
-        gather_g<R>(gin, g.stride, n, b, gg);
+        gather_g<R, true>(gin, g.stride, n, b, gg);
         const Coupled<R> cp = lorentz_solve<R>(f, gg, Fx, Fy, Fz, c, m);
         Fx = cp.Fx;
         Fy = cp.Fy;
@@ -370,32 +368,21 @@ hipError_t launch_glbe_step(const GridArgs& g, const CollideArgs<typename Storag
   const S* a = static_cast<const S*>(fin);
   S* b = static_cast<S*>(fout);
   const R* F = static_cast<const R*>(force);
-#define LBM_STEP(CH, FL, NTS) \
-  glbe_step<S, CH, FL, NTS, false><<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials)
-#define LBM_STEP_MOVING(CH, FL) \
-  glbe_step<S, CH, FL, false, true><<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials)
-  if (c.moving) {  // moving walls: small problems, regular stores
-    if (check) {
-      if (field) LBM_STEP_MOVING(true, true); else LBM_STEP_MOVING(true, false);
-    } else {
-      if (field) LBM_STEP_MOVING(false, true); else LBM_STEP_MOVING(false, false);
-    }
-  } else if (nt) {
-    if (check) {
-      if (field) LBM_STEP(true, true, true); else LBM_STEP(true, false, true);
-    } else {
-      if (field) LBM_STEP(false, true, true); else LBM_STEP(false, false, true);
-    }
-  } else {
-    if (check) {
-      if (field) LBM_STEP(true, true, false); else LBM_STEP(true, false, false);
-    } else {
-      if (field) LBM_STEP(false, true, false); else LBM_STEP(false, false, false);
-    }
-  }
-#undef LBM_STEP
-#undef LBM_STEP_MOVING
-  return hipGetLastError();
+  // moving walls: small problems, regular stores
+  return with_flag(check, [&](auto CH) {
+    return with_flag(field, [&](auto FL) {
+      return with_flag(wide_offsets(g, sizeof(R)), [&](auto W) {
+        constexpr bool ch = decltype(CH)::value, fl = decltype(FL)::value, w = decltype(W)::value;
+        if (c.moving)
+          glbe_step<S, ch, fl, false, true, w><<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
+        else if (nt)
+          glbe_step<S, ch, fl, true, false, w><<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
+        else
+          glbe_step<S, ch, fl, false, false, w><<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
+        return hipGetLastError();
+      });
+    });
+  });
 }
 
 #define LBM_INST_STEP(S)                                                                          \
@@ -420,24 +407,20 @@ hipError_t launch_mhd_step(const GridArgs& g, const CollideArgs<R>& c, const Mag
   R* gb = static_cast<R*>(gout);
   const R* F = static_cast<const R*>(force);
   const bool ext = g.flo[0] > 0 || g.flo[1] > 0 || g.flo[2] > 0;
-#define LBM_MHD(CH, FL, MV, EX) \
-  mhd_step<R, CH, FL, MV, EX><<<step_grid(g), kBlock, 0, st>>>(g, c, m, a, b, ga, gb, F, usnap, partials)
-#define LBM_MHD_MV(CH, FL)                         \
-  if (ext) {                                       \
-    if (c.moving) LBM_MHD(CH, FL, true, true);     \
-    else LBM_MHD(CH, FL, false, true);             \
-  } else {                                         \
-    if (c.moving) LBM_MHD(CH, FL, true, false);    \
-    else LBM_MHD(CH, FL, false, false);            \
-  }
-  if (check) {
-    if (field) { LBM_MHD_MV(true, true); } else { LBM_MHD_MV(true, false); }
-  } else {
-    if (field) { LBM_MHD_MV(false, true); } else { LBM_MHD_MV(false, false); }
-  }
-#undef LBM_MHD_MV
-#undef LBM_MHD
-  return hipGetLastError();
+  return with_flag(check, [&](auto CH) {
+    return with_flag(field, [&](auto FL) {
+      return with_flag(c.moving != 0, [&](auto MV) {
+        return with_flag(ext, [&](auto EX) {
+          return with_flag(wide_offsets(g, sizeof(R)), [&](auto W) {
+            mhd_step<R, decltype(CH)::value, decltype(FL)::value, decltype(MV)::value,
+                     decltype(EX)::value, decltype(W)::value>
+                <<<step_grid(g), kBlock, 0, st>>>(g, c, m, a, b, ga, gb, F, usnap, partials);
+            return hipGetLastError();
+          });
+        });
+      });
+    });
+  });
 }
 
 template hipError_t launch_mhd_step<double>(const GridArgs&, const CollideArgs<double>&,

@@ -14,51 +14,52 @@
 
 namespace lbm {
 
-template <typename S, int A = 0>
+// Opposite directions are adjacent planes (pairs 1-2, 3-4, ...), as in 3D, so
+// the pull offsets are taken relative to each pair's lower plane.
+template <typename S, bool WIDE, int A = 0>
 __device__ __forceinline__ void gather9(const S* __restrict__ fin, int64_t stride, uint32_t n,
                                         const Nbr& b, typename Storage<S>::R (&f)[Q9]) {
   if constexpr (A < Q9) {
     int32_t off;
     const bool bounce = pull_source<EX9[A], EY9[A], 0>(b, off);
-    const int64_t idx = bounce ? static_cast<int64_t>(OPP9(A)) * stride + n
-                               : static_cast<int64_t>(A) * stride + static_cast<int64_t>(n) + off;
-    f[A] = Storage<S>::ld(fin + idx);
-    gather9<S, A + 1>(fin, stride, n, b, f);
+    const S* base = fin + static_cast<int64_t>(pair_plane<A>()) * stride;
+    f[A] = Storage<S>::ld(elem<WIDE>(base, pull_offset<A>(bounce, off, n, static_cast<uint32_t>(stride))));
+    gather9<S, WIDE, A + 1>(fin, stride, n, b, f);
   }
 }
 
-template <typename S, bool NT>
+template <typename S, bool NT, bool WIDE>
 __device__ __forceinline__ void store9(S* __restrict__ fout, int64_t stride, uint32_t n,
                                        const typename Storage<S>::R (&f)[Q9]) {
 #pragma unroll
   for (int a = 0; a < Q9; ++a)
-    Storage<S>::template st<NT>(fout + static_cast<int64_t>(a) * stride + n, f[a]);
+    Storage<S>::template st<NT>(elem<WIDE>(fout + static_cast<int64_t>(a) * stride, n), f[a]);
 }
 
 // Anti-bounce-back at a wall in deviation form: d_a = -d~_opp(a).
-template <typename R, int A = 0>
+template <typename R, bool WIDE, int A = 0>
 __device__ __forceinline__ void gather_g5(const R* __restrict__ gin, int64_t stride, uint32_t n,
                                           const Nbr& b, R (&g)[2][Q5]) {
   if constexpr (A < Q5) {
     int32_t off;
     const bool bounce = pull_source<EX5[A], EY5[A], 0>(b, off);
+    const uint32_t i = pull_offset<A>(bounce, off, n, static_cast<uint32_t>(stride));
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      const int64_t base = static_cast<int64_t>(j * Q5) * stride;
-      g[j][A] = bounce ? -gin[base + static_cast<int64_t>(OPP5(A)) * stride + n]
-                       : gin[base + static_cast<int64_t>(A) * stride + static_cast<int64_t>(n) + off];
+      const R v = *elem<WIDE>(gin + static_cast<int64_t>(j * Q5 + pair_plane<A>()) * stride, i);
+      g[j][A] = bounce ? -v : v;
     }
-    gather_g5<R, A + 1>(gin, stride, n, b, g);
+    gather_g5<R, WIDE, A + 1>(gin, stride, n, b, g);
   }
 }
 
-template <typename R>
+template <typename R, bool WIDE>
 __device__ __forceinline__ void load_force2(const GridArgs& g, const CollideArgs<R>& c,
                                             const R* __restrict__ force, bool field, uint32_t n,
                                             R& Fx, R& Fy) {
   if (field) {
-    Fx = force[n];
-    Fy = force[g.stride + n];
+    Fx = *elem<WIDE>(force, n);
+    Fy = *elem<WIDE>(force + g.stride, n);
   } else {
     Fx = c.F[0];
     Fy = c.F[1];
@@ -66,16 +67,16 @@ __device__ __forceinline__ void load_force2(const GridArgs& g, const CollideArgs
 }
 
 // FP64 residual bookkeeping of one node with a two-component velocity snapshot.
-template <typename R>
+template <typename R, bool WIDE>
 __device__ __forceinline__ void check_node2(const GridArgs& g, R* __restrict__ usnap, uint32_t n,
                                             const NodeMacro<R>& mac, double (&acc)[kPartials]) {
   const R ur[2] = {mac.ux, mac.uy};
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
-    const int64_t i = static_cast<int64_t>(k) * g.stride + n;
+    R* p = elem<WIDE>(usnap + static_cast<int64_t>(k) * g.stride, n);
     const double uk = static_cast<double>(ur[k]);
-    const double d = uk - static_cast<double>(usnap[i]);
-    usnap[i] = ur[k];
+    const double d = uk - static_cast<double>(*p);
+    *p = ur[k];
     acc[0] += d * d;
     acc[1] += uk * uk;
   }
@@ -145,7 +146,7 @@ __device__ __forceinline__ void collide_g5(R (&g)[2][Q5], const Coupled2<R>& cp,
   }
 }
 
-template <typename S, bool CHECK, bool FIELD, bool NT>
+template <typename S, bool CHECK, bool FIELD, bool NT, bool WIDE>
 __global__ __launch_bounds__(kBlock) void glbe2_step(GridArgs g, CollideArgs<typename Storage<S>::R> c,
                                                      const S* __restrict__ fin, S* __restrict__ fout,
                                                      const typename Storage<S>::R* __restrict__ force,
@@ -159,17 +160,17 @@ __global__ __launch_bounds__(kBlock) void glbe2_step(GridArgs g, CollideArgs<typ
   if (n < static_cast<uint32_t>(g.N)) {
     const Nbr b = neighbours(g, n);
     R f[Q9];
-    gather9<S>(fin, g.stride, n, b, f);
+    gather9<S, WIDE>(fin, g.stride, n, b, f);
     R Fx, Fy;
-    load_force2<R>(g, c, force, FIELD, n, Fx, Fy);
+    load_force2<R, WIDE>(g, c, force, FIELD, n, Fx, Fy);
     const NodeMacro<R> mac = collide9<R>(f, Fx, Fy, c);
-    store9<S, NT>(fout, g.stride, n, f);
-    if constexpr (CHECK) check_node2<R>(g, usnap, n, mac, acc);
+    store9<S, NT, WIDE>(fout, g.stride, n, f);
+    if constexpr (CHECK) check_node2<R, WIDE>(g, usnap, n, mac, acc);
   }
   if constexpr (CHECK) write_partials(partials, lb, acc);
 }
 
-template <typename R, bool CHECK, bool FIELD>
+template <typename R, bool CHECK, bool FIELD, bool WIDE>
 __global__ __launch_bounds__(kBlock) void mhd2_step(GridArgs g, CollideArgs<R> c, MagArgs<R> m,
                                                     const R* __restrict__ fin, R* __restrict__ fout,
                                                     const R* __restrict__ gin, R* __restrict__ gout,
@@ -183,21 +184,21 @@ __global__ __launch_bounds__(kBlock) void mhd2_step(GridArgs g, CollideArgs<R> c
   if (n < static_cast<uint32_t>(g.N)) {
     const Nbr b = neighbours(g, n);
     R f[Q9];
-    gather9<R>(fin, g.stride, n, b, f);
+    gather9<R, WIDE>(fin, g.stride, n, b, f);
     R gg[2][Q5];
-    gather_g5<R>(gin, g.stride, n, b, gg);
+    gather_g5<R, WIDE>(gin, g.stride, n, b, gg);
     R Fx, Fy;
-    load_force2<R>(g, c, force, FIELD, n, Fx, Fy);
+    load_force2<R, WIDE>(g, c, force, FIELD, n, Fx, Fy);
     const Coupled2<R> cp = lorentz_solve2<R>(f, gg, Fx, Fy, c, m);
     const NodeMacro<R> mac = collide9<R>(f, cp.Fx, cp.Fy, c);
     collide_g5<R>(gg, cp, mac.ux, mac.uy, m);
-    store9<R, false>(fout, g.stride, n, f);
+    store9<R, false, WIDE>(fout, g.stride, n, f);
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int a = 0; a < Q5; ++a)
-        gout[static_cast<int64_t>(j * Q5 + a) * g.stride + n] = gg[j][a];
-    if constexpr (CHECK) check_node2<R>(g, usnap, n, mac, acc);
+        *elem<WIDE>(gout + static_cast<int64_t>(j * Q5 + a) * g.stride, n) = gg[j][a];
+    if constexpr (CHECK) check_node2<R, WIDE>(g, usnap, n, mac, acc);
   }
   if constexpr (CHECK) write_partials(partials, lb, acc);
 }
@@ -218,13 +219,13 @@ __global__ __launch_bounds__(kBlock) void fields2_kernel(
   if (n < static_cast<uint32_t>(g.N)) {
     const Nbr b = neighbours(g, n);
     R f[Q9];
-    gather9<S>(fin, g.stride, n, b, f);
+    gather9<S, true>(fin, g.stride, n, b, f);
     R Fx, Fy;
-    load_force2<R>(g, c, force, field != 0, n, Fx, Fy);
+    load_force2<R, true>(g, c, force, field != 0, n, Fx, Fy);
     R Bx = 0, By = 0;
     if constexpr (MHD) {
       R gg[2][Q5];
-      gather_g5<R>(gin, g.stride, n, b, gg);
+      gather_g5<R, true>(gin, g.stride, n, b, gg);
       const Coupled2<R> cp = lorentz_solve2<R>(f, gg, Fx, Fy, c, m);
       Fx = cp.Fx;
       Fy = cp.Fy;
@@ -263,23 +264,17 @@ hipError_t launch_glbe2_step(const GridArgs& g, const CollideArgs<typename Stora
   const S* a = static_cast<const S*>(fin);
   S* b = static_cast<S*>(fout);
   const R* F = static_cast<const R*>(force);
-#define LBM_STEP2(CH, FL, NTS) \
-  glbe2_step<S, CH, FL, NTS><<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials)
-  if (nt) {
-    if (check) {
-      if (field) LBM_STEP2(true, true, true); else LBM_STEP2(true, false, true);
-    } else {
-      if (field) LBM_STEP2(false, true, true); else LBM_STEP2(false, false, true);
-    }
-  } else {
-    if (check) {
-      if (field) LBM_STEP2(true, true, false); else LBM_STEP2(true, false, false);
-    } else {
-      if (field) LBM_STEP2(false, true, false); else LBM_STEP2(false, false, false);
-    }
-  }
-#undef LBM_STEP2
-  return hipGetLastError();
+  return with_flag(check, [&](auto CH) {
+    return with_flag(field, [&](auto FL) {
+      return with_flag(nt, [&](auto NTS) {
+        return with_flag(wide_offsets(g, sizeof(R)), [&](auto W) {
+          glbe2_step<S, decltype(CH)::value, decltype(FL)::value, decltype(NTS)::value,
+                     decltype(W)::value><<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
+          return hipGetLastError();
+        });
+      });
+    });
+  });
 }
 
 #define LBM_INST_STEP2(S)                                                                         \
@@ -303,15 +298,15 @@ hipError_t launch_mhd2_step(const GridArgs& g, const CollideArgs<R>& c, const Ma
   const R* ga = static_cast<const R*>(gin);
   R* gb = static_cast<R*>(gout);
   const R* F = static_cast<const R*>(force);
-#define LBM_MHD2(CH, FL) \
-  mhd2_step<R, CH, FL><<<step_grid(g), kBlock, 0, st>>>(g, c, m, a, b, ga, gb, F, usnap, partials)
-  if (check) {
-    if (field) LBM_MHD2(true, true); else LBM_MHD2(true, false);
-  } else {
-    if (field) LBM_MHD2(false, true); else LBM_MHD2(false, false);
-  }
-#undef LBM_MHD2
-  return hipGetLastError();
+  return with_flag(check, [&](auto CH) {
+    return with_flag(field, [&](auto FL) {
+      return with_flag(wide_offsets(g, sizeof(R)), [&](auto W) {
+        mhd2_step<R, decltype(CH)::value, decltype(FL)::value, decltype(W)::value>
+            <<<step_grid(g), kBlock, 0, st>>>(g, c, m, a, b, ga, gb, F, usnap, partials);
+        return hipGetLastError();
+      });
+    });
+  });
 }
 
 template hipError_t launch_mhd2_step<double>(const GridArgs&, const CollideArgs<double>&,

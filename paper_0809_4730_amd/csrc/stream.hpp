@@ -5,6 +5,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace lbm {
@@ -12,6 +15,23 @@ namespace lbm {
 // Launched grid of a node kernel: kXcd * blocks_per_xcd workgroups (see
 // logical_block).
 inline dim3 step_grid(const GridArgs& g) { return dim3(kXcd * g.blocks_per_xcd); }
+
+// Call f with std::true_type or std::false_type: a run-time flag becomes a
+// template argument of the kernel f launches.
+template <typename F>
+inline hipError_t with_flag(bool b, F&& f) {
+  return b ? f(std::true_type{}) : f(std::false_type{});
+}
+
+// Whether a launch needs 64-bit element offsets: a kernel addresses at most
+// 2 * stride elements of `elem_bytes` from any of its base pointers.
+// LBM_WIDE_OFFSETS=1 in the environment forces the 64-bit form (read at each
+// launch, so that tests can run both forms on small lattices).
+inline bool wide_offsets(const GridArgs& g, size_t elem_bytes) {
+  const char* e = std::getenv("LBM_WIDE_OFFSETS");
+  if (e && e[0] == '1') return true;
+  return 2.0 * static_cast<double>(g.stride) * static_cast<double>(elem_bytes) >= 4294967296.0;
+}
 
 // Per-node neighbour offsets for pull streaming.
 struct Nbr {
@@ -97,57 +117,88 @@ __device__ __forceinline__ R wall_term(const Nbr& b, const CollideArgs<R>& c) {
   return cnt > 1 ? sum / R(cnt) : sum;
 }
 
+// Element i of an array reached from a launch-uniform base pointer.  Narrow
+// form (WIDE = false): the byte offset is formed in 32 bits, which the load and
+// store instructions take directly beside the scalar base; the host selects it
+// when every byte offset of the launch fits (2 * stride * element size < 2^32).
+template <bool WIDE, typename T>
+__device__ __forceinline__ T* elem(T* base, uint32_t i) {
+  if constexpr (WIDE) {
+    return base + i;
+  } else {
+    using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return reinterpret_cast<T*>(reinterpret_cast<B*>(base) + i * static_cast<uint32_t>(sizeof(T)));
+  }
+}
+
+// Where direction A of node n is pulled from, relative to the lower plane P of
+// A's opposite pair (opposites are adjacent planes): the shifted neighbour in
+// plane A, or node n itself in plane opp(A) when the link crosses a wall.  Both
+// offsets are below 2 * stride, so the choice is a 32-bit select.
+template <int A>
+__device__ __forceinline__ uint32_t pull_offset(bool bounce, int32_t off, uint32_t n,
+                                                uint32_t stride) {
+  constexpr bool lower = (A == 0) || (A & 1);
+  const uint32_t self = lower ? 0u : stride;
+  const uint32_t opp = lower ? stride : 0u;
+  return bounce ? opp + n : self + n + static_cast<uint32_t>(off);
+}
+
+template <int A>
+constexpr int pair_plane() {
+  return (A == 0 || (A & 1)) ? A : A - 1;
+}
+
 // MOVING = false compiles the wall-momentum term out (the plain step); with
 // MOVING = true it is added on bounced links when c.moving is set.
-template <typename S, int A, bool MOVING>
+template <typename S, int A, bool MOVING, bool WIDE>
 __device__ __forceinline__ typename Storage<S>::R gather_one(
     const S* __restrict__ fin, int64_t stride, uint32_t n, const Nbr& b,
     const CollideArgs<typename Storage<S>::R>& c) {
   using R = typename Storage<S>::R;
   int32_t off;
   const bool bounce = pull_source<EX19[A], EY19[A], EZ19[A]>(b, off);
-  const int64_t idx = bounce ? static_cast<int64_t>(OPP19(A)) * stride + n
-                             : static_cast<int64_t>(A) * stride + static_cast<int64_t>(n) + off;
-  R v = Storage<S>::ld(fin + idx);
+  const S* base = fin + static_cast<int64_t>(pair_plane<A>()) * stride;
+  R v = Storage<S>::ld(elem<WIDE>(base, pull_offset<A>(bounce, off, n, static_cast<uint32_t>(stride))));
   if constexpr (MOVING) {
     if (bounce && c.moving) v += wall_term<R, A>(b, c);
   }
   return v;
 }
 
-template <typename S, bool MOVING, int A = 0>
+template <typename S, bool MOVING, bool WIDE, int A = 0>
 __device__ __forceinline__ void gather19(const S* __restrict__ fin, int64_t stride, uint32_t n,
                                          const Nbr& b,
                                          const CollideArgs<typename Storage<S>::R>& c,
                                          typename Storage<S>::R (&f)[Q19]) {
   if constexpr (A < Q19) {
-    f[A] = gather_one<S, A, MOVING>(fin, stride, n, b, c);
-    gather19<S, MOVING, A + 1>(fin, stride, n, b, c, f);
+    f[A] = gather_one<S, A, MOVING, WIDE>(fin, stride, n, b, c);
+    gather19<S, MOVING, WIDE, A + 1>(fin, stride, n, b, c, f);
   }
 }
 
-template <typename S, bool NT = false>
+template <typename S, bool NT, bool WIDE>
 __device__ __forceinline__ void store19(S* __restrict__ fout, int64_t stride, uint32_t n,
                                         const typename Storage<S>::R (&f)[Q19]) {
 #pragma unroll
   for (int a = 0; a < Q19; ++a)
-    Storage<S>::template st<NT>(fout + static_cast<int64_t>(a) * stride + n, f[a]);
+    Storage<S>::template st<NT>(elem<WIDE>(fout + static_cast<int64_t>(a) * stride, n), f[a]);
 }
 
 // Residual / reduction bookkeeping of one node, accumulated in FP64.  The
 // velocity snapshot is kept in the compute type R: u is an R value, so the
 // FP64 difference of two snapshots is exact.
-template <typename R>
+template <typename R, bool WIDE>
 __device__ __forceinline__ void check_node(const GridArgs& g, R* __restrict__ usnap, uint32_t n,
                                            R drho, R jx, R jy, R jz, R ux, R uy, R uz,
                                            double (&acc)[kPartials]) {
   const R ur[3] = {ux, uy, uz};
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const int64_t i = static_cast<int64_t>(k) * g.stride + n;
+    R* p = elem<WIDE>(usnap + static_cast<int64_t>(k) * g.stride, n);
     const double uk = static_cast<double>(ur[k]);
-    const double d = uk - static_cast<double>(usnap[i]);
-    usnap[i] = ur[k];
+    const double d = uk - static_cast<double>(*p);
+    *p = ur[k];
     acc[0] += d * d;
     acc[1] += uk * uk;
   }

@@ -1,0 +1,122 @@
+"""Both addressing forms of every step kernel give bitwise identical results.
+
+The kernels address populations from a launch-uniform base pointer with either
+32-bit byte offsets (when every offset of the launch fits) or 64-bit ones
+(larger lattices).  LBM_WIDE_OFFSETS=1 forces the 64-bit form, so that it runs
+on the small lattices of these tests; only addressing differs, so states,
+residual histories and verdicts must agree bit for bit."""
+import numpy as np
+import pytest
+
+from oracle import d2q9, glbe
+from paper_0809_4730_amd import inputs
+from tests.gpu_util import announce
+
+pytestmark = pytest.mark.gpu
+PER, WALL = "periodic", "wall"
+
+
+def _both(monkeypatch, run):
+    monkeypatch.delenv("LBM_WIDE_OFFSETS", raising=False)
+    narrow = run()
+    monkeypatch.setenv("LBM_WIDE_OFFSETS", "1")
+    wide = run()
+    monkeypatch.delenv("LBM_WIDE_OFFSETS", raising=False)
+    return narrow, wide
+
+
+def _same(a, b):
+    import torch
+    if isinstance(a, (tuple, list)):
+        assert len(a) == len(b)
+        for x, y in zip(a, b):
+            _same(x, y)
+    elif torch.is_tensor(a):
+        assert torch.equal(a, b)
+    else:
+        assert np.array_equal(np.asarray(a), np.asarray(b))
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_d3q19_step_forms_agree(monkeypatch, storage):
+    import torch
+    import paper_0809_4730_amd as pkg
+    announce("wide vs narrow d3q19 %s" % storage)
+    shape, bc = (33, 6, 10), (PER, WALL, WALL)
+    dt = torch.float64 if storage == "f64" else torch.float32
+    F = torch.tensor(inputs.random_force(shape, seed=5, amp=1e-5), dtype=dt, device="cuda")
+
+    def run():
+        sim = pkg.Simulation(shape, bc, 0.2, glbe.rates(0.05, 0.2), storage=storage, force=F)
+        sim.step(47)
+        return sim.get_state(), sim.history(16)
+    _same(*_both(monkeypatch, run))
+
+
+def test_moving_wall_and_extended_mhd_forms_agree(monkeypatch):
+    import paper_0809_4730_amd as pkg
+    announce("wide vs narrow moving wall + extended mhd")
+    wall_u = np.zeros((6, 3))
+    wall_u[5] = (0.02, 0.0, 0.0)
+
+    def run_flow():
+        sim = pkg.Simulation((9, 8, 7), (WALL, WALL, WALL), 0.3, glbe.rates(0.05, 0.3),
+                             storage="f32", wall_u=wall_u)
+        sim.step(31)
+        return sim.get_state(), sim.history(8)
+
+    def run_mhd():
+        sim = pkg.Simulation((12, 10, 9), (WALL, WALL, WALL), 0.3, glbe.rates(0.05, 0.3),
+                             storage="f64", wall_u=wall_u,
+                             mhd=dict(gamma_m=0.3, chi=0.05, eta=0.03, B0=(0.0, 0.02, 0.0),
+                                      pad=(2, 2, 1)))
+        sim.step(31)
+        return sim.get_state(), sim.history(8)
+    _same(*_both(monkeypatch, run_flow))
+    _same(*_both(monkeypatch, run_mhd))
+
+
+def test_d2q9_forms_agree(monkeypatch):
+    import torch
+    import paper_0809_4730_amd as pkg
+    announce("wide vs narrow d2q9 / d2q5")
+
+    def run_flow():
+        sim = pkg.Simulation((35, 12, 1), (PER, WALL, PER), 0.2, d2q9.rates(0.05, 0.2),
+                             storage="f32", force=(1e-5, 0.0), lattice="d2q9")
+        sim.step(41)
+        return sim.get_state(), sim.history(8)
+
+    def run_mhd():
+        sim = pkg.Simulation((10, 12, 1), (PER, WALL, PER), 0.2, d2q9.rates(0.05, 0.2),
+                             storage="f64", force=(1e-5, 0.0), lattice="d2q9",
+                             mhd=dict(gamma_m=0.3, chi=0.05, eta=0.02, B0=(0.0, 0.03)))
+        sim.step(41)
+        return sim.get_state(), sim.history(8)
+    _same(*_both(monkeypatch, run_flow))
+    _same(*_both(monkeypatch, run_mhd))
+
+
+def test_batch_forms_agree(monkeypatch):
+    from paper_0809_4730_amd import stability
+    announce("wide vs narrow batch")
+    pts = [(0.02, 0.05, 1.0), (0.02, 0.05, 1e-3), (0.1, 0.02, 0.3)]
+    narrow, wide = _both(monkeypatch, lambda: stability.march_batch(pts, max_steps=2000))
+    assert narrow == wide
+
+
+def test_adjoint_forms_agree(monkeypatch):
+    import torch
+    import paper_0809_4730_amd as pkg
+    announce("wide vs narrow adjoint")
+    shape, bc = (6, 8, 8), (PER, WALL, WALL)
+    F = torch.tensor(inputs.duct_force(shape, 1e-5), dtype=torch.float64, device="cuda")
+
+    def run():
+        sim = pkg.Simulation(shape, bc, 0.5, glbe.rates(0.131, 0.5), storage="f64", force=F)
+        sim.run_to_residual(1e-10, 20000, poll_every=500)
+        g_s, it, ch = sim.adjoint_steady(tol=1e-8, max_iter=20000)
+        sim2 = pkg.Simulation(shape, bc, 0.5, glbe.rates(0.131, 0.5), storage="f64", force=F)
+        g_u = sim2.adjoint_unrolled(60, 7)
+        return g_s, it, g_u
+    _same(*_both(monkeypatch, run))
