@@ -61,7 +61,7 @@ typedef enum {
   LBM_EHIP = -3,       /* a HIP runtime call failed (hipGetErrorString text kept) */
   LBM_EUNSTABLE = -4,  /* non-finite values or residual blow-up detected          */
   LBM_ESTATE = -5,     /* call not valid in the context's current state           */
-  LBM_EUNSUPPORTED = -6 /* valid request this build does not implement            */
+  LBM_EUNSUPPORTED = -6 /* valid request the library does not implement          */
 } lbm_status;
 
 /* Population storage type.  F64 storage computes in FP64; F32, BF16 and F16
