@@ -243,6 +243,19 @@ def extras(args):
     out["hartmann_mhd_step"] = {"shape": cfg["shape"], "MLUPS": round(mlups, 1),
                                 "kernel_us": round(us, 2), "alg_bytes_per_node": bpn,
                                 "achieved_GBs": round(bpn * sim.N / (us * 1e-6) / 1e9, 1)}
+    del sim
+    # the coupled step at HBM scale: 256^3, FP32, walls normal to B0, plain kernel
+    big = pkg.Simulation((256, 256, 256), cfg["bc"], 0.1, pkg.default_rates(cfg["nu"], 0.1),
+                         storage="f32", force=cfg["F"], check_every=NO_CHECK, mhd=mp)
+    us = kernel_time_us(big, 30, warmup=5)
+    bpn = 2 * (19 + 21) * 4
+    out["mhd_step_256"] = {"kernel_us": round(us, 2), "kernel_MLUPS": round(big.N / us, 1),
+                           "alg_bytes_per_node": bpn,
+                           "achieved_GBs": round(bpn * big.N / (us * 1e-6) / 1e9, 1),
+                           "frac_hbm": round(bpn * big.N / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+    big.close()
+    del big
+    torch.cuda.empty_cache()
     ttm = []
     for g, gm in ((1.0, 1.0), (0.1, 0.1), (0.1, 1.0), (1.0, 0.1), (0.1, 0.3), (0.3, 0.1)):
         e = time_to_residual(None, "f32", g, 2e-7, 400000, make=lambda g=g, gm=gm: hart(g, gm))

@@ -59,7 +59,7 @@ __device__ __forceinline__ void gather_transpose(const R* __restrict__ mu, int64
 // GRAD: 0 none; 1 accumulate into grad; 3 write half the gradient (with the
 // direct term) into gpre; 2 (check) grad = half the gradient + gpre, and
 // accumulate the change against the previous content of grad.
-template <typename R, bool CHECK, int GRAD, bool FIELD, bool WIDE>
+template <typename R, bool CHECK, int GRAD, bool FIELD, bool WIDE, bool NT>
 __global__ __launch_bounds__(kBlock) void adjoint_step(
     GridArgs g, CollideArgs<R> c, const R* __restrict__ state, const R* __restrict__ force,
     const R* __restrict__ mu_in, R* __restrict__ mu_out, R* __restrict__ grad,
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_step(
 #pragma unroll
     for (int a = 0; a < Q19; ++a) {
       const R v = nu[a] + q_scale * R(EX19[a]);
-      *elem<WIDE>(mu_out + int64_t(a) * g.stride, n) = v;
+      Storage<R>::template st<NT>(elem<WIDE>(mu_out + int64_t(a) * g.stride, n), v);
       if (CHECK) acc[2] += static_cast<double>(v);
     }
     if constexpr (GRAD == 1) {
@@ -181,7 +181,7 @@ template <typename R>
 hipError_t launch_adjoint(const GridArgs& g, const CollideArgs<R>& c, const void* state,
                           const void* force, bool field, const void* mu_in, void* mu_out,
                           void* grad, void* gpre, int64_t grad_stride, int grad_mode,
-                          const double* shift, R q_scale, R grad_direct, bool check,
+                          const double* shift, R q_scale, R grad_direct, bool check, bool nt,
                           double* partials, hipStream_t st) {
   const dim3 grid(kXcd * g.blocks_per_xcd);
   const R* s = static_cast<const R*>(state);
@@ -194,25 +194,27 @@ hipError_t launch_adjoint(const GridArgs& g, const CollideArgs<R>& c, const void
   const int gm = check ? 2 : grad_mode;
   return with_flag(field, [&](auto FL) {
     return with_flag(wide_offsets(g, sizeof(R)), [&](auto W) {
-      constexpr bool fl = decltype(FL)::value, w = decltype(W)::value;
+     return with_flag(nt, [&](auto NTS) {
+      constexpr bool fl = decltype(FL)::value, w = decltype(W)::value, ns = decltype(NTS)::value;
       switch (gm) {
         case 2:
-          adjoint_step<R, true, 2, fl, w><<<grid, kBlock, 0, st>>>(g, c, s, F, mi, mo, gr, gp, grad_stride,
+          adjoint_step<R, true, 2, fl, w, ns><<<grid, kBlock, 0, st>>>(g, c, s, F, mi, mo, gr, gp, grad_stride,
                                                                    shift, q_scale, grad_direct, partials);
           break;
         case 3:
-          adjoint_step<R, false, 3, fl, w><<<grid, kBlock, 0, st>>>(g, c, s, F, mi, mo, gr, gp, grad_stride,
+          adjoint_step<R, false, 3, fl, w, ns><<<grid, kBlock, 0, st>>>(g, c, s, F, mi, mo, gr, gp, grad_stride,
                                                                     shift, q_scale, grad_direct, partials);
           break;
         case 1:
-          adjoint_step<R, false, 1, fl, w><<<grid, kBlock, 0, st>>>(g, c, s, F, mi, mo, gr, gp, grad_stride,
+          adjoint_step<R, false, 1, fl, w, ns><<<grid, kBlock, 0, st>>>(g, c, s, F, mi, mo, gr, gp, grad_stride,
                                                                     shift, q_scale, grad_direct, partials);
           break;
         default:
-          adjoint_step<R, false, 0, fl, w><<<grid, kBlock, 0, st>>>(g, c, s, F, mi, mo, gr, gp, grad_stride,
+          adjoint_step<R, false, 0, fl, w, ns><<<grid, kBlock, 0, st>>>(g, c, s, F, mi, mo, gr, gp, grad_stride,
                                                                     shift, q_scale, grad_direct, partials);
       }
       return hipGetLastError();
+     });
     });
   });
 }
@@ -305,7 +307,7 @@ lbm_status steady_impl(lbm_ctx* c, char* ws, double tol, int64_t max_iter, void*
     const double* sh = prev_check ? shift : nullptr;
     LBM_HIP(c, launch_adjoint<R>(c->ga, cargs<R>(c), c->f(c->cur), c->force(), c->field(),
                                  mu[cur], mu[cur ^ 1], dQdF, gpre, N, check ? 2 : (pre ? 3 : 0),
-                                 sh, q, direct, check, partials, c->stream),
+                                 sh, q, direct, check, c->nt_store, partials, c->stream),
             "adjoint launch");
     cur ^= 1;
     done = it;
@@ -385,7 +387,7 @@ lbm_status unrolled_impl(lbm_ctx* c, char* ws, int64_t n_steps, int64_t K, void*
     for (int64_t n = e; n >= s0 + 1; --n) {
       LBM_HIP(c, launch_adjoint<R>(c->ga, cargs<R>(c), seg + size_t(n - 1 - s0) * state_bytes,
                                    c->force(), c->field(), mu[cur], mu[cur ^ 1], dQdF, nullptr, N,
-                                   1, nullptr, R(0), R(0), false, nullptr, c->stream),
+                                   1, nullptr, R(0), R(0), false, c->nt_store, nullptr, c->stream),
               "adjoint launch");
       cur ^= 1;
     }
@@ -398,12 +400,12 @@ lbm_status unrolled_impl(lbm_ctx* c, char* ws, int64_t n_steps, int64_t K, void*
 
 template hipError_t launch_adjoint<double>(const GridArgs&, const CollideArgs<double>&, const void*,
                                            const void*, bool, const void*, void*, void*, void*,
-                                           int64_t, int, const double*, double, double, bool,
+                                           int64_t, int, const double*, double, double, bool, bool,
                                            double*, hipStream_t);
 template hipError_t launch_adjoint<float>(const GridArgs&, const CollideArgs<float>&, const void*,
                                           const void*, bool, const void*, void*, void*, void*,
-                                          int64_t, int, const double*, float, float, bool, double*,
-                                          hipStream_t);
+                                          int64_t, int, const double*, float, float, bool, bool,
+                                          double*, hipStream_t);
 
 }  // namespace lbm
 

@@ -60,7 +60,7 @@ template <typename R>
 hipError_t launch_adjoint(const GridArgs& g, const CollideArgs<R>& c, const void* state,
                           const void* force, bool field, const void* mu_in, void* mu_out,
                           void* grad, void* gpre, int64_t grad_stride, int grad_mode,
-                          const double* shift, R q_scale, R grad_direct, bool check,
+                          const double* shift, R q_scale, R grad_direct, bool check, bool nt,
                           double* partials, hipStream_t st);
 
 }  // namespace lbm
