@@ -459,3 +459,74 @@ class Simulation:
                                                int(ckpt_every), grad.data_ptr()))
         del raw
         return grad
+
+
+# ------------------------------------------------------------- autograd ----
+def _autograd():
+    torch = _torch()
+
+    class SteadyFlowRate(torch.autograd.Function):
+        """Q(F): steady flow rate (1/nx) sum j_x for the force field F
+        (3, nz, ny, nx); the backward pass is the steady adjoint."""
+
+        @staticmethod
+        def forward(ctx, F, cfg):
+            shape, bc, gamma, s, storage, tol, max_steps, adj_tol = cfg
+            sim = Simulation(shape, bc, gamma, s, storage=storage, force=F.detach().contiguous())
+            steps, r = sim.run_to_residual(tol, max_steps)
+            if steps < 0:
+                sim.close()
+                raise RuntimeError("steady state not reached in %d steps (residual %g)"
+                                   % (max_steps, r))
+            _, q = sim.reductions()
+            ctx.sim, ctx.adj_tol = sim, adj_tol
+            return torch.tensor(q, dtype=torch.float64, device=F.device)
+
+        @staticmethod
+        def backward(ctx, gq):
+            grad, _, _ = ctx.sim.adjoint_steady(tol=ctx.adj_tol)
+            ctx.sim.close()
+            return (gq.to(grad.dtype) * grad), None
+
+    class UnrolledFlowRate(torch.autograd.Function):
+        """Q_N(F): flow rate after n_steps from rest; the backward pass is the
+        checkpointed adjoint of the march."""
+
+        @staticmethod
+        def forward(ctx, F, cfg):
+            shape, bc, gamma, s, storage, n_steps, ckpt_every = cfg
+            Fc = F.detach().contiguous()
+            sim = Simulation(shape, bc, gamma, s, storage=storage, force=Fc)
+            sim.step(n_steps)
+            _, q = sim.reductions()
+            sim.close()
+            ctx.cfg, ctx.F = cfg, Fc
+            return torch.tensor(q, dtype=torch.float64, device=F.device)
+
+        @staticmethod
+        def backward(ctx, gq):
+            shape, bc, gamma, s, storage, n_steps, ckpt_every = ctx.cfg
+            sim = Simulation(shape, bc, gamma, s, storage=storage, force=ctx.F)
+            grad = sim.adjoint_unrolled(n_steps, ckpt_every)
+            sim.close()
+            return (gq.to(grad.dtype) * grad), None
+
+    return SteadyFlowRate, UnrolledFlowRate
+
+
+def steady_flow_rate(F, shape, bc, gamma, s, storage="f32", tol=1e-8, max_steps=10 ** 6,
+                     adj_tol=1e-7):
+    """Differentiable steady flow rate Q(F) (torch.autograd): F is a device tensor
+    (3, nz, ny, nx) in the compute dtype; the gradient comes from the library's
+    steady adjoint (lbm_adjoint_steady)."""
+    SteadyFlowRate, _ = _autograd()
+    return SteadyFlowRate.apply(F, (tuple(shape), tuple(bc), gamma, tuple(s), storage, tol,
+                                    max_steps, adj_tol))
+
+
+def unrolled_flow_rate(F, shape, bc, gamma, s, n_steps, ckpt_every, storage="f32"):
+    """Differentiable flow rate after n_steps from rest (torch.autograd); the
+    gradient comes from the checkpointed adjoint (lbm_adjoint_unrolled)."""
+    _, UnrolledFlowRate = _autograd()
+    return UnrolledFlowRate.apply(F, (tuple(shape), tuple(bc), gamma, tuple(s), storage,
+                                      int(n_steps), int(ckpt_every)))

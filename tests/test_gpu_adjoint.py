@@ -152,3 +152,33 @@ def test_unrolled_adjoint_32cubed_2000_steps_vs_fd():
     assert abs(d64 - fd) < 1e-8 * abs(fd), (d64, fd)
     assert abs(d32 - d64) < 1e-4 * abs(d64), (d32, d64)
     assert rel(g32, g64) < 1e-4
+
+
+def test_autograd_flow_rate_matches_finite_differences():
+    """torch.autograd over the library: Q(F) for the steady state and after a
+    finite march; F.grad along a direction against central differences of Q."""
+    import torch
+    import paper_0809_4730_amd as pkg
+    shape, bc, gamma = (6, 8, 8), ("periodic", "wall", "wall"), 0.5
+    s = glbe.rates(0.131, gamma)
+    F0 = torch.tensor(inputs.duct_force(shape, 1e-5), dtype=torch.float64, device="cuda")
+    v = torch.tensor(inputs.random_force(shape, seed=9, amp=1e-5), dtype=torch.float64,
+                     device="cuda")
+    eps = 1e-2
+
+    def steady(F):
+        return pkg.steady_flow_rate(F, shape, bc, gamma, s, storage="f64", tol=1e-13,
+                                    max_steps=200000, adj_tol=1e-11)
+
+    def unrolled(F):
+        return pkg.unrolled_flow_rate(F, shape, bc, gamma, s, 80, 9, storage="f64")
+
+    for fn in (steady, unrolled):
+        F = F0.clone().requires_grad_(True)
+        q = fn(F)
+        q.backward()
+        d = float((F.grad * v).sum())
+        with torch.no_grad():
+            fd = (float(fn(F0 + eps * v)) - float(fn(F0 - eps * v))) / (2 * eps)
+        announce("autograd %s: <dQ/dF, v> %.6e fd %.6e" % (fn.__name__, d, fd))
+        assert abs(d - fd) < 1e-6 * abs(fd), (d, fd)
