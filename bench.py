@@ -190,7 +190,7 @@ def extras(args):
     out = {}
     # time to residual 1e-8 on the 64^3 duct: gamma sweep vs plain gamma = 1 (FP64 and FP32)
     tt = []
-    for g in (1.0, 0.5, 0.1, 0.05):
+    for g in (1.0, 0.5, 0.1, 0.05, 0.02, 0.01):
         tt.append(time_to_residual((64, 64, 64), "f64", g, 1e-8, 400000))
     for g in (1.0, 0.5, 0.1, 0.05):
         e = time_to_residual((64, 64, 64), "f32", g, 1e-7, 400000)
@@ -371,6 +371,32 @@ def cavity_extras():
         mlups, wall = timed_region(sim, 500, 50)
         out[name] = {"time_to_residual_tol1e-6": rows, "lattice_nodes": sim.N,
                      "us_per_step": round(1e6 * wall / 500, 2), "MLUPS": round(mlups, 1)}
+    # stability of the SRT limit (all rates equal to the shear rate, Sec. 3.1)
+    # against the paper's MRT rates on the same cavity, without and with the
+    # Ha = 45 field (gamma_m = gamma), at gamma = 1 and 0.1
+    srt = []
+    for field in (False, True):
+        for g in (1.0, 0.1):
+            for v in ((0.015, 0.05, 0.166) if not field else (0.015, 0.166)):
+                for form in ("mrt", "srt"):
+                    r = pkg.default_rates(v, g)
+                    if form == "srt":
+                        r = np.full(19, r[9])
+
+                    def mk(r=r, g=g, v=v, field=field):
+                        if not field:
+                            return pkg.Simulation((W, W, W), walls, g, r, storage="f32",
+                                                  wall_u=wall_u)
+                        Bv, cv = inputs.cavity_field(c["Ha"], c["Pm"], W, v, c["eta"])
+                        return pkg.Simulation((n, n, n), walls, g, r, storage="f32",
+                                              wall_u=wall_u,
+                                              mhd=dict(gamma_m=g, chi=cv, eta=c["eta"],
+                                                       B0=(0.0, Bv, 0.0), pad=(pad, pad, pad)))
+                    e = time_to_residual(None, "f32", g, c["tol"], 60000, make=mk)
+                    srt.append({"field": "Ha45" if field else "none", "gamma": g, "nu": v,
+                                "rates": form, "status": e["status"][:60], "steps": e["steps"],
+                                "steps_run": e["steps_run"]})
+    out["cavity64_srt_vs_mrt"] = srt
     return out
 
 
