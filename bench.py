@@ -181,6 +181,28 @@ def time_to_residual(shape, storage, gamma, tol, max_steps, make=None, poll=200,
             "final_residual": r, "min_residual_seen": floor, "status": status, "steps_run": sim.t}
 
 
+def time_to_residual_mixed(shape, gamma, tol, switch_tol, max_steps, poll=200):
+    """Wall time to tol marching FP32 storage until switch_tol, then continuing
+    the same state in FP64 storage (lbm_convert_state); both simulations are
+    built before the clock starts."""
+    import torch
+
+    import paper_0809_4730_amd as pkg
+    lo, hi = make_sim(shape, "f32", gamma), make_sim(shape, "f64", gamma)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    try:
+        steps, r = pkg.run_to_residual_mixed(lo, hi, tol, switch_tol, max_steps, poll)
+        status = "ok" if steps > 0 else "not reached"
+    except Exception as e:  # unstable
+        steps, r, status = -1, float("nan"), "error: %s" % e
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return {"gamma": gamma, "storage": "f32 then f64", "switch_at": switch_tol,
+            "f32_steps": lo.t, "steps": int(steps), "wall_s": round(wall, 4),
+            "final_residual": r, "status": status}
+
+
 def extras(args):
     import numpy as np
     import torch
@@ -197,6 +219,12 @@ def extras(args):
         e["note"] = "FP32 storage stalls near 6e-8 at this Mach number; tol 1e-7"
         tt.append(e)
     out["time_to_residual_duct64"] = tt
+    # the same to 1e-8 marching FP32 until 1e-6, then the same state in FP64
+    tm = [time_to_residual_mixed((64, 64, 64), g, 1e-8, 1e-6, 400000) for g in (1.0, 0.5, 0.1, 0.05)]
+    for e in tm:
+        if tt[0]["steps"] > 0 and e["steps"] > 0:
+            e["speedup_vs_f64_gamma1_wall"] = round(tt[0]["wall_s"] / e["wall_s"], 3)
+    out["time_to_residual_duct64_mixed_f32_f64"] = tm
     # plane Poiseuille 8x8x32 (uniform force) to 1e-10, FP64
     pc = inputs.POISEUILLE
 

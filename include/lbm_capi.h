@@ -246,6 +246,14 @@ lbm_status lbm_state_bytes(const lbm_ctx* ctx, size_t* bytes);
  * mag_pad, f outside the fluid box keeps the values last set here (zero
  * deviations after lbm_create). */
 lbm_status lbm_get_state(lbm_ctx* ctx, void* dst);
+/* Continue src's march in dst's precision: dst's state becomes src's current
+ * state converted to dst's storage type on the device (through FP64; rounding
+ * to nearest even when narrowing), its step counter becomes src's, and its
+ * residual snapshot and history are cleared as by lbm_set_state.  Both contexts
+ * need the same grid, boundaries, lattice, rho0, mhd, B0 and mag_pad.  Enqueued
+ * on dst's stream after the work already enqueued on src's stream.  Errors:
+ * LBM_EINVAL (mismatch), LBM_EHIP. */
+lbm_status lbm_convert_state(lbm_ctx* dst, const lbm_ctx* src);
 lbm_status lbm_set_state(lbm_ctx* ctx, const void* src, int64_t step);
 lbm_status lbm_get_step(const lbm_ctx* ctx, int64_t* step);
 

@@ -119,6 +119,7 @@ def load_library():
         "lbm_get_state": [c_void_p, c_void_p],
         "lbm_set_state": [c_void_p, c_void_p, c_int64],
         "lbm_get_step": [c_void_p, P(c_int64)],
+        "lbm_convert_state": [c_void_p, c_void_p],
         "lbm_adjoint_workspace_bytes": [c_void_p, c_int32, c_int64, c_int64, P(c_size_t)],
         "lbm_adjoint_steady": [c_void_p, c_void_p, c_size_t, c_double, c_int64, c_void_p,
                                P(c_int64), P(c_double)],
@@ -424,6 +425,11 @@ class Simulation:
             raise ValueError("state dtype must be %s" % _state_torch_dtype(self.storage))
         self._c(self._lib.lbm_set_state(self._ctx, f.data_ptr(), int(step)))
 
+    def convert_from(self, other):
+        """Continue `other`'s march here: its current state converted to this
+        simulation's storage type (lbm_convert_state), with its step counter."""
+        self._c(self._lib.lbm_convert_state(self._ctx, other._ctx))
+
     # ----------------------------------------------------------- adjoint
     def _adj_ws(self, mode, n_steps=0, ckpt_every=1):
         torch = _torch()
@@ -459,6 +465,17 @@ class Simulation:
                                                int(ckpt_every), grad.data_ptr()))
         del raw
         return grad
+
+
+def run_to_residual_mixed(lo, hi, tol, switch_tol, max_steps, poll_every=200):
+    """March `lo` (cheaper storage, e.g. FP32) until its residual falls below
+    switch_tol, continue the same state in `hi` (e.g. FP64: lbm_convert_state)
+    and march it to tol.  Both must describe the same lattice, force and
+    parameters.  Returns (steps to tol or -1, final residual); the step count is
+    the total over both."""
+    n_lo, _ = lo.run_to_residual(switch_tol, max_steps, poll_every)
+    hi.convert_from(lo)
+    return hi.run_to_residual(tol, max_steps, poll_every)
 
 
 # ------------------------------------------------------------- autograd ----

@@ -358,6 +358,47 @@ __global__ __launch_bounds__(kBlock) void fill_zero_f64(double* __restrict__ p, 
   if (i < count) p[i] = 0.0;
 }
 
+// ------------------------------------------------------------- convert --
+// planes x N values from one storage type to another (through FP64): the state
+// of one context continued in another precision.
+template <typename Ss, typename Sd>
+__global__ __launch_bounds__(kBlock) void convert_planes(const Ss* __restrict__ src,
+                                                         Sd* __restrict__ dst, int64_t stride,
+                                                         int64_t N, int planes) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= N) return;
+  using Rd = typename Storage<Sd>::R;
+  for (int a = 0; a < planes; ++a) {
+    const double v = static_cast<double>(Storage<Ss>::ld(src + a * stride + i));
+    Storage<Sd>::st(dst + a * stride + i, static_cast<Rd>(v));
+  }
+}
+
+template <typename Ss>
+hipError_t launch_convert_to(int dst_storage, const void* src, void* dst, int64_t stride,
+                             int64_t N, int planes, hipStream_t st) {
+  const dim3 grid(static_cast<unsigned>((N + kBlock - 1) / kBlock));
+  const Ss* s = static_cast<const Ss*>(src);
+  switch (dst_storage) {
+    case 0: convert_planes<Ss, double><<<grid, kBlock, 0, st>>>(s, static_cast<double*>(dst), stride, N, planes); break;
+    case 1: convert_planes<Ss, float><<<grid, kBlock, 0, st>>>(s, static_cast<float*>(dst), stride, N, planes); break;
+    case 2: convert_planes<Ss, bf16_t><<<grid, kBlock, 0, st>>>(s, static_cast<bf16_t*>(dst), stride, N, planes); break;
+    default: convert_planes<Ss, _Float16><<<grid, kBlock, 0, st>>>(s, static_cast<_Float16*>(dst), stride, N, planes);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_convert(int src_storage, int dst_storage, const void* src, void* dst,
+                          int64_t stride, int64_t N, int planes, hipStream_t st) {
+  if (N <= 0 || planes <= 0) return hipSuccess;
+  switch (src_storage) {
+    case 0: return launch_convert_to<double>(dst_storage, src, dst, stride, N, planes, st);
+    case 1: return launch_convert_to<float>(dst_storage, src, dst, stride, N, planes, st);
+    case 2: return launch_convert_to<bf16_t>(dst_storage, src, dst, stride, N, planes, st);
+    default: return launch_convert_to<_Float16>(dst_storage, src, dst, stride, N, planes, st);
+  }
+}
+
 // ------------------------------------------------------------- launchers --
 template <typename S>
 hipError_t launch_glbe_step(const GridArgs& g, const CollideArgs<typename Storage<S>::R>& c,

@@ -53,6 +53,11 @@ hipError_t launch_finalize(const double* partials, int nblocks, int pslots, int6
 template <typename S>
 hipError_t launch_fill_zero(void* p, int64_t count, hipStream_t st);
 
+// planes x N values (plane stride `stride`) from src to dst, converting between
+// storage types (lbm_dtype codes 0..3).
+hipError_t launch_convert(int src_storage, int dst_storage, const void* src, void* dst,
+                          int64_t stride, int64_t N, int planes, hipStream_t st);
+
 
 // ---------------------------------------------------------------- adjoint --
 // One transposed step of the linearised map (adjoint.hip).

@@ -668,6 +668,48 @@ lbm_status lbm_set_state(lbm_ctx* c, const void* src, int64_t step) {
   return LBM_OK;
 }
 
+lbm_status lbm_convert_state(lbm_ctx* d, const lbm_ctx* s) {
+  if (!d || !s) return fail(d, LBM_EINVAL, "ctx is NULL");
+  for (int a = 0; a < 3; ++a)
+    if (d->grid.n[a] != s->grid.n[a] || d->grid.bc[a] != s->grid.bc[a] ||
+        d->p.mag_pad[a] != s->p.mag_pad[a])
+      return fail(d, LBM_EINVAL, "contexts differ in grid, boundaries or mag_pad");
+  if (d->p.lattice != s->p.lattice || d->p.mhd != s->p.mhd || d->p.rho0 != s->p.rho0)
+    return fail(d, LBM_EINVAL, "contexts differ in lattice, mhd or rho0");
+  if (d->p.mhd)
+    for (int a = 0; a < 3; ++a)
+      if (d->p.B0[a] != s->p.B0[a]) return fail(d, LBM_EINVAL, "contexts differ in B0");
+  // dst's stream waits for the work already enqueued on src's stream
+  if (s->stream != d->stream) {
+    hipEvent_t ev;
+    LBM_HIP(d, hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate");
+    hipError_t e = hipEventRecord(ev, s->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(d->stream, ev, 0);
+    const hipError_t e2 = hipEventDestroy(ev);
+    LBM_HIP(d, e, "stream ordering");
+    LBM_HIP(d, e2, "hipEventDestroy");
+  }
+  const int64_t st = d->L.stride, N = d->L.N;
+  LBM_HIP(d, launch_convert(s->p.storage, d->p.storage, s->f(s->cur), d->f(d->cur), st, N, d->qf(),
+                            d->stream),
+          "convert launch");
+  // with an extended induction lattice f outside the fluid box lives in both buffers
+  if (d->p.mag_pad[0] || d->p.mag_pad[1] || d->p.mag_pad[2])
+    LBM_HIP(d, launch_convert(s->p.storage, d->p.storage, s->f(s->cur), d->f(d->cur ^ 1), st, N,
+                              d->qf(), d->stream),
+            "convert launch");
+  if (d->p.mhd) {
+    const int cs_s = s->celem() == 8 ? LBM_F64 : LBM_F32, cs_d = d->celem() == 8 ? LBM_F64 : LBM_F32;
+    LBM_HIP(d, launch_convert(cs_s, cs_d, s->g(s->cur), d->g(d->cur), st, N, d->qg(), d->stream),
+            "convert launch");
+  }
+  LBM_HIP(d, (d->celem() == 8) ? launch_fill_zero<double>(d->usnap(), 3 * st, d->stream)
+                               : launch_fill_zero<float>(d->usnap(), 3 * st, d->stream),
+          "fill");
+  reset_checks(d, s->step);
+  return LBM_OK;
+}
+
 lbm_status lbm_get_step(const lbm_ctx* c, int64_t* step) {
   if (!c || !step) return fail(nullptr, LBM_EINVAL, "NULL argument");
   *step = c->step;
