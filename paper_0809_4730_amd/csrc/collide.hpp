@@ -21,20 +21,75 @@ struct NodeMacro {
   R drho;        // rho - rho0
   R jx, jy, jz;  // momentum including F/(2 gamma)
   R ux, uy, uz;  // j / rho
+  R irho;        // 1 / rho
 };
+
+// Opposite directions are stored as adjacent pairs: their sums carry the even
+// moments, their differences the odd ones.
+template <typename R>
+struct Pairs19 {
+  R f0;
+  R sx, dx, sy, dy, sz, dz;                      // axis pairs
+  R sa, Ad, sb, Bd, sc, Cd, sd, Dd, se, Ed, sg, Gd;  // diagonal pairs
+  R sax, sab, scd, seg, sdg;                     // partial sums of the pair sums
+  R oxd, oyd, ozd;                               // diagonal parts of sum f e
+  R drho;                                        // sum f (deviations)
+};
+
+template <typename R>
+__host__ __device__ __forceinline__ Pairs19<R> pairs19(const R (&f)[Q19]) {
+  Pairs19<R> p;
+  p.f0 = f[0];
+  p.sx = f[1] + f[2], p.dx = f[1] - f[2];
+  p.sy = f[3] + f[4], p.dy = f[3] - f[4];
+  p.sz = f[5] + f[6], p.dz = f[5] - f[6];
+  p.sa = f[7] + f[8], p.Ad = f[7] - f[8];      // (+1,+1,0)
+  p.sb = f[9] + f[10], p.Bd = f[9] - f[10];    // (+1,-1,0)
+  p.sc = f[11] + f[12], p.Cd = f[11] - f[12];  // (+1,0,+1)
+  p.sd = f[13] + f[14], p.Dd = f[13] - f[14];  // (+1,0,-1)
+  p.se = f[15] + f[16], p.Ed = f[15] - f[16];  // (0,+1,+1)
+  p.sg = f[17] + f[18], p.Gd = f[17] - f[18];  // (0,+1,-1)
+  p.sax = p.sx + p.sy + p.sz;
+  p.sab = p.sa + p.sb, p.scd = p.sc + p.sd, p.seg = p.se + p.sg;
+  p.sdg = p.sab + p.scd + p.seg;
+  p.drho = p.f0 + p.sax + p.sdg;
+  p.oxd = p.Ad + p.Bd + p.Cd + p.Dd;
+  p.oyd = p.Ad - p.Bd + p.Ed + p.Gd;
+  p.ozd = p.Cd - p.Dd + p.Ed - p.Gd;
+  return p;
+}
 
 // Density deviation and raw momentum sum_a f_a e_a (no force term).
 template <typename R>
 __host__ __device__ __forceinline__ void raw_moments(const R (&f)[Q19], R& drho, R& jx, R& jy, R& jz) {
-  const R dx = f[1] - f[2], dy = f[3] - f[4], dz = f[5] - f[6];
-  const R Ad = f[7] - f[8], Bd = f[9] - f[10], Cd = f[11] - f[12];
-  const R Dd = f[13] - f[14], Ed = f[15] - f[16], Gd = f[17] - f[18];
-  drho = f[0] + ((f[1] + f[2]) + (f[3] + f[4]) + (f[5] + f[6])) +
-         ((f[7] + f[8]) + (f[9] + f[10]) + (f[11] + f[12]) + (f[13] + f[14]) +
-          (f[15] + f[16]) + (f[17] + f[18]));
-  jx = dx + Ad + Bd + Cd + Dd;
-  jy = dy + Ad - Bd + Ed + Gd;
-  jz = dz + Cd - Dd + Ed - Gd;
+  const Pairs19<R> p = pairs19<R>(f);
+  drho = p.drho;
+  jx = p.dx + p.oxd;
+  jy = p.dy + p.oyd;
+  jz = p.dz + p.ozd;
+}
+
+// Fields of a node under force F: j = sum f e + F/(2 gamma), u = j / rho
+// (Sec. 3, preconditioned hydrodynamic fields).
+template <typename R>
+__host__ __device__ __forceinline__ NodeMacro<R> macro_of(const Pairs19<R>& p, R Fx, R Fy, R Fz,
+                                                          const CollideArgs<R>& c) {
+  NodeMacro<R> o;
+  o.drho = p.drho;
+  o.jx = p.dx + p.oxd + Fx * c.half_inv_gamma;
+  o.jy = p.dy + p.oyd + Fy * c.half_inv_gamma;
+  o.jz = p.dz + p.ozd + Fz * c.half_inv_gamma;
+  o.irho = R(1) / (c.rho0 + p.drho);
+  o.ux = o.jx * o.irho;
+  o.uy = o.jy * o.irho;
+  o.uz = o.jz * o.irho;
+  return o;
+}
+
+template <typename R>
+__host__ __device__ __forceinline__ NodeMacro<R> macro19(const R (&f)[Q19], R Fx, R Fy, R Fz,
+                                                         const CollideArgs<R>& c) {
+  return macro_of<R>(pairs19<R>(f), Fx, Fy, Fz, c);
 }
 
 // f_a += sum_k T_ka k_k for the scaled moment changes k_k (k_k = dm_k / |T_k|^2;
@@ -95,32 +150,17 @@ __host__ __device__ __forceinline__ void scatter_moments(R (&f)[Q19], R k1, R k2
 template <typename R>
 __host__ __device__ __forceinline__ NodeMacro<R> collide19(R (&f)[Q19], R Fx, R Fy, R Fz,
                                                   const CollideArgs<R>& c) {
-  // pair sums (even part) and differences (odd part)
-  const R sx = f[1] + f[2], dx = f[1] - f[2];
-  const R sy = f[3] + f[4], dy = f[3] - f[4];
-  const R sz = f[5] + f[6], dz = f[5] - f[6];
-  const R sa = f[7] + f[8], Ad = f[7] - f[8];     // (+1,+1,0)
-  const R sb = f[9] + f[10], Bd = f[9] - f[10];   // (+1,-1,0)
-  const R sc = f[11] + f[12], Cd = f[11] - f[12]; // (+1,0,+1)
-  const R sd = f[13] + f[14], Dd = f[13] - f[14]; // (+1,0,-1)
-  const R se = f[15] + f[16], Ed = f[15] - f[16]; // (0,+1,+1)
-  const R sg = f[17] + f[18], Gd = f[17] - f[18]; // (0,+1,-1)
-
-  const R sax = sx + sy + sz;
-  const R sab = sa + sb, scd = sc + sd, seg = se + sg;
-  const R sdg = sab + scd + seg;
-  const R drho = f[0] + sax + sdg;
-  const R oxd = Ad + Bd + Cd + Dd;  // diagonal part of sum f e_x
-  const R oyd = Ad - Bd + Ed + Gd;
-  const R ozd = Cd - Dd + Ed - Gd;
-
-  const R jx = dx + oxd + Fx * c.half_inv_gamma;
-  const R jy = dy + oyd + Fy * c.half_inv_gamma;
-  const R jz = dz + ozd + Fz * c.half_inv_gamma;
-  const R rho = c.rho0 + drho;
-  const R irho = R(1) / rho;
-  const R ux = jx * irho, uy = jy * irho, uz = jz * irho;
-  const R igr = c.inv_gamma * irho;  // 1/(gamma rho)
+  const Pairs19<R> p = pairs19<R>(f);
+  const NodeMacro<R> mac = macro_of<R>(p, Fx, Fy, Fz, c);
+  const R sx = p.sx, dx = p.dx, sy = p.sy, dy = p.dy, sz = p.sz, dz = p.dz;
+  const R sa = p.sa, Ad = p.Ad, sb = p.sb, Bd = p.Bd, sc = p.sc, Cd = p.Cd;
+  const R sd = p.sd, Dd = p.Dd, se = p.se, Ed = p.Ed, sg = p.sg, Gd = p.Gd;
+  const R sax = p.sax, sab = p.sab, scd = p.scd, seg = p.seg, sdg = p.sdg;
+  const R oxd = p.oxd, oyd = p.oyd, ozd = p.ozd;
+  const R drho = p.drho;
+  const R jx = mac.jx, jy = mac.jy, jz = mac.jz;
+  const R ux = mac.ux, uy = mac.uy, uz = mac.uz;
+  const R igr = c.inv_gamma * mac.irho;  // 1/(gamma rho)
 
   // non-conserved moments of the deviations (T d)
   const R m1 = R(-30) * f[0] - R(11) * sax + R(8) * sdg;
@@ -183,15 +223,7 @@ __host__ __device__ __forceinline__ NodeMacro<R> collide19(R (&f)[Q19], R Fx, R 
   scatter_moments<R>(f, k1, k2, k4, k6, k8, k9, k10, k11, k12, k13, k14, k15, k16, k17, k18, bx,
                      by, bz);
 
-  NodeMacro<R> out;
-  out.drho = drho;
-  out.jx = jx;
-  out.jy = jy;
-  out.jz = jz;
-  out.ux = ux;
-  out.uy = uy;
-  out.uz = uz;
-  return out;
+  return mac;
 }
 
 
