@@ -51,6 +51,7 @@ struct lbm_ctx {
   char* ws = nullptr;
   int cur = 0;
   bool nt_store = false;  // streaming (cache-bypassing) population stores
+  bool tune_chunk = false;  // time the XCD chunk candidates at create
   int64_t step = 0;
   int64_t checks = 0;            // residual checks launched since the last reset
   int64_t finalized = 0;         // checks whose history records have been written

@@ -148,6 +148,17 @@ __device__ __forceinline__ void collide_g(R (&g)[3][Q7], const Coupled<R>& cp, R
   }
 }
 
+template <typename R, bool NT, bool WIDE>
+__device__ __forceinline__ void store_g(R* __restrict__ gout, int64_t stride, uint32_t n,
+                                        const R (&g)[3][Q7]) {
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int a = 0; a < Q7; ++a)
+      Storage<R>::template st<NT>(elem<WIDE>(gout + static_cast<int64_t>(j * Q7 + a) * stride, n),
+                                  g[j][a]);
+}
+
 template <typename R, bool WIDE>
 __device__ __forceinline__ void load_force(const GridArgs& g, const CollideArgs<R>& c,
                                            const R* __restrict__ force, bool field, uint32_t n,
@@ -190,8 +201,8 @@ __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<type
 }
 
 // EXT: the induction lattice extends beyond the fluid box; nodes outside it
-// relax g with u = 0 and leave f untouched.
-template <typename R, bool CHECK, bool FIELD, bool MOVING, bool EXT, bool WIDE>
+// relax g with u = 0 and leave f untouched.  NT: streaming stores.
+template <typename R, bool CHECK, bool FIELD, bool MOVING, bool EXT, bool WIDE, bool NT>
 __global__ __launch_bounds__(kBlock) void mhd_step(GridArgs g, CollideArgs<R> c, MagArgs<R> m,
                                                    const R* __restrict__ fin, R* __restrict__ fout,
                                                    const R* __restrict__ gin, R* __restrict__ gout,
@@ -218,18 +229,14 @@ __global__ __launch_bounds__(kBlock) void mhd_step(GridArgs g, CollideArgs<R> c,
       const Coupled<R> cp = lorentz_solve<R>(f, gg, Fx, Fy, Fz, c, m);
       const NodeMacro<R> mac = collide19<R>(f, cp.Fx, cp.Fy, cp.Fz, c);
       collide_g<R>(gg, cp, mac.ux, mac.uy, mac.uz, m);
-      store19<R, false, WIDE>(fout, g.stride, n, f);
+      store19<R, NT, WIDE>(fout, g.stride, n, f);
       if constexpr (CHECK)
         check_node<R, WIDE>(g, usnap, n, mac.drho, mac.jx, mac.jy, mac.jz, mac.ux, mac.uy, mac.uz, acc);
     } else {
       const Coupled<R> cp = field_only<R>(gg, m);
       collide_g<R>(gg, cp, R(0), R(0), R(0), m);
     }
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-#pragma unroll
-      for (int a = 0; a < Q7; ++a)
-        *elem<WIDE>(gout + static_cast<int64_t>(j * Q7 + a) * g.stride, n) = gg[j][a];
+    store_g<R, NT, WIDE>(gout, g.stride, n, gg);
   }
   if constexpr (CHECK) write_partials(partials, lb, acc);
 }
@@ -439,7 +446,7 @@ LBM_INST_STEP(_Float16)
 template <typename R>
 hipError_t launch_mhd_step(const GridArgs& g, const CollideArgs<R>& c, const MagArgs<R>& m,
                            const void* fin, void* fout, const void* gin, void* gout,
-                           const void* force, bool field, bool check, void* usnap_v,
+                           const void* force, bool field, bool check, bool nt, void* usnap_v,
                            double* partials, hipStream_t st) {
   R* usnap = static_cast<R*>(usnap_v);
   const R* a = static_cast<const R*>(fin);
@@ -453,10 +460,16 @@ hipError_t launch_mhd_step(const GridArgs& g, const CollideArgs<R>& c, const Mag
       return with_flag(c.moving != 0, [&](auto MV) {
         return with_flag(ext, [&](auto EX) {
           return with_flag(wide_offsets(g, sizeof(R)), [&](auto W) {
-            mhd_step<R, decltype(CH)::value, decltype(FL)::value, decltype(MV)::value,
-                     decltype(EX)::value, decltype(W)::value>
-                <<<step_grid(g), kBlock, 0, st>>>(g, c, m, a, b, ga, gb, F, usnap, partials);
-            return hipGetLastError();
+            return with_flag(nt, [&](auto NTF) {
+              // streaming stores only in the plain variant: moving walls and the
+              // extended lattice are the (cache-resident) cavity
+              constexpr bool kNt =
+                  decltype(NTF)::value && !decltype(MV)::value && !decltype(EX)::value;
+              mhd_step<R, decltype(CH)::value, decltype(FL)::value, decltype(MV)::value,
+                       decltype(EX)::value, decltype(W)::value, kNt>
+                  <<<step_grid(g), kBlock, 0, st>>>(g, c, m, a, b, ga, gb, F, usnap, partials);
+              return hipGetLastError();
+            });
           });
         });
       });
@@ -466,11 +479,11 @@ hipError_t launch_mhd_step(const GridArgs& g, const CollideArgs<R>& c, const Mag
 
 template hipError_t launch_mhd_step<double>(const GridArgs&, const CollideArgs<double>&,
                                             const MagArgs<double>&, const void*, void*, const void*,
-                                            void*, const void*, bool, bool, void*, double*,
+                                            void*, const void*, bool, bool, bool, void*, double*,
                                             hipStream_t);
 template hipError_t launch_mhd_step<float>(const GridArgs&, const CollideArgs<float>&,
                                            const MagArgs<float>&, const void*, void*, const void*,
-                                           void*, const void*, bool, bool, void*, double*,
+                                           void*, const void*, bool, bool, bool, void*, double*,
                                            hipStream_t);
 
 template <typename S>

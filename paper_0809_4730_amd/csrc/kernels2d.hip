@@ -170,7 +170,7 @@ __global__ __launch_bounds__(kBlock) void glbe2_step(GridArgs g, CollideArgs<typ
   if constexpr (CHECK) write_partials(partials, lb, acc);
 }
 
-template <typename R, bool CHECK, bool FIELD, bool WIDE>
+template <typename R, bool CHECK, bool FIELD, bool WIDE, bool NT>
 __global__ __launch_bounds__(kBlock) void mhd2_step(GridArgs g, CollideArgs<R> c, MagArgs<R> m,
                                                     const R* __restrict__ fin, R* __restrict__ fout,
                                                     const R* __restrict__ gin, R* __restrict__ gout,
@@ -192,12 +192,13 @@ __global__ __launch_bounds__(kBlock) void mhd2_step(GridArgs g, CollideArgs<R> c
     const Coupled2<R> cp = lorentz_solve2<R>(f, gg, Fx, Fy, c, m);
     const NodeMacro<R> mac = collide9<R>(f, cp.Fx, cp.Fy, c);
     collide_g5<R>(gg, cp, mac.ux, mac.uy, m);
-    store9<R, false, WIDE>(fout, g.stride, n, f);
+    store9<R, NT, WIDE>(fout, g.stride, n, f);
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int a = 0; a < Q5; ++a)
-        *elem<WIDE>(gout + static_cast<int64_t>(j * Q5 + a) * g.stride, n) = gg[j][a];
+        Storage<R>::template st<NT>(elem<WIDE>(gout + static_cast<int64_t>(j * Q5 + a) * g.stride, n),
+                                    gg[j][a]);
     if constexpr (CHECK) check_node2<R, WIDE>(g, usnap, n, mac, acc);
   }
   if constexpr (CHECK) write_partials(partials, lb, acc);
@@ -290,7 +291,7 @@ LBM_INST_STEP2(_Float16)
 template <typename R>
 hipError_t launch_mhd2_step(const GridArgs& g, const CollideArgs<R>& c, const MagArgs<R>& m,
                             const void* fin, void* fout, const void* gin, void* gout,
-                            const void* force, bool field, bool check, void* usnap_v,
+                            const void* force, bool field, bool check, bool nt, void* usnap_v,
                             double* partials, hipStream_t st) {
   R* usnap = static_cast<R*>(usnap_v);
   const R* a = static_cast<const R*>(fin);
@@ -301,9 +302,12 @@ hipError_t launch_mhd2_step(const GridArgs& g, const CollideArgs<R>& c, const Ma
   return with_flag(check, [&](auto CH) {
     return with_flag(field, [&](auto FL) {
       return with_flag(wide_offsets(g, sizeof(R)), [&](auto W) {
-        mhd2_step<R, decltype(CH)::value, decltype(FL)::value, decltype(W)::value>
-            <<<step_grid(g), kBlock, 0, st>>>(g, c, m, a, b, ga, gb, F, usnap, partials);
-        return hipGetLastError();
+        return with_flag(nt, [&](auto NTF) {
+          mhd2_step<R, decltype(CH)::value, decltype(FL)::value, decltype(W)::value,
+                    decltype(NTF)::value>
+              <<<step_grid(g), kBlock, 0, st>>>(g, c, m, a, b, ga, gb, F, usnap, partials);
+          return hipGetLastError();
+        });
       });
     });
   });
@@ -311,11 +315,11 @@ hipError_t launch_mhd2_step(const GridArgs& g, const CollideArgs<R>& c, const Ma
 
 template hipError_t launch_mhd2_step<double>(const GridArgs&, const CollideArgs<double>&,
                                              const MagArgs<double>&, const void*, void*,
-                                             const void*, void*, const void*, bool, bool, void*,
+                                             const void*, void*, const void*, bool, bool, bool, void*,
                                              double*, hipStream_t);
 template hipError_t launch_mhd2_step<float>(const GridArgs&, const CollideArgs<float>&,
                                             const MagArgs<float>&, const void*, void*,
-                                            const void*, void*, const void*, bool, bool, void*,
+                                            const void*, void*, const void*, bool, bool, bool, void*,
                                             double*, hipStream_t);
 
 template <typename S>

@@ -16,7 +16,7 @@ hipError_t launch_glbe_step(const GridArgs& g, const CollideArgs<typename Storag
 template <typename R>
 hipError_t launch_mhd_step(const GridArgs& g, const CollideArgs<R>& c, const MagArgs<R>& m,
                            const void* fin, void* fout, const void* gin, void* gout,
-                           const void* force, bool field, bool check, void* usnap,
+                           const void* force, bool field, bool check, bool nt, void* usnap,
                            double* partials, hipStream_t st);
 
 template <typename S>
@@ -35,7 +35,7 @@ hipError_t launch_glbe2_step(const GridArgs& g, const CollideArgs<typename Stora
 template <typename R>
 hipError_t launch_mhd2_step(const GridArgs& g, const CollideArgs<R>& c, const MagArgs<R>& m,
                             const void* fin, void* fout, const void* gin, void* gout,
-                            const void* force, bool field, bool check, void* usnap,
+                            const void* force, bool field, bool check, bool nt, void* usnap,
                             double* partials, hipStream_t st);
 
 template <typename S>

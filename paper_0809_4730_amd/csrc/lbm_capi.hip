@@ -145,10 +145,11 @@ hipError_t launch_step_kernel(lbm_ctx* c, bool check) {
     if (c->p.mhd) {
       if (c->p.storage == LBM_F64)
         return launch_mhd2_step<double>(c->ga, c->cd, c->md, fin, fout, c->g(c->cur),
-                                        c->g(c->cur ^ 1), c->force(), fld, check, c->usnap(),
-                                        partials, c->stream);
+                                        c->g(c->cur ^ 1), c->force(), fld, check, c->nt_store,
+                                        c->usnap(), partials, c->stream);
       return launch_mhd2_step<float>(c->ga, c->cf, c->mf, fin, fout, c->g(c->cur), c->g(c->cur ^ 1),
-                                     c->force(), fld, check, c->usnap(), partials, c->stream);
+                                     c->force(), fld, check, c->nt_store, c->usnap(), partials,
+                                     c->stream);
     }
     switch (c->p.storage) {
       case LBM_F64:
@@ -168,9 +169,11 @@ hipError_t launch_step_kernel(lbm_ctx* c, bool check) {
   if (c->p.mhd) {
     if (c->p.storage == LBM_F64)
       return launch_mhd_step<double>(c->ga, c->cd, c->md, fin, fout, c->g(c->cur), c->g(c->cur ^ 1),
-                                     c->force(), fld, check, c->usnap(), partials, c->stream);
+                                     c->force(), fld, check, c->nt_store, c->usnap(), partials,
+                                     c->stream);
     return launch_mhd_step<float>(c->ga, c->cf, c->mf, fin, fout, c->g(c->cur), c->g(c->cur ^ 1),
-                                  c->force(), fld, check, c->usnap(), partials, c->stream);
+                                  c->force(), fld, check, c->nt_store, c->usnap(), partials,
+                                  c->stream);
   }
   switch (c->p.storage) {
     case LBM_F64:
@@ -189,30 +192,45 @@ hipError_t launch_step_kernel(lbm_ctx* c, bool check) {
 }
 
 // Launch shape, from the bytes of the two population buffers (measured on
-// MI355X, FP32/BF16/FP64 duct at 64^3 .. 256^3):
+// MI355X, 3D and 2D lattices from 64^3 and 2048^2 to 256^3 and 8192^2):
 //  * <= 256 MB (fits the MALL): each XCD sweeps one contiguous slab, so pulled
 //    neighbour rows hit its own L2; stores stay cacheable.
 //  * <= 512 MB (partly MALL-resident): slabs, streaming stores.
-//  * larger (streams from HBM): XCDs take 2 consecutive blocks in turn, so all
-//    XCDs work on the same DRAM pages; streaming stores.  (256^3 FP32: 479 us
-//    per step vs 541 us with slabs.)
+//  * larger (streams from HBM): streaming stores, and the chunk is timed at
+//    create (tune_launch_shape) among 2, 8 and whole slabs.  No rule of the
+//    lattice shape picked the winner: chunks of 2 beat slabs by 7% for the 256^3
+//    flow step, slabs beat chunks by 22% for the 2048^2 coupled 2D step, and
+//    chunks of 8 lead for 16-bit storage by 2-3%.
 // LBM_XCD_CHUNK and LBM_NT_STORE in the environment override the choice.
-void choose_launch_shape(lbm_ctx* c) {
-  constexpr double kMallBytes = 256.0 * 1024 * 1024;
-  const double pop_bytes =
-      2.0 * double(c->L.stride) * (c->qf() * double(storage_bytes(c->p.storage)) +
-                                   (c->p.mhd ? c->qg() * double(compute_bytes(c->p.storage)) : 0.0));
+void set_chunk(lbm_ctx* c, int chunk) {
   const int bpx0 = (c->L.nblocks + kXcd - 1) / kXcd;
-  int chunk = pop_bytes > 2.0 * kMallBytes ? 2 : bpx0;
-  c->nt_store = pop_bytes > kMallBytes;
-  if (const char* e = std::getenv("LBM_XCD_CHUNK")) {
-    const int v = std::atoi(e);
-    if (v > 0) chunk = v;
-  }
-  if (const char* e = std::getenv("LBM_NT_STORE")) c->nt_store = std::atoi(e) != 0;
   chunk = std::max(1, std::min(chunk, bpx0));
   c->ga.xcd_chunk = chunk;
   c->ga.blocks_per_xcd = (bpx0 + chunk - 1) / chunk * chunk;
+}
+
+double population_bytes(const lbm_ctx* c) {
+  return 2.0 * double(c->L.stride) *
+         (c->qf() * double(storage_bytes(c->p.storage)) +
+          (c->p.mhd ? c->qg() * double(compute_bytes(c->p.storage)) : 0.0));
+}
+
+void choose_launch_shape(lbm_ctx* c) {
+  constexpr double kMallBytes = 256.0 * 1024 * 1024;
+  const double pop_bytes = population_bytes(c);
+  const int bpx0 = (c->L.nblocks + kXcd - 1) / kXcd;
+  int chunk = pop_bytes > 2.0 * kMallBytes ? 2 : bpx0;
+  c->tune_chunk = pop_bytes > 2.0 * kMallBytes;
+  c->nt_store = pop_bytes > kMallBytes;
+  if (const char* e = std::getenv("LBM_XCD_CHUNK")) {
+    const int v = std::atoi(e);
+    if (v > 0) {
+      chunk = v;
+      c->tune_chunk = false;
+    }
+  }
+  if (const char* e = std::getenv("LBM_NT_STORE")) c->nt_store = std::atoi(e) != 0;
+  set_chunk(c, chunk);
 }
 
 // Turn every pending check's partial sums into history records (one batched
@@ -289,6 +307,72 @@ hipError_t zero_storage(lbm_ctx* c, void* p, int64_t count) {
     case LBM_BF16: return launch_fill_zero<bf16_t>(p, count, c->stream);
     default: return launch_fill_zero<_Float16>(p, count, c->stream);
   }
+}
+
+// The rest state: both population buffers (and both magnetic ones) zero, as
+// deviations from w rho0 and W B0.
+hipError_t zero_populations(lbm_ctx* c) {
+  hipError_t e = zero_storage(c, c->f(0), int64_t(c->qf()) * c->L.stride);
+  if (e == hipSuccess) e = zero_storage(c, c->f(1), int64_t(c->qf()) * c->L.stride);
+  if (e == hipSuccess && c->p.mhd) {
+    const size_t cs = compute_bytes(c->p.storage);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i)
+      e = (cs == 8) ? launch_fill_zero<double>(c->g(i), int64_t(c->qg()) * c->L.stride, c->stream)
+                    : launch_fill_zero<float>(c->g(i), int64_t(c->qg()) * c->L.stride, c->stream);
+  }
+  return e;
+}
+
+// Times the plain step for each chunk candidate and keeps the fastest (two
+// rounds, about 2 ms of launches per candidate and round, best of the two).
+// The timed steps alternate buffers as a march does (a step that rereads one
+// buffer finds it in the MALL and favours other shapes); the rest state is
+// restored afterwards.  The chunk only decides which workgroup updates which
+// nodes, so results do not depend on it.
+hipError_t tune_launch_shape(lbm_ctx* c) {
+  if (!c->tune_chunk) return hipSuccess;
+  const int bpx0 = (c->L.nblocks + kXcd - 1) / kXcd;
+  constexpr int kCand = 3;
+  const int cand[kCand] = {2, 8, bpx0};
+  // launches per timing: ~2 ms at ~5.5 TB/s (each step moves the population bytes)
+  const int reps =
+      static_cast<int>(std::max(4.0, std::min(32.0, 2e-3 * 5.5e12 / population_bytes(c))));
+  hipEvent_t ev[2];
+  hipError_t e = hipEventCreate(&ev[0]);
+  if (e != hipSuccess) return e;
+  e = hipEventCreate(&ev[1]);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return e;
+  }
+  float best_ms[kCand] = {};
+  for (int r = 0; r < 2 && e == hipSuccess; ++r) {
+    for (int i = 0; i < kCand && e == hipSuccess; ++i) {
+      set_chunk(c, cand[i]);
+      e = launch_step_kernel(c, false);  // warm-up
+      c->cur ^= 1;
+      if (e == hipSuccess) e = hipEventRecord(ev[0], c->stream);
+      for (int k = 0; k < reps && e == hipSuccess; ++k) {
+        e = launch_step_kernel(c, false);
+        c->cur ^= 1;
+      }
+      if (e == hipSuccess) e = hipEventRecord(ev[1], c->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+      if (e == hipSuccess) best_ms[i] = (r == 0) ? ms : std::min(best_ms[i], ms);
+    }
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  int best = 0;
+  if (e == hipSuccess)
+    for (int i = 1; i < kCand; ++i)
+      if (best_ms[i] < best_ms[best]) best = i;
+  set_chunk(c, cand[best]);
+  c->cur = 0;
+  if (e == hipSuccess) e = zero_populations(c);
+  return e;
 }
 
 lbm_status copy_force_in(lbm_ctx* c, const void* force) {
@@ -437,21 +521,13 @@ lbm_status lbm_create(const lbm_grid* grid, const lbm_params* params, const void
   c->md = mag_args<double>(c->p);
   c->mf = mag_args<float>(c->p);
 
-  hipError_t e = zero_storage(c, c->f(0), int64_t(c->qf()) * L.stride);
-  if (e == hipSuccess) e = zero_storage(c, c->f(1), int64_t(c->qf()) * L.stride);
+  hipError_t e = zero_populations(c);
   if (e == hipSuccess)
     e = (compute_bytes(params->storage) == 8)
             ? launch_fill_zero<double>(c->usnap(), 3 * L.stride, c->stream)
             : launch_fill_zero<float>(c->usnap(), 3 * L.stride, c->stream);
   reset_checks(c, 0);
   if (e == hipSuccess) e = launch_fill_zero<double>(c->ring(), int64_t(params->history_len) * kRecordDoubles, c->stream);
-  if (e == hipSuccess && params->mhd) {
-    // magnetic populations are stored as deviations from W_a B0: zero at rest
-    const size_t cs = compute_bytes(params->storage);
-    for (int i = 0; i < 2 && e == hipSuccess; ++i)
-      e = (cs == 8) ? launch_fill_zero<double>(c->g(i), int64_t(c->qg()) * L.stride, c->stream)
-                    : launch_fill_zero<float>(c->g(i), int64_t(c->qg()) * L.stride, c->stream);
-  }
   if (e != hipSuccess) {
     g_create_error = std::string("initialisation: ") + hipGetErrorString(e);
     delete c;
@@ -463,6 +539,12 @@ lbm_status lbm_create(const lbm_grid* grid, const lbm_params* params, const void
       delete c;
       return LBM_EHIP;
     }
+  }
+  e = tune_launch_shape(c);
+  if (e != hipSuccess) {
+    g_create_error = std::string("launch-shape timing: ") + hipGetErrorString(e);
+    delete c;
+    return LBM_EHIP;
   }
   *out = c;
   return LBM_OK;

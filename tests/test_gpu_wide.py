@@ -1,10 +1,13 @@
-"""Both addressing forms of every step kernel give bitwise identical results.
+"""Both addressing forms and both store forms of the step kernels give bitwise
+identical results.
 
 The kernels address populations from a launch-uniform base pointer with either
 32-bit byte offsets (when every offset of the launch fits) or 64-bit ones
 (larger lattices).  LBM_WIDE_OFFSETS=1 forces the 64-bit form, so that it runs
 on the small lattices of these tests; only addressing differs, so states,
-residual histories and verdicts must agree bit for bit."""
+residual histories and verdicts must agree bit for bit.  Likewise the
+streaming-store variants, chosen for lattices larger than the last-level cache
+and forced here with LBM_NT_STORE=1, differ only in cache policy."""
 import numpy as np
 import pytest
 
@@ -16,12 +19,15 @@ pytestmark = pytest.mark.gpu
 PER, WALL = "periodic", "wall"
 
 
-def _both(monkeypatch, run):
-    monkeypatch.delenv("LBM_WIDE_OFFSETS", raising=False)
+def _both(monkeypatch, run, var="LBM_WIDE_OFFSETS", off=None):
+    if off is None:
+        monkeypatch.delenv(var, raising=False)
+    else:
+        monkeypatch.setenv(var, off)
     narrow = run()
-    monkeypatch.setenv("LBM_WIDE_OFFSETS", "1")
+    monkeypatch.setenv(var, "1")
     wide = run()
-    monkeypatch.delenv("LBM_WIDE_OFFSETS", raising=False)
+    monkeypatch.delenv(var, raising=False)
     return narrow, wide
 
 
@@ -120,3 +126,66 @@ def test_adjoint_forms_agree(monkeypatch):
         g_u = sim2.adjoint_unrolled(60, 7)
         return g_s, it, g_u
     _same(*_both(monkeypatch, run))
+
+
+def test_streaming_store_forms_agree(monkeypatch):
+    """Cacheable and streaming stores: flow (3D, 2D) and coupled (3D, 2D) steps,
+    with the residual check on."""
+    import torch
+    import paper_0809_4730_amd as pkg
+    announce("streaming vs cacheable stores")
+    shape, bc = (16, 10, 9), (PER, WALL, WALL)
+    F = torch.tensor(inputs.random_force(shape, seed=6, amp=1e-5), dtype=torch.float32,
+                     device="cuda")
+
+    def run3(storage, mhd):
+        def run():
+            kw = dict(mhd=dict(gamma_m=0.3, chi=0.05, eta=0.03, B0=(0.01, 0.02, -0.01))) if mhd else {}
+            sim = pkg.Simulation(shape, bc, 0.3, glbe.rates(0.05, 0.3), storage=storage,
+                                 force=F if storage != "f64" else F.double(), **kw)
+            sim.step(33)
+            return sim.get_state(), sim.history(8)
+        return run
+
+    def run2(mhd):
+        def run():
+            kw = dict(mhd=dict(gamma_m=0.3, chi=0.05, eta=0.02, B0=(0.0, 0.03))) if mhd else {}
+            sim = pkg.Simulation((20, 12, 1), (PER, WALL, PER), 0.2, d2q9.rates(0.05, 0.2),
+                                 storage="f32", force=(1e-5, 0.0), lattice="d2q9", **kw)
+            sim.step(41)
+            return sim.get_state(), sim.history(8)
+        return run
+    for run in (run3("f32", False), run3("bf16", False), run3("f32", True), run3("f64", True),
+                run2(False), run2(True)):
+        _same(*_both(monkeypatch, run, "LBM_NT_STORE", "0"))
+
+
+@pytest.mark.parametrize("chunk", ["1", "3", "100000"])
+def test_results_do_not_depend_on_the_xcd_chunk(monkeypatch, chunk):
+    """The chunk (timed at create for large lattices) only decides which
+    workgroup updates which nodes: states and residual histories are bitwise
+    those of the default launch shape."""
+    import torch
+    import paper_0809_4730_amd as pkg
+    announce("xcd chunk %s" % chunk)
+    shape, bc = (16, 10, 9), (PER, WALL, WALL)
+    F = torch.tensor(inputs.random_force(shape, seed=7, amp=1e-5), dtype=torch.float32,
+                     device="cuda")
+
+    def run():
+        out = []
+        for mhd in (False, True):
+            kw = dict(mhd=dict(gamma_m=0.3, chi=0.05, eta=0.03, B0=(0.01, 0.02, -0.01))) if mhd else {}
+            sim = pkg.Simulation(shape, bc, 0.3, glbe.rates(0.05, 0.3), storage="f32", force=F, **kw)
+            sim.step(27)
+            out += [sim.get_state(), sim.history(8)]
+        sim = pkg.Simulation((20, 12, 1), (PER, WALL, PER), 0.2, d2q9.rates(0.05, 0.2),
+                             storage="f32", force=(1e-5, 0.0), lattice="d2q9")
+        sim.step(27)
+        return out + [sim.get_state(), sim.history(8)]
+    monkeypatch.delenv("LBM_XCD_CHUNK", raising=False)
+    ref = run()
+    monkeypatch.setenv("LBM_XCD_CHUNK", chunk)
+    got = run()
+    monkeypatch.delenv("LBM_XCD_CHUNK", raising=False)
+    _same(ref, got)
