@@ -185,6 +185,7 @@ lbm_status batch_run(const lbm_grid* grid, int32_t storage, double rho0, int32_t
   g.nblocks = L.nblocks;
   g.blocks_per_xcd = (L.nblocks + kXcd - 1) / kXcd;
   g.xcd_chunk = g.blocks_per_xcd;
+  g.div_chunk = make_fastdiv(uint32_t(g.xcd_chunk));
   g.stride = L.stride;
   g.div_nx = make_fastdiv(uint32_t(g.nx));
   g.div_nxny = make_fastdiv(uint32_t(g.nx * g.ny));

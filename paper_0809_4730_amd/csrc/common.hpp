@@ -58,6 +58,7 @@ struct GridArgs {
   int32_t xcd_chunk;       // consecutive logical blocks an XCD takes at a time
   int64_t stride;          // elements between direction planes (N rounded up to 64)
   FastDiv div_nx, div_nxny;
+  FastDiv div_chunk;       // division by xcd_chunk
   // Fluid box [flo, fhi) per axis (x, y, z).  The whole lattice, unless the
   // induction lattice extends beyond the fluid; its faces are then no-slip
   // walls of the flow, while the induction lattice's walls stay at the lattice
@@ -71,11 +72,12 @@ struct GridArgs {
 // in its L2: best when the lattice lives in the caches), chunk = 1 interleaves
 // single blocks (all XCDs stream the same DRAM pages: best from HBM).
 __device__ __forceinline__ int logical_block(const GridArgs& g) {
-  const int b = blockIdx.x;
-  const int xcd = b & (kXcd - 1);
-  const int i = b >> 3;
-  const int C = g.xcd_chunk;
-  return ((i / C) * kXcd + xcd) * C + (i % C);
+  const uint32_t b = blockIdx.x;
+  const uint32_t xcd = b & (kXcd - 1);
+  const uint32_t i = b >> 3;
+  const uint32_t C = static_cast<uint32_t>(g.xcd_chunk);
+  const uint32_t q = fdiv(i, g.div_chunk);  // i / C
+  return static_cast<int>((q * kXcd + xcd) * C + (i - q * C));
 }
 
 // Collision constants for compute type R (host-prepared).

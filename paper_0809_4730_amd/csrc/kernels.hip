@@ -175,7 +175,8 @@ __device__ __forceinline__ void load_force(const GridArgs& g, const CollideArgs<
 }
 
 // ------------------------------------------------------------------ steps --
-template <typename S, bool CHECK, bool FIELD, bool NT, bool MOVING, bool WIDE>
+// ROWS: every wave lies in one x-row (nx a multiple of 64; neighbours_rows).
+template <typename S, bool CHECK, bool FIELD, bool NT, bool MOVING, bool WIDE, bool ROWS>
 __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<typename Storage<S>::R> c,
                                                     const S* __restrict__ fin, S* __restrict__ fout,
                                                     const typename Storage<S>::R* __restrict__ force,
@@ -187,7 +188,7 @@ __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<type
   const uint32_t n = static_cast<uint32_t>(lb) * kBlock + threadIdx.x;
   double acc[kPartials] = {};
   if (n < static_cast<uint32_t>(g.N)) {
-    const Nbr b = neighbours(g, n);
+    const Nbr b = ROWS ? neighbours_rows(g, n) : neighbours(g, n);
     R f[Q19];
     gather19<S, MOVING, WIDE>(fin, g.stride, n, b, c, f);
     R Fx, Fy, Fz;
@@ -416,18 +417,24 @@ hipError_t launch_glbe_step(const GridArgs& g, const CollideArgs<typename Storag
   const S* a = static_cast<const S*>(fin);
   S* b = static_cast<S*>(fout);
   const R* F = static_cast<const R*>(force);
-  // moving walls: small problems, regular stores
+  // moving walls: small problems, regular stores, general addressing
   return with_flag(check, [&](auto CH) {
     return with_flag(field, [&](auto FL) {
       return with_flag(wide_offsets(g, sizeof(R)), [&](auto W) {
-        constexpr bool ch = decltype(CH)::value, fl = decltype(FL)::value, w = decltype(W)::value;
-        if (c.moving)
-          glbe_step<S, ch, fl, false, true, w><<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
-        else if (nt)
-          glbe_step<S, ch, fl, true, false, w><<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
-        else
-          glbe_step<S, ch, fl, false, false, w><<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
-        return hipGetLastError();
+        return with_flag(rows_per_wave(g), [&](auto RW) {
+          constexpr bool ch = decltype(CH)::value, fl = decltype(FL)::value,
+                         w = decltype(W)::value, rw = decltype(RW)::value;
+          if (c.moving)
+            glbe_step<S, ch, fl, false, true, w, false>
+                <<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
+          else if (nt)
+            glbe_step<S, ch, fl, true, false, w, rw>
+                <<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
+          else
+            glbe_step<S, ch, fl, false, false, w, rw>
+                <<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
+          return hipGetLastError();
+        });
       });
     });
   });

@@ -206,6 +206,7 @@ void set_chunk(lbm_ctx* c, int chunk) {
   const int bpx0 = (c->L.nblocks + kXcd - 1) / kXcd;
   chunk = std::max(1, std::min(chunk, bpx0));
   c->ga.xcd_chunk = chunk;
+  c->ga.div_chunk = make_fastdiv(static_cast<uint32_t>(chunk));
   c->ga.blocks_per_xcd = (bpx0 + chunk - 1) / chunk * chunk;
 }
 

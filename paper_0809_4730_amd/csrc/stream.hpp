@@ -76,6 +76,24 @@ __device__ __forceinline__ Nbr neighbours(const GridArgs& g, uint32_t n) {
   return neighbours_at(g, coords(g, n));
 }
 
+// When nx is a multiple of the wave size, the nodes of a wave lie in one
+// x-row: y and z, and with them the y/z neighbour offsets and wall flags, are
+// the same for every lane and are taken from one active lane's node (scalar
+// registers); only the x part is per lane.
+__device__ __forceinline__ Nbr neighbours_rows(const GridArgs& g, uint32_t n) {
+  const uint32_t n0 = __builtin_amdgcn_readfirstlane(n);
+  const uint32_t yz = fdiv(n0, g.div_nx);
+  const uint32_t z = fdiv(n0, g.div_nxny);
+  Coord q;
+  q.x = static_cast<int>(n - yz * static_cast<uint32_t>(g.nx));
+  q.y = static_cast<int>(yz - z * static_cast<uint32_t>(g.ny));
+  q.z = static_cast<int>(z);
+  return neighbours_at(g, q);
+}
+
+// Whether every wave of a launch lies in one x-row.
+inline bool rows_per_wave(const GridArgs& g) { return g.nx % 64 == 0; }
+
 // The same node seen by the flow: walls at the fluid box faces.
 __device__ __forceinline__ Nbr box_walls(const GridArgs& g, const Coord& q, Nbr b) {
   b.bxm = g.wall_x && q.x == g.flo[0];
@@ -141,7 +159,8 @@ __device__ __forceinline__ uint32_t pull_offset(bool bounce, int32_t off, uint32
   constexpr bool lower = (A == 0) || (A & 1);
   const uint32_t self = lower ? 0u : stride;
   const uint32_t opp = lower ? stride : 0u;
-  return bounce ? opp + n : self + n + static_cast<uint32_t>(off);
+  // node-independent part first: wave-uniform when the offsets and wall flags are
+  return (bounce ? opp : self + static_cast<uint32_t>(off)) + n;
 }
 
 template <int A>

@@ -77,6 +77,44 @@ def test_fp64_many_steps_match_oracle(shape, bc):
     assert rel(out, ref) < 1e-12
 
 
+# nx a multiple of 64: every wave lies in one x-row, and the step takes its y/z
+# neighbours and wall flags as wave-uniform values (the row-aligned variant)
+ROW_GRIDS = [
+    ((64, 3, 4), (PER, WALL, WALL)),
+    ((64, 2, 3), (WALL, PER, WALL)),
+    ((128, 2, 2), (WALL, WALL, PER)),
+]
+
+
+@pytest.mark.parametrize("shape,bc", ROW_GRIDS)
+def test_row_aligned_lattices_match_oracle(shape, bc):
+    """One step and 40 steps in FP64, and the residual history of the check
+    steps, against the oracle on lattices that take the row-aligned variant."""
+    torch = _torch()
+    announce("row-aligned %s %s" % (shape, bc))
+    gamma = 0.3
+    d0 = inputs.random_deviations(shape, seed=4, amp=1e-3)
+    F = inputs.random_force(shape, seed=4, amp=1e-5)
+    s = glbe.rates(0.05, gamma)
+    sim = _sim(shape, bc, gamma, s, "f64", F)
+    sim.set_state(to_gpu_f(d0, torch.float64))
+    sim.step(1)
+    ref, _ = glbe.step(d0, F, gamma, s, bc)
+    out = from_gpu_f(sim.get_state())
+    assert rel(out - d0, ref - d0) < 1e-13
+    sim.step(39)
+    for _ in range(39):
+        ref, _ = glbe.step(ref, F, gamma, s, bc)
+    assert rel(from_gpu_f(sim.get_state()), ref) < 1e-12
+    fl = glbe.Flow(shape, bc, F, gamma, s)
+    sim2 = _sim(shape, bc, gamma, s, "f64", F)
+    sim2.step(60)
+    fl.step(60)
+    steps = {int(h[0]): h for h in sim2.history()}
+    for t, r in fl.history:
+        assert abs(steps[t][1] - r) <= 1e-14 + 1e-8 * r
+
+
 def test_uniform_force_equals_field_of_constants():
     torch = _torch()
     shape, bc = (8, 6, 10), (PER, WALL, WALL)
