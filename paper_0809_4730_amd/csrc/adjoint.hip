@@ -90,12 +90,13 @@ __global__ __launch_bounds__(kBlock) void adjoint_step(
     }
     R nu[Q19], gx, gy, gz;
     collide19_adjoint<R>(f, Fx, Fy, Fz, c, lam, nu, gx, gy, gz);
+    R mu[Q19];
 #pragma unroll
     for (int a = 0; a < Q19; ++a) {
-      const R v = nu[a] + q_scale * R(EX19[a]);
-      Storage<R>::template st<NT>(elem<WIDE>(mu_out + int64_t(a) * g.stride, n), v);
-      if (CHECK) acc[2] += static_cast<double>(v);
+      mu[a] = nu[a] + q_scale * R(EX19[a]);
+      if (CHECK) acc[2] += static_cast<double>(mu[a]);
     }
+    store_planes<R, NT, WIDE, Q19>(mu_out, g, n, mu);
     if constexpr (GRAD == 1) {
       *elem<WIDE>(grad, n) += gx;
       *elem<WIDE>(grad + grad_stride, n) += gy;

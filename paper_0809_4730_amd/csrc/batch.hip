@@ -54,7 +54,7 @@ __global__ __launch_bounds__(kBlock) void batch_step(GridArgs g, BatchArgs ba,
     R f[Q19];
     gather19<S, false, WIDE>(fin, g.stride, n, b, c, f);
     const NodeMacro<R> mac = collide19<R>(f, c.F[0], c.F[1], c.F[2], c);
-    store19<S, false, WIDE>(fout, g.stride, n, f);
+    store19<S, false, WIDE>(fout, g, n, f);
     if constexpr (CHECK)
       check_node<R, WIDE>(g, usnap, n, mac.drho, mac.jx, mac.jy, mac.jz, mac.ux, mac.uy, mac.uz, acc);
   }

@@ -130,12 +130,33 @@ __device__ __forceinline__ void st_pop(T* p, T v) {
     *p = v;
 }
 
+// Buffer resource over an array (raw addressing, no range limit): stores
+// through it take a scalar and a 32-bit vector byte offset.  Word 3 is the
+// gfx9 raw-buffer format.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(p, 0, 0xffffffff, 0x00020000);
+}
+
+// cache policy of a buffer store: nt (streaming) or default
+template <bool NT>
+constexpr int buf_policy() {
+  return NT ? 2 : 0;
+}
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
 template <>
 struct Storage<double> {
   using R = double;
   __device__ __forceinline__ static R ld(const double* p) { return ld_pop(p); }
   template <bool NT = false>
   __device__ __forceinline__ static void st(double* p, R v) { st_pop<NT>(p, v); }
+  template <bool NT = false>
+  __device__ __forceinline__ static void st_buf(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                uint32_t soff, R v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff,
+                                          buf_policy<NT>());
+  }
 };
 
 template <>
@@ -144,6 +165,11 @@ struct Storage<float> {
   __device__ __forceinline__ static R ld(const float* p) { return ld_pop(p); }
   template <bool NT = false>
   __device__ __forceinline__ static void st(float* p, R v) { st_pop<NT>(p, v); }
+  template <bool NT = false>
+  __device__ __forceinline__ static void st_buf(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                uint32_t soff, R v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, buf_policy<NT>());
+  }
 };
 
 template <>
@@ -157,6 +183,12 @@ struct Storage<bf16_t> {
   __device__ __forceinline__ static void st(bf16_t* p, R v) {
     st_pop<NT>(&p->bits, __builtin_bit_cast(uint16_t, static_cast<__bf16>(v)));
   }
+  template <bool NT = false>
+  __device__ __forceinline__ static void st_buf(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                uint32_t soff, R v) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, static_cast<__bf16>(v)), r,
+                                          voff, soff, buf_policy<NT>());
+  }
 };
 
 template <>
@@ -166,6 +198,12 @@ struct Storage<_Float16> {
   template <bool NT = false>
   __device__ __forceinline__ static void st(_Float16* p, R v) {
     st_pop<NT>(p, static_cast<_Float16>(v));
+  }
+  template <bool NT = false>
+  __device__ __forceinline__ static void st_buf(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                uint32_t soff, R v) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, static_cast<_Float16>(v)),
+                                          r, voff, soff, buf_policy<NT>());
   }
 };
 

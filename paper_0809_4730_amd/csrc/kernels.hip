@@ -149,14 +149,14 @@ __device__ __forceinline__ void collide_g(R (&g)[3][Q7], const Coupled<R>& cp, R
 }
 
 template <typename R, bool NT, bool WIDE>
-__device__ __forceinline__ void store_g(R* __restrict__ gout, int64_t stride, uint32_t n,
+__device__ __forceinline__ void store_g(R* __restrict__ gout, const GridArgs& ga, uint32_t n,
                                         const R (&g)[3][Q7]) {
+  R flat[3 * Q7];
 #pragma unroll
   for (int j = 0; j < 3; ++j)
 #pragma unroll
-    for (int a = 0; a < Q7; ++a)
-      Storage<R>::template st<NT>(elem<WIDE>(gout + static_cast<int64_t>(j * Q7 + a) * stride, n),
-                                  g[j][a]);
+    for (int a = 0; a < Q7; ++a) flat[j * Q7 + a] = g[j][a];
+  store_planes<R, NT, WIDE, 3 * Q7>(gout, ga, n, flat);
 }
 
 template <typename R, bool WIDE>
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<type
     R Fx, Fy, Fz;
     load_force<R, WIDE>(g, c, force, FIELD, n, Fx, Fy, Fz);
     const NodeMacro<R> mac = collide19<R>(f, Fx, Fy, Fz, c);
-    store19<S, NT, WIDE>(fout, g.stride, n, f);
+    store19<S, NT, WIDE>(fout, g, n, f);
     if constexpr (CHECK)
       check_node<R, WIDE>(g, usnap, n, mac.drho, mac.jx, mac.jy, mac.jz, mac.ux, mac.uy, mac.uz, acc);
   }
@@ -230,14 +230,14 @@ __global__ __launch_bounds__(kBlock) void mhd_step(GridArgs g, CollideArgs<R> c,
       const Coupled<R> cp = lorentz_solve<R>(f, gg, Fx, Fy, Fz, c, m);
       const NodeMacro<R> mac = collide19<R>(f, cp.Fx, cp.Fy, cp.Fz, c);
       collide_g<R>(gg, cp, mac.ux, mac.uy, mac.uz, m);
-      store19<R, NT, WIDE>(fout, g.stride, n, f);
+      store19<R, NT, WIDE>(fout, g, n, f);
       if constexpr (CHECK)
         check_node<R, WIDE>(g, usnap, n, mac.drho, mac.jx, mac.jy, mac.jz, mac.ux, mac.uy, mac.uz, acc);
     } else {
       const Coupled<R> cp = field_only<R>(gg, m);
       collide_g<R>(gg, cp, R(0), R(0), R(0), m);
     }
-    store_g<R, NT, WIDE>(gout, g.stride, n, gg);
+    store_g<R, NT, WIDE>(gout, g, n, gg);
   }
   if constexpr (CHECK) write_partials(partials, lb, acc);
 }

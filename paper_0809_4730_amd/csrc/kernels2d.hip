@@ -29,11 +29,9 @@ __device__ __forceinline__ void gather9(const S* __restrict__ fin, int64_t strid
 }
 
 template <typename S, bool NT, bool WIDE>
-__device__ __forceinline__ void store9(S* __restrict__ fout, int64_t stride, uint32_t n,
+__device__ __forceinline__ void store9(S* __restrict__ fout, const GridArgs& g, uint32_t n,
                                        const typename Storage<S>::R (&f)[Q9]) {
-#pragma unroll
-  for (int a = 0; a < Q9; ++a)
-    Storage<S>::template st<NT>(elem<WIDE>(fout + static_cast<int64_t>(a) * stride, n), f[a]);
+  store_planes<S, NT, WIDE, Q9>(fout, g, n, f);
 }
 
 // Anti-bounce-back at a wall in deviation form: d_a = -d~_opp(a).
@@ -164,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void glbe2_step(GridArgs g, CollideArgs<typ
     R Fx, Fy;
     load_force2<R, WIDE>(g, c, force, FIELD, n, Fx, Fy);
     const NodeMacro<R> mac = collide9<R>(f, Fx, Fy, c);
-    store9<S, NT, WIDE>(fout, g.stride, n, f);
+    store9<S, NT, WIDE>(fout, g, n, f);
     if constexpr (CHECK) check_node2<R, WIDE>(g, usnap, n, mac, acc);
   }
   if constexpr (CHECK) write_partials(partials, lb, acc);
@@ -192,13 +190,13 @@ __global__ __launch_bounds__(kBlock) void mhd2_step(GridArgs g, CollideArgs<R> c
     const Coupled2<R> cp = lorentz_solve2<R>(f, gg, Fx, Fy, c, m);
     const NodeMacro<R> mac = collide9<R>(f, cp.Fx, cp.Fy, c);
     collide_g5<R>(gg, cp, mac.ux, mac.uy, m);
-    store9<R, NT, WIDE>(fout, g.stride, n, f);
+    store9<R, NT, WIDE>(fout, g, n, f);
+    R gflat[2 * Q5];
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int a = 0; a < Q5; ++a)
-        Storage<R>::template st<NT>(elem<WIDE>(gout + static_cast<int64_t>(j * Q5 + a) * g.stride, n),
-                                    gg[j][a]);
+      for (int a = 0; a < Q5; ++a) gflat[j * Q5 + a] = gg[j][a];
+    store_planes<R, NT, WIDE, 2 * Q5>(gout, g, n, gflat);
     if constexpr (CHECK) check_node2<R, WIDE>(g, usnap, n, mac, acc);
   }
   if constexpr (CHECK) write_partials(partials, lb, acc);

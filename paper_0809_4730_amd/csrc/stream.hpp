@@ -23,14 +23,17 @@ inline hipError_t with_flag(bool b, F&& f) {
   return b ? f(std::true_type{}) : f(std::false_type{});
 }
 
-// Whether a launch needs 64-bit element offsets: a kernel addresses at most
-// 2 * stride elements of `elem_bytes` from any of its base pointers.
-// LBM_WIDE_OFFSETS=1 in the environment forces the 64-bit form (read at each
-// launch, so that tests can run both forms on small lattices).
+// Whether a launch needs 64-bit element offsets.  The narrow form reaches
+// every array through 32-bit byte offsets from one base: loads within 2 planes
+// of a pair's base, stores anywhere in an array of up to 21 planes (the
+// magnetic populations), so it needs 21 * stride * elem_bytes < 2^32 (FP32:
+// lattices up to ~51 M nodes).  LBM_WIDE_OFFSETS=1 in the environment forces
+// the 64-bit form (read at each launch, so that tests can run both forms on
+// small lattices).
 inline bool wide_offsets(const GridArgs& g, size_t elem_bytes) {
   const char* e = std::getenv("LBM_WIDE_OFFSETS");
   if (e && e[0] == '1') return true;
-  return 2.0 * static_cast<double>(g.stride) * static_cast<double>(elem_bytes) >= 4294967296.0;
+  return 21.0 * static_cast<double>(g.stride) * static_cast<double>(elem_bytes) >= 4294967296.0;
 }
 
 // Per-node neighbour offsets for pull streaming.
@@ -196,12 +199,31 @@ __device__ __forceinline__ void gather19(const S* __restrict__ fin, int64_t stri
   }
 }
 
-template <typename S, bool NT, bool WIDE>
-__device__ __forceinline__ void store19(S* __restrict__ fout, int64_t stride, uint32_t n,
-                                        const typename Storage<S>::R (&f)[Q19]) {
+// Narrow form: buffer stores through one resource at the array's base, the
+// plane's byte offset in the scalar offset and the node's in the vector offset
+// (no address arithmetic per store; wide_offsets keeps every offset below
+// 2^32).
+template <typename S, bool NT, bool WIDE, int Q>
+__device__ __forceinline__ void store_planes(S* __restrict__ out, const GridArgs& g, uint32_t n,
+                                             const typename Storage<S>::R (&v)[Q]) {
+  if constexpr (WIDE) {
 #pragma unroll
-  for (int a = 0; a < Q19; ++a)
-    Storage<S>::template st<NT>(elem<WIDE>(fout + static_cast<int64_t>(a) * stride, n), f[a]);
+    for (int a = 0; a < Q; ++a)
+      Storage<S>::template st<NT>(out + static_cast<int64_t>(a) * g.stride + n, v[a]);
+  } else {
+    const __amdgpu_buffer_rsrc_t r = raw_rsrc(out);
+    const uint32_t plane = static_cast<uint32_t>(g.stride) * static_cast<uint32_t>(sizeof(S));
+    const uint32_t voff = n * static_cast<uint32_t>(sizeof(S));
+#pragma unroll
+    for (int a = 0; a < Q; ++a)
+      Storage<S>::template st_buf<NT>(r, voff, static_cast<uint32_t>(a) * plane, v[a]);
+  }
+}
+
+template <typename S, bool NT, bool WIDE>
+__device__ __forceinline__ void store19(S* __restrict__ fout, const GridArgs& g, uint32_t n,
+                                        const typename Storage<S>::R (&f)[Q19]) {
+  store_planes<S, NT, WIDE, Q19>(fout, g, n, f);
 }
 
 // Residual / reduction bookkeeping of one node, accumulated in FP64.  The
