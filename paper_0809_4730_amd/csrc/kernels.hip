@@ -417,7 +417,7 @@ hipError_t launch_glbe_step(const GridArgs& g, const CollideArgs<typename Storag
   const S* a = static_cast<const S*>(fin);
   S* b = static_cast<S*>(fout);
   const R* F = static_cast<const R*>(force);
-  // moving walls: small problems, regular stores, general addressing
+  // moving walls: small problems, regular stores
   return with_flag(check, [&](auto CH) {
     return with_flag(field, [&](auto FL) {
       return with_flag(wide_offsets(g, sizeof(R)), [&](auto W) {
@@ -425,7 +425,7 @@ hipError_t launch_glbe_step(const GridArgs& g, const CollideArgs<typename Storag
           constexpr bool ch = decltype(CH)::value, fl = decltype(FL)::value,
                          w = decltype(W)::value, rw = decltype(RW)::value;
           if (c.moving)
-            glbe_step<S, ch, fl, false, true, w, false>
+            glbe_step<S, ch, fl, false, true, w, rw>
                 <<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
           else if (nt)
             glbe_step<S, ch, fl, true, false, w, rw>

@@ -316,11 +316,13 @@ def test_naive_source_mode_matches_oracle(storage):
     assert rel(cons, ref) > 1e-6
 
 
-def test_moving_walls_match_oracle():
+@pytest.mark.parametrize("shape", [(5, 7, 9), (64, 3, 4)])
+def test_moving_walls_match_oracle(shape):
     """Every face moving with its own velocity (edges and corners take the mean
-    of the crossed faces' wall terms): FP64 steps against the oracle."""
+    of the crossed faces' wall terms): FP64 steps against the oracle (nx = 64:
+    the row-aligned variant)."""
     torch = _torch()
-    shape, bc = (5, 7, 9), (WALL, WALL, WALL)
+    bc = (WALL, WALL, WALL)
     rng = np.random.default_rng(31)
     wu = 0.01 * rng.uniform(-1, 1, (6, 3))
     d0 = inputs.random_deviations(shape, seed=31, amp=1e-3)
