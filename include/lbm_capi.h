@@ -180,6 +180,13 @@ lbm_status lbm_workspace_bytes(const lbm_grid* grid, const lbm_params* params, s
  * [3][N], FP64 for F64 storage, FP32 otherwise) into the workspace.
  * `workspace` is a device pointer owned by the caller that must outlive the
  * context; `hip_stream` is a hipStream_t (NULL = default stream).
+ * Launch shape: when the two population buffers exceed 512 MB (lattices that
+ * stream from HBM), lbm_create times a few dozen plain steps on the stream for
+ * each of three XCD workgroup mappings, keeps the fastest and restores the
+ * rest state; it then synchronizes (a few ms to a few tens of ms).  The
+ * mapping decides only which workgroup updates which nodes: results are the
+ * same whichever is chosen.  LBM_XCD_CHUNK=<n> in the environment fixes it
+ * instead (and LBM_NT_STORE=0/1 the store type).
  * Errors: LBM_EINVAL (grid, rates, gamma, mhd parameters, unsupported
  * combination), LBM_ENOWS, LBM_EHIP.  On error *out is NULL and the message
  * is available from lbm_last_error(NULL). */

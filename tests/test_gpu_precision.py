@@ -66,3 +66,30 @@ def test_precision_forms_transient_duct256():
         err = rel(us[st], us["f64"])
         announce("256^3 storage %s: u_x rel L2 vs FP64 after %d steps = %.3e" % (st, n, err))
         assert err < {"f32": 1e-5, "bf16": 0.05, "f16": 0.02}[st]
+
+
+def test_create_time_launch_shape_choice_keeps_the_rest_state(monkeypatch):
+    """256^3 FP32 (2.5 GB of populations): lbm_create times three workgroup
+    mappings on the plain step, then restores the rest state.  The state is
+    zero and the step counter 0 after create, and the first 12 steps (one
+    residual check) agree bit for bit with a context whose mapping is fixed (no timing)."""
+    import torch
+    announce("create-time launch shape, 256^3")
+    shape, gamma = (256, 256, 256), 1.0
+    monkeypatch.delenv("LBM_XCD_CHUNK", raising=False)
+    tuned = _sim(shape, "f32", gamma)
+    assert tuned.t == 0
+    assert int(torch.count_nonzero(tuned.get_state())) == 0
+    tuned.step(12)
+    a = tuned.get_state()
+    h = tuned.history(4)
+    del tuned
+    torch.cuda.empty_cache()
+    monkeypatch.setenv("LBM_XCD_CHUNK", "2")
+    fixed = _sim(shape, "f32", gamma)
+    monkeypatch.delenv("LBM_XCD_CHUNK", raising=False)
+    fixed.step(12)
+    assert torch.equal(a, fixed.get_state())
+    assert np.array_equal(h, fixed.history(4))
+    del fixed, a
+    torch.cuda.empty_cache()
