@@ -69,8 +69,9 @@ struct GridArgs {
 // Workgroup b of the launch runs on XCD (b mod 8) as that XCD's (b / 8)-th
 // workgroup.  XCDs take chunks of xcd_chunk consecutive logical blocks in turn:
 // chunk = blocks_per_xcd gives each XCD one contiguous slab (neighbour rows stay
-// in its L2: best when the lattice lives in the caches), chunk = 1 interleaves
-// single blocks (all XCDs stream the same DRAM pages: best from HBM).
+// in its L2: best when the lattice lives in the caches); small chunks keep all
+// XCDs on the same DRAM pages (the host picks among them for lattices that
+// stream from HBM).
 __device__ __forceinline__ int logical_block(const GridArgs& g) {
   const uint32_t b = blockIdx.x;
   const uint32_t xcd = b & (kXcd - 1);

@@ -12,7 +12,8 @@
 // Every population is read once and written once per step; the step is
 // bandwidth-bound, so there is no LDS staging and no MFMA.  Halfway bounce-back
 // needs no solid nodes: a link crossing a wall reads the opposite direction's
-// post-collision value at the same node.
+// post-collision value at the same node.  Loads take a scalar base and a
+// 32-bit node offset; stores go through a buffer resource (store_planes).
 #include "collide.hpp"
 #include "launch.hpp"
 #include "stream.hpp"
