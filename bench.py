@@ -293,8 +293,55 @@ def extras(args):
     out["precision_duct64"] = precision_table()
     out["adjoint"] = adjoint_extras()
     out.update(cavity_extras())
+    out["naive_source_control"] = naive_source_extras()
     out["d2q9"] = d2q9_extras()
     out["stability_envelope"] = stability_extras()
+    return out
+
+
+def naive_source_extras():
+    """Sec. 3.1 negative control on the GPU: steady states of a two-mode forcing
+    F = F0 (sin ky, sin 2kx, 0) on a periodic LxLx1 lattice (FP64, MRT rates,
+    residual 1e-11) with the preconditioned source and with the naive S/gamma.
+    The naive form departs from the consistent one in proportion to
+    (1 - gamma)/gamma^2.  The consistent form's own gamma-dependence is the
+    lattice's truncation error, which grows with tau* = 3 nu/gamma + 1/2 and
+    falls as (k dx)^2: shown at L = 64 and 128 with the same velocity amplitude."""
+    import numpy as np
+    import torch
+
+    import paper_0809_4730_amd as pkg
+    nu, F64 = 0.1, 1e-6
+    per = ("periodic",) * 3
+
+    def steady(L, gamma, source):
+        F0 = F64 * (64 / L) ** 2  # the same velocity amplitude at every L
+        k = 2 * np.pi / L
+        x = np.arange(L) + 0.5
+        F = np.zeros((3, 1, L, L))
+        F[0] = F0 * np.sin(k * x)[None, :, None]
+        F[1] = F0 * np.sin(2 * k * x)[None, None, :]
+        sim = pkg.Simulation((L, L, 1), per, gamma, pkg.default_rates(nu, gamma), storage="f64",
+                             force=torch.tensor(F, dtype=torch.float64, device="cuda"),
+                             source=source)
+        steps, r = sim.run_to_residual(1e-11, 4000000, poll_every=2000)
+        _, u, _ = sim.moments("f64")
+        return u.cpu().numpy(), steps
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    out = {"nu": nu, "F0_at_L64": F64, "F0": "F0_at_L64 (64/L)^2"}
+    for L in (64, 128):
+        u1, _ = steady(L, 1.0, "precond")
+        rows = []
+        for g in ((0.5, 0.2, 0.1) if L == 64 else (0.1,)):
+            uc, nc = steady(L, g, "precond")
+            un, nn = steady(L, g, "naive")
+            d = rel(un, uc)
+            rows.append({"gamma": g, "consistent_vs_gamma1": rel(uc, u1), "naive_vs_consistent": d,
+                         "naive_vs_consistent_over_(1-g)/g^2": d / ((1 - g) / g ** 2),
+                         "steps_consistent": nc, "steps_naive": nn})
+        out["L%d" % L] = rows
     return out
 
 
