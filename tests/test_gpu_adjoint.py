@@ -107,6 +107,45 @@ def test_steady_adjoint_duct_vs_finite_differences(storage, tol):
     assert abs(d - fd) < tol * abs(fd), (d, fd)
 
 
+def test_steady_adjoint_duct128_vs_finite_differences():
+    """The adjoint workload at full size and in the bench's configuration:
+    128^3 duct, FP32 storage, gamma = 0.1.  <dQ/dF, v> against central
+    differences of two FP64 forward marches to steady state."""
+    import torch
+    cfg = inputs.ADJOINT
+    shape, bc, gamma = cfg["shape"], cfg["bc"], 0.1
+    announce("steady adjoint duct128 fp32")
+    s = glbe.rates(cfg["nu"], gamma)
+    F = inputs.duct_force(shape, cfg["F0"])
+    nx, ny, nz = shape
+    y = np.arange(ny) + 0.5
+    z = np.arange(nz) + 0.5
+    v = np.zeros_like(F)
+    v[0] = 1e-5 * ((1 + 0.3 * np.cos(np.pi * z / nz))[:, None] *
+                   (1 + 0.2 * np.sin(2 * np.pi * y / ny))[None, :])[:, :, None]
+    v[1] = 3e-6 * np.sin(np.pi * y / ny)[None, :, None]
+    ref = _sim(shape, bc, gamma, s, "f64", F)
+    assert ref.run_to_residual(1e-10, 400000, poll_every=1000)[0] > 0
+    sim = _sim(shape, bc, gamma, s, "f32", F)
+    sim.step(ref.t + 2000)
+    grad, iters, change = sim.adjoint_steady(tol=1e-6, max_iter=2 * ref.t + 40000)
+    d = float((grad.double().cpu().numpy() * v).sum())
+    del ref, sim, grad
+    torch.cuda.empty_cache()
+    eps = 1e-2
+    q = []
+    for sg in (1, -1):
+        simf = _sim(shape, bc, gamma, s, "f64", F + sg * eps * v)
+        assert simf.run_to_residual(1e-12, 400000, poll_every=1000)[0] > 0
+        simf.step(1000)
+        q.append(simf.reductions()[1])
+        del simf
+        torch.cuda.empty_cache()
+    fd = (q[0] - q[1]) / (2 * eps)
+    assert abs(fd) > 0
+    assert abs(d - fd) < 2e-3 * abs(fd), (d, fd)
+
+
 def test_unrolled_adjoint_matches_oracle_elementwise():
     announce("unrolled adjoint tiny")
     shape, bc, gamma, n = (1, 2, 4), (PER, WALL, WALL), 1.0, 40

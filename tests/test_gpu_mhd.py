@@ -62,9 +62,13 @@ def test_mhd_fp64_matches_oracle(shape, bc, nsteps):
     assert rel(Bg.cpu().numpy(), B_o) < 1e-14
 
 
-def test_mhd_fp32_single_step():
+@pytest.mark.parametrize("shape", [(6, 8, 5), (32, 32, 128)])
+def test_mhd_fp32_single_step(shape):
+    """One coupled FP32 step from a random state against the oracle, on a small
+    lattice and at the Hartmann workload's full size (its launch shape)."""
     import torch
-    shape, bc = (6, 8, 5), (PER, WALL, PER)
+    announce("mhd fp32 single step %s" % (shape,))
+    bc = (PER, WALL, PER)
     gamma, gm = 0.1, 0.1
     B0 = np.array([0.0, 0.03, 0.0])
     p = dict(gamma_m=gm, chi=0.01, eta=0.025, B0=tuple(B0))
