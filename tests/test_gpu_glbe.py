@@ -78,9 +78,13 @@ def test_fp64_many_steps_match_oracle(shape, bc):
 
 
 # nx a multiple of 64: every wave lies in one x-row, and the step takes its y/z
-# neighbours and wall flags as wave-uniform values (the row-aligned variant)
+# neighbours and wall flags as wave-uniform values (the row-aligned variants:
+# through the row table when x is periodic, else per-face flags)
 ROW_GRIDS = [
     ((64, 3, 4), (PER, WALL, WALL)),
+    ((64, 1, 3), (PER, WALL, WALL)),   # ny = 1: every row touches both y faces
+    ((128, 3, 1), (PER, PER, WALL)),   # nz = 1
+    ((64, 2, 5), (PER, PER, PER)),
     ((64, 2, 3), (WALL, PER, WALL)),
     ((128, 2, 2), (WALL, WALL, PER)),
 ]
