@@ -294,6 +294,7 @@ def extras(args):
     out["adjoint"] = adjoint_extras()
     out.update(cavity_extras())
     out["naive_source_control"] = naive_source_extras()
+    out["paper_poiseuille_nu0.001"] = paper_poiseuille_extras()
     out["d2q9"] = d2q9_extras()
     out["stability_envelope"] = stability_extras()
     return out
@@ -343,6 +344,41 @@ def naive_source_extras():
                          "steps_consistent": nc, "steps_naive": nn})
         out["L%d" % L] = rows
     return out
+
+
+def paper_poiseuille_extras():
+    """The paper's low-viscosity plane Poiseuille case (Sec. 5): gap 2L = 64
+    between halfway bounce-back walls, nu = 0.001, u_max = 0.00051 (Re = 32.6),
+    FP64, residual 1e-8, for gamma = 1 ... 0.001: steps, wall time and the
+    profile's error against the parabola."""
+    import numpy as np
+    import torch
+
+    import paper_0809_4730_amd as pkg
+    from paper_0809_4730_amd import stability
+    nu, umax, H = 0.001, 0.00051, 64
+    F = stability.poiseuille_force(nu, umax, H)
+    z = np.arange(H) + 0.5
+    exact = umax * (1.0 - ((z - H / 2) / (H / 2)) ** 2)
+    rows = []
+    for g in (1.0, 0.1, 0.01, 0.001):
+        sim = pkg.Simulation((4, 4, H), ("periodic", "periodic", "wall"), g,
+                             pkg.default_rates(nu, g), storage="f64", force=(F, 0.0, 0.0))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps, r = sim.run_to_residual(1e-8, 6000000, poll_every=5000)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        _, u, _ = sim.moments("f64")
+        ux = u[0].cpu().numpy()[:, 0, 0]
+        rows.append({"gamma": g, "steps": int(steps), "wall_s": round(wall, 3),
+                     "profile_rel_error": float(np.linalg.norm(ux - exact) / np.linalg.norm(exact))})
+        sim.close()
+    for e in rows[1:]:
+        if e["steps"] > 0 and rows[0]["steps"] > 0:
+            e["step_ratio_vs_gamma1"] = round(rows[0]["steps"] / e["steps"], 1)
+            e["wall_ratio_vs_gamma1"] = round(rows[0]["wall_s"] / e["wall_s"], 1)
+    return {"nu": nu, "u_max": umax, "gap": H, "Re": umax * H / nu, "rows": rows}
 
 
 def stability_extras():
