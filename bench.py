@@ -295,6 +295,7 @@ def extras(args):
     out.update(cavity_extras())
     out["naive_source_control"] = naive_source_extras()
     out["paper_poiseuille_nu0.001"] = paper_poiseuille_extras()
+    out["paper_hartmann_Re286_Ha71.6"] = paper_hartmann_extras()
     out["d2q9"] = d2q9_extras()
     out["stability_envelope"] = stability_extras()
     return out
@@ -379,6 +380,45 @@ def paper_poiseuille_extras():
             e["step_ratio_vs_gamma1"] = round(rows[0]["steps"] / e["steps"], 1)
             e["wall_ratio_vs_gamma1"] = round(rows[0]["wall_s"] / e["wall_s"], 1)
     return {"nu": nu, "u_max": umax, "gap": H, "Re": umax * H / nu, "rows": rows}
+
+
+def paper_hartmann_extras():
+    """The paper's Hartmann case for the (gamma, gamma_m) study (Sec. 5):
+    Re = 286, Ha = 71.6, Pm = 1e-6, nu = eta = 0.004, half-width L = 64 (128
+    nodes between walls normal to y and the applied field), FP64, residual 1e-8:
+    steps for gamma = 0.05 with several gamma_m, for gamma = 1, and for equal
+    pairs; the centreline velocity against the Re = 286 target."""
+    import torch
+
+    import paper_0809_4730_amd as pkg
+    from paper_0809_4730_amd import inputs
+    nu = eta = 0.004
+    ny, Ha, Pm = 128, 71.6, 1e-6
+    B0, chi = inputs.hartmann_parameters(Ha, Pm, ny, nu, eta)
+    uc = 286 * nu / (ny / 2)
+    F = uc * nu * Ha / (ny / 2) ** 2  # flat-core Hartmann centreline u = F L^2 / (nu Ha)
+    rows = []
+    for g, gm in ((0.05, 1.0), (0.05, 0.2), (0.05, 0.05), (0.05, 0.02), (1.0, 1.0), (1.0, 0.2),
+                  (1.0, 0.05), (0.2, 0.2), (0.1, 0.1), (0.02, 0.02)):
+        sim = pkg.Simulation((4, ny, 4), ("periodic", "wall", "periodic"), g,
+                             pkg.default_rates(nu, g), storage="f64", force=(F, 0.0, 0.0),
+                             mhd=dict(gamma_m=gm, chi=chi, eta=eta, B0=(0.0, B0, 0.0)))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            steps, r = sim.run_to_residual(1e-8, 2000000, poll_every=2000)
+            status = "ok" if steps > 0 else "not reached"
+        except pkg.LbmError as e:
+            steps, status = -1, "error: %s" % e
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        _, u, _ = sim.moments("f64")
+        rows.append({"gamma": g, "gamma_m": gm, "steps": int(steps), "wall_s": round(wall, 3),
+                     "status": status,
+                     "u_center_over_target": float(u[0, 0, ny // 2, 0].item()) / uc})
+        sim.close()
+    return {"Re": 286, "Ha": Ha, "Pm": Pm, "nu": nu, "eta": eta, "B0": B0, "chi": chi, "F": F,
+            "rows": rows}
 
 
 def stability_extras():
