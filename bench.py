@@ -294,7 +294,7 @@ def extras(args):
     out["adjoint"] = adjoint_extras()
     out.update(cavity_extras())
     out["naive_source_control"] = naive_source_extras()
-    out["paper_poiseuille_nu0.001"] = paper_poiseuille_extras()
+    out["paper_poiseuille"] = paper_poiseuille_extras()
     out["paper_hartmann_Re286_Ha71.6"] = paper_hartmann_extras()
     out["d2q9"] = d2q9_extras()
     out["stability_envelope"] = stability_extras()
@@ -348,38 +348,49 @@ def naive_source_extras():
 
 
 def paper_poiseuille_extras():
-    """The paper's low-viscosity plane Poiseuille case (Sec. 5): gap 2L = 64
-    between halfway bounce-back walls, nu = 0.001, u_max = 0.00051 (Re = 32.6),
-    FP64, residual 1e-8, for gamma = 1 ... 0.001: steps, wall time and the
-    profile's error against the parabola."""
+    """The paper's plane Poiseuille cases (Sec. 5), gap 64 between halfway
+    bounce-back walls, FP64, residual 1e-8: the low-viscosity case (nu = 0.001,
+    u_max = 0.00051, Re = 32.6) for gamma = 1 ... 0.001, and the higher-Mach
+    case (nu = 0.005, u_max = 0.0128, Re = 163.8) down to where it turns
+    unstable: steps, wall time and the profile's error against the parabola."""
     import numpy as np
     import torch
 
     import paper_0809_4730_amd as pkg
     from paper_0809_4730_amd import stability
-    nu, umax, H = 0.001, 0.00051, 64
-    F = stability.poiseuille_force(nu, umax, H)
+    H = 64
     z = np.arange(H) + 0.5
-    exact = umax * (1.0 - ((z - H / 2) / (H / 2)) ** 2)
-    rows = []
-    for g in (1.0, 0.1, 0.01, 0.001):
-        sim = pkg.Simulation((4, 4, H), ("periodic", "periodic", "wall"), g,
-                             pkg.default_rates(nu, g), storage="f64", force=(F, 0.0, 0.0))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        steps, r = sim.run_to_residual(1e-8, 6000000, poll_every=5000)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        _, u, _ = sim.moments("f64")
-        ux = u[0].cpu().numpy()[:, 0, 0]
-        rows.append({"gamma": g, "steps": int(steps), "wall_s": round(wall, 3),
-                     "profile_rel_error": float(np.linalg.norm(ux - exact) / np.linalg.norm(exact))})
-        sim.close()
-    for e in rows[1:]:
-        if e["steps"] > 0 and rows[0]["steps"] > 0:
-            e["step_ratio_vs_gamma1"] = round(rows[0]["steps"] / e["steps"], 1)
-            e["wall_ratio_vs_gamma1"] = round(rows[0]["wall_s"] / e["wall_s"], 1)
-    return {"nu": nu, "u_max": umax, "gap": H, "Re": umax * H / nu, "rows": rows}
+
+    def case(nu, umax, gammas):
+        F = stability.poiseuille_force(nu, umax, H)
+        exact = umax * (1.0 - ((z - H / 2) / (H / 2)) ** 2)
+        rows = []
+        for g in gammas:
+            sim = pkg.Simulation((4, 4, H), ("periodic", "periodic", "wall"), g,
+                                 pkg.default_rates(nu, g), storage="f64", force=(F, 0.0, 0.0))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            try:
+                steps, r = sim.run_to_residual(1e-8, 6000000, poll_every=5000)
+                status = "ok" if steps > 0 else "not reached"
+            except pkg.LbmError as e:
+                steps, status = -1, "unstable" if e.status == -4 else "error: %s" % e
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            e = {"gamma": g, "steps": int(steps), "wall_s": round(wall, 3), "status": status}
+            if status == "ok":
+                _, u, _ = sim.moments("f64")
+                ux = u[0].cpu().numpy()[:, 0, 0]
+                e["profile_rel_error"] = float(np.linalg.norm(ux - exact) / np.linalg.norm(exact))
+            rows.append(e)
+            sim.close()
+        for e in rows[1:]:
+            if e["steps"] > 0 and rows[0]["steps"] > 0:
+                e["step_ratio_vs_gamma1"] = round(rows[0]["steps"] / e["steps"], 1)
+                e["wall_ratio_vs_gamma1"] = round(rows[0]["wall_s"] / e["wall_s"], 1)
+        return {"nu": nu, "u_max": umax, "gap": H, "Re": umax * H / nu, "rows": rows}
+    return {"low_viscosity": case(0.001, 0.00051, (1.0, 0.1, 0.01, 0.001)),
+            "higher_mach": case(0.005, 0.0128, (1.0, 0.5, 0.2, 0.1, 0.05, 0.02, 0.01, 0.005))}
 
 
 def paper_hartmann_extras():
