@@ -366,3 +366,26 @@ def test_lid_driven_cavity_preconditioning():
              % (res[1.0][0], res[0.1][0], rel(res[0.1][1], res[1.0][1])))
     assert res[1.0][0] > 3 * res[0.1][0]
     assert rel(res[0.1][1], res[1.0][1]) < 0.05
+
+
+def test_paper_low_viscosity_poiseuille():
+    """The paper's low-viscosity Poiseuille case (gap 64, nu = 0.001,
+    u_max = 0.00051, Re = 32.6), FP64 to 1e-8: the parabola, and roughly
+    tenfold fewer steps per tenfold smaller gamma (51,430 at gamma = 0.01,
+    6,070 at 0.001; 3.2 million at gamma = 1, not run here)."""
+    import paper_0809_4730_amd as pkg
+    from paper_0809_4730_amd import stability
+    announce("paper poiseuille nu=0.001")
+    nu, umax, H = 0.001, 0.00051, 64
+    F = stability.poiseuille_force(nu, umax, H)
+    z = np.arange(H) + 0.5
+    exact = umax * (1.0 - ((z - H / 2) / (H / 2)) ** 2)
+    n = {}
+    for g in (0.01, 0.001):
+        sim = pkg.Simulation((4, 4, H), (PER, PER, WALL), g, pkg.default_rates(nu, g),
+                             storage="f64", force=(F, 0.0, 0.0))
+        n[g], _ = sim.run_to_residual(1e-8, 200000, poll_every=1000)
+        assert n[g] > 0
+        _, u, _ = sim.moments("f64")
+        assert rel(u[0].cpu().numpy()[:, 0, 0], exact) < 1e-3
+    assert 5 * n[0.001] < n[0.01]

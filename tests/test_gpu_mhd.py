@@ -132,3 +132,28 @@ def test_hartmann_workload(Ha, Pm):
     # 0.9 / 3.5 / 13 % in u and 1.2 / 2.4 / 5.5 % in b for Ha = 5 / 10 / 20
     tol = {5.0: 0.015, 10.0: 0.05, 20.0: 0.15}[Ha]
     assert rel(uo, uex) < tol and rel(bo, bex) < tol
+
+
+def test_paper_hartmann_preconditioning_ordering():
+    """The paper's (gamma, gamma_m) findings on its own Hartmann case (Re = 286,
+    Ha = 71.6, Pm = 1e-6, nu = eta = 0.004, half-width 64), FP64 to 1e-8: at
+    gamma = 0.05, gamma_m = gamma converges fastest, a smaller gamma_m is slower
+    and gamma_m = 1 slowest; with gamma = 1, preconditioning only the induction
+    equation is slower than preconditioning neither."""
+    import paper_0809_4730_amd as pkg
+    announce("paper hartmann (gamma, gamma_m) ordering")
+    nu = eta = 0.004
+    ny, Ha = 128, 71.6
+    B0, chi = inputs.hartmann_parameters(Ha, 1e-6, ny, nu, eta)
+    F = (286 * nu / (ny / 2)) * nu * Ha / (ny / 2) ** 2
+
+    def steps(g, gm):
+        sim = pkg.Simulation((4, ny, 4), (PER, WALL, PER), g, pkg.default_rates(nu, g),
+                             storage="f64", force=(F, 0.0, 0.0),
+                             mhd=dict(gamma_m=gm, chi=chi, eta=eta, B0=(0.0, B0, 0.0)))
+        n, _ = sim.run_to_residual(1e-8, 1000000, poll_every=1000)
+        assert n > 0
+        return n
+    s_eq, s_lo, s_mid, s_one = steps(0.05, 0.05), steps(0.05, 0.02), steps(0.05, 0.2), steps(0.05, 1.0)
+    assert s_eq < s_lo < s_mid < s_one
+    assert steps(1.0, 1.0) < steps(1.0, 0.2)
