@@ -161,6 +161,26 @@ def cpu_baseline(budget_s=12.0):
                       "cores = BLAS threads" % n}
 
 
+def cpu_time_to_residual_poiseuille():
+    """The FP64 oracle (numpy, on the host) marched to steady state on the plane
+    Poiseuille 8x8x32 workload (nu = 0.1, residual 1e-10) at gamma = 1 and 0.1:
+    the CPU-side time to steady state, next to the GPU's in the extras."""
+    import numpy as np
+
+    from oracle import glbe
+    from paper_0809_4730_amd import inputs
+    cfg = inputs.POISEUILLE
+    rows = []
+    for g in (1.0, 0.1):
+        fl = glbe.Flow(cfg["shape"], cfg["bc"], np.array(cfg["F"]), g, glbe.rates(cfg["nu"], g))
+        t0 = time.perf_counter()
+        ok = fl.run_to(cfg["tol"], 100000)
+        rows.append({"gamma": g, "steps": fl.t if ok else -1,
+                     "wall_s": round(time.perf_counter() - t0, 2)})
+    return {"kind": "oracle", "workload": "plane Poiseuille 8x8x32, FP64, residual 1e-10",
+            "rows": rows}
+
+
 def time_to_residual(shape, storage, gamma, tol, max_steps, make=None, poll=200, **kw):
     """Steps and wall time to a residual below tol; `make` builds the simulation
     (default: the duct of make_sim)."""
@@ -237,6 +257,8 @@ def extras(args):
         if tp[0]["steps"] > 0 and e["steps"] > 0:
             e["step_ratio_vs_gamma1"] = round(tp[0]["steps"] / e["steps"], 3)
     out["time_to_residual_poiseuille8x8x32_tol1e-10"] = tp
+    if not args.no_cpu:  # the oracle on the host, same workload (about a minute)
+        out["cpu_oracle_time_to_residual_poiseuille8x8x32"] = cpu_time_to_residual_poiseuille()
     ref = tt[0]
     if ref["steps"] > 0:
         for e in tt[1:]:
