@@ -189,3 +189,42 @@ def test_results_do_not_depend_on_the_xcd_chunk(monkeypatch, chunk):
     got = run()
     monkeypatch.delenv("LBM_XCD_CHUNK", raising=False)
     _same(ref, got)
+
+
+@pytest.mark.parametrize("case", ["mhd3d_128", "mhd2d_2048"])
+def test_create_time_shape_choice_coupled_lattices(monkeypatch, case):
+    """Coupled lattices above 512 MB of populations (128^3 flow + induction,
+    2048^2 D2Q9 + D2Q5): after the create-time timing of workgroup mappings
+    the state is the rest state and the first 12 steps match a context with a
+    fixed mapping bit for bit."""
+    import torch
+    import paper_0809_4730_amd as pkg
+    announce("create-time shape choice %s" % case)
+
+    def make():
+        if case == "mhd3d_128":
+            return pkg.Simulation((128, 128, 128), (PER, WALL, PER), 0.1, glbe.rates(0.1, 0.1),
+                                  storage="f32", force=(1e-5, 0.0, 0.0),
+                                  mhd=dict(gamma_m=0.1, chi=0.01, eta=0.025, B0=(0.0, 0.01, 0.0)))
+        return pkg.Simulation((2048, 2048, 1), (PER, WALL, PER), 0.1, d2q9.rates(0.1, 0.1),
+                              storage="f32", force=(1e-6, 0.0), lattice="d2q9",
+                              mhd=dict(gamma_m=0.1, chi=0.01, eta=0.025, B0=(0.0, 0.01)))
+    monkeypatch.delenv("LBM_XCD_CHUNK", raising=False)
+    tuned = make()
+    f, g = tuned.get_state()
+    assert int(torch.count_nonzero(f)) == 0 and int(torch.count_nonzero(g)) == 0
+    tuned.step(12)
+    a = tuned.get_state()
+    h = tuned.history(4)
+    tuned.close()
+    del tuned, f, g
+    torch.cuda.empty_cache()
+    monkeypatch.setenv("LBM_XCD_CHUNK", "2")
+    fixed = make()
+    monkeypatch.delenv("LBM_XCD_CHUNK", raising=False)
+    fixed.step(12)
+    _same(a, fixed.get_state())
+    _same(h, fixed.history(4))
+    fixed.close()
+    del fixed, a
+    torch.cuda.empty_cache()
