@@ -640,6 +640,59 @@ def adjoint_extras():
     return out
 
 
+def kernel_probe(name, launches, copy_probe):
+    """One JSON line for the profilers: `launches` plain launches of one
+    kernel at its HBM-scale size (coupled step 256^3 FP32, steady adjoint
+    128^3 FP32, D2Q9 step 4096^2 FP32), timed with HIP events, with its
+    algorithmic bytes per launch; optionally the calibration copy."""
+    import torch
+
+    import paper_0809_4730_amd as pkg
+    from paper_0809_4730_amd import inputs
+    if name == "mhd256":
+        cfg = inputs.HARTMANN
+        B0, chi = inputs.hartmann_parameters(10.0, 0.01, cfg["shape"][1], cfg["nu"], cfg["eta"])
+        sim = pkg.Simulation((256, 256, 256), cfg["bc"], 0.1, pkg.default_rates(cfg["nu"], 0.1),
+                             storage="f32", force=cfg["F"], check_every=NO_CHECK,
+                             mhd=dict(gamma_m=0.1, chi=chi, eta=cfg["eta"], B0=(0.0, B0, 0.0)))
+        us = kernel_time_us(sim, launches, warmup=5)
+        alg = 2 * (19 + 21) * 4 * sim.N
+        kernel = "mhd_step<float, check=false, field=false> (256^3)"
+    elif name == "adjoint128":
+        cfg = inputs.ADJOINT
+        sim = make_sim(cfg["shape"], "f32", 0.1)
+        sim.step(200)
+        sim.adjoint_steady(tol=1e-30, max_iter=20)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.adjoint_steady(tol=1e-30, max_iter=launches)
+        torch.cuda.synchronize()
+        us = 1e6 * (time.perf_counter() - t0) / launches
+        alg = (3 * 19 * 4 + 12) * sim.N  # mu in/out and the forward state; force
+        kernel = "adjoint_step<float> (128^3, iterations with their gradient checks)"
+    elif name == "d2q9_4096":
+        sim = pkg.Simulation((4096, 4096, 1), ("periodic", "wall", "periodic"), 0.1,
+                             pkg.default_rates_d2q9(0.1, 0.1), storage="f32", force=(1e-7, 0.0),
+                             check_every=NO_CHECK, lattice="d2q9")
+        us = kernel_time_us(sim, launches, warmup=5)
+        alg = 2 * 9 * 4 * sim.N
+        kernel = "glbe2_step<float, check=false> (4096^2)"
+    else:
+        raise SystemExit("unknown probe %s" % name)
+    sim.close()
+    line = {"probe": name, "kernel": kernel, "launches": launches, "kernel_us": round(us, 3),
+            "alg_bytes_per_launch": alg, "achieved_GBs": round(alg / (us * 1e-6) / 1e9, 1),
+            "kernel_hash": kernel_hash()}
+    if copy_probe:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_probe_bytes"] = src.numel() * 4
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -652,6 +705,9 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f32", "f64", "bf16", "f16"])
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
+    ap.add_argument("--probe", choices=["mhd256", "adjoint128", "d2q9_4096"],
+                    help="only time one other kernel at HBM scale (for the profilers)")
+    ap.add_argument("--launches", type=int, default=30)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -663,6 +719,9 @@ def main():
         sys.exit(1)
     import paper_0809_4730_amd as pkg
     pkg.load_library()
+    if args.probe:
+        kernel_probe(args.probe, args.launches, args.copy_probe)
+        return
 
     shape, gamma, storage = (args.grid,) * 3, 0.1, args.storage
     mlups, wall, mean_us = measure(shape, storage, gamma, args.steps, args.warmup)
