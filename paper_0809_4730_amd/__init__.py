@@ -304,6 +304,9 @@ class Simulation:
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self._stream = stream
+        # the library works on `stream`: the caching allocator must not hand this
+        # memory out again before that stream's work on it has finished
+        raw.record_stream(stream)
         ctx = ctypes.c_void_p()
         fptr = self._force_tensor.data_ptr() if self._force_tensor is not None else None
         _check(self._lib.lbm_create(ctypes.byref(self._grid), ctypes.byref(p), fptr,
