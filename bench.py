@@ -640,6 +640,50 @@ def adjoint_extras():
     return out
 
 
+def precision_steady_256():
+    """The precision form at full size: the 256^3 duct (C1 force, nu = 0.131,
+    gamma = 1) marched in FP64 to a residual of 1e-8, then FP32, BF16 and FP16
+    storage marched the same number of steps; u against FP64 per storage type,
+    and each one's residual floor."""
+    import numpy as np
+    import torch
+    shape = (256, 256, 256)
+    out = {"workload": "square duct 256^3, gamma = 1, nu = 0.131, C1 force"}
+    ref = make_sim(shape, "f64", 1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n = -1
+    while n < 0 and ref.t < 400000:  # in chunks, with a progress line each
+        n, r = ref.run_to_residual(1e-8, 20000, poll_every=2000)
+        print("f64 step %d residual %.3e" % (ref.t, r), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    out["f64"] = {"steps": int(n), "wall_s": round(time.perf_counter() - t0, 2), "residual": r}
+    _, u_ref, _ = ref.moments("f64")
+    u_ref = u_ref[0].cpu().numpy()
+    ref.close()
+    del ref
+    torch.cuda.empty_cache()
+    for st in ("f32", "bf16", "f16"):
+        sim = make_sim(shape, st, 1.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while sim.t < n:
+            sim.step(min(20000, int(n) - sim.t))
+            torch.cuda.synchronize()
+            print("%s step %d" % (st, sim.t), file=sys.stderr, flush=True)
+        wall = time.perf_counter() - t0
+        h = np.asarray(sim.history())
+        _, u, _ = sim.moments("f64")
+        ux = u[0].cpu().numpy()
+        out[st] = {"steps": int(n), "wall_s": round(wall, 2),
+                   "u_rel_L2_vs_f64": float(np.linalg.norm(ux - u_ref) / np.linalg.norm(u_ref)),
+                   "residual_floor": float(h[:, 1].min()) if len(h) else None}
+        sim.close()
+        del sim, u
+        torch.cuda.empty_cache()
+    print(json.dumps({"probe": "precision256", **out}), flush=True)
+
+
 def kernel_probe(name, launches, copy_probe):
     """One JSON line for the profilers: `launches` plain launches of one
     kernel at its HBM-scale size (coupled step 256^3 FP32, steady adjoint
@@ -677,6 +721,9 @@ def kernel_probe(name, launches, copy_probe):
         us = kernel_time_us(sim, launches, warmup=5)
         alg = 2 * 9 * 4 * sim.N
         kernel = "glbe2_step<float, check=false> (4096^2)"
+    elif name == "precision256":
+        precision_steady_256()
+        return
     else:
         raise SystemExit("unknown probe %s" % name)
     sim.close()
@@ -705,8 +752,9 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f32", "f64", "bf16", "f16"])
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
-    ap.add_argument("--probe", choices=["mhd256", "adjoint128", "d2q9_4096"],
-                    help="only time one other kernel at HBM scale (for the profilers)")
+    ap.add_argument("--probe", choices=["mhd256", "adjoint128", "d2q9_4096", "precision256"],
+                    help="only one other measurement: another kernel at HBM scale (for the "
+                         "profilers), or the 256^3 precision form at steady state")
     ap.add_argument("--launches", type=int, default=30)
     args = ap.parse_args()
     if args.gpus != 1:
