@@ -28,4 +28,6 @@ lattice  D3Q19 / D3Q7 velocity sets, weights, moment basis (Sec. 2, Sec. 4, App.
 glbe     preconditioned GLBE collide/stream step, fields, residual (Sec. 2-3, Sec. 5)
 mhd      preconditioned vector LKE with chi-scaling and Lorentz coupling (Sec. 4, 4.1)
 adjoint  complex-step and dense-Jacobian gradients of the steady flow rate
+rounding stochastic rounding to BF16 with counter-based random bits (a storage
+         option of the library, not part of the paper)
 """
