@@ -53,7 +53,7 @@ NO_CHECK = 1 << 30   # check_every that never fires: a march of the plain step k
 
 
 def make_sim(shape, storage, gamma, nu=0.131, F0=1e-5, bc=("periodic", "wall", "wall"),
-             check_every=10):
+             check_every=10, **kw):
     import torch
 
     import paper_0809_4730_amd as pkg
@@ -61,7 +61,8 @@ def make_sim(shape, storage, gamma, nu=0.131, F0=1e-5, bc=("periodic", "wall", "
     dt = torch.float64 if storage == "f64" else torch.float32
     F = torch.tensor(inputs.duct_force(shape, F0), dtype=dt, device="cuda")
     s = pkg.default_rates(nu, gamma)
-    return pkg.Simulation(shape, bc, gamma, s, storage=storage, force=F, check_every=check_every)
+    return pkg.Simulation(shape, bc, gamma, s, storage=storage, force=F, check_every=check_every,
+                          **kw)
 
 
 def timed_region(sim, steps, warmup):
@@ -91,13 +92,13 @@ def kernel_time_us(sim, launches, warmup=20):
     return 1000.0 * e0.elapsed_time(e1) / launches
 
 
-def measure(shape, storage, gamma, steps, warmup):
+def measure(shape, storage, gamma, steps, warmup, **kw):
     """(MLUPS with checks, wall s, mean plain-kernel us)."""
     import torch
-    sim = make_sim(shape, storage, gamma)
+    sim = make_sim(shape, storage, gamma, **kw)
     mlups, wall = timed_region(sim, steps, warmup)
     del sim
-    sim = make_sim(shape, storage, gamma, check_every=NO_CHECK)
+    sim = make_sim(shape, storage, gamma, check_every=NO_CHECK, **kw)
     us = kernel_time_us(sim, steps)
     del sim
     torch.cuda.empty_cache()
@@ -267,8 +268,9 @@ def extras(args):
                 e["step_ratio_vs_f64_gamma1"] = round(ref["steps"] / e["steps"], 3)
     # 256^3 throughput per storage type (kernel roofline at HBM scale)
     big = []
-    for st, nb in (("f32", 4), ("bf16", 2), ("f16", 2), ("f64", 8)):
-        mlups, wall, us = measure((256, 256, 256), st, 1.0, args.big_steps, 10)
+    for st, nb in (("f32", 4), ("bf16", 2), ("bf16_sr", 2), ("f16", 2), ("f64", 8)):
+        kw = {"rounding": "stochastic"} if st == "bf16_sr" else {}
+        mlups, wall, us = measure((256, 256, 256), st.split("_")[0], 1.0, args.big_steps, 10, **kw)
         bpn = algorithmic_bytes_per_node(nb, True, NO_CHECK)
         gbs = bpn * 256 ** 3 / (us * 1e-6) / 1e9
         big.append({"storage": st, "MLUPS_with_checks": round(mlups, 1), "kernel_us": round(us, 2),
@@ -594,8 +596,9 @@ def precision_table():
     n = ref.t
     _, u64, _ = ref.moments("f64")
     out = {"steps": n}
-    for st in ("f32", "bf16", "f16"):
-        sim = make_sim((64, 64, 64), st, 0.1)
+    for st in ("f32", "bf16", "bf16_sr", "f16"):
+        kw = {"rounding": "stochastic"} if st == "bf16_sr" else {}
+        sim = make_sim((64, 64, 64), st.split("_")[0], 0.1, **kw)
         sim.step(n)
         _, u, _ = sim.moments("f64")
         err = float(torch.linalg.vector_norm(u - u64) / torch.linalg.vector_norm(u64))
@@ -642,9 +645,9 @@ def adjoint_extras():
 
 def precision_steady_256():
     """The precision form at full size: the 256^3 duct (C1 force, nu = 0.131,
-    gamma = 1) marched in FP64 to a residual of 1e-8, then FP32, BF16 and FP16
-    storage marched the same number of steps; u against FP64 per storage type,
-    and each one's residual floor."""
+    gamma = 1) marched in FP64 to a residual of 1e-8, then FP32, BF16 (nearest
+    and stochastic rounding) and FP16 storage marched the same number of steps;
+    u against FP64 per storage type, and each one's residual floor."""
     import numpy as np
     import torch
     shape = (256, 256, 256)
@@ -663,19 +666,20 @@ def precision_steady_256():
     ref.close()
     del ref
     torch.cuda.empty_cache()
-    for st in ("f32", "bf16", "f16"):
-        sim = make_sim(shape, st, 1.0)
+    for key in ("f32", "bf16", "bf16_sr", "f16"):
+        st = key.split("_")[0]
+        sim = make_sim(shape, st, 1.0, **({"rounding": "stochastic"} if key == "bf16_sr" else {}))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         while sim.t < n:
             sim.step(min(20000, int(n) - sim.t))
             torch.cuda.synchronize()
-            print("%s step %d" % (st, sim.t), file=sys.stderr, flush=True)
+            print("%s step %d" % (key, sim.t), file=sys.stderr, flush=True)
         wall = time.perf_counter() - t0
         h = np.asarray(sim.history())
         _, u, _ = sim.moments("f64")
         ux = u[0].cpu().numpy()
-        out[st] = {"steps": int(n), "wall_s": round(wall, 2),
+        out[key] = {"steps": int(n), "wall_s": round(wall, 2),
                    "u_rel_L2_vs_f64": float(np.linalg.norm(ux - u_ref) / np.linalg.norm(u_ref)),
                    "residual_floor": float(h[:, 1].min()) if len(h) else None}
         sim.close()

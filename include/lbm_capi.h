@@ -132,7 +132,27 @@ typedef struct {
                              keep their [3][N] layout (z components unused on
                              input, zero on output); the state blob holds f as
                              [9][N] and (mhd) g as [2][5][N]. */
+  int32_t rounding;       /* lbm_rounding: how the step rounds the populations it
+                             stores.  LBM_ROUND_STOCHASTIC needs LBM_BF16 storage
+                             and the D3Q19 flow step (no mhd); see below. */
+  uint32_t seed;          /* stochastic rounding: seed of the counter-based
+                             random bits (any value; the same seed gives the
+                             same march bit for bit) */
 } lbm_params;
+
+/* Rounding of stored populations.  LBM_ROUND_NEAREST: nearest, ties to even.
+ * LBM_ROUND_STOCHASTIC (BF16 storage only): each FP32 result is rounded up
+ * in magnitude with probability equal to its distance from the BF16 value
+ * below, so that the stored value is unbiased and per-step changes smaller
+ * than the BF16 spacing still accumulate.  Stored bits = the upper 16 bits of
+ * (FP32 bits + r) for finite values, r the 16 random bits of that value
+ * (non-finite values are kept as NaN/Inf).  The random bits are counter-based:
+ * for node n, directions 2k and 2k+1 (k = 0..9), and the step number t being
+ * computed, h = fmix32(n*0x9E3779B1 + t*0x85EBCA77 + k*0xC2B2AE3D + seed)
+ * (32-bit wrap-around; fmix32 is the 32-bit finalizer of MurmurHash3:
+ * h ^= h >> 16; h *= 0x85EBCA6B; h ^= h >> 13; h *= 0xC2B2AE35; h ^= h >> 16);
+ * direction 2k takes the low 16 bits of h, direction 2k+1 the high 16. */
+typedef enum { LBM_ROUND_NEAREST = 0, LBM_ROUND_STOCHASTIC = 1 } lbm_rounding;
 
 typedef struct lbm_ctx lbm_ctx;
 

@@ -56,6 +56,8 @@ class _Params(ctypes.Structure):
         ("wall_u", (ctypes.c_double * 3) * 6),
         ("mag_pad", ctypes.c_int32 * 3),
         ("lattice", ctypes.c_int32),
+        ("rounding", ctypes.c_int32),
+        ("seed", ctypes.c_uint32),
     ]
 
 
@@ -232,11 +234,13 @@ class Simulation:
          induction lattice, the fluid box is pad nodes in from each wall face).
     source: "precond" (P_S, the paper's form) or "naive" (S/gamma, its negative control).
     wall_u: None or (6, 3) face velocities (x-low, x-high, y-low, y-high, z-low, z-high).
+    rounding: "nearest" or "stochastic" (bf16 storage, D3Q19 flow step only): how
+              stored populations are rounded; seed: the stochastic rounding seed.
     """
 
     def __init__(self, shape, bc, gamma, s, storage="f32", force=(0.0, 0.0, 0.0), rho0=1.0,
                  mhd=None, check_every=10, history_len=4096, device="cuda", stream=None,
-                 source="precond", wall_u=None, lattice="d3q19"):
+                 source="precond", wall_u=None, lattice="d3q19", rounding="nearest", seed=0):
         torch = _torch()
         self._lib = load_library()
         self.device = torch.device(device)
@@ -254,6 +258,8 @@ class Simulation:
         p = _Params()
         p.lattice = self.lattice
         p.storage = self.storage
+        p.rounding = {"nearest": 0, "stochastic": 1}[rounding]
+        p.seed = int(seed) & 0xFFFFFFFF
         p.gamma = gamma
         for k in range(len(s)):
             p.s[k] = float(s[k])

@@ -383,7 +383,7 @@ lbm_status unrolled_impl(lbm_ctx* c, char* ws, int64_t n_steps, int64_t K, void*
     for (int64_t i = 1; i < len; ++i)
       LBM_HIP(c, launch_glbe_step<R>(c->ga, cargs<R>(c), seg + size_t(i - 1) * state_bytes,
                                      seg + size_t(i) * state_bytes, c->force(), c->field(), false,
-                                     c->nt_store, nullptr, nullptr, c->stream),
+                                     c->nt_store, false, nullptr, nullptr, c->stream),
               "segment recompute");
     for (int64_t n = e; n >= s0 + 1; --n) {
       LBM_HIP(c, launch_adjoint<R>(c->ga, cargs<R>(c), seg + size_t(n - 1 - s0) * state_bytes,

@@ -59,6 +59,8 @@ struct GridArgs {
   int64_t stride;          // elements between direction planes (N rounded up to 64)
   FastDiv div_nx, div_nxny;
   FastDiv div_chunk;       // division by xcd_chunk
+  uint32_t step;           // the step number a step launch computes (stochastic rounding)
+  uint32_t seed;           // stochastic rounding seed
   // Fluid box [flo, fhi) per axis (x, y, z).  The whole lattice, unless the
   // induction lattice extends beyond the fluid; its faces are then no-slip
   // walls of the flow, while the induction lattice's walls stay at the lattice

@@ -14,6 +14,7 @@
 // needs no solid nodes: a link crossing a wall reads the opposite direction's
 // post-collision value at the same node.  Loads take a scalar base and a
 // 32-bit node offset; stores go through a buffer resource (store_planes).
+#include <type_traits>
 #include "collide.hpp"
 #include "launch.hpp"
 #include "stream.hpp"
@@ -177,7 +178,8 @@ __device__ __forceinline__ void load_force(const GridArgs& g, const CollideArgs<
 
 // ------------------------------------------------------------------ steps --
 // ROWS: every wave lies in one x-row (nx a multiple of 64; neighbours_rows).
-template <typename S, bool CHECK, bool FIELD, bool NT, bool MOVING, bool WIDE, bool ROWS>
+// SR: BF16 stores with stochastic rounding (store19_stochastic).
+template <typename S, bool CHECK, bool FIELD, bool NT, bool MOVING, bool WIDE, bool ROWS, bool SR>
 __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<typename Storage<S>::R> c,
                                                     const S* __restrict__ fin, S* __restrict__ fout,
                                                     const typename Storage<S>::R* __restrict__ force,
@@ -195,7 +197,10 @@ __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<type
     R Fx, Fy, Fz;
     load_force<R, WIDE>(g, c, force, FIELD, n, Fx, Fy, Fz);
     const NodeMacro<R> mac = collide19<R>(f, Fx, Fy, Fz, c);
-    store19<S, NT, WIDE>(fout, g, n, f);
+    if constexpr (SR)
+      store19_stochastic<NT, WIDE>(fout, g, n, f);
+    else
+      store19<S, NT, WIDE>(fout, g, n, f);
     if constexpr (CHECK)
       check_node<R, WIDE>(g, usnap, n, mac.drho, mac.jx, mac.jy, mac.jz, mac.ux, mac.uy, mac.uz, acc);
   }
@@ -412,7 +417,8 @@ hipError_t launch_convert(int src_storage, int dst_storage, const void* src, voi
 template <typename S>
 hipError_t launch_glbe_step(const GridArgs& g, const CollideArgs<typename Storage<S>::R>& c,
                             const void* fin, void* fout, const void* force, bool field, bool check,
-                            bool nt, void* usnap_v, double* partials, hipStream_t st) {
+                            bool nt, bool stochastic, void* usnap_v, double* partials,
+                            hipStream_t st) {
   using R = typename Storage<S>::R;
   R* usnap = static_cast<R*>(usnap_v);
   const S* a = static_cast<const S*>(fin);
@@ -425,14 +431,28 @@ hipError_t launch_glbe_step(const GridArgs& g, const CollideArgs<typename Storag
         return with_flag(rows_per_wave(g), [&](auto RW) {
           constexpr bool ch = decltype(CH)::value, fl = decltype(FL)::value,
                          w = decltype(W)::value, rw = decltype(RW)::value;
+          if constexpr (std::is_same_v<S, bf16_t>) {
+            if (stochastic) {
+              if (c.moving)
+                glbe_step<S, ch, fl, false, true, w, rw, true>
+                    <<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
+              else if (nt)
+                glbe_step<S, ch, fl, true, false, w, rw, true>
+                    <<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
+              else
+                glbe_step<S, ch, fl, false, false, w, rw, true>
+                    <<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
+              return hipGetLastError();
+            }
+          }
           if (c.moving)
-            glbe_step<S, ch, fl, false, true, w, rw>
+            glbe_step<S, ch, fl, false, true, w, rw, false>
                 <<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
           else if (nt)
-            glbe_step<S, ch, fl, true, false, w, rw>
+            glbe_step<S, ch, fl, true, false, w, rw, false>
                 <<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
           else
-            glbe_step<S, ch, fl, false, false, w, rw>
+            glbe_step<S, ch, fl, false, false, w, rw, false>
                 <<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
           return hipGetLastError();
         });
@@ -443,7 +463,7 @@ hipError_t launch_glbe_step(const GridArgs& g, const CollideArgs<typename Storag
 
 #define LBM_INST_STEP(S)                                                                          \
   template hipError_t launch_glbe_step<S>(const GridArgs&, const CollideArgs<Storage<S>::R>&,      \
-                                          const void*, void*, const void*, bool, bool, bool,       \
+                                          const void*, void*, const void*, bool, bool, bool, bool, \
                                           void*, double*, hipStream_t);
 LBM_INST_STEP(double)
 LBM_INST_STEP(float)

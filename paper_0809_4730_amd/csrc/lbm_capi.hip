@@ -61,6 +61,11 @@ std::string validate(const lbm_grid* grid, const lbm_params* p) {
     for (int a = 0; a < 3; ++a)
       if (!std::isfinite(p->B0[a])) return "B0 must be finite";
   }
+  if (p->rounding != LBM_ROUND_NEAREST && p->rounding != LBM_ROUND_STOCHASTIC)
+    return "rounding must be LBM_ROUND_NEAREST or LBM_ROUND_STOCHASTIC";
+  if (p->rounding == LBM_ROUND_STOCHASTIC &&
+      (p->storage != LBM_BF16 || p->lattice != LBM_D3Q19 || p->mhd))
+    return "stochastic rounding needs LBM_BF16 storage and the D3Q19 flow step (mhd = 0)";
   if (p->check_every < 1) return "check_every must be >= 1";
   if (p->history_len < 1) return "history_len must be >= 1";
   if (p->source_mode != 0 && p->source_mode != 1) return "source_mode must be 0 or 1";
@@ -141,6 +146,7 @@ hipError_t launch_step_kernel(lbm_ctx* c, bool check) {
   const void* fin = c->f(c->cur);
   void* fout = c->f(c->cur ^ 1);
   const bool fld = c->field();
+  c->ga.step = static_cast<uint32_t>(c->step + 1);  // the step this launch computes
   if (c->p.lattice == LBM_D2Q9) {
     if (c->p.mhd) {
       if (c->p.storage == LBM_F64)
@@ -178,16 +184,17 @@ hipError_t launch_step_kernel(lbm_ctx* c, bool check) {
   switch (c->p.storage) {
     case LBM_F64:
       return launch_glbe_step<double>(c->ga, c->cd, fin, fout, c->force(), fld, check, c->nt_store,
-                                      c->usnap(), partials, c->stream);
+                                      false, c->usnap(), partials, c->stream);
     case LBM_F32:
       return launch_glbe_step<float>(c->ga, c->cf, fin, fout, c->force(), fld, check, c->nt_store,
-                                     c->usnap(), partials, c->stream);
+                                     false, c->usnap(), partials, c->stream);
     case LBM_BF16:
       return launch_glbe_step<bf16_t>(c->ga, c->cf, fin, fout, c->force(), fld, check, c->nt_store,
-                                      c->usnap(), partials, c->stream);
+                                      c->p.rounding == LBM_ROUND_STOCHASTIC, c->usnap(), partials,
+                                      c->stream);
     default:
       return launch_glbe_step<_Float16>(c->ga, c->cf, fin, fout, c->force(), fld, check,
-                                        c->nt_store, c->usnap(), partials, c->stream);
+                                        c->nt_store, false, c->usnap(), partials, c->stream);
   }
 }
 
@@ -509,6 +516,8 @@ lbm_status lbm_create(const lbm_grid* grid, const lbm_params* params, const void
   g.wall_z = grid->bc[2] == LBM_WALL;
   g.N = static_cast<int32_t>(L.N);
   g.nblocks = L.nblocks;
+  g.step = 0;
+  g.seed = params->seed;
   choose_launch_shape(c);
   g.stride = L.stride;
   g.div_nx = make_fastdiv(static_cast<uint32_t>(g.nx));

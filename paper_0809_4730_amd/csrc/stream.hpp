@@ -226,6 +226,52 @@ __device__ __forceinline__ void store19(S* __restrict__ fout, const GridArgs& g,
   store_planes<S, NT, WIDE, Q19>(fout, g, n, f);
 }
 
+// 32-bit finalizer of MurmurHash3 (a bijection with full avalanche).
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85EBCA6Bu;
+  h ^= h >> 13;
+  h *= 0xC2B2AE35u;
+  h ^= h >> 16;
+  return h;
+}
+
+// BF16 with stochastic rounding: the upper 16 bits of (FP32 bits + r), r
+// uniform in [0, 2^16), round the magnitude up with probability equal to the
+// fraction below; non-finite values are kept (NaN stays NaN).
+__device__ __forceinline__ uint16_t bf16_stochastic(float v, uint32_t r16) {
+  uint32_t bits = __float_as_uint(v);
+  if ((bits & 0x7F800000u) != 0x7F800000u) bits += r16;
+  else if (bits & 0x007FFFFFu) bits |= 0x00400000u;  // quiet NaN survives truncation
+  return static_cast<uint16_t>(bits >> 16);
+}
+
+// The 19 BF16 stores of node n with stochastic rounding (the counter-based
+// random bits documented with lbm_rounding in the C header).
+template <bool NT, bool WIDE>
+__device__ __forceinline__ void store19_stochastic(bf16_t* __restrict__ fout, const GridArgs& g,
+                                                   uint32_t n, const float (&f)[Q19]) {
+  const uint32_t base = n * 0x9E3779B1u + g.step * 0x85EBCA77u + g.seed;
+#pragma unroll
+  for (int k = 0; k < (Q19 + 1) / 2; ++k) {
+    const uint32_t h = fmix32(base + static_cast<uint32_t>(k) * 0xC2B2AE3Du);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int a = 2 * k + j;
+      if (a < Q19) {
+        const uint16_t bits = bf16_stochastic(f[a], j ? (h >> 16) : (h & 0xFFFFu));
+        if constexpr (WIDE) {
+          st_pop<NT>(&(fout + static_cast<int64_t>(a) * g.stride + n)->bits, bits);
+        } else {
+          __builtin_amdgcn_raw_buffer_store_b16(
+              bits, raw_rsrc(fout), n * 2u,
+              static_cast<uint32_t>(a) * static_cast<uint32_t>(g.stride) * 2u, buf_policy<NT>());
+        }
+      }
+    }
+  }
+}
+
 // Residual / reduction bookkeeping of one node, accumulated in FP64.  The
 // velocity snapshot is kept in the compute type R: u is an R value, so the
 // FP64 difference of two snapshots is exact.

@@ -85,12 +85,17 @@ def _grid_params(pkg, **kw):
     p.history_len = 16
     p.mhd = kw.get("mhd", 0)
     p.gamma_m, p.chi, p.eta, p.mu = 0.1, 0.01, 0.025, 1.0
+    p.rounding = kw.get("rounding", 0)
+    p.lattice = kw.get("lattice", 0)
     return g, p
 
 
 @pytest.mark.parametrize("bad", [
     dict(gamma=0.0), dict(gamma=1.5), dict(n=(0, 4, 4)), dict(storage=7),
     dict(mhd=1, storage=2), dict(n=(2048, 2048, 1024)),
+    # stochastic rounding: bf16 storage and the D3Q19 flow step only
+    dict(rounding=2, storage=2), dict(rounding=1, storage=1), dict(rounding=1, storage=3),
+    dict(rounding=1, storage=2, mhd=1), dict(rounding=1, storage=2, lattice=1, n=(8, 8, 1)),
 ])
 def test_validation_rejects(lib, bad):
     import paper_0809_4730_amd as pkg
@@ -99,6 +104,15 @@ def test_validation_rejects(lib, bad):
     st = lib.lbm_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nbytes))
     assert st == -1
     assert lib.lbm_last_error(None)
+
+
+def test_validation_accepts_stochastic_bf16(lib):
+    import paper_0809_4730_amd as pkg
+    g, p = _grid_params(pkg, rounding=1, storage=pkg.BF16)
+    p.seed = 0xFFFFFFFF
+    nbytes = ctypes.c_size_t()
+    assert lib.lbm_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nbytes)) == 0
+    assert nbytes.value > 0
 
 
 def test_rate_outside_interval_rejected(lib):
