@@ -688,6 +688,91 @@ def precision_steady_256():
     print(json.dumps({"probe": "precision256", **out}), flush=True)
 
 
+def ladder_256():
+    """Wall time to a residual of 1e-8 on the 256^3 duct of precision_steady_256
+    for precision ladders, each rung continuing the previous rung's state on
+    the device (lbm_convert_state).  A rung ends on the velocity residual R
+    ("r") or, for BF16, on the kinetic energy sum |u|^2 ("e"): its relative
+    change over 1000 steps, a global sum in which the rounding noise of the
+    stored values averages out while R measures it (the duct's net flow rate
+    is zero by symmetry, so it cannot serve).  A ladder's contexts are built before its
+    clock starts; u of each final state against the FP64-alone steady state."""
+    import numpy as np
+    import torch
+    shape = (256, 256, 256)
+    out = {"workload": "square duct 256^3, gamma = 1, nu = 0.131, C1 force; residual 1e-8",
+           "ladders": []}
+    ladders = [
+        (("f64", "r", 1e-8),),
+        (("f32", "r", 2e-7), ("f64", "r", 1e-8)),
+        (("bf16_sr", "e", 1e-4), ("f32", "r", 2e-7), ("f64", "r", 1e-8)),
+        (("bf16_sr", "e", 1e-5), ("f32", "r", 2e-7), ("f64", "r", 1e-8)),
+        (("bf16", "e", 1e-4), ("f32", "r", 2e-7), ("f64", "r", 1e-8)),
+    ]
+
+    def energy(sim):
+        return float(sim.history(1)[-1, 3])
+
+    u_ref = None
+    for lad in ladders:
+        name = " -> ".join("%s(%s<%g)" % rung for rung in lad)
+        sims = [make_sim(shape, k.split("_")[0], 1.0,
+                         **({"rounding": "stochastic"} if k == "bf16_sr" else {})) for k, _, _ in lad]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rungs, prev, ok = [], None, True
+        for (k, crit, tol), sim in zip(lad, sims):
+            if prev is not None:
+                sim.convert_from(prev)
+            t1 = time.perf_counter()
+            done = False
+            if crit == "r":
+                while not done and sim.t < 400000:  # in chunks, with a progress line each
+                    n, r = sim.run_to_residual(tol, 20000, poll_every=1000)
+                    done = n > 0
+                    print("%s: %s step %d R %.3e" % (name, k, sim.t, r), file=sys.stderr, flush=True)
+            else:
+                sim.step(1000)
+                e0 = energy(sim)
+                while not done and sim.t < 400000:
+                    sim.step(1000)
+                    e1 = energy(sim)
+                    de = abs(e1 - e0) / max(abs(e1), 1e-300)
+                    done = de < tol
+                    e0 = e1
+                    if sim.t % 10000 == 0 or done:
+                        print("%s: %s step %d dE/E %.3e" % (name, k, sim.t, de), file=sys.stderr,
+                              flush=True)
+            torch.cuda.synchronize()
+            rungs.append({"storage": k, "until": "%s < %g" % ({"r": "R", "e": "dE/E per 1000"}[crit], tol),
+                          "until_step": int(sim.t), "wall_s": round(time.perf_counter() - t1, 2)})
+            if not done:
+                ok = False
+                break
+            prev = sim
+        wall = time.perf_counter() - t0
+        e = {"ladder": name, "reached": ok, "steps": int(sims[-1].t) if ok else -1,
+             "wall_s": round(wall, 2), "rungs": rungs}
+        if ok:
+            _, u, _ = sims[-1].moments("f64")
+            ux = u[0].cpu().numpy()
+            if u_ref is None:
+                u_ref = ux
+            e["u_rel_L2_vs_f64_alone"] = float(np.linalg.norm(ux - u_ref) / np.linalg.norm(u_ref))
+            del u
+        for sim in sims:
+            sim.close()
+        del sims, prev
+        torch.cuda.empty_cache()
+        out["ladders"].append(e)
+        print(json.dumps(e), file=sys.stderr, flush=True)
+    base = out["ladders"][0]["wall_s"]
+    for e in out["ladders"]:
+        if e["reached"]:
+            e["speedup_vs_f64_alone"] = round(base / e["wall_s"], 3)
+    print(json.dumps({"probe": "ladder256", **out}), flush=True)
+
+
 def kernel_probe(name, launches, copy_probe):
     """One JSON line for the profilers: `launches` plain launches of one
     kernel at its HBM-scale size (coupled step 256^3 FP32, steady adjoint
@@ -728,6 +813,9 @@ def kernel_probe(name, launches, copy_probe):
     elif name == "precision256":
         precision_steady_256()
         return
+    elif name == "ladder256":
+        ladder_256()
+        return
     else:
         raise SystemExit("unknown probe %s" % name)
     sim.close()
@@ -756,7 +844,8 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f32", "f64", "bf16", "f16"])
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
-    ap.add_argument("--probe", choices=["mhd256", "adjoint128", "d2q9_4096", "precision256"],
+    ap.add_argument("--probe", choices=["mhd256", "adjoint128", "d2q9_4096", "precision256",
+                                        "ladder256"],
                     help="only one other measurement: another kernel at HBM scale (for the "
                          "profilers), or the 256^3 precision form at steady state")
     ap.add_argument("--launches", type=int, default=30)
