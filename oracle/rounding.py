@@ -73,10 +73,15 @@ def murmur3_x86_32(key: bytes, seed: int) -> int:
 
 def random_bits(n_nodes, q, step, seed):
     """The 16-bit random values r[a, n] (a in the library's direction order)."""
-    n = np.arange(n_nodes, dtype=np.uint64)
+    return random_bits_at(np.arange(n_nodes), q, step, seed)
+
+
+def random_bits_at(nodes, q, step, seed):
+    """random_bits at the given linear node indices only: r[a, i] for nodes[i]."""
+    n = np.asarray(nodes).astype(np.uint64)
     base = (n * np.uint64(0x9E3779B1) + np.uint64((step * 0x85EBCA77) & M32)
             + np.uint64(seed & M32)) & np.uint64(M32)
-    r = np.empty((q, n_nodes), dtype=np.uint32)
+    r = np.empty((q, n.size), dtype=np.uint32)
     for k in range((q + 1) // 2):
         h = fmix32((base + np.uint64((k * 0xC2B2AE3D) & M32)) & np.uint64(M32))
         r[2 * k] = h & np.uint32(0xFFFF)

@@ -121,3 +121,5 @@ def test_random_bits_layout_and_statistics():
     z8 = (r8.astype(np.float64) - mu) / np.sqrt(var)
     assert abs(np.mean(z * z8)) < lim * 0.5
     assert not np.array_equal(r, rounding.random_bits(N, q, step=7, seed=100))
+    sel = np.array([0, 5, N - 1, 977])
+    assert np.array_equal(rounding.random_bits_at(sel, q, 7, 99), r[:, sel])
