@@ -134,7 +134,7 @@ typedef struct {
                              [9][N] and (mhd) g as [2][5][N]. */
   int32_t rounding;       /* lbm_rounding: how the step rounds the populations it
                              stores.  LBM_ROUND_STOCHASTIC needs LBM_BF16 storage
-                             and the D3Q19 flow step (no mhd); see below. */
+                             and the flow step alone (no mhd); see below. */
   uint32_t seed;          /* stochastic rounding: seed of the counter-based
                              random bits (any value; the same seed gives the
                              same march bit for bit) */
@@ -147,7 +147,8 @@ typedef struct {
  * than the BF16 spacing still accumulate.  Stored bits = the upper 16 bits of
  * (FP32 bits + r) for finite values, r the 16 random bits of that value
  * (non-finite values are kept as NaN/Inf).  The random bits are counter-based:
- * for node n, directions 2k and 2k+1 (k = 0..9), and the step number t being
+ * for node n, directions 2k and 2k+1 (k = 0..9 for D3Q19, 0..4 for D2Q9, in
+ * the order of lbm_lattice_velocities), and the step number t being
  * computed, h = fmix32(n*0x9E3779B1 + t*0x85EBCA77 + k*0xC2B2AE3D + seed)
  * (32-bit wrap-around; fmix32 is the 32-bit finalizer of MurmurHash3:
  * h ^= h >> 16; h *= 0x85EBCA6B; h ^= h >> 13; h *= 0xC2B2AE35; h ^= h >> 16);

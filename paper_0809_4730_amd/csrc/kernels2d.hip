@@ -8,6 +8,8 @@
 // In 2D the field is in-plane, B = (B_x, B_y), the current is out of plane,
 // J_z, and the Lorentz force is J_z (-B_y, B_x).  Magnetic populations are held
 // as deviations from W B0, field component outermost: g[j][a], j in {x, y}.
+#include <type_traits>
+
 #include "collide2d.hpp"
 #include "launch.hpp"
 #include "stream.hpp"
@@ -144,7 +146,8 @@ __device__ __forceinline__ void collide_g5(R (&g)[2][Q5], const Coupled2<R>& cp,
   }
 }
 
-template <typename S, bool CHECK, bool FIELD, bool NT, bool WIDE>
+// SR: BF16 stores with stochastic rounding (store_stochastic).
+template <typename S, bool CHECK, bool FIELD, bool NT, bool WIDE, bool SR>
 __global__ __launch_bounds__(kBlock) void glbe2_step(GridArgs g, CollideArgs<typename Storage<S>::R> c,
                                                      const S* __restrict__ fin, S* __restrict__ fout,
                                                      const typename Storage<S>::R* __restrict__ force,
@@ -162,7 +165,10 @@ __global__ __launch_bounds__(kBlock) void glbe2_step(GridArgs g, CollideArgs<typ
     R Fx, Fy;
     load_force2<R, WIDE>(g, c, force, FIELD, n, Fx, Fy);
     const NodeMacro<R> mac = collide9<R>(f, Fx, Fy, c);
-    store9<S, NT, WIDE>(fout, g, n, f);
+    if constexpr (SR)
+      store_stochastic<NT, WIDE, Q9>(fout, g, n, f);
+    else
+      store9<S, NT, WIDE>(fout, g, n, f);
     if constexpr (CHECK) check_node2<R, WIDE>(g, usnap, n, mac, acc);
   }
   if constexpr (CHECK) write_partials(partials, lb, acc);
@@ -257,7 +263,8 @@ __global__ __launch_bounds__(kBlock) void fields2_kernel(
 template <typename S>
 hipError_t launch_glbe2_step(const GridArgs& g, const CollideArgs<typename Storage<S>::R>& c,
                              const void* fin, void* fout, const void* force, bool field, bool check,
-                             bool nt, void* usnap_v, double* partials, hipStream_t st) {
+                             bool nt, bool stochastic, void* usnap_v, double* partials,
+                             hipStream_t st) {
   using R = typename Storage<S>::R;
   R* usnap = static_cast<R*>(usnap_v);
   const S* a = static_cast<const S*>(fin);
@@ -267,8 +274,17 @@ hipError_t launch_glbe2_step(const GridArgs& g, const CollideArgs<typename Stora
     return with_flag(field, [&](auto FL) {
       return with_flag(nt, [&](auto NTS) {
         return with_flag(wide_offsets(g, sizeof(R)), [&](auto W) {
-          glbe2_step<S, decltype(CH)::value, decltype(FL)::value, decltype(NTS)::value,
-                     decltype(W)::value><<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
+          constexpr bool ch = decltype(CH)::value, fl = decltype(FL)::value,
+                         nts = decltype(NTS)::value, w = decltype(W)::value;
+          if constexpr (std::is_same_v<S, bf16_t>) {
+            if (stochastic) {
+              glbe2_step<S, ch, fl, nts, w, true>
+                  <<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
+              return hipGetLastError();
+            }
+          }
+          glbe2_step<S, ch, fl, nts, w, false>
+              <<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
           return hipGetLastError();
         });
       });
@@ -279,7 +295,7 @@ hipError_t launch_glbe2_step(const GridArgs& g, const CollideArgs<typename Stora
 #define LBM_INST_STEP2(S)                                                                         \
   template hipError_t launch_glbe2_step<S>(const GridArgs&, const CollideArgs<Storage<S>::R>&,     \
                                            const void*, void*, const void*, bool, bool, bool,      \
-                                           void*, double*, hipStream_t);
+                                           bool, void*, double*, hipStream_t);
 LBM_INST_STEP2(double)
 LBM_INST_STEP2(float)
 LBM_INST_STEP2(bf16_t)

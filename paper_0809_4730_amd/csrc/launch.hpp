@@ -30,7 +30,8 @@ hipError_t launch_fields(const GridArgs& g, const CollideArgs<typename Storage<S
 template <typename S>
 hipError_t launch_glbe2_step(const GridArgs& g, const CollideArgs<typename Storage<S>::R>& c,
                              const void* fin, void* fout, const void* force, bool field, bool check,
-                             bool nt, void* usnap, double* partials, hipStream_t st);
+                             bool nt, bool stochastic, void* usnap, double* partials,
+                             hipStream_t st);
 
 template <typename R>
 hipError_t launch_mhd2_step(const GridArgs& g, const CollideArgs<R>& c, const MagArgs<R>& m,

@@ -63,9 +63,8 @@ std::string validate(const lbm_grid* grid, const lbm_params* p) {
   }
   if (p->rounding != LBM_ROUND_NEAREST && p->rounding != LBM_ROUND_STOCHASTIC)
     return "rounding must be LBM_ROUND_NEAREST or LBM_ROUND_STOCHASTIC";
-  if (p->rounding == LBM_ROUND_STOCHASTIC &&
-      (p->storage != LBM_BF16 || p->lattice != LBM_D3Q19 || p->mhd))
-    return "stochastic rounding needs LBM_BF16 storage and the D3Q19 flow step (mhd = 0)";
+  if (p->rounding == LBM_ROUND_STOCHASTIC && (p->storage != LBM_BF16 || p->mhd))
+    return "stochastic rounding needs LBM_BF16 storage and the flow step alone (mhd = 0)";
   if (p->check_every < 1) return "check_every must be >= 1";
   if (p->history_len < 1) return "history_len must be >= 1";
   if (p->source_mode != 0 && p->source_mode != 1) return "source_mode must be 0 or 1";
@@ -160,16 +159,17 @@ hipError_t launch_step_kernel(lbm_ctx* c, bool check) {
     switch (c->p.storage) {
       case LBM_F64:
         return launch_glbe2_step<double>(c->ga, c->cd, fin, fout, c->force(), fld, check,
-                                         c->nt_store, c->usnap(), partials, c->stream);
+                                         c->nt_store, false, c->usnap(), partials, c->stream);
       case LBM_F32:
         return launch_glbe2_step<float>(c->ga, c->cf, fin, fout, c->force(), fld, check,
-                                        c->nt_store, c->usnap(), partials, c->stream);
+                                        c->nt_store, false, c->usnap(), partials, c->stream);
       case LBM_BF16:
         return launch_glbe2_step<bf16_t>(c->ga, c->cf, fin, fout, c->force(), fld, check,
-                                         c->nt_store, c->usnap(), partials, c->stream);
+                                         c->nt_store, c->p.rounding == LBM_ROUND_STOCHASTIC,
+                                         c->usnap(), partials, c->stream);
       default:
         return launch_glbe2_step<_Float16>(c->ga, c->cf, fin, fout, c->force(), fld, check,
-                                           c->nt_store, c->usnap(), partials, c->stream);
+                                           c->nt_store, false, c->usnap(), partials, c->stream);
     }
   }
   if (c->p.mhd) {

@@ -246,19 +246,19 @@ __device__ __forceinline__ uint16_t bf16_stochastic(float v, uint32_t r16) {
   return static_cast<uint16_t>(bits >> 16);
 }
 
-// The 19 BF16 stores of node n with stochastic rounding (the counter-based
+// The Q BF16 stores of node n with stochastic rounding (the counter-based
 // random bits documented with lbm_rounding in the C header).
-template <bool NT, bool WIDE>
-__device__ __forceinline__ void store19_stochastic(bf16_t* __restrict__ fout, const GridArgs& g,
-                                                   uint32_t n, const float (&f)[Q19]) {
+template <bool NT, bool WIDE, int Q>
+__device__ __forceinline__ void store_stochastic(bf16_t* __restrict__ fout, const GridArgs& g,
+                                                 uint32_t n, const float (&f)[Q]) {
   const uint32_t base = n * 0x9E3779B1u + g.step * 0x85EBCA77u + g.seed;
 #pragma unroll
-  for (int k = 0; k < (Q19 + 1) / 2; ++k) {
+  for (int k = 0; k < (Q + 1) / 2; ++k) {
     const uint32_t h = fmix32(base + static_cast<uint32_t>(k) * 0xC2B2AE3Du);
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int a = 2 * k + j;
-      if (a < Q19) {
+      if (a < Q) {
         const uint16_t bits = bf16_stochastic(f[a], j ? (h >> 16) : (h & 0xFFFFu));
         if constexpr (WIDE) {
           st_pop<NT>(&(fout + static_cast<int64_t>(a) * g.stride + n)->bits, bits);

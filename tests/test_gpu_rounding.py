@@ -90,6 +90,47 @@ def test_stochastic_step_bits_match_oracle(shape, bc, start, moving):
     assert _check_bits(out, ref, r, eps) > 0.9
 
 
+@pytest.mark.parametrize("shape,bc,start", [
+    ((33, 17), (PER, WALL), 0),
+    ((70, 12), (WALL, WALL), 500),
+])
+def test_stochastic_d2q9_step_bits_match_oracle(shape, bc, start):
+    """The D2Q9 step with BF16 stochastic rounding (directions 2k, 2k+1 for
+    k = 0..4 in the library's D2Q9 order) against the 2D oracle."""
+    import torch
+
+    import paper_0809_4730_amd as pkg
+    from oracle import d2q9
+    announce("bf16 stochastic D2Q9 step %s start=%d" % (shape, start))
+    seed, gamma = 31337, 0.2
+    nx, ny = shape
+    e_lib = pkg.lattice_velocities(9)[:, :2]
+    pos = {tuple(v): a for a, v in enumerate(d2q9.E9)}
+    p9 = np.array([pos[tuple(v)] for v in e_lib])           # library direction i = oracle p9[i]
+    f0 = inputs.random_deviations((nx, ny, 1), seed=43, amp=1e-3, q=9)[:, 0]
+    f0 = _bf16_exact(f0)
+    F = (2e-5, -1e-5)
+    Ff = np.broadcast_to(np.array(F).reshape(2, 1, 1), (2, ny, nx))
+    s = d2q9.rates(0.04, gamma)
+
+    def run(storage, dt, **kw):
+        sim = pkg.Simulation((nx, ny, 1), (bc[0], bc[1], PER), gamma, s, storage=storage, force=F,
+                             lattice="d2q9", **kw)
+        sim.set_state(torch.tensor(np.ascontiguousarray(f0[p9][:, None])).to(dt).cuda(),
+                      step=start)
+        sim.step(1)
+        return sim.get_state().double().cpu().numpy()[:, 0].reshape(9, -1)
+    out = run("bf16", torch.bfloat16, rounding="stochastic", seed=seed)
+    out32 = run("f32", torch.float32)
+    ref = d2q9.step(f0, Ff, gamma, s, bc)[0][p9].reshape(9, -1)
+    err32 = np.abs(out32 - ref).max()
+    eps = 1e-6 * np.abs(ref).max()
+    announce("FP32 step error %.3e, bound used %.3e" % (err32, eps))
+    assert err32 <= eps / 4, (err32, eps)
+    r = rounding.random_bits(nx * ny, 9, start + 1, seed).astype(np.int64)
+    assert _check_bits(out, ref, r, eps) > 0.9
+
+
 def test_stochastic_full_size_sampled_nodes():
     """256^3 duct in BF16 with stochastic rounding, in the launch shape such a
     lattice gets (streaming stores, create-time workgroup mapping, row-aligned

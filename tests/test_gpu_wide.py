@@ -90,11 +90,13 @@ def test_d2q9_forms_agree(monkeypatch):
     import paper_0809_4730_amd as pkg
     announce("wide vs narrow d2q9 / d2q5")
 
-    def run_flow():
-        sim = pkg.Simulation((35, 12, 1), (PER, WALL, PER), 0.2, d2q9.rates(0.05, 0.2),
-                             storage="f32", force=(1e-5, 0.0), lattice="d2q9")
-        sim.step(41)
-        return sim.get_state(), sim.history(8)
+    def run_flow(storage="f32", **kw):
+        def run():
+            sim = pkg.Simulation((35, 12, 1), (PER, WALL, PER), 0.2, d2q9.rates(0.05, 0.2),
+                                 storage=storage, force=(1e-5, 0.0), lattice="d2q9", **kw)
+            sim.step(41)
+            return sim.get_state(), sim.history(8)
+        return run
 
     def run_mhd():
         sim = pkg.Simulation((10, 12, 1), (PER, WALL, PER), 0.2, d2q9.rates(0.05, 0.2),
@@ -102,7 +104,8 @@ def test_d2q9_forms_agree(monkeypatch):
                              mhd=dict(gamma_m=0.3, chi=0.05, eta=0.02, B0=(0.0, 0.03)))
         sim.step(41)
         return sim.get_state(), sim.history(8)
-    _same(*_both(monkeypatch, run_flow))
+    _same(*_both(monkeypatch, run_flow()))
+    _same(*_both(monkeypatch, run_flow("bf16", rounding="stochastic", seed=80)))
     _same(*_both(monkeypatch, run_mhd))
 
 
@@ -152,16 +155,19 @@ def test_streaming_store_forms_agree(monkeypatch):
             return sim.get_state(), sim.history(8)
         return run
 
-    def run2(mhd):
+    def run2(mhd, storage="f32"):
         def run():
             kw = dict(mhd=dict(gamma_m=0.3, chi=0.05, eta=0.02, B0=(0.0, 0.03))) if mhd else {}
+            if storage == "bf16_sr":
+                kw = dict(rounding="stochastic", seed=81)
             sim = pkg.Simulation((20, 12, 1), (PER, WALL, PER), 0.2, d2q9.rates(0.05, 0.2),
-                                 storage="f32", force=(1e-5, 0.0), lattice="d2q9", **kw)
+                                 storage=storage.split("_")[0], force=(1e-5, 0.0), lattice="d2q9",
+                                 **kw)
             sim.step(41)
             return sim.get_state(), sim.history(8)
         return run
     for run in (run3("f32", False), run3("bf16", False), run3("bf16_sr", False), run3("f32", True),
-                run3("f64", True), run2(False), run2(True)):
+                run3("f64", True), run2(False), run2(True), run2(False, "bf16_sr")):
         _same(*_both(monkeypatch, run, "LBM_NT_STORE", "0"))
 
 
