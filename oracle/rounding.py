@@ -1,5 +1,5 @@
-"""Stochastic rounding of stored populations to BF16: a storage option of the
-library (the paper computes in double precision and has no such step).
+"""Stochastic rounding of stored populations to BF16 or FP16: a storage option
+of the library (the paper computes in double precision and has no such step).
 
 TEST INFRASTRUCTURE ONLY, like the rest of this package.
 
@@ -12,16 +12,22 @@ Definition (the contract the library documents for its BF16 storage):
   direction 2k takes the low 16 bits of h, direction 2k+1 the high 16 bits.
   fmix32 is the 32-bit finalizer of Austin Appleby's MurmurHash3 (SMHasher,
   public domain).
-* rounding: a finite FP32 value with bit pattern b and random r in [0, 2^16)
+* BF16: a finite FP32 value with bit pattern b and random r in [0, 2^16)
   is stored as the BF16 pattern (b + r) >> 16.  The magnitude therefore rounds
   up with probability equal to its distance above the BF16 value below it, in
   units of the BF16 spacing, so the stored value is unbiased.  Inf stays Inf
   and NaN stays NaN.
+* FP16, |v| >= 2^-14 (its normal range): the FP32 bits of |v| plus r >> 3,
+  with the 13 fraction bits FP16 lacks cleared, then an exact conversion (Inf
+  on overflow).  |v| < 2^-14 (subnormal, spacing 2^-24): with q = |v| 2^24,
+  k = floor(q) and t = floor((q - k) 2^16), the magnitude is (k + 1) 2^-24 if
+  t + r >= 2^16, else k 2^-24.  Unbiased up to the 2^-16 resolution of t.
 
 Pins (tests/test_oracle_rounding.py): MurmurHash3_x86_32 published test
 vectors, whose last step is fmix32 (``murmur3_x86_32`` below exists only to
-reach them); exhaustive unbiasedness over all 2^16 random values; bracketing,
-sign symmetry and the special values.
+reach them); exhaustive unbiasedness over all 2^16 random values; bracketing
+by the neighbours numpy's float16 gives, sign symmetry and the special
+values.
 """
 import numpy as np
 
@@ -99,3 +105,27 @@ def stochastic_bf16(v32, r16):
     out = (out >> np.uint64(16)) << np.uint64(16)
     res = out.astype(np.uint32).view(np.float32).astype(np.float64)
     return np.where(np.isnan(v32), np.nan, res)
+
+
+def stochastic_f16(v32, r16):
+    """FP16 values (as float64) of FP32 values v32 rounded with random r16."""
+    v32 = np.asarray(v32, dtype=np.float32)
+    r = np.broadcast_to(np.asarray(r16, dtype=np.uint64), v32.shape)
+    b = v32.view(np.uint32).astype(np.uint64)
+    a = b & np.uint64(0x7FFFFFFF)
+    finite = a < 0x7F800000
+    normal = a >= 0x38800000
+    # normal range: drop 13 fraction bits after adding 13 random bits
+    an = (a + (r >> np.uint64(3))) & np.uint64(0xFFFFE000)
+    mag_n = an.astype(np.uint32).view(np.float32).astype(np.float64)
+    # subnormal range: spacing 2^-24, position resolved to 2^-16 of it
+    with np.errstate(invalid="ignore"):         # Inf / NaN lanes are replaced below
+        q = np.abs(v32.astype(np.float64)) * 2.0 ** 24
+        k = np.floor(q)
+        t = np.floor((q - k) * 65536.0)
+        mag_s = (k + ((t + r.astype(np.float64)) >= 65536.0)) * 2.0 ** -24
+    mag = np.where(normal, mag_n, mag_s)
+    with np.errstate(over="ignore"):
+        out = np.where(b >> np.uint64(31) != 0, -mag, mag).astype(np.float16).astype(np.float64)
+        special = v32.astype(np.float16).astype(np.float64)
+    return np.where(finite, out, special)

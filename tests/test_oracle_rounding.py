@@ -1,4 +1,4 @@
-"""Pins of the BF16 stochastic-rounding oracle (oracle/rounding.py).
+"""Pins of the BF16 / FP16 stochastic-rounding oracle (oracle/rounding.py).
 
 The hash is pinned to MurmurHash3's published test vectors; the rounding rule
 to what defines stochastic rounding: the result brackets the value, exact BF16
@@ -123,3 +123,76 @@ def test_random_bits_layout_and_statistics():
     assert not np.array_equal(r, rounding.random_bits(N, q, step=7, seed=100))
     sel = np.array([0, 5, N - 1, 977])
     assert np.array_equal(rounding.random_bits_at(sel, q, 7, 99), r[:, sel])
+
+
+# ------------------------------------------------------------------ FP16 ----
+def _f16_neighbours(v):
+    """(FP16 value toward zero, next FP16 value away from zero), from numpy's
+    float16 rounding and nextafter."""
+    v = np.asarray(v, dtype=np.float64)
+    h = v.astype(np.float16)
+    toward = np.where(np.abs(h.astype(np.float64)) > np.abs(v),
+                      np.nextafter(h, np.float16(0)), h).astype(np.float64)
+    inf16 = np.float16(np.inf)
+    with np.errstate(over="ignore"):               # the neighbour of 65504 is Inf
+        away = np.nextafter(toward.astype(np.float16), np.where(v < 0, -inf16, inf16))
+    away = away.astype(np.float64)
+    return toward, away
+
+
+def _f16_samples():
+    rng = np.random.default_rng(12)
+    v = np.concatenate([
+        rng.standard_normal(30) * 10.0 ** rng.uniform(-4, 4, 30),        # normal range
+        rng.uniform(-6e-5, 6e-5, 20),                                    # FP16 subnormal range
+        [1.0, -2.0 ** -14, 2.0 ** -14 * (1 - 2.0 ** -11), 3 * 2.0 ** -25, 65504.0, -1e-30],
+    ]).astype(np.float32)
+    return v
+
+
+def test_f16_unbiased_over_all_random_values():
+    r = np.arange(1 << 16, dtype=np.uint32)
+    for v in _f16_samples():
+        out = rounding.stochastic_f16(np.full(r.size, v, dtype=np.float32), r)
+        mean = out.sum() / r.size                     # exact: 2^16 FP16 values
+        if abs(v) >= 2.0 ** -14:
+            assert mean == float(v), v
+        else:   # the position within the 2^-24 spacing is resolved to 2^-16 of it
+            assert mean == np.floor(abs(float(v)) * 2.0 ** 40) * 2.0 ** -40 * np.sign(v), v
+            assert abs(mean - float(v)) < 2.0 ** -40
+
+
+def test_f16_brackets_and_extreme_random_values():
+    v = _f16_samples()
+    lo, hi = _f16_neighbours(v)
+    exact = lo == v.astype(np.float64)
+    for r in (0, 1, 7, 8, 0x7FFF, 0x8000, 0xFFFF):
+        out = rounding.stochastic_f16(v, np.full(v.size, r))
+        assert np.all((out == lo) | (out == hi)), r
+        assert np.all(out[exact] == lo[exact])
+    assert np.all(rounding.stochastic_f16(v, np.zeros(v.size)) == lo)       # r = 0: truncation
+    up = rounding.stochastic_f16(v, np.full(v.size, 0xFFFF))
+    resolved = np.abs(v.astype(np.float64) - lo) >= 2.0 ** -40              # not below 2^-16 spacing
+    assert np.all(up[~exact & resolved] == hi[~exact & resolved])
+
+
+def test_f16_probability_of_rounding_up():
+    r = np.arange(1 << 16, dtype=np.uint32)
+    for v, lo, hi in ((np.float32(1.0 + 5 * 2.0 ** -13), 1.0, 1.0 + 2.0 ** -10),
+                      (np.float32(3.25 * 2.0 ** -24), 3 * 2.0 ** -24, 4 * 2.0 ** -24)):
+        out = rounding.stochastic_f16(np.full(r.size, v), r)
+        assert set(np.unique(out)) == {lo, hi}
+        assert np.mean(out == hi) == (float(v) - lo) / (hi - lo)
+
+
+def test_f16_sign_symmetry_and_special_values():
+    v = _f16_samples()
+    r = np.random.default_rng(4).integers(0, 1 << 16, v.size)
+    assert np.array_equal(rounding.stochastic_f16(-v, r), -rounding.stochastic_f16(v, r))
+    sp = np.float32([np.inf, -np.inf, np.nan, 0.0, -0.0, 7e4, -7e4])
+    out = rounding.stochastic_f16(sp, np.full(sp.size, 0xFFFF))
+    assert out[0] == np.inf and out[1] == -np.inf and np.isnan(out[2])
+    assert out[3] == 0.0 and out[4] == 0.0 and np.signbit(out[4])
+    assert out[5] == np.inf and out[6] == -np.inf                            # beyond 65504
+    assert rounding.stochastic_f16(np.float32([65519.0]), [0])[0] == 65504.0
+    assert rounding.stochastic_f16(np.float32([65519.0]), [0xFFFF])[0] == np.inf
