@@ -268,8 +268,8 @@ def extras(args):
                 e["step_ratio_vs_f64_gamma1"] = round(ref["steps"] / e["steps"], 3)
     # 256^3 throughput per storage type (kernel roofline at HBM scale)
     big = []
-    for st, nb in (("f32", 4), ("bf16", 2), ("bf16_sr", 2), ("f16", 2), ("f64", 8)):
-        kw = {"rounding": "stochastic"} if st == "bf16_sr" else {}
+    for st, nb in (("f32", 4), ("bf16", 2), ("bf16_sr", 2), ("f16", 2), ("f16_sr", 2), ("f64", 8)):
+        kw = {"rounding": "stochastic"} if st.endswith("_sr") else {}
         mlups, wall, us = measure((256, 256, 256), st.split("_")[0], 1.0, args.big_steps, 10, **kw)
         bpn = algorithmic_bytes_per_node(nb, True, NO_CHECK)
         gbs = bpn * 256 ** 3 / (us * 1e-6) / 1e9
@@ -596,8 +596,8 @@ def precision_table():
     n = ref.t
     _, u64, _ = ref.moments("f64")
     out = {"steps": n}
-    for st in ("f32", "bf16", "bf16_sr", "f16"):
-        kw = {"rounding": "stochastic"} if st == "bf16_sr" else {}
+    for st in ("f32", "bf16", "bf16_sr", "f16", "f16_sr"):
+        kw = {"rounding": "stochastic"} if st.endswith("_sr") else {}
         sim = make_sim((64, 64, 64), st.split("_")[0], 0.1, **kw)
         sim.step(n)
         _, u, _ = sim.moments("f64")
@@ -645,8 +645,8 @@ def adjoint_extras():
 
 def precision_steady_256():
     """The precision form at full size: the 256^3 duct (C1 force, nu = 0.131,
-    gamma = 1) marched in FP64 to a residual of 1e-8, then FP32, BF16 (nearest
-    and stochastic rounding) and FP16 storage marched the same number of steps;
+    gamma = 1) marched in FP64 to a residual of 1e-8, then FP32, BF16 and FP16
+    (nearest and stochastic rounding) storage marched the same number of steps;
     u against FP64 per storage type, and each one's residual floor."""
     import numpy as np
     import torch
@@ -666,9 +666,9 @@ def precision_steady_256():
     ref.close()
     del ref
     torch.cuda.empty_cache()
-    for key in ("f32", "bf16", "bf16_sr", "f16"):
+    for key in ("f32", "bf16", "bf16_sr", "f16", "f16_sr"):
         st = key.split("_")[0]
-        sim = make_sim(shape, st, 1.0, **({"rounding": "stochastic"} if key == "bf16_sr" else {}))
+        sim = make_sim(shape, st, 1.0, **({"rounding": "stochastic"} if key.endswith("_sr") else {}))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         while sim.t < n:

@@ -133,20 +133,27 @@ typedef struct {
                              input, zero on output); the state blob holds f as
                              [9][N] and (mhd) g as [2][5][N]. */
   int32_t rounding;       /* lbm_rounding: how the step rounds the populations it
-                             stores.  LBM_ROUND_STOCHASTIC needs LBM_BF16 storage
-                             and the flow step alone (no mhd); see below. */
+                             stores.  LBM_ROUND_STOCHASTIC needs LBM_BF16 or LBM_F16
+                             storage and the flow step alone (no mhd); see below. */
   uint32_t seed;          /* stochastic rounding: seed of the counter-based
                              random bits (any value; the same seed gives the
                              same march bit for bit) */
 } lbm_params;
 
 /* Rounding of stored populations.  LBM_ROUND_NEAREST: nearest, ties to even.
- * LBM_ROUND_STOCHASTIC (BF16 storage only): each FP32 result is rounded up
- * in magnitude with probability equal to its distance from the BF16 value
- * below, so that the stored value is unbiased and per-step changes smaller
- * than the BF16 spacing still accumulate.  Stored bits = the upper 16 bits of
- * (FP32 bits + r) for finite values, r the 16 random bits of that value
- * (non-finite values are kept as NaN/Inf).  The random bits are counter-based:
+ * LBM_ROUND_STOCHASTIC (16-bit storage): each FP32 result v is rounded to
+ * the 16-bit value above it in magnitude with probability equal to its
+ * distance from the value below (in units of their spacing, resolved to
+ * 2^-16 or, FP16 normal range, 2^-13), so that the stored value is unbiased
+ * and per-step changes smaller than the spacing still accumulate.  With r the
+ * 16 random bits of that value:
+ *   BF16: stored bits = the upper 16 bits of (FP32 bits of v + r);
+ *   FP16, |v| >= 2^-14: the FP32 bits of |v| plus (r >> 3), with their low 13
+ *     bits cleared, converted exactly (Inf on overflow);
+ *   FP16, |v| < 2^-14: with q = |v| 2^24, k = floor(q) and
+ *     t = floor((q - k) 2^16), the magnitude (k + 1) 2^-24 if t + r >= 2^16,
+ *     else k 2^-24;
+ * Inf and NaN are kept.  The random bits are counter-based:
  * for node n, directions 2k and 2k+1 (k = 0..9 for D3Q19, 0..4 for D2Q9, in
  * the order of lbm_lattice_velocities), and the step number t being
  * computed, h = fmix32(n*0x9E3779B1 + t*0x85EBCA77 + k*0xC2B2AE3D + seed)

@@ -234,7 +234,7 @@ class Simulation:
          induction lattice, the fluid box is pad nodes in from each wall face).
     source: "precond" (P_S, the paper's form) or "naive" (S/gamma, its negative control).
     wall_u: None or (6, 3) face velocities (x-low, x-high, y-low, y-high, z-low, z-high).
-    rounding: "nearest" or "stochastic" (bf16 storage, flow step without mhd): how
+    rounding: "nearest" or "stochastic" (bf16/f16 storage, flow step without mhd): how
               stored populations are rounded; seed: the stochastic rounding seed.
     """
 

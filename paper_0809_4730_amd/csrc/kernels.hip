@@ -178,7 +178,7 @@ __device__ __forceinline__ void load_force(const GridArgs& g, const CollideArgs<
 
 // ------------------------------------------------------------------ steps --
 // ROWS: every wave lies in one x-row (nx a multiple of 64; neighbours_rows).
-// SR: BF16 stores with stochastic rounding (store_stochastic).
+// SR: 16-bit stores with stochastic rounding (store_stochastic).
 template <typename S, bool CHECK, bool FIELD, bool NT, bool MOVING, bool WIDE, bool ROWS, bool SR>
 __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<typename Storage<S>::R> c,
                                                     const S* __restrict__ fin, S* __restrict__ fout,
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<type
     load_force<R, WIDE>(g, c, force, FIELD, n, Fx, Fy, Fz);
     const NodeMacro<R> mac = collide19<R>(f, Fx, Fy, Fz, c);
     if constexpr (SR)
-      store_stochastic<NT, WIDE, Q19>(fout, g, n, f);
+      store_stochastic<S, NT, WIDE, Q19>(fout, g, n, f);
     else
       store19<S, NT, WIDE>(fout, g, n, f);
     if constexpr (CHECK)
@@ -431,7 +431,7 @@ hipError_t launch_glbe_step(const GridArgs& g, const CollideArgs<typename Storag
         return with_flag(rows_per_wave(g), [&](auto RW) {
           constexpr bool ch = decltype(CH)::value, fl = decltype(FL)::value,
                          w = decltype(W)::value, rw = decltype(RW)::value;
-          if constexpr (std::is_same_v<S, bf16_t>) {
+          if constexpr (sizeof(S) == 2) {
             if (stochastic) {
               if (c.moving)
                 glbe_step<S, ch, fl, false, true, w, rw, true>

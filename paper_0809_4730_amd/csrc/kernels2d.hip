@@ -146,7 +146,7 @@ __device__ __forceinline__ void collide_g5(R (&g)[2][Q5], const Coupled2<R>& cp,
   }
 }
 
-// SR: BF16 stores with stochastic rounding (store_stochastic).
+// SR: 16-bit stores with stochastic rounding (store_stochastic).
 template <typename S, bool CHECK, bool FIELD, bool NT, bool WIDE, bool SR>
 __global__ __launch_bounds__(kBlock) void glbe2_step(GridArgs g, CollideArgs<typename Storage<S>::R> c,
                                                      const S* __restrict__ fin, S* __restrict__ fout,
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void glbe2_step(GridArgs g, CollideArgs<typ
     load_force2<R, WIDE>(g, c, force, FIELD, n, Fx, Fy);
     const NodeMacro<R> mac = collide9<R>(f, Fx, Fy, c);
     if constexpr (SR)
-      store_stochastic<NT, WIDE, Q9>(fout, g, n, f);
+      store_stochastic<S, NT, WIDE, Q9>(fout, g, n, f);
     else
       store9<S, NT, WIDE>(fout, g, n, f);
     if constexpr (CHECK) check_node2<R, WIDE>(g, usnap, n, mac, acc);
@@ -276,7 +276,7 @@ hipError_t launch_glbe2_step(const GridArgs& g, const CollideArgs<typename Stora
         return with_flag(wide_offsets(g, sizeof(R)), [&](auto W) {
           constexpr bool ch = decltype(CH)::value, fl = decltype(FL)::value,
                          nts = decltype(NTS)::value, w = decltype(W)::value;
-          if constexpr (std::is_same_v<S, bf16_t>) {
+          if constexpr (sizeof(S) == 2) {
             if (stochastic) {
               glbe2_step<S, ch, fl, nts, w, true>
                   <<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);

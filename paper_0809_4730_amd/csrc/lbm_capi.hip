@@ -63,8 +63,9 @@ std::string validate(const lbm_grid* grid, const lbm_params* p) {
   }
   if (p->rounding != LBM_ROUND_NEAREST && p->rounding != LBM_ROUND_STOCHASTIC)
     return "rounding must be LBM_ROUND_NEAREST or LBM_ROUND_STOCHASTIC";
-  if (p->rounding == LBM_ROUND_STOCHASTIC && (p->storage != LBM_BF16 || p->mhd))
-    return "stochastic rounding needs LBM_BF16 storage and the flow step alone (mhd = 0)";
+  if (p->rounding == LBM_ROUND_STOCHASTIC &&
+      ((p->storage != LBM_BF16 && p->storage != LBM_F16) || p->mhd))
+    return "stochastic rounding needs LBM_BF16 or LBM_F16 storage and the flow step alone (mhd = 0)";
   if (p->check_every < 1) return "check_every must be >= 1";
   if (p->history_len < 1) return "history_len must be >= 1";
   if (p->source_mode != 0 && p->source_mode != 1) return "source_mode must be 0 or 1";
@@ -169,7 +170,8 @@ hipError_t launch_step_kernel(lbm_ctx* c, bool check) {
                                          c->usnap(), partials, c->stream);
       default:
         return launch_glbe2_step<_Float16>(c->ga, c->cf, fin, fout, c->force(), fld, check,
-                                           c->nt_store, false, c->usnap(), partials, c->stream);
+                                           c->nt_store, c->p.rounding == LBM_ROUND_STOCHASTIC,
+                                           c->usnap(), partials, c->stream);
     }
   }
   if (c->p.mhd) {
@@ -194,7 +196,8 @@ hipError_t launch_step_kernel(lbm_ctx* c, bool check) {
                                       c->stream);
     default:
       return launch_glbe_step<_Float16>(c->ga, c->cf, fin, fout, c->force(), fld, check,
-                                        c->nt_store, false, c->usnap(), partials, c->stream);
+                                        c->nt_store, c->p.rounding == LBM_ROUND_STOCHASTIC,
+                                        c->usnap(), partials, c->stream);
   }
 }
 

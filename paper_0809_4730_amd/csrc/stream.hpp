@@ -246,11 +246,43 @@ __device__ __forceinline__ uint16_t bf16_stochastic(float v, uint32_t r16) {
   return static_cast<uint16_t>(bits >> 16);
 }
 
-// The Q BF16 stores of node n with stochastic rounding (the counter-based
+// FP16 with stochastic rounding, on the magnitude.  FP16 normal range
+// (|v| >= 2^-14): 13 of the 23 FP32 fraction bits are dropped after adding
+// r >> 3, and the result converts exactly.  Subnormal range: with
+// q = |v| 2^24 (exact), k = floor(q) and t = floor((q - k) 2^16), the result is
+// (k + [t + r >= 2^16]) 2^-24.  Overflow gives Inf; Inf and NaN are kept.
+__device__ __forceinline__ uint16_t f16_stochastic(float v, uint32_t r16) {
+  const uint32_t bits = __float_as_uint(v);
+  uint32_t a = bits & 0x7FFFFFFFu;
+  if (a >= 0x7F800000u) return __builtin_bit_cast(uint16_t, static_cast<_Float16>(v));
+  float m;
+  if (a >= 0x38800000u) {
+    a = (a + (r16 >> 3)) & ~0x1FFFu;
+    m = __uint_as_float(a);
+  } else {
+    const float q = __uint_as_float(a) * 16777216.0f;
+    const float k = __builtin_floorf(q);
+    const uint32_t t = static_cast<uint32_t>((q - k) * 65536.0f);
+    m = (k + static_cast<float>((t + r16) >> 16)) * 5.9604644775390625e-8f;
+  }
+  m = __uint_as_float(__float_as_uint(m) | (bits & 0x80000000u));
+  return __builtin_bit_cast(uint16_t, static_cast<_Float16>(m));
+}
+
+template <typename S>
+__device__ __forceinline__ uint16_t stochastic16(float v, uint32_t r16) {
+  if constexpr (std::is_same_v<S, bf16_t>)
+    return bf16_stochastic(v, r16);
+  else
+    return f16_stochastic(v, r16);
+}
+
+// The Q 16-bit stores of node n with stochastic rounding (the counter-based
 // random bits documented with lbm_rounding in the C header).
-template <bool NT, bool WIDE, int Q>
-__device__ __forceinline__ void store_stochastic(bf16_t* __restrict__ fout, const GridArgs& g,
+template <typename S, bool NT, bool WIDE, int Q>
+__device__ __forceinline__ void store_stochastic(S* __restrict__ fout, const GridArgs& g,
                                                  uint32_t n, const float (&f)[Q]) {
+  static_assert(sizeof(S) == 2, "stochastic rounding stores 16-bit values");
   const uint32_t base = n * 0x9E3779B1u + g.step * 0x85EBCA77u + g.seed;
 #pragma unroll
   for (int k = 0; k < (Q + 1) / 2; ++k) {
@@ -259,9 +291,9 @@ __device__ __forceinline__ void store_stochastic(bf16_t* __restrict__ fout, cons
     for (int j = 0; j < 2; ++j) {
       const int a = 2 * k + j;
       if (a < Q) {
-        const uint16_t bits = bf16_stochastic(f[a], j ? (h >> 16) : (h & 0xFFFFu));
+        const uint16_t bits = stochastic16<S>(f[a], j ? (h >> 16) : (h & 0xFFFFu));
         if constexpr (WIDE) {
-          st_pop<NT>(&(fout + static_cast<int64_t>(a) * g.stride + n)->bits, bits);
+          st_pop<NT>(reinterpret_cast<uint16_t*>(fout + static_cast<int64_t>(a) * g.stride + n), bits);
         } else {
           __builtin_amdgcn_raw_buffer_store_b16(
               bits, raw_rsrc(fout), n * 2u,

@@ -93,8 +93,8 @@ def _grid_params(pkg, **kw):
 @pytest.mark.parametrize("bad", [
     dict(gamma=0.0), dict(gamma=1.5), dict(n=(0, 4, 4)), dict(storage=7),
     dict(mhd=1, storage=2), dict(n=(2048, 2048, 1024)),
-    # stochastic rounding: bf16 storage and the flow step without mhd only
-    dict(rounding=2, storage=2), dict(rounding=1, storage=1), dict(rounding=1, storage=3),
+    # stochastic rounding: 16-bit storage and the flow step without mhd only
+    dict(rounding=2, storage=2), dict(rounding=1, storage=1), dict(rounding=1, storage=0),
     dict(rounding=1, storage=2, mhd=1), dict(rounding=1, storage=0, lattice=1, n=(8, 8, 1)),
 ])
 def test_validation_rejects(lib, bad):
@@ -106,10 +106,11 @@ def test_validation_rejects(lib, bad):
     assert lib.lbm_last_error(None)
 
 
+@pytest.mark.parametrize("storage", [2, 3])
 @pytest.mark.parametrize("lattice,n", [(0, (8, 8, 8)), (1, (8, 8, 1))])
-def test_validation_accepts_stochastic_bf16(lib, lattice, n):
+def test_validation_accepts_stochastic_16bit(lib, lattice, n, storage):
     import paper_0809_4730_amd as pkg
-    g, p = _grid_params(pkg, rounding=1, storage=pkg.BF16, lattice=lattice, n=n)
+    g, p = _grid_params(pkg, rounding=1, storage=storage, lattice=lattice, n=n)
     p.seed = 0xFFFFFFFF
     nbytes = ctypes.c_size_t()
     assert lib.lbm_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nbytes)) == 0

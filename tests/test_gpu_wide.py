@@ -43,7 +43,7 @@ def _same(a, b):
         assert np.array_equal(np.asarray(a), np.asarray(b))
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "bf16", "bf16_sr"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16", "bf16_sr", "f16_sr"])
 def test_d3q19_step_forms_agree(monkeypatch, storage):
     import torch
     import paper_0809_4730_amd as pkg
@@ -52,7 +52,7 @@ def test_d3q19_step_forms_agree(monkeypatch, storage):
     dt = torch.float64 if storage == "f64" else torch.float32
     F = torch.tensor(inputs.random_force(shape, seed=5, amp=1e-5), dtype=dt, device="cuda")
 
-    kw = dict(rounding="stochastic", seed=77) if storage == "bf16_sr" else {}
+    kw = dict(rounding="stochastic", seed=77) if storage.endswith("_sr") else {}
 
     def run():
         sim = pkg.Simulation(shape, bc, 0.2, glbe.rates(0.05, 0.2), storage=storage.split("_")[0],
@@ -147,7 +147,7 @@ def test_streaming_store_forms_agree(monkeypatch):
     def run3(storage, mhd):
         def run():
             kw = dict(mhd=dict(gamma_m=0.3, chi=0.05, eta=0.03, B0=(0.01, 0.02, -0.01))) if mhd else {}
-            if storage == "bf16_sr":
+            if storage.endswith("_sr"):
                 kw = dict(rounding="stochastic", seed=78)
             sim = pkg.Simulation(shape, bc, 0.3, glbe.rates(0.05, 0.3), storage=storage.split("_")[0],
                                  force=F if storage != "f64" else F.double(), **kw)
@@ -166,7 +166,8 @@ def test_streaming_store_forms_agree(monkeypatch):
             sim.step(41)
             return sim.get_state(), sim.history(8)
         return run
-    for run in (run3("f32", False), run3("bf16", False), run3("bf16_sr", False), run3("f32", True),
+    for run in (run3("f32", False), run3("bf16", False), run3("bf16_sr", False),
+                run3("f16_sr", False), run3("f32", True),
                 run3("f64", True), run2(False), run2(True), run2(False, "bf16_sr")):
         _same(*_both(monkeypatch, run, "LBM_NT_STORE", "0"))
 
