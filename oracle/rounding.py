@@ -19,9 +19,10 @@ Definition (the contract the library documents for its BF16 storage):
   and NaN stays NaN.
 * FP16, |v| >= 2^-14 (its normal range): the FP32 bits of |v| plus r >> 3,
   with the 13 fraction bits FP16 lacks cleared, then an exact conversion (Inf
-  on overflow).  |v| < 2^-14 (subnormal, spacing 2^-24): with q = |v| 2^24,
-  k = floor(q) and t = floor((q - k) 2^16), the magnitude is (k + 1) 2^-24 if
-  t + r >= 2^16, else k 2^-24.  Unbiased up to the 2^-16 resolution of t.
+  on overflow).  |v| < 2^-14 (subnormal, spacing 2^-24): the same on
+  s = |v| + 2^-14 rounded to FP32 (whose grid in [2^-14, 2^-13] is 2^-37, 13
+  bits below the subnormal spacing), then the 2^-14 taken back off exactly.
+  Unbiased up to that FP32 rounding of s (at most 2^-38).
 
 Pins (tests/test_oracle_rounding.py): MurmurHash3_x86_32 published test
 vectors, whose last step is fmix32 (``murmur3_x86_32`` below exists only to
@@ -114,17 +115,14 @@ def stochastic_f16(v32, r16):
     b = v32.view(np.uint32).astype(np.uint64)
     a = b & np.uint64(0x7FFFFFFF)
     finite = a < 0x7F800000
-    normal = a >= 0x38800000
-    # normal range: drop 13 fraction bits after adding 13 random bits
-    an = (a + (r >> np.uint64(3))) & np.uint64(0xFFFFE000)
-    mag_n = an.astype(np.uint32).view(np.float32).astype(np.float64)
-    # subnormal range: spacing 2^-24, position resolved to 2^-16 of it
+    sub = a < 0x38800000                         # below FP16's smallest normal, 2^-14
+    mag32 = a.astype(np.uint32).view(np.float32)
     with np.errstate(invalid="ignore"):         # Inf / NaN lanes are replaced below
-        q = np.abs(v32.astype(np.float64)) * 2.0 ** 24
-        k = np.floor(q)
-        t = np.floor((q - k) * 65536.0)
-        mag_s = (k + ((t + r.astype(np.float64)) >= 65536.0)) * 2.0 ** -24
-    mag = np.where(normal, mag_n, mag_s)
+        # FP16 subnormals: offset by 2^-14 (an FP32 addition, rounded to nearest)
+        s = np.where(sub, mag32 + np.float32(2.0 ** -14), mag32).astype(np.float32)
+        sb = s.view(np.uint32).astype(np.uint64)
+        y = ((sb + (r >> np.uint64(3))) & np.uint64(0xFFFFE000)).astype(np.uint32).view(np.float32)
+        mag = np.where(sub, y.astype(np.float64) - 2.0 ** -14, y.astype(np.float64))
     with np.errstate(over="ignore"):
         out = np.where(b >> np.uint64(31) != 0, -mag, mag).astype(np.float16).astype(np.float64)
         special = v32.astype(np.float16).astype(np.float64)

@@ -145,7 +145,8 @@ def _f16_samples():
     v = np.concatenate([
         rng.standard_normal(30) * 10.0 ** rng.uniform(-4, 4, 30),        # normal range
         rng.uniform(-6e-5, 6e-5, 20),                                    # FP16 subnormal range
-        [1.0, -2.0 ** -14, 2.0 ** -14 * (1 - 2.0 ** -11), 3 * 2.0 ** -25, 65504.0, -1e-30],
+        [1.0, -2.0 ** -14, 2.0 ** -14 * (1 - 2.0 ** -11), 3 * 2.0 ** -25, 65504.0, -1e-30,
+         1234 * 2.0 ** -37, -5 * 2.0 ** -37],
     ]).astype(np.float32)
     return v
 
@@ -155,11 +156,10 @@ def test_f16_unbiased_over_all_random_values():
     for v in _f16_samples():
         out = rounding.stochastic_f16(np.full(r.size, v, dtype=np.float32), r)
         mean = out.sum() / r.size                     # exact: 2^16 FP16 values
-        if abs(v) >= 2.0 ** -14:
+        if abs(v) >= 2.0 ** -14 or float(v) % 2.0 ** -37 == 0.0:
             assert mean == float(v), v
-        else:   # the position within the 2^-24 spacing is resolved to 2^-16 of it
-            assert mean == np.floor(abs(float(v)) * 2.0 ** 40) * 2.0 ** -40 * np.sign(v), v
-            assert abs(mean - float(v)) < 2.0 ** -40
+        else:   # subnormal range: resolved to 2^-37, 2^-13 of the 2^-24 spacing
+            assert abs(mean - float(v)) <= 2.0 ** -38, v
 
 
 def test_f16_brackets_and_extreme_random_values():
@@ -172,7 +172,7 @@ def test_f16_brackets_and_extreme_random_values():
         assert np.all(out[exact] == lo[exact])
     assert np.all(rounding.stochastic_f16(v, np.zeros(v.size)) == lo)       # r = 0: truncation
     up = rounding.stochastic_f16(v, np.full(v.size, 0xFFFF))
-    resolved = np.abs(v.astype(np.float64) - lo) >= 2.0 ** -40              # not below 2^-16 spacing
+    resolved = np.abs(v.astype(np.float64) - lo) >= 2.0 ** -37              # not below the 2^-37 grid
     assert np.all(up[~exact & resolved] == hi[~exact & resolved])
 
 
