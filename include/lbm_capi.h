@@ -144,15 +144,14 @@ typedef struct {
  * LBM_ROUND_STOCHASTIC (16-bit storage): each FP32 result v is rounded to
  * the 16-bit value above it in magnitude with probability equal to its
  * distance from the value below (in units of their spacing, resolved to
- * 2^-16 or, FP16 normal range, 2^-13), so that the stored value is unbiased
+ * 2^-16 for BF16 and 2^-13 for FP16), so that the stored value is unbiased
  * and per-step changes smaller than the spacing still accumulate.  With r the
  * 16 random bits of that value:
  *   BF16: stored bits = the upper 16 bits of (FP32 bits of v + r);
- *   FP16, |v| >= 2^-14: the FP32 bits of |v| plus (r >> 3), with their low 13
- *     bits cleared, converted exactly (Inf on overflow);
- *   FP16, |v| < 2^-14: with q = |v| 2^24, k = floor(q) and
- *     t = floor((q - k) 2^16), the magnitude (k + 1) 2^-24 if t + r >= 2^16,
- *     else k 2^-24;
+ *   FP16: with s = |v| (|v| >= 2^-14) or s = |v| + 2^-14 rounded to FP32
+ *     (|v| < 2^-14, FP16's subnormal range), the FP32 bits of s plus (r >> 3)
+ *     with their low 13 bits cleared, minus the 2^-14 offset if added (an
+ *     exact subtraction), converted exactly (Inf on overflow);
  * Inf and NaN are kept.  The random bits are counter-based:
  * for node n, directions 2k and 2k+1 (k = 0..9 for D3Q19, 0..4 for D2Q9, in
  * the order of lbm_lattice_velocities), and the step number t being

@@ -246,27 +246,23 @@ __device__ __forceinline__ uint16_t bf16_stochastic(float v, uint32_t r16) {
   return static_cast<uint16_t>(bits >> 16);
 }
 
-// FP16 with stochastic rounding, on the magnitude.  FP16 normal range
-// (|v| >= 2^-14): 13 of the 23 FP32 fraction bits are dropped after adding
-// r >> 3, and the result converts exactly.  Subnormal range: with
-// q = |v| 2^24 (exact), k = floor(q) and t = floor((q - k) 2^16), the result is
-// (k + [t + r >= 2^16]) 2^-24.  Overflow gives Inf; Inf and NaN are kept.
+// FP16 with stochastic rounding, on the magnitude: 13 of the 23 FP32
+// fraction bits are dropped after adding r >> 3, and the result converts
+// exactly (Inf on overflow).  Below 2^-14 (FP16 subnormals, spacing 2^-24)
+// the magnitude is first offset by 2^-14, which puts the subnormal grid on
+// the 13-bit grid of [2^-14, 2^-13], and the offset is taken back exactly
+// afterwards: one branch-free sequence for both ranges.  Inf and NaN are kept.
 __device__ __forceinline__ uint16_t f16_stochastic(float v, uint32_t r16) {
+  constexpr float kMinNormal = 6.103515625e-05f;  // 2^-14
   const uint32_t bits = __float_as_uint(v);
-  uint32_t a = bits & 0x7FFFFFFFu;
+  const uint32_t a = bits & 0x7FFFFFFFu;
   if (a >= 0x7F800000u) return __builtin_bit_cast(uint16_t, static_cast<_Float16>(v));
-  float m;
-  if (a >= 0x38800000u) {
-    a = (a + (r16 >> 3)) & ~0x1FFFu;
-    m = __uint_as_float(a);
-  } else {
-    const float q = __uint_as_float(a) * 16777216.0f;
-    const float k = __builtin_floorf(q);
-    const uint32_t t = static_cast<uint32_t>((q - k) * 65536.0f);
-    m = (k + static_cast<float>((t + r16) >> 16)) * 5.9604644775390625e-8f;
-  }
-  m = __uint_as_float(__float_as_uint(m) | (bits & 0x80000000u));
-  return __builtin_bit_cast(uint16_t, static_cast<_Float16>(m));
+  const bool sub = a < 0x38800000u;
+  const float s = sub ? __uint_as_float(a) + kMinNormal : __uint_as_float(a);
+  const float y = __uint_as_float((__float_as_uint(s) + (r16 >> 3)) & ~0x1FFFu);
+  const float m = sub ? y - kMinNormal : y;
+  return __builtin_bit_cast(
+      uint16_t, static_cast<_Float16>(__uint_as_float(__float_as_uint(m) | (bits & 0x80000000u))));
 }
 
 template <typename S>

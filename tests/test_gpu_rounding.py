@@ -3,9 +3,8 @@
 The step computes in FP32 like the nearest-even form; only the store differs:
 each FP32 result is rounded up or down with the counter-based random bits of
 oracle/rounding.py.  The decision is floor((P + r') / W) for an integer
-position P of the value: BF16 P = its FP32 bits, r' = r, W = 2^16; FP16 normal
-range P = its FP32 bits, r' = r >> 3, W = 2^13; FP16 subnormal range
-P = floor(|v| 2^40), r' = r, W = 2^16.  The oracle's FP64 step gives the value
+position P of the value: BF16 P = its FP32 bits, r' = r, W = 2^16; FP16
+P = the FP32 bits of |v| (of |v| + 2^-14 below 2^-14), r' = r >> 3, W = 2^13.  The oracle's FP64 step gives the value
 before rounding to within FP32 error, so wherever that error cannot move
 P + r' across a multiple of W (almost every population) the stored bits are
 fixed by the oracle alone and must match exactly; everywhere the result must
@@ -60,10 +59,10 @@ def _check_bits(out, ref, r, eps, fmt):
         edge = np.zeros(ref.shape, dtype=bool)
     else:
         normal = a >= 0x38800000
-        pos_s = (np.floor(np.abs(ref32.astype(np.float64)) * 2.0 ** 40).astype(np.int64) + r) & 0xFFFF
-        pos = np.where(normal, (a + (r >> 3)) & 0x1FFF, pos_s)
-        width = np.where(normal, 8192, 65536)
-        margin = np.where(normal, m32, np.ceil(2 * eps * 2.0 ** 40) + 2)
+        off = (np.abs(ref32) + np.float32(2.0 ** -14)).astype(np.float32)     # grid 2^-37
+        p = np.where(normal, a, off.view(np.uint32).astype(np.int64))
+        pos, width = (p + (r >> 3)) & 0x1FFF, 8192
+        margin = np.where(normal, m32, np.ceil(2 * eps * 2.0 ** 37) + 2)
         edge = np.abs(np.abs(ref) - 2.0 ** -14) <= 2 * eps      # the two ranges meet
         announce("FP16 subnormal range: %.3f of the populations" % np.mean(~normal))
     decided = (pos >= margin) & (pos < width - margin) & (np.abs(ref) > 2 * eps) & ~edge
