@@ -842,6 +842,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--grid", type=int, default=64, help="cube edge of the duct (64 = headline)")
     ap.add_argument("--storage", default="f32", choices=["f32", "f64", "bf16", "f16"])
+    ap.add_argument("--rounding", default="nearest", choices=["nearest", "stochastic"],
+                    help="rounding of 16-bit stores (stochastic: bf16 / f16 only)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--probe", choices=["mhd256", "adjoint128", "d2q9_4096", "precision256",
@@ -865,13 +867,17 @@ def main():
         return
 
     shape, gamma, storage = (args.grid,) * 3, 0.1, args.storage
-    mlups, wall, mean_us = measure(shape, storage, gamma, args.steps, args.warmup)
+    if args.rounding == "stochastic" and storage not in ("bf16", "f16"):
+        raise SystemExit("--rounding stochastic needs --storage bf16 or f16")
+    rkw = {"rounding": "stochastic"} if args.rounding == "stochastic" else {}
+    mlups, wall, mean_us = measure(shape, storage, gamma, args.steps, args.warmup, **rkw)
     N = shape[0] * shape[1] * shape[2]
     sb = {"f32": 4, "f64": 8, "bf16": 2, "f16": 2}[storage]
     bpn = algorithmic_bytes_per_node(sb, True, NO_CHECK)
     achieved = bpn * N / (mean_us * 1e-6) / 1e9
     khash = kernel_hash()
-    traffic = traffic_from_profiles("glbe_step_%s_duct%d" % (storage, args.grid), khash)
+    tag = "glbe_step_%s%s_duct%d" % (storage, "_sr" if rkw else "", args.grid)
+    traffic = traffic_from_profiles(tag, khash)
     line = {
         "metric": "MLUPS, % HBM roofline; wall time to 1e-8 residual, gamma<1 vs plain gamma=1",
         "value": round(mlups, 2),
@@ -887,13 +893,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": "square duct %dx%dx%d, D3Q19 preconditioned MRT-GLBE, "
                                "spatially varying force F0=1e-5, nu=0.131, gamma=0.1, "
-                               "%s deviation storage, FP64 residual every 10 steps"
-                               % (shape + (storage.upper(),)),
-                   "grid": list(shape), "gamma": gamma, "storage": storage},
+                               "%s deviation storage%s, FP64 residual every 10 steps"
+                               % (shape + (storage.upper(),
+                                           " (stochastic rounding)" if rkw else "")),
+                   "grid": list(shape), "gamma": gamma, "storage": storage,
+                   "rounding": args.rounding},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": "glbe_step<%s, check=false, field=true>" % storage,
+                     "kernel": "glbe_step<%s, check=false, field=true%s>"
+                               % (storage, ", stochastic" if rkw else ""),
                      "alg_bytes_per_node": bpn, "mean_kernel_us": round(mean_us, 3),
                      "kernel_hash": khash},
     }
