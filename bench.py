@@ -692,11 +692,12 @@ def ladder_256():
     """Wall time to a residual of 1e-8 on the 256^3 duct of precision_steady_256
     for precision ladders, each rung continuing the previous rung's state on
     the device (lbm_convert_state).  A rung ends on the velocity residual R
-    ("r") or, for BF16, on the kinetic energy sum |u|^2 ("e"): its relative
-    change over 1000 steps, a global sum in which the rounding noise of the
-    stored values averages out while R measures it (the duct's net flow rate
-    is zero by symmetry, so it cannot serve).  A ladder's contexts are built before its
-    clock starts; u of each final state against the FP64-alone steady state."""
+    ("r") or, for 16-bit storage, on the kinetic energy sum |u|^2 ("e"): its
+    relative change over 1000 steps, a global sum in which the rounding noise
+    of the stored values averages out while R measures it (the duct's net flow
+    rate is zero by symmetry, so it cannot serve).  A ladder's contexts are
+    built before its clock starts; u of each final state against the
+    FP64-alone steady state."""
     import numpy as np
     import torch
     shape = (256, 256, 256)
@@ -708,6 +709,8 @@ def ladder_256():
         (("bf16_sr", "e", 1e-4), ("f32", "r", 2e-7), ("f64", "r", 1e-8)),
         (("bf16_sr", "e", 1e-5), ("f32", "r", 2e-7), ("f64", "r", 1e-8)),
         (("bf16", "e", 1e-4), ("f32", "r", 2e-7), ("f64", "r", 1e-8)),
+        (("f16_sr", "e", 1e-5), ("f32", "r", 2e-7), ("f64", "r", 1e-8)),
+        (("f16_sr", "e", 1e-6), ("f32", "r", 2e-7), ("f64", "r", 1e-8)),
     ]
 
     def energy(sim):
@@ -717,7 +720,8 @@ def ladder_256():
     for lad in ladders:
         name = " -> ".join("%s(%s<%g)" % rung for rung in lad)
         sims = [make_sim(shape, k.split("_")[0], 1.0,
-                         **({"rounding": "stochastic"} if k == "bf16_sr" else {})) for k, _, _ in lad]
+                         **({"rounding": "stochastic"} if k.endswith("_sr") else {}))
+                for k, _, _ in lad]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         rungs, prev, ok = [], None, True
