@@ -14,6 +14,7 @@ import os
 import numpy as np
 
 __all__ = ["Simulation", "default_rates", "lattice_velocities", "LbmError", "library_path",
+           "run_ladder",
            "load_library", "F64", "F32", "BF16", "F16", "PERIODIC", "WALL"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -369,6 +370,39 @@ class Simulation:
                                               ctypes.byref(steps), ctypes.byref(r)))
         return steps.value, r.value
 
+    def run_to_energy_change(self, tol, max_steps, window=1000):
+        """March until the relative change of the kinetic-energy sum |u|^2 over
+        `window` steps (read from the residual history) falls below tol.  Unlike
+        the residual R, this global sum averages out the rounding noise of
+        16-bit storage, so it can end a 16-bit march once the flow itself has
+        converged.  For a slow mode of relative amplitude a decaying at rate
+        lambda per step the change per window is about
+        2 a (1 - exp(-lambda window)), so the tol that matches a given R
+        depends on the lattice (1e-6 per 1000 steps suits the 256^3 duct).
+        `window` must be a multiple of check_every.  Returns (the step at which
+        the change fell below tol, or -1 after max_steps; the last change);
+        raises LbmError on non-finite values."""
+        ce = self._params.check_every
+        if window < ce or window % ce:
+            raise ValueError("window must be a multiple of check_every (%d)" % ce)
+
+        def energy():
+            rec = self.history(1)[-1]
+            if rec[6] > 0:
+                raise LbmError(-4, "non-finite values at step %d" % int(rec[0]))
+            return float(rec[3])
+        start = self.t
+        self.step(window)
+        e0, change = energy(), float("inf")
+        while self.t - start < max_steps:
+            self.step(window)
+            e1 = energy()
+            change = abs(e1 - e0) / max(abs(e1), 1e-300)
+            if change < tol:
+                return self.t, change
+            e0 = e1
+        return -1, change
+
     @property
     def t(self):
         s = ctypes.c_int64()
@@ -485,6 +519,31 @@ def run_to_residual_mixed(lo, hi, tol, switch_tol, max_steps, poll_every=200):
     n_lo, _ = lo.run_to_residual(switch_tol, max_steps, poll_every)
     hi.convert_from(lo)
     return hi.run_to_residual(tol, max_steps, poll_every)
+
+
+def run_ladder(rungs, max_steps, poll_every=1000):
+    """March one flow through a ladder of storage precisions: each rung is
+    (simulation, criterion, tol) with criterion "residual" (run_to_residual)
+    or "energy" (run_to_energy_change, for 16-bit rungs whose rounding noise
+    holds R up); each rung continues the previous rung's state on the device
+    (convert_from).  All simulations must describe the same lattice, force and
+    parameters.  Returns (step at which the last rung met its tol, or -1 if a
+    rung did not within max_steps of its own; [(step, value) per rung])."""
+    out, prev = [], None
+    for sim, crit, tol in rungs:
+        if prev is not None:
+            sim.convert_from(prev)
+        if crit == "residual":
+            n, v = sim.run_to_residual(tol, max_steps, poll_every)
+        elif crit == "energy":
+            n, v = sim.run_to_energy_change(tol, max_steps, poll_every)
+        else:
+            raise ValueError("criterion must be 'residual' or 'energy'")
+        out.append((n, v))
+        if n < 0:
+            return -1, out
+        prev = sim
+    return out[-1][0], out
 
 
 # ------------------------------------------------------------- autograd ----

@@ -243,3 +243,36 @@ def test_stochastic_rounding_tracks_fp64_where_nearest_stalls():
     assert errs["bf16", "stochastic"] < errs["bf16", "nearest"] / 3
     assert errs["f16", "stochastic"] < 5e-4
     assert errs["f16", "stochastic"] < errs["f16", "nearest"] / 5
+
+
+def test_precision_ladder_reaches_the_fp64_steady_state():
+    """run_ladder on the 64^3 duct (gamma = 1): FP16 with stochastic rounding
+    until the kinetic energy settles, FP32 to R < 2e-7, FP64 to R < 1e-8.  The
+    final state is FP64 alone's steady state to within what R < 1e-8 leaves
+    in the slowest mode."""
+    import torch
+
+    import paper_0809_4730_amd as pkg
+    announce("precision ladder, 64^3 duct")
+    cfg = inputs.DUCT64
+    shape, gamma = (64, 64, 64), 1.0
+    F = torch.tensor(inputs.duct_force(shape, cfg["F0"]), dtype=torch.float64, device="cuda")
+    s = pkg.default_rates(cfg["nu"], gamma)
+
+    def sim(storage, **kw):
+        return pkg.Simulation(shape, cfg["bc"], gamma, s, storage=storage,
+                              force=F if storage == "f64" else F.float(), **kw)
+    ref = sim("f64")
+    n_ref, _ = ref.run_to_residual(1e-8, 200000, poll_every=1000)
+    assert n_ref > 0
+    u64 = ref.moments("f64")[1].cpu().numpy()
+    with pytest.raises(ValueError):
+        sim("f16").run_to_energy_change(1e-6, 1000, window=15)
+    lo, mid, hi = sim("f16", rounding="stochastic", seed=3), sim("f32"), sim("f64")
+    n, per_rung = pkg.run_ladder([(lo, "energy", 1e-5), (mid, "residual", 2e-7),
+                                  (hi, "residual", 1e-8)], 200000)
+    err = rel(hi.moments("f64")[1].cpu().numpy(), u64)
+    announce("ladder: %s, FP64 alone %d steps; u rel L2 vs FP64 alone %.2e" % (per_rung, n_ref, err))
+    assert n > 0 and all(k > 0 for k, _ in per_rung)
+    assert per_rung[0][0] < per_rung[1][0] < per_rung[2][0] == n <= hi.t  # hi.t: poll boundary
+    assert err < 1e-4
