@@ -269,3 +269,35 @@ def test_batch_workspace_and_validation(lib):
     st = lib.lbm_batch_run(ctypes.byref(g), pkg.F64, 1.0, 2, members, None, 0, None, 1e-9, 100, 10,
                            100, res)
     assert st == -2  # no workspace: rejected before any device call
+
+
+def test_ctypes_mirrors_match_the_c_header(tmp_path):
+    """The binding's ctypes structures have the size and field offsets the C
+    header gives them (compiled here as C99 by gcc)."""
+    import shutil
+    import subprocess
+
+    import paper_0809_4730_amd as pkg
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    mirrors = {"lbm_grid": pkg._Grid, "lbm_params": pkg._Params, "lbm_record": pkg._Record,
+               "lbm_member": pkg._Member, "lbm_member_result": pkg._MemberResult}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "lbm_capi.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append('  printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for fname, _ in py._fields_:
+            lines.append('  printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, fname, cname, fname))
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    include = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Werror", "-I", include, str(src), "-o", str(exe)],
+                   check=True)
+    got = dict(line.rsplit(" ", 1) for line in
+               subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines())
+    for cname, py in mirrors.items():
+        assert int(got["%s size" % cname]) == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert int(got["%s.%s" % (cname, fname)]) == getattr(py, fname).offset, (cname, fname)
