@@ -4,6 +4,7 @@ must bracket g* within their stated resolution, flag the edge cases, and (for
 the batched search) put every point of a round into one march."""
 import math
 
+import numpy as np
 import pytest
 
 from paper_0809_4730_amd import stability
@@ -62,3 +63,77 @@ def test_batched_search_edges(fake):
     assert env[0]["gamma_min"] == math.inf
     assert env[1]["gamma_min"] == 0.01
     assert fake["batch"] == [2 * 9]  # both decided in the first round
+
+
+# ------------------------------------------------ precision-ladder host logic
+class _FakeSim:
+    """Stands in for Simulation in the host-side ladder logic: a march whose
+    kinetic energy approaches 1 as 1 - exp(-t / tau), checked every 10 steps."""
+
+    def __init__(self, name, log, tau=2000.0, reach=None, nonfinite_at=None):
+        import types
+        self.name, self.log, self.tau, self.reach, self.nonfinite_at = name, log, tau, reach, nonfinite_at
+        self.t = 0
+        self._params = types.SimpleNamespace(check_every=10)
+
+    def step(self, n):
+        self.t += n
+
+    def history(self, k):
+        import math
+        bad = 1.0 if self.nonfinite_at is not None and self.t >= self.nonfinite_at else 0.0
+        return np.array([[self.t, 0.0, 0.0, 1.0 - math.exp(-self.t / self.tau), 0.0, 0.0, bad, 0.0]])
+
+    def convert_from(self, other):
+        self.log.append(("convert", other.name, self.name))
+        self.t = other.t
+
+    def run_to_residual(self, tol, max_steps, poll_every):
+        self.log.append(("residual", self.name, tol))
+        if self.reach is None:
+            self.t += max_steps
+            return -1, 1.0
+        self.t = max(self.t, self.reach)
+        return self.t, tol / 2
+
+    def run_to_energy_change(self, tol, max_steps, window):
+        import paper_0809_4730_amd as pkg
+        self.log.append(("energy", self.name, tol))
+        return pkg.Simulation.run_to_energy_change(self, tol, max_steps, window)
+
+
+def test_energy_change_stops_when_the_window_change_falls_below_tol():
+    import math
+
+    import paper_0809_4730_amd as pkg
+    sim = _FakeSim("a", [])
+    n, change = pkg.Simulation.run_to_energy_change(sim, 1e-4, 10 ** 6, 1000)
+    # change over a window ending at t: (exp(-(t-1000)/tau) - exp(-t/tau)) / (1 - exp(-t/tau))
+    def ch(t):
+        return (math.exp(-(t - 1000) / 2000) - math.exp(-t / 2000)) / (1 - math.exp(-t / 2000))
+    assert n % 1000 == 0 and ch(n) < 1e-4 <= ch(n - 1000)
+    assert abs(change - ch(n)) < 1e-12
+    sim = _FakeSim("b", [])
+    assert pkg.Simulation.run_to_energy_change(sim, 1e-30, 5000, 1000)[0] == -1
+    assert sim.t == 5000                         # max_steps, the first window included
+    with pytest.raises(ValueError):
+        pkg.Simulation.run_to_energy_change(_FakeSim("c", []), 1e-4, 1000, 25)
+    with pytest.raises(pkg.LbmError):
+        pkg.Simulation.run_to_energy_change(_FakeSim("d", [], nonfinite_at=3000), 1e-9, 10 ** 5, 1000)
+
+
+def test_run_ladder_chains_rungs_and_stops_at_a_failed_one():
+    import paper_0809_4730_amd as pkg
+    log = []
+    a, b, c = _FakeSim("a", log), _FakeSim("b", log, reach=30000), _FakeSim("c", log, reach=40000)
+    n, per = pkg.run_ladder([(a, "energy", 1e-4), (b, "residual", 2e-7), (c, "residual", 1e-8)], 10 ** 6)
+    assert n == 40000 and [k for k, _ in per] == [a.t, 30000, 40000]
+    assert [e[0] for e in log] == ["energy", "convert", "residual", "convert", "residual"]
+    assert log[1] == ("convert", "a", "b") and log[3] == ("convert", "b", "c")
+    log.clear()
+    a, b, c = _FakeSim("a", log, tau=200.0), _FakeSim("b", log), _FakeSim("c", log, reach=40000)
+    n, per = pkg.run_ladder([(a, "energy", 1e-4), (b, "residual", 2e-7), (c, "residual", 1e-8)], 5000)
+    assert n == -1 and len(per) == 2             # c never runs
+    assert not any(e[0] == "convert" and e[2] == "c" for e in log)
+    with pytest.raises(ValueError):
+        pkg.run_ladder([(_FakeSim("x", []), "bogus", 1.0)], 10)
