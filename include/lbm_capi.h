@@ -282,7 +282,8 @@ lbm_status lbm_state_bytes(const lbm_ctx* ctx, size_t* bytes);
 lbm_status lbm_get_state(lbm_ctx* ctx, void* dst);
 /* Continue src's march in dst's precision: dst's state becomes src's current
  * state converted to dst's storage type on the device (through FP64; rounding
- * to nearest even when narrowing), its step counter becomes src's, and its
+ * to nearest even when narrowing, whatever dst's rounding option; the option
+ * applies to the steps dst then takes), its step counter becomes src's, and its
  * residual snapshot and history are cleared as by lbm_set_state.  Both contexts
  * need the same grid, boundaries, lattice, rho0, mhd, B0 and mag_pad.  Enqueued
  * on dst's stream after the work already enqueued on src's stream.  Errors:
