@@ -289,7 +289,11 @@ __device__ __forceinline__ void store_stochastic(S* __restrict__ fout, const Gri
       if (a < Q) {
         const uint16_t bits = stochastic16<S>(f[a], j ? (h >> 16) : (h & 0xFFFFu));
         if constexpr (WIDE) {
-          st_pop<NT>(reinterpret_cast<uint16_t*>(fout + static_cast<int64_t>(a) * g.stride + n), bits);
+          S* p = fout + static_cast<int64_t>(a) * g.stride + n;
+          if constexpr (std::is_same_v<S, bf16_t>)
+            st_pop<NT>(&p->bits, bits);
+          else
+            st_pop<NT>(p, __builtin_bit_cast(S, bits));
         } else {
           __builtin_amdgcn_raw_buffer_store_b16(
               bits, raw_rsrc(fout), n * 2u,
