@@ -92,19 +92,29 @@ def _fp32_error(shape, bc, gamma, s, F, d0, ref, start=0, **kw):
 
 
 @pytest.mark.parametrize("fmt", FORMATS)
-@pytest.mark.parametrize("shape,bc,start,moving", [
-    ((33, 6, 10), (PER, WALL, WALL), 0, False),        # ragged
-    ((64, 5, 7), (WALL, WALL, PER), 1000, False),      # row-aligned lattice, later step number
-    ((9, 8, 7), (WALL, WALL, WALL), 5, True),          # every face moving
+@pytest.mark.parametrize("shape,bc,start,moving,uniform", [
+    ((33, 6, 10), (PER, WALL, WALL), 0, False, False),     # ragged
+    ((64, 5, 7), (WALL, WALL, PER), 1000, False, False),   # row-aligned lattice, later step number
+    ((9, 8, 7), (WALL, WALL, WALL), 5, True, False),       # every face moving
+    ((16, 12, 10), (PER, WALL, WALL), 9, False, True),     # residual-check step, uniform force
 ])
-def test_stochastic_step_bits_match_oracle(shape, bc, start, moving, fmt):
-    announce("%s stochastic single step %s start=%d moving=%s" % (fmt, shape, start, moving))
+def test_stochastic_step_bits_match_oracle(shape, bc, start, moving, uniform, fmt):
+    import paper_0809_4730_amd as pkg
+    announce("%s stochastic single step %s start=%d moving=%s uniform=%s"
+             % (fmt, shape, start, moving, uniform))
     seed, gamma = 0xC0FFEE, 0.5
     d0 = _exact(inputs.random_deviations(shape, seed=21, amp=1e-3), fmt)
     F = inputs.random_force(shape, seed=21, amp=1e-4).astype(np.float32).astype(np.float64)
+    if uniform:
+        Fu = (2e-5, -1e-5, 5e-6)
+        F = np.broadcast_to(np.array(Fu).reshape(3, 1, 1, 1), (3,) + F.shape[1:]).copy()
     s = glbe.rates(0.05, gamma)
     wu = 0.01 * np.random.default_rng(21).uniform(-1, 1, (6, 3)) if moving else None
-    sim = _sim(shape, bc, gamma, s, fmt, F, rounding="stochastic", seed=seed, wall_u=wu)
+    if uniform:
+        sim = pkg.Simulation(shape, bc, gamma, s, storage=fmt, force=Fu, rounding="stochastic",
+                             seed=seed)
+    else:
+        sim = _sim(shape, bc, gamma, s, fmt, F, rounding="stochastic", seed=seed, wall_u=wu)
     sim.set_state(to_gpu_f(d0, _torch_dtype(fmt)), step=start)
     sim.step(1)
     p19, _ = perms()
@@ -117,12 +127,14 @@ def test_stochastic_step_bits_match_oracle(shape, bc, start, moving, fmt):
     announce("FP32 step error %.3e, bound used %.3e" % (err32, eps))
     assert err32 <= eps / 2, (err32, eps)
     assert _check_bits(out, ref, r, eps, fmt) > 0.8
+    if start % 10 == 9:      # the step was a residual check: its record is there
+        assert int(sim.history(1)[-1, 0]) == start + 1
 
 
 @pytest.mark.parametrize("fmt", FORMATS)
 @pytest.mark.parametrize("shape,bc,start", [
     ((33, 17), (PER, WALL), 0),
-    ((70, 12), (WALL, WALL), 500),
+    ((70, 12), (WALL, WALL), 509),     # a residual-check step
 ])
 def test_stochastic_d2q9_step_bits_match_oracle(shape, bc, start, fmt):
     """The D2Q9 step with stochastic rounding (directions 2k, 2k+1 for
