@@ -688,38 +688,28 @@ def precision_steady_256():
     print(json.dumps({"probe": "precision256", **out}), flush=True)
 
 
-def ladder_256():
-    """Wall time to a residual of 1e-8 on the 256^3 duct of precision_steady_256
-    for precision ladders, each rung continuing the previous rung's state on
-    the device (lbm_convert_state).  A rung ends on the velocity residual R
-    ("r") or, for 16-bit storage, on the kinetic energy sum |u|^2 ("e"): its
-    relative change over 1000 steps, a global sum in which the rounding noise
-    of the stored values averages out while R measures it (the duct's net flow
-    rate is zero by symmetry, so it cannot serve).  A ladder's contexts are
-    built before its clock starts; u of each final state against the
-    FP64-alone steady state."""
+def run_ladders(probe, shape, ladders, window, workload):
+    """Wall time to a residual of 1e-8 for precision ladders on the duct of
+    make_sim, each rung continuing the previous rung's state on the device
+    (lbm_convert_state).  ladders: (gamma, rungs) with rungs of (storage,
+    criterion, tol).  A rung ends on the velocity residual R ("r") or, for
+    16-bit storage, on the kinetic energy sum |u|^2 ("e"): its relative change
+    over `window` steps, a global sum in which the rounding noise of the
+    stored values averages out while R measures it (the duct's net flow rate
+    is zero by symmetry, so it cannot serve).  A ladder's contexts are built
+    before its clock starts; u of each final state against the first ladder's
+    (FP64 alone at gamma = 1)."""
     import numpy as np
     import torch
-    shape = (256, 256, 256)
-    out = {"workload": "square duct 256^3, gamma = 1, nu = 0.131, C1 force; residual 1e-8",
-           "ladders": []}
-    ladders = [
-        (("f64", "r", 1e-8),),
-        (("f32", "r", 2e-7), ("f64", "r", 1e-8)),
-        (("bf16_sr", "e", 1e-4), ("f32", "r", 2e-7), ("f64", "r", 1e-8)),
-        (("bf16_sr", "e", 1e-5), ("f32", "r", 2e-7), ("f64", "r", 1e-8)),
-        (("bf16", "e", 1e-4), ("f32", "r", 2e-7), ("f64", "r", 1e-8)),
-        (("f16_sr", "e", 1e-5), ("f32", "r", 2e-7), ("f64", "r", 1e-8)),
-        (("f16_sr", "e", 1e-6), ("f32", "r", 2e-7), ("f64", "r", 1e-8)),
-    ]
+    out = {"workload": workload, "ladders": []}
 
     def energy(sim):
         return float(sim.history(1)[-1, 3])
 
     u_ref = None
-    for lad in ladders:
-        name = " -> ".join("%s(%s<%g)" % rung for rung in lad)
-        sims = [make_sim(shape, k.split("_")[0], 1.0,
+    for gamma, lad in ladders:
+        name = "gamma %g: " % gamma + " -> ".join("%s(%s<%g)" % rung for rung in lad)
+        sims = [make_sim(shape, k.split("_")[0], gamma,
                          **({"rounding": "stochastic"} if k.endswith("_sr") else {}))
                 for k, _, _ in lad]
         torch.cuda.synchronize()
@@ -730,39 +720,44 @@ def ladder_256():
                 sim.convert_from(prev)
             t1 = time.perf_counter()
             done = False
-            if crit == "r":
-                while not done and sim.t < 400000:  # in chunks, with a progress line each
-                    n, r = sim.run_to_residual(tol, 20000, poll_every=1000)
-                    done = n > 0
-                    print("%s: %s step %d R %.3e" % (name, k, sim.t, r), file=sys.stderr, flush=True)
-            else:
-                sim.step(1000)
-                e0 = energy(sim)
-                while not done and sim.t < 400000:
-                    sim.step(1000)
-                    e1 = energy(sim)
-                    de = abs(e1 - e0) / max(abs(e1), 1e-300)
-                    done = de < tol
-                    e0 = e1
-                    if sim.t % 10000 == 0 or done:
-                        print("%s: %s step %d dE/E %.3e" % (name, k, sim.t, de), file=sys.stderr,
+            try:
+                if crit == "r":
+                    while not done and sim.t < 400000:  # in chunks, with a progress line each
+                        n, r = sim.run_to_residual(tol, 20000, poll_every=window)
+                        done = n > 0
+                        print("%s: %s step %d R %.3e" % (name, k, sim.t, r), file=sys.stderr,
                               flush=True)
+                else:
+                    sim.step(window)
+                    e0 = energy(sim)
+                    while not done and sim.t < 400000:
+                        sim.step(window)
+                        e1 = energy(sim)
+                        de = abs(e1 - e0) / max(abs(e1), 1e-300)
+                        done = de < tol
+                        e0 = e1
+                        if sim.t % 10000 == 0 or done:
+                            print("%s: %s step %d dE/E %.3e" % (name, k, sim.t, de),
+                                  file=sys.stderr, flush=True)
+            except Exception as ex:  # unstable
+                print("%s: %s failed: %s" % (name, k, ex), file=sys.stderr, flush=True)
             torch.cuda.synchronize()
-            rungs.append({"storage": k, "until": "%s < %g" % ({"r": "R", "e": "dE/E per 1000"}[crit], tol),
+            rungs.append({"storage": k,
+                          "until": "%s < %g" % ({"r": "R", "e": "dE/E per %d" % window}[crit], tol),
                           "until_step": int(sim.t), "wall_s": round(time.perf_counter() - t1, 2)})
             if not done:
                 ok = False
                 break
             prev = sim
         wall = time.perf_counter() - t0
-        e = {"ladder": name, "reached": ok, "steps": int(sims[-1].t) if ok else -1,
-             "wall_s": round(wall, 2), "rungs": rungs}
+        e = {"ladder": name, "gamma": gamma, "reached": ok,
+             "steps": int(sims[-1].t) if ok else -1, "wall_s": round(wall, 2), "rungs": rungs}
         if ok:
             _, u, _ = sims[-1].moments("f64")
             ux = u[0].cpu().numpy()
             if u_ref is None:
                 u_ref = ux
-            e["u_rel_L2_vs_f64_alone"] = float(np.linalg.norm(ux - u_ref) / np.linalg.norm(u_ref))
+            e["u_rel_L2_vs_first"] = float(np.linalg.norm(ux - u_ref) / np.linalg.norm(u_ref))
             del u
         for sim in sims:
             sim.close()
@@ -773,8 +768,40 @@ def ladder_256():
     base = out["ladders"][0]["wall_s"]
     for e in out["ladders"]:
         if e["reached"]:
-            e["speedup_vs_f64_alone"] = round(base / e["wall_s"], 3)
-    print(json.dumps({"probe": "ladder256", **out}), flush=True)
+            e["speedup_vs_first"] = round(base / e["wall_s"], 3)
+    print(json.dumps({"probe": probe, **out}), flush=True)
+
+
+def ladder_256():
+    """The 256^3 duct of precision_steady_256 (gamma = 1): FP64 alone, FP32
+    then FP64, and BF16 / FP16 rungs (nearest and stochastic rounding) before
+    them, the 16-bit rungs ended on the energy change per 1000 steps."""
+    r64, r32 = ("f64", "r", 1e-8), ("f32", "r", 2e-7)
+    run_ladders("ladder256", (256, 256, 256), [
+        (1.0, (r64,)),
+        (1.0, (r32, r64)),
+        (1.0, (("bf16_sr", "e", 1e-4), r32, r64)),
+        (1.0, (("bf16_sr", "e", 1e-5), r32, r64)),
+        (1.0, (("bf16", "e", 1e-4), r32, r64)),
+        (1.0, (("f16_sr", "e", 1e-5), r32, r64)),
+        (1.0, (("f16_sr", "e", 1e-6), r32, r64)),
+    ], 1000, "square duct 256^3, gamma = 1, nu = 0.131, C1 force; residual 1e-8")
+
+
+def ladder_128():
+    """The 128^3 duct (C1 force, nu = 0.131): preconditioning and precision
+    ladders together.  FP64 at gamma = 1 and 0.1, then at gamma = 0.1 FP32
+    then FP64, and an FP16 rung with stochastic rounding before them (energy
+    change per 100 steps: the preconditioned march settles in a few thousand
+    steps)."""
+    r64, r32 = ("f64", "r", 1e-8), ("f32", "r", 2e-7)
+    run_ladders("ladder128", (128, 128, 128), [
+        (1.0, (r64,)),
+        (0.1, (r64,)),
+        (0.1, (r32, r64)),
+        (0.1, (("f16_sr", "e", 1e-5), r32, r64)),
+        (0.1, (("f16_sr", "e", 1e-6), r32, r64)),
+    ], 100, "square duct 128^3, nu = 0.131, C1 force; residual 1e-8")
 
 
 def kernel_probe(name, launches, copy_probe):
@@ -820,6 +847,9 @@ def kernel_probe(name, launches, copy_probe):
     elif name == "ladder256":
         ladder_256()
         return
+    elif name == "ladder128":
+        ladder_128()
+        return
     else:
         raise SystemExit("unknown probe %s" % name)
     sim.close()
@@ -851,7 +881,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--probe", choices=["mhd256", "adjoint128", "d2q9_4096", "precision256",
-                                        "ladder256"],
+                                        "ladder256", "ladder128"],
                     help="only one other measurement: another kernel at HBM scale (for the "
                          "profilers), or the 256^3 precision form at steady state")
     ap.add_argument("--launches", type=int, default=30)
