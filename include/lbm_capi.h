@@ -259,6 +259,21 @@ lbm_status lbm_history(lbm_ctx* ctx, lbm_record* out, int64_t max_records, int64
 lbm_status lbm_run_to_residual(lbm_ctx* ctx, double tol, int64_t max_steps, int64_t poll_every,
                                int64_t* steps_to_tol, double* final_residual);
 
+/* March until the relative change of the kinetic-energy sum |u|^2 (the u2
+ * field of the history records) over `window` steps falls below tol, or
+ * max_steps steps have been taken in this call.  Unlike the residual, this
+ * global sum averages out the rounding noise of 16-bit storage (stochastic
+ * rounding included), so it can end a 16-bit march once the flow itself has
+ * converged.  For a slow mode of relative amplitude a decaying at rate lambda
+ * per step the change per window is about 2 a (1 - exp(-lambda window)).
+ * window must be a positive multiple of check_every; steps are enqueued one
+ * window at a time and the first window only sets the reference.
+ * *step_out = the step of the record at which the change fell below tol, or
+ * -1; *change_out = the last change computed (NaN before two windows).
+ * Returns LBM_EUNSTABLE on non-finite values.  Synchronizes. */
+lbm_status lbm_run_to_energy_change(lbm_ctx* ctx, double tol, int64_t max_steps, int64_t window,
+                                    int64_t* step_out, double* change_out);
+
 /* FP64 mass drift sum(rho - rho0) and flow rate (1/nx) sum j_x of the
  * current state (streamed populations; j includes F/(2 gamma); with mhd the
  * Lorentz force is included).  Synchronizes. */

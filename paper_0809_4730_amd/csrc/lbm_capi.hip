@@ -690,6 +690,40 @@ lbm_status lbm_run_to_residual(lbm_ctx* c, double tol, int64_t max_steps, int64_
   return LBM_OK;
 }
 
+lbm_status lbm_run_to_energy_change(lbm_ctx* c, double tol, int64_t max_steps, int64_t window,
+                                    int64_t* step_out, double* change_out) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  const int64_t ce = c->p.check_every;
+  if (!(tol > 0.0) || max_steps < 0 || !step_out || !change_out)
+    return fail(c, LBM_EINVAL, "bad arguments");
+  if (window < ce || window % ce != 0)
+    return fail(c, LBM_EINVAL, "window must be a positive multiple of check_every");
+  *step_out = -1;
+  *change_out = NAN;
+  std::vector<double> r;
+  double e0 = 0.0;
+  bool have = false;
+  for (int64_t taken = 0; taken < max_steps; taken += window) {
+    lbm_status s = lbm_step(c, window);
+    if (s != LBM_OK) return s;
+    s = read_records(c, c->checks - 1, 1, r);  // the window's last record
+    if (s != LBM_OK) return s;
+    if (r[6] > 0.0 || !std::isfinite(r[3]))
+      return fail(c, LBM_EUNSTABLE, "non-finite values during the march");
+    const double e1 = r[3];
+    if (have) {
+      *change_out = std::fabs(e1 - e0) / std::max(std::fabs(e1), 1e-300);
+      if (*change_out < tol) {
+        *step_out = static_cast<int64_t>(r[0]);
+        return LBM_OK;
+      }
+    }
+    e0 = e1;
+    have = true;
+  }
+  return LBM_OK;
+}
+
 lbm_status lbm_reductions(lbm_ctx* c, double* mass_drift, double* flow_rate) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (!mass_drift || !flow_rate) return fail(c, LBM_EINVAL, "outputs are NULL");

@@ -278,7 +278,7 @@ def test_precision_ladder_reaches_the_fp64_steady_state():
     n_ref, _ = ref.run_to_residual(1e-8, 200000, poll_every=1000)
     assert n_ref > 0
     u64 = ref.moments("f64")[1].cpu().numpy()
-    with pytest.raises(ValueError):
+    with pytest.raises(pkg.LbmError):
         sim("f16").run_to_energy_change(1e-6, 1000, window=15)
     lo, mid, hi = sim("f16", rounding="stochastic", seed=3), sim("f32"), sim("f64")
     n, per_rung = pkg.run_ladder([(lo, "energy", 1e-5), (mid, "residual", 2e-7),
@@ -288,3 +288,26 @@ def test_precision_ladder_reaches_the_fp64_steady_state():
     assert n > 0 and all(k > 0 for k, _ in per_rung)
     assert per_rung[0][0] < per_rung[1][0] < per_rung[2][0] == n <= hi.t  # hi.t: poll boundary
     assert err < 1e-4
+
+
+def test_energy_change_march_matches_its_history():
+    """lbm_run_to_energy_change stops at the first window whose relative change
+    of sum |u|^2, recomputed here from the history records, is below tol, and
+    rejects windows that are not multiples of check_every."""
+    import paper_0809_4730_amd as pkg
+    announce("energy-change march, FP16 stochastic")
+    shape, bc, gamma = (32, 24, 20), (PER, WALL, WALL), 0.5
+    F = inputs.duct_force(shape, 1e-5).astype(np.float32)
+    sim = _sim(shape, bc, gamma, glbe.rates(0.1, gamma), "f16", F, rounding="stochastic", seed=9)
+    step, change = sim.run_to_energy_change(1e-4, 30000, window=200)
+    assert 0 < step < 30000
+    e = {int(r[0]): r[3] for r in sim.history()}
+    ends = list(range(200, step + 1, 200))
+    ch = [abs(e[b] - e[a]) / abs(e[b]) for a, b in zip(ends, ends[1:])]
+    announce("stopped at step %d, change %.3e (%d windows)" % (step, change, len(ends)))
+    assert change == ch[-1] < 1e-4
+    assert all(c >= 1e-4 for c in ch[:-1])
+    with pytest.raises(pkg.LbmError):
+        sim.run_to_energy_change(1e-4, 1000, window=15)
+    n, c = sim.run_to_energy_change(1e-30, 600, window=200)
+    assert n == -1 and c == c                    # never below 1e-30; a change was computed
