@@ -196,3 +196,29 @@ def test_f16_sign_symmetry_and_special_values():
     assert out[5] == np.inf and out[6] == -np.inf                            # beyond 65504
     assert rounding.stochastic_f16(np.float32([65519.0]), [0])[0] == 65504.0
     assert rounding.stochastic_f16(np.float32([65519.0]), [0xFFFF])[0] == np.inf
+
+
+# ------------------------------------------------------ property-based checks
+from hypothesis import given, settings  # noqa: E402
+from hypothesis import strategies as st  # noqa: E402
+
+_finite32 = st.floats(width=32, allow_nan=False, allow_infinity=False)
+
+
+@settings(max_examples=400, deadline=None)
+@given(v=_finite32, r=st.integers(0, 0xFFFF))
+def test_bf16_result_is_a_neighbour_for_any_value(v, r):
+    lo, hi = _bf16_neighbours(np.float32([v]))
+    out = rounding.stochastic_bf16(np.float32([v]), [r])[0]
+    assert out == lo[0] or out == hi[0]
+
+
+@settings(max_examples=400, deadline=None)
+@given(v=st.floats(min_value=-65504.0, max_value=65504.0, width=32), r=st.integers(0, 0xFFFF))
+def test_f16_result_is_a_neighbour_for_any_value(v, r):
+    lo, hi = _f16_neighbours(np.float32([v]))
+    out = rounding.stochastic_f16(np.float32([v]), [r])[0]
+    assert out == lo[0] or out == hi[0]
+    # monotone in r: a larger random value never rounds down where a smaller rounded up
+    up = rounding.stochastic_f16(np.float32([v]), [min(r + 4096, 0xFFFF)])[0]
+    assert abs(up) >= abs(out)
