@@ -261,7 +261,9 @@ class Simulation:
         p = _Params()
         p.lattice = self.lattice
         p.storage = self.storage
-        p.rounding = {"nearest": 0, "stochastic": 1}[rounding]
+        if rounding not in ("nearest", "stochastic"):
+            raise ValueError("rounding must be 'nearest' or 'stochastic'")
+        p.rounding = 1 if rounding == "stochastic" else 0
         p.seed = int(seed) & 0xFFFFFFFF
         p.gamma = gamma
         for k in range(len(s)):
