@@ -267,6 +267,21 @@ def residual(u_now, u_prev):
 
 
 # -------------------------------------------------------- sampled nodes -----
+def upstream(nodes, e, dims, bc):
+    """Upstream node x - e of each node (n, 3) for pull streaming (Sec. 2,
+    eq. streaming): wrapped on periodic axes; ``bounce`` marks the nodes whose
+    link crosses a wall (halfway bounce-back, Sec. 5), whose source entries are
+    then meaningless."""
+    src = nodes - np.asarray(e)[None, :]
+    bounce = np.zeros(len(nodes), dtype=bool)
+    for c in range(3):
+        if bc[c] == WALL:
+            bounce |= (src[:, c] < 0) | (src[:, c] >= dims[c])
+        else:
+            src[:, c] %= dims[c]
+    return src, bounce
+
+
 def step_nodes(post, F, gamma, s, bc, nodes, rho0=1.0):
     """One step evaluated only at the given nodes (for large-grid parity).
 
@@ -279,13 +294,7 @@ def step_nodes(post, F, gamma, s, bc, nodes, rho0=1.0):
     n = len(nodes)
     f = np.empty((Q19, n), dtype=post.dtype)
     for a in range(Q19):
-        src = nodes - E19[a][None, :]
-        bounce = np.zeros(n, dtype=bool)
-        for c in range(3):
-            if bc[c] == WALL:
-                bounce |= (src[:, c] < 0) | (src[:, c] >= dims[c])
-            else:
-                src[:, c] %= dims[c]
+        src, bounce = upstream(nodes, E19[a], dims, bc)
         own = post[OPP19[a], nodes[:, 2], nodes[:, 1], nodes[:, 0]]
         srcc = np.where(bounce[:, None], nodes, src)
         pulled = post[a, srcc[:, 2], srcc[:, 1], srcc[:, 0]]

@@ -1,0 +1,140 @@
+"""Pins of the two oracle routines the full-size GPU parity tests rest on.
+
+* ``glbe.step_nodes`` (one step evaluated at chosen nodes, for lattices too
+  large for the whole-lattice oracle) must equal ``glbe.step`` -- the
+  ``numpy.roll`` streaming of Sec. 2 (eq. streaming) with halfway bounce-back
+  (Sec. 5) -- at every node of lattices that put nodes on every face, edge and
+  corner, for periodic, wall and mixed axes, with a field force and a uniform
+  one.  Planted mistakes in ``step_nodes`` (a wrong periodic wrap, a wrong
+  opposite direction at the wall) must fail the comparison.
+* ``glbe.flow_rate`` (Q = (1/n_x) sum_x j_x of the streamed state, j including
+  F/(2 gamma)) must equal the exact steady body-force Poiseuille flow of
+  Sec. 5 summed over the cross-section.  With the energy-flux and third-order
+  rates tied (fixed Lambda = (3 nu/gamma)(1/s_q - 1/2)) the steady momentum of
+  halfway bounce-back is exactly
+      j_x(z) = F z (H - z) / (2 nu) + F (16 Lambda - 3) / (24 nu),  z = k + 1/2,
+  (pinned node by node in test_oracle_flows.py), and with
+  sum_k (k + 1/2) = H^2/2, sum_k (k + 1/2)^2 = H^3/3 - H/12 the flow rate of
+  an nx x ny x H lattice (walls normal to z) is
+      Q = ny [F (H^3/6 + H/12) / (2 nu) + H F (16 Lambda - 3) / (24 nu)].
+  Planted mistakes (Q of the unstreamed post-collision state; j without the
+  half-force F/(2 gamma), which is 6 nu/(gamma H^2) of Q here) must fail it.
+"""
+import numpy as np
+import pytest
+
+from oracle import glbe
+from oracle.lattice import OPP19
+from paper_0809_4730_amd import inputs
+
+PER, WALL = glbe.PERIODIC, glbe.WALL
+
+GRIDS = [
+    ((8, 6, 10), (PER, WALL, WALL)),
+    ((5, 7, 9), (WALL, WALL, WALL)),
+    ((33, 3, 4), (PER, WALL, PER)),
+    ((1, 1, 12), (PER, PER, WALL)),
+    ((4, 5, 3), (PER, PER, PER)),
+    ((3, 4, 2), (WALL, PER, WALL)),
+]
+
+
+def _all_nodes(shape):
+    nx, ny, nz = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+
+
+def _compare(shape, bc, seed, uniform=False):
+    d0 = inputs.random_deviations(shape, seed=seed, amp=1e-3)
+    F = np.array([2e-5, -1e-5, 3e-5]) if uniform else inputs.random_force(shape, seed, amp=1e-4)
+    s = glbe.rates(0.05, 0.3)
+    Ff = inputs.uniform_force(shape, F) if uniform else F
+    ref, _ = glbe.step(d0, Ff, 0.3, s, bc)
+    nodes = _all_nodes(shape)
+    got = glbe.step_nodes(d0, F, 0.3, s, bc, nodes)
+    want = ref[:, nodes[:, 2], nodes[:, 1], nodes[:, 0]]
+    return float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+
+
+@pytest.mark.parametrize("shape,bc", GRIDS)
+@pytest.mark.parametrize("uniform", [False, True])
+def test_step_nodes_equals_step_at_every_node(shape, bc, uniform):
+    assert _compare(shape, bc, seed=3, uniform=uniform) < 1e-15
+
+
+def test_step_nodes_pin_catches_a_wrong_wrap(monkeypatch):
+    """Planted in the oracle: the periodic wrap clamps instead of wrapping."""
+    def clamped(nodes, e, dims, bc):
+        src = nodes - np.asarray(e)[None, :]
+        bounce = np.zeros(len(nodes), dtype=bool)
+        for c in range(3):
+            if bc[c] == WALL:
+                bounce |= (src[:, c] < 0) | (src[:, c] >= dims[c])
+            else:
+                src[:, c] = np.clip(src[:, c], 0, dims[c] - 1)
+        return src, bounce
+
+    monkeypatch.setattr(glbe, "upstream", clamped)
+    assert _compare((8, 6, 10), (PER, WALL, WALL), seed=3) > 1e-3
+
+
+def test_step_nodes_pin_catches_a_wrong_reflection(monkeypatch):
+    """Planted in the oracle: bounce-back reads the direction itself instead of
+    its opposite (a wrong opposite table)."""
+    monkeypatch.setattr(glbe, "OPP19", np.arange(19))
+    assert _compare((5, 7, 9), (WALL, WALL, WALL), seed=3) > 1e-3
+    monkeypatch.setattr(glbe, "OPP19", OPP19)
+    assert _compare((5, 7, 9), (WALL, WALL, WALL), seed=3) < 1e-15
+
+
+# ------------------------------------------------------------- flow rate ---
+def _steady_poiseuille(shape, nu, gamma, Lam, F):
+    s = glbe.rates(nu, gamma, "lambda", Lam)
+    fl = glbe.Flow(shape, (PER, PER, WALL), np.array([F, 0.0, 0.0]), gamma, s)
+    assert fl.run_to(1e-15, 400000)
+    return fl
+
+
+def _q_exact(shape, nu, Lam, F):
+    nx, ny, H = shape
+    return ny * (F * (H ** 3 / 6 + H / 12) / (2 * nu) + H * F * (16 * Lam - 3) / (24 * nu))
+
+
+CASES = [((2, 3, 8), 0.1, 0.1, 3 / 16), ((3, 2, 8), 0.1, 0.5, 0.5), ((1, 2, 10), 0.1, 1.0, 0.3)]
+
+
+@pytest.mark.parametrize("shape,nu,gamma,Lam", CASES)
+def test_flow_rate_equals_exact_poiseuille_flux(shape, nu, gamma, Lam):
+    F = 1e-6
+    fl = _steady_poiseuille(shape, nu, gamma, Lam, F)
+    q = glbe.flow_rate(fl.post, fl.F, gamma, fl.bc)
+    want = _q_exact(shape, nu, Lam, F)
+    assert abs(q - want) < 1e-11 * want, (q, want)
+    # the half-force term is far above the tolerance in every case
+    half = shape[1] * shape[2] * F / (2 * gamma)
+    assert half > 1e-4 * want
+
+
+def test_flow_rate_pin_catches_the_unstreamed_state(monkeypatch):
+    """Planted in the oracle: Q taken from the post-collision populations
+    without streaming them."""
+    shape, nu, gamma, Lam = CASES[0]
+    F = 1e-6
+    fl = _steady_poiseuille(shape, nu, gamma, Lam, F)
+    monkeypatch.setattr(glbe, "stream", lambda post, bc, **kw: post)
+    q = glbe.flow_rate(fl.post, fl.F, gamma, fl.bc)
+    want = _q_exact(shape, nu, Lam, F)
+    assert abs(q - want) > 1e-3 * want
+
+
+def test_flow_rate_pin_catches_a_dropped_half_force(monkeypatch):
+    """Planted in the oracle: j without F/(2 gamma)."""
+    shape, nu, gamma, Lam = CASES[0]
+    F = 1e-6
+    fl = _steady_poiseuille(shape, nu, gamma, Lam, F)
+    fields = glbe.fields
+    monkeypatch.setattr(glbe, "fields", lambda d, F, g, rho0=1.0: fields(d, 0.0 * F, g, rho0))
+    q = glbe.flow_rate(fl.post, fl.F, gamma, fl.bc)
+    want = _q_exact(shape, nu, Lam, F)
+    assert abs(q - want) > 1e-3 * want
