@@ -84,6 +84,21 @@ typedef struct {
   int32_t bc[3];  /* lbm_bc per axis */
 } lbm_grid;
 
+/* Launch shape of the step kernels.  None of these changes a result: they
+ * decide which workgroup updates which nodes, the cache policy of the
+ * population stores and the width of the address arithmetic, and every
+ * combination gives bitwise the same states and histories (tested).  All zero
+ * (the default) lets the library choose (see lbm_create). */
+typedef struct {
+  int32_t xcd_chunk;  /* 0: library's choice; n > 0: the XCDs take n consecutive
+                         workgroups of the node range in turn (n >= the
+                         workgroups per XCD: one contiguous slab per XCD) */
+  int32_t store;      /* 0: library's choice; 1: cacheable stores; 2: streaming
+                         (non-temporal) stores of the populations */
+  int32_t offsets;    /* 0: 32-bit byte offsets wherever they fit, else 64-bit
+                         element offsets; 1: 64-bit element offsets always */
+} lbm_launch;
+
 typedef struct {
   int32_t storage;        /* lbm_dtype */
   double gamma;           /* preconditioning parameter, 0 < gamma <= 1 (Sec. 3) */
@@ -138,6 +153,7 @@ typedef struct {
   uint32_t seed;          /* stochastic rounding: seed of the counter-based
                              random bits (any value; the same seed gives the
                              same march bit for bit) */
+  lbm_launch launch;      /* launch shape (all zero: the library's choice) */
 } lbm_params;
 
 /* Rounding of stored populations.  LBM_ROUND_NEAREST: nearest, ties to even.
@@ -207,19 +223,28 @@ lbm_status lbm_workspace_bytes(const lbm_grid* grid, const lbm_params* params, s
  * [3][N], FP64 for F64 storage, FP32 otherwise) into the workspace.
  * `workspace` is a device pointer owned by the caller that must outlive the
  * context; `hip_stream` is a hipStream_t (NULL = default stream).
- * Launch shape: when the two population buffers exceed 512 MB (lattices that
- * stream from HBM), lbm_create times a few dozen plain steps on the stream for
- * each of three XCD workgroup mappings, keeps the fastest and restores the
- * rest state; it then synchronizes (a few ms to a few tens of ms).  The
+ * Launch shape (params->launch, all zero: the library's choice): lattices
+ * whose two population buffers fit the 256 MB last-level cache get one
+ * contiguous slab per XCD and cacheable stores; up to 512 MB, slabs and
+ * streaming stores; above that (lattices that stream from HBM) streaming
+ * stores, and lbm_create times a few dozen plain steps on the stream for each
+ * of three XCD workgroup mappings (chunks of 2 and 8 workgroups, slabs), keeps
+ * the fastest and restores the rest state; it then synchronizes (a few ms to
+ * a few tens of ms).  A non-zero launch.xcd_chunk skips the timing.  The
  * mapping decides only which workgroup updates which nodes: results are the
- * same whichever is chosen.  LBM_XCD_CHUNK=<n> in the environment fixes it
- * instead (and LBM_NT_STORE=0/1 the store type).
+ * same whichever is chosen.
  * Errors: LBM_EINVAL (grid, rates, gamma, mhd parameters, unsupported
  * combination), LBM_ENOWS, LBM_EHIP.  On error *out is NULL and the message
  * is available from lbm_last_error(NULL). */
 lbm_status lbm_create(const lbm_grid* grid, const lbm_params* params, const void* force,
                       void* workspace, size_t workspace_bytes, void* hip_stream,
                       lbm_ctx** out);
+
+/* The launch shape the context uses (after lbm_create's choice): the XCD
+ * chunk in workgroups, store 1 (cacheable) or 2 (streaming), offsets 0 (32-bit
+ * byte offsets) or 1 (64-bit element offsets) of the flow step.  Host only.
+ * Errors: LBM_EINVAL for a NULL argument. */
+lbm_status lbm_get_launch(const lbm_ctx* ctx, lbm_launch* out);
 
 /* Release the host-side context (no device memory is freed). */
 void lbm_destroy(lbm_ctx* ctx);
@@ -238,6 +263,12 @@ lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
  * measure the kernel alone, not launch gaps) and the wall time of the whole
  * call in milliseconds. */
 lbm_status lbm_step_timed(lbm_ctx* ctx, int64_t n, double* mean_kernel_us, double* wall_ms);
+
+/* Like lbm_step_timed, but writes every step's kernel duration in
+ * microseconds to the host array kernel_us[n] (step i of the call is the
+ * context's step t0 + i + 1, a residual-check step when that number is a
+ * multiple of check_every).  Synchronizes. */
+lbm_status lbm_step_times(lbm_ctx* ctx, int64_t n, double* kernel_us, double* wall_ms);
 
 /* Latest history record: residual and the step it was taken at.  Synchronizes.
  * Returns LBM_ESTATE if no check has run yet, LBM_EUNSTABLE (after filling
@@ -372,12 +403,15 @@ lbm_status lbm_batch_workspace_bytes(const lbm_grid* grid, int32_t storage, int3
  * every poll_every steps and stops early once all are decided.  members and
  * results are host arrays of `count`; workspace is caller device memory
  * (256-byte aligned, lbm_batch_workspace_bytes).  Blocks the calling thread
- * until the march ends.  Errors: LBM_EINVAL (arguments, with the member
+ * until the march ends.  launch may be NULL (the library's choice); only its
+ * offsets field applies (members are laid out in whole workgroups, one slab
+ * per XCD, cacheable stores).  Errors: LBM_EINVAL (arguments, with the member
  * index), LBM_ENOWS (workspace), LBM_EHIP. */
 lbm_status lbm_batch_run(const lbm_grid* grid, int32_t storage, double rho0, int32_t count,
                          const lbm_member* members, void* workspace, size_t workspace_bytes,
                          void* stream, double tol, int64_t max_steps, int32_t check_every,
-                         int64_t poll_every, lbm_member_result* results);
+                         int64_t poll_every, const lbm_launch* launch,
+                         lbm_member_result* results);
 
 #ifdef __cplusplus
 }

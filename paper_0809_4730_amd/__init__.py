@@ -37,6 +37,28 @@ class _Grid(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32 * 3), ("bc", ctypes.c_int32 * 3)]
 
 
+class _Launch(ctypes.Structure):
+    _fields_ = [("xcd_chunk", ctypes.c_int32), ("store", ctypes.c_int32),
+                ("offsets", ctypes.c_int32)]
+
+
+_STORES = {"auto": 0, "cached": 1, "streaming": 2}
+
+
+def _launch(launch):
+    """lbm_launch from None or dict(xcd_chunk=int, store="auto"|"cached"|"streaming",
+    offsets="auto"|"wide")."""
+    out = _Launch()
+    if launch:
+        unknown = set(launch) - {"xcd_chunk", "store", "offsets"}
+        if unknown:
+            raise ValueError("unknown launch keys %s" % sorted(unknown))
+        out.xcd_chunk = int(launch.get("xcd_chunk", 0))
+        out.store = _STORES[launch.get("store", "auto")]
+        out.offsets = {"auto": 0, "wide": 1}[launch.get("offsets", "auto")]
+    return out
+
+
 class _Params(ctypes.Structure):
     _fields_ = [
         ("storage", ctypes.c_int32),
@@ -59,6 +81,7 @@ class _Params(ctypes.Structure):
         ("lattice", ctypes.c_int32),
         ("rounding", ctypes.c_int32),
         ("seed", ctypes.c_uint32),
+        ("launch", _Launch),
     ]
 
 
@@ -106,13 +129,15 @@ def load_library():
         "lbm_default_rates_d2q9": [c_double, c_double, c_int32, c_double, P(c_double)],
         "lbm_batch_workspace_bytes": [P(_Grid), c_int32, c_int32, P(c_size_t)],
         "lbm_batch_run": [P(_Grid), c_int32, c_double, c_int32, P(_Member), c_void_p, c_size_t,
-                          c_void_p, c_double, c_int64, c_int32, c_int64, P(_MemberResult)],
+                          c_void_p, c_double, c_int64, c_int32, c_int64, P(_Launch),
+                          P(_MemberResult)],
         "lbm_lattice_velocities": [c_int32, P(c_int32)],
         "lbm_workspace_bytes": [P(_Grid), P(_Params), P(c_size_t)],
         "lbm_create": [P(_Grid), P(_Params), c_void_p, c_void_p, c_size_t, c_void_p, P(c_void_p)],
         "lbm_set_force": [c_void_p, c_void_p],
         "lbm_step": [c_void_p, c_int64],
         "lbm_step_timed": [c_void_p, c_int64, P(c_double), P(c_double)],
+        "lbm_step_times": [c_void_p, c_int64, P(c_double), P(c_double)],
         "lbm_residual": [c_void_p, P(c_double), P(c_int64)],
         "lbm_history": [c_void_p, P(_Record), c_int64, P(c_int64)],
         "lbm_run_to_residual": [c_void_p, c_double, c_int64, c_int64, P(c_int64), P(c_double)],
@@ -124,6 +149,7 @@ def load_library():
         "lbm_get_state": [c_void_p, c_void_p],
         "lbm_set_state": [c_void_p, c_void_p, c_int64],
         "lbm_get_step": [c_void_p, P(c_int64)],
+        "lbm_get_launch": [c_void_p, P(_Launch)],
         "lbm_convert_state": [c_void_p, c_void_p],
         "lbm_adjoint_workspace_bytes": [c_void_p, c_int32, c_int64, c_int64, P(c_size_t)],
         "lbm_adjoint_steady": [c_void_p, c_void_p, c_size_t, c_double, c_int64, c_void_p,
@@ -175,11 +201,12 @@ VERDICTS = {0: "undecided", 1: "converged", 2: "unstable"}
 
 
 def batch_run(shape, bc, members, storage="f64", rho0=1.0, tol=1e-9, max_steps=20000,
-              check_every=10, poll_every=1000, device="cuda", stream=None):
+              check_every=10, poll_every=1000, device="cuda", stream=None, launch=None):
     """March independent lattices of one grid together (lbm_batch_run).
 
-    members: sequence of (gamma, rates[19], force[3]).  Returns a list of
-    (verdict, step, last residual), verdict one of VERDICTS' values."""
+    members: sequence of (gamma, rates[19], force[3]).  launch: None or
+    dict(offsets="wide") (see Simulation).  Returns a list of (verdict, step,
+    last residual), verdict one of VERDICTS' values."""
     torch = _torch()
     lib = load_library()
     g = _Grid()
@@ -202,10 +229,15 @@ def batch_run(shape, bc, members, storage="f64", rho0=1.0, tol=1e-9, max_steps=2
     ptr = raw.data_ptr() + (-raw.data_ptr()) % 256
     if stream is None:
         stream = torch.cuda.current_stream(dev)
+    cur = torch.cuda.current_stream(dev)
+    if stream != cur:  # the workspace was allocated on the current stream
+        stream.wait_stream(cur)
+        raw.record_stream(stream)
     res = (_MemberResult * count)()
+    lp = _launch(launch)
     _check(lib.lbm_batch_run(ctypes.byref(g), st, float(rho0), count, arr, ptr, nbytes.value,
                              stream.cuda_stream, float(tol), int(max_steps), int(check_every),
-                             int(poll_every), res))
+                             int(poll_every), ctypes.byref(lp), res))
     del raw
     return [(VERDICTS[r.verdict], r.step, r.residual) for r in res]
 
@@ -239,11 +271,14 @@ class Simulation:
     wall_u: None or (6, 3) face velocities (x-low, x-high, y-low, y-high, z-low, z-high).
     rounding: "nearest" or "stochastic" (bf16/f16 storage, flow step without mhd): how
               stored populations are rounded; seed: the stochastic rounding seed.
+    launch: None (the library's choice) or dict(xcd_chunk=n, store="cached"|"streaming",
+            offsets="wide"): the launch shape (lbm_launch; results do not depend on it).
     """
 
     def __init__(self, shape, bc, gamma, s, storage="f32", force=(0.0, 0.0, 0.0), rho0=1.0,
                  mhd=None, check_every=10, history_len=4096, device="cuda", stream=None,
-                 source="precond", wall_u=None, lattice="d3q19", rounding="nearest", seed=0):
+                 source="precond", wall_u=None, lattice="d3q19", rounding="nearest", seed=0,
+                 launch=None):
         torch = _torch()
         self._lib = load_library()
         self.device = torch.device(device)
@@ -265,6 +300,7 @@ class Simulation:
             raise ValueError("rounding must be 'nearest' or 'stochastic'")
         p.rounding = 1 if rounding == "stochastic" else 0
         p.seed = int(seed) & 0xFFFFFFFF
+        p.launch = _launch(launch)
         p.gamma = gamma
         for k in range(len(s)):
             p.s[k] = float(s[k])
@@ -318,12 +354,38 @@ class Simulation:
         # the library works on `stream`: the caching allocator must not hand this
         # memory out again before that stream's work on it has finished
         raw.record_stream(stream)
+        self._enter()  # the force field was written on the caller's stream
         ctx = ctypes.c_void_p()
         fptr = self._force_tensor.data_ptr() if self._force_tensor is not None else None
         _check(self._lib.lbm_create(ctypes.byref(self._grid), ctypes.byref(p), fptr,
                                     self._ws_ptr, self._ws_bytes, stream.cuda_stream,
                                     ctypes.byref(ctx)))
         self._ctx = ctx
+        self._leave(self._force_tensor)
+
+    # ------------------------------------------------------------- streams
+    # The library enqueues its work on self._stream, while the caller's tensors
+    # are produced and consumed on torch's current stream.  Before a call that
+    # reads or writes caller memory the library stream waits for the current
+    # one (_enter); after it the current stream waits for the library's work
+    # and every caller tensor the library touched is recorded on the library
+    # stream, so that the caching allocator does not reuse it before that work
+    # has run (_leave).  With stream=None both are the same stream and nothing
+    # is added.
+    def _enter(self):
+        torch = _torch()
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self._stream:
+            self._stream.wait_stream(cur)
+
+    def _leave(self, *tensors):
+        torch = _torch()
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self._stream:
+            for t in tensors:
+                if t is not None:
+                    t.record_stream(self._stream)
+            cur.wait_stream(self._stream)
 
     # ----------------------------------------------------------- lifetime
     def close(self):
@@ -354,6 +416,15 @@ class Simulation:
         us, ms = ctypes.c_double(), ctypes.c_double()
         self._c(self._lib.lbm_step_timed(self._ctx, int(n), ctypes.byref(us), ctypes.byref(ms)))
         return us.value, ms.value
+
+    def step_times(self, n):
+        """n steps with HIP events around every step kernel on the library's
+        stream (lbm_step_times): (numpy array of n kernel durations in us,
+        wall time of the call in ms).  Step i of the call is step self.t + i + 1."""
+        buf = (ctypes.c_double * int(n))()
+        ms = ctypes.c_double()
+        self._c(self._lib.lbm_step_times(self._ctx, int(n), buf, ctypes.byref(ms)))
+        return np.frombuffer(buf, dtype=np.float64).copy(), ms.value
 
     def residual(self):
         r, t = ctypes.c_double(), ctypes.c_int64()
@@ -386,6 +457,15 @@ class Simulation:
         return step.value, change.value
 
     @property
+    def launch(self):
+        """The launch shape in use: dict(xcd_chunk=, store="cached"|"streaming",
+        offsets="narrow"|"wide") (lbm_get_launch)."""
+        lp = _Launch()
+        self._c(self._lib.lbm_get_launch(self._ctx, ctypes.byref(lp)))
+        return {"xcd_chunk": lp.xcd_chunk, "store": {1: "cached", 2: "streaming"}[lp.store],
+                "offsets": {0: "narrow", 1: "wide"}[lp.offsets]}
+
+    @property
     def t(self):
         s = ctypes.c_int64()
         self._c(self._lib.lbm_get_step(self._ctx, ctypes.byref(s)))
@@ -405,14 +485,18 @@ class Simulation:
         rho = torch.empty((nz, ny, nx), dtype=td, device=self.device)
         u = torch.empty((3, nz, ny, nx), dtype=td, device=self.device)
         B = torch.empty((3, nz, ny, nx), dtype=td, device=self.device) if self._params.mhd else None
+        self._enter()
         self._c(self._lib.lbm_moments(self._ctx, F64 if dtype == "f64" else F32, rho.data_ptr(),
                                       u.data_ptr(), B.data_ptr() if B is not None else None))
+        self._leave(rho, u, B)
         return rho, u, B
 
     def set_force(self, force):
         force = force.contiguous()
         self._force_tensor = force
+        self._enter()
         self._c(self._lib.lbm_set_force(self._ctx, force.data_ptr()))
+        self._leave(force)
 
     # ------------------------------------------------------------- state
     def get_state(self):
@@ -424,15 +508,18 @@ class Simulation:
         nx, ny, nz = self.shape
         q, (gj, ga) = self.q, self.qg
         f = torch.empty((q, nz, ny, nx), dtype=_state_torch_dtype(self.storage), device=self.device)
+        self._enter()
         if self._params.mhd:
             blob = torch.empty((q + gj * ga) * self.N * f.element_size(),
                                dtype=torch.uint8, device=self.device)
             self._c(self._lib.lbm_get_state(self._ctx, blob.data_ptr()))
+            self._leave(blob)
             nf = q * self.N * f.element_size()
             f = blob[:nf].view(f.dtype).reshape(q, nz, ny, nx)
             g = blob[nf:].view(f.dtype).reshape(gj, ga, nz, ny, nx)
             return f, g
         self._c(self._lib.lbm_get_state(self._ctx, f.data_ptr()))
+        self._leave(f)
         return f
 
     def set_state(self, f, g=None, step=0):
@@ -442,13 +529,16 @@ class Simulation:
                 raise ValueError("mhd state needs g")
             blob = torch.cat([f.contiguous().view(torch.uint8).reshape(-1),
                               g.contiguous().view(torch.uint8).reshape(-1)])
+            self._enter()
             self._c(self._lib.lbm_set_state(self._ctx, blob.data_ptr(), int(step)))
-            torch.cuda.current_stream(self.device).synchronize()
+            self._leave(blob)
             return
         f = f.contiguous()
         if f.dtype != _state_torch_dtype(self.storage):
             raise ValueError("state dtype must be %s" % _state_torch_dtype(self.storage))
+        self._enter()
         self._c(self._lib.lbm_set_state(self._ctx, f.data_ptr(), int(step)))
+        self._leave(f)
 
     def convert_from(self, other):
         """Continue `other`'s march here: its current state converted to this
@@ -473,9 +563,11 @@ class Simulation:
         grad = torch.empty((3, nz, ny, nx), dtype=_compute_torch_dtype(self.storage),
                            device=self.device)
         iters, change = ctypes.c_int64(), ctypes.c_double()
+        self._enter()
         self._c(self._lib.lbm_adjoint_steady(self._ctx, ptr, nbytes, tol, int(max_iter),
                                              grad.data_ptr(), ctypes.byref(iters),
                                              ctypes.byref(change)))
+        self._leave(raw, grad)
         del raw
         return grad, iters.value, change.value
 
@@ -486,8 +578,10 @@ class Simulation:
         nx, ny, nz = self.shape
         grad = torch.empty((3, nz, ny, nx), dtype=_compute_torch_dtype(self.storage),
                            device=self.device)
+        self._enter()
         self._c(self._lib.lbm_adjoint_unrolled(self._ctx, ptr, nbytes, int(n_steps),
                                                int(ckpt_every), grad.data_ptr()))
+        self._leave(raw, grad)
         del raw
         return grad
 

@@ -172,7 +172,7 @@ template <typename S>
 lbm_status batch_run(const lbm_grid* grid, int32_t storage, double rho0, int32_t count,
                      const lbm_member* members, char* ws, const BatchLayout& L, hipStream_t st,
                      double tol, int64_t max_steps, int32_t check_every, int64_t poll_every,
-                     lbm_member_result* results) {
+                     int32_t wide, lbm_member_result* results) {
   using R = typename Storage<S>::R;
   GridArgs g{};
   g.nx = grid->n[0];
@@ -186,6 +186,7 @@ lbm_status batch_run(const lbm_grid* grid, int32_t storage, double rho0, int32_t
   g.blocks_per_xcd = (L.nblocks + kXcd - 1) / kXcd;
   g.xcd_chunk = g.blocks_per_xcd;
   g.div_chunk = make_fastdiv(uint32_t(g.xcd_chunk));
+  g.wide = wide;
   g.stride = L.stride;
   g.div_nx = make_fastdiv(uint32_t(g.nx));
   g.div_nxny = make_fastdiv(uint32_t(g.nx * g.ny));
@@ -237,13 +238,13 @@ lbm_status batch_run(const lbm_grid* grid, int32_t storage, double rho0, int32_t
                           hipMemcpyHostToDevice, st), "status copy");
 
   const dim3 grid_dim(kXcd * g.blocks_per_xcd), check_dim((count + kBlock - 1) / kBlock);
-  const bool wide = wide_offsets(g, sizeof(R));
+  const bool use_wide = wide_offsets(g, sizeof(R));
   int cur = 0;
   int64_t checks = 0;
   for (int64_t step = 1; step <= max_steps; ++step) {
     const bool check = step % check_every == 0;
     LBM_BHIP(with_flag(check, [&](auto CH) {
-               return with_flag(wide, [&](auto W) {
+               return with_flag(use_wide, [&](auto W) {
                  batch_step<S, decltype(CH)::value, decltype(W)::value>
                      <<<grid_dim, kBlock, 0, st>>>(g, ba, dargs, dverdict, f[cur], f[cur ^ 1], usnap,
                                                    partials);
@@ -304,12 +305,15 @@ lbm_status lbm_batch_workspace_bytes(const lbm_grid* grid, int32_t storage, int3
 lbm_status lbm_batch_run(const lbm_grid* grid, int32_t storage, double rho0, int32_t count,
                          const lbm_member* members, void* workspace, size_t workspace_bytes,
                          void* stream, double tol, int64_t max_steps, int32_t check_every,
-                         int64_t poll_every, lbm_member_result* results) {
+                         int64_t poll_every, const lbm_launch* launch,
+                         lbm_member_result* results) {
   BatchLayout L;
   std::string e = make_batch_layout(grid, storage, count, L);
   if (!e.empty()) return fail(nullptr, LBM_EINVAL, e);
   if (!members || !results) return fail(nullptr, LBM_EINVAL, "members and results must be non-null");
   if (!(rho0 > 0.0)) return fail(nullptr, LBM_EINVAL, "rho0 must be positive");
+  const int32_t wide = launch ? launch->offsets : 0;
+  if (wide != 0 && wide != 1) return fail(nullptr, LBM_EINVAL, "launch->offsets must be 0 or 1");
   if (!(tol > 0.0) || max_steps < 0 || check_every < 1 || poll_every < 1)
     return fail(nullptr, LBM_EINVAL, "need tol > 0, max_steps >= 0, check_every >= 1, poll_every >= 1");
   for (int i = 0; i < count; ++i) {
@@ -324,16 +328,16 @@ lbm_status lbm_batch_run(const lbm_grid* grid, int32_t storage, double rho0, int
   switch (storage) {
     case LBM_F64:
       return batch_run<double>(grid, storage, rho0, count, members, ws, L, st, tol, max_steps,
-                               check_every, poll_every, results);
+                               check_every, poll_every, wide, results);
     case LBM_F32:
       return batch_run<float>(grid, storage, rho0, count, members, ws, L, st, tol, max_steps,
-                              check_every, poll_every, results);
+                              check_every, poll_every, wide, results);
     case LBM_BF16:
       return batch_run<bf16_t>(grid, storage, rho0, count, members, ws, L, st, tol, max_steps,
-                               check_every, poll_every, results);
+                               check_every, poll_every, wide, results);
     default:
       return batch_run<_Float16>(grid, storage, rho0, count, members, ws, L, st, tol, max_steps,
-                                 check_every, poll_every, results);
+                                 check_every, poll_every, wide, results);
   }
 }
 

@@ -13,7 +13,8 @@ namespace lbm {
 
 // Build-time knob: LBM_NT_LOAD 1 marks population loads non-temporal (measured
 // slower for FP32, so off).  Streaming stores and the XCD block mapping are
-// chosen at run time (GridArgs::xcd_chunk, the NT template flag of the step).
+// chosen per context at create (GridArgs::xcd_chunk, the NT template flag of
+// the step; lbm_params.launch).
 #ifndef LBM_NT_LOAD
 #define LBM_NT_LOAD 0
 #endif
@@ -59,6 +60,7 @@ struct GridArgs {
   int64_t stride;          // elements between direction planes (N rounded up to 64)
   FastDiv div_nx, div_nxny;
   FastDiv div_chunk;       // division by xcd_chunk
+  int32_t wide;            // 1: 64-bit element offsets even where 32-bit byte offsets fit
   uint32_t step;           // the step number a step launch computes (stochastic rounding)
   uint32_t seed;           // stochastic rounding seed
   // Fluid box [flo, fhi) per axis (x, y, z).  The whole lattice, unless the

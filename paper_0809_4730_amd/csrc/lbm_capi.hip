@@ -14,6 +14,7 @@
 #include "../../include/lbm_capi.h"
 #include "args.hpp"
 #include "ctx.hpp"
+#include "stream.hpp"
 
 using namespace lbm;
 
@@ -66,6 +67,9 @@ std::string validate(const lbm_grid* grid, const lbm_params* p) {
   if (p->rounding == LBM_ROUND_STOCHASTIC &&
       ((p->storage != LBM_BF16 && p->storage != LBM_F16) || p->mhd))
     return "stochastic rounding needs LBM_BF16 or LBM_F16 storage and the flow step alone (mhd = 0)";
+  if (p->launch.xcd_chunk < 0) return "launch.xcd_chunk must be >= 0";
+  if (p->launch.store < 0 || p->launch.store > 2) return "launch.store must be 0, 1 or 2";
+  if (p->launch.offsets != 0 && p->launch.offsets != 1) return "launch.offsets must be 0 or 1";
   if (p->check_every < 1) return "check_every must be >= 1";
   if (p->history_len < 1) return "history_len must be >= 1";
   if (p->source_mode != 0 && p->source_mode != 1) return "source_mode must be 0 or 1";
@@ -211,7 +215,7 @@ hipError_t launch_step_kernel(lbm_ctx* c, bool check) {
 //    lattice shape picked the winner: chunks of 2 beat slabs by 7% for the 256^3
 //    flow step, slabs beat chunks by 22% for the 2048^2 coupled 2D step, and
 //    chunks of 8 lead for 16-bit storage by 2-3%.
-// LBM_XCD_CHUNK and LBM_NT_STORE in the environment override the choice.
+// Non-zero fields of lbm_params.launch override the choice.
 void set_chunk(lbm_ctx* c, int chunk) {
   const int bpx0 = (c->L.nblocks + kXcd - 1) / kXcd;
   chunk = std::max(1, std::min(chunk, bpx0));
@@ -233,14 +237,13 @@ void choose_launch_shape(lbm_ctx* c) {
   int chunk = pop_bytes > 2.0 * kMallBytes ? 2 : bpx0;
   c->tune_chunk = pop_bytes > 2.0 * kMallBytes;
   c->nt_store = pop_bytes > kMallBytes;
-  if (const char* e = std::getenv("LBM_XCD_CHUNK")) {
-    const int v = std::atoi(e);
-    if (v > 0) {
-      chunk = v;
-      c->tune_chunk = false;
-    }
+  const lbm_launch& l = c->p.launch;
+  if (l.xcd_chunk > 0) {
+    chunk = l.xcd_chunk;
+    c->tune_chunk = false;
   }
-  if (const char* e = std::getenv("LBM_NT_STORE")) c->nt_store = std::atoi(e) != 0;
+  if (l.store != 0) c->nt_store = l.store == 2;
+  c->ga.wide = l.offsets;
   set_chunk(c, chunk);
 }
 
@@ -563,6 +566,14 @@ lbm_status lbm_create(const lbm_grid* grid, const lbm_params* params, const void
   return LBM_OK;
 }
 
+lbm_status lbm_get_launch(const lbm_ctx* c, lbm_launch* out) {
+  if (!c || !out) return fail(nullptr, LBM_EINVAL, "NULL argument");
+  out->xcd_chunk = c->ga.xcd_chunk;
+  out->store = c->nt_store ? 2 : 1;
+  out->offsets = wide_offsets(c->ga, c->celem()) ? 1 : 0;
+  return LBM_OK;
+}
+
 void lbm_destroy(lbm_ctx* ctx) {
   if (!ctx) return;
   for (hipEvent_t ev : ctx->events) (void)hipEventDestroy(ev);
@@ -586,9 +597,14 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
   return LBM_OK;
 }
 
-lbm_status lbm_step_timed(lbm_ctx* c, int64_t n, double* mean_kernel_us, double* wall_ms) {
-  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
-  if (n < 1 || !mean_kernel_us || !wall_ms) return fail(c, LBM_EINVAL, "need n >= 1 and outputs");
+}  // extern "C"
+
+namespace {
+
+// n steps with a pair of HIP events around every step kernel on the context's
+// stream; each[i] (if non-null) receives step i's kernel duration in us.
+lbm_status step_with_events(lbm_ctx* c, int64_t n, double* each, double* mean_kernel_us,
+                            double* wall_ms) {
   constexpr int kPool = 512;
   while (c->events.size() < 2 * kPool + 2) {
     hipEvent_t ev;
@@ -610,6 +626,7 @@ lbm_status lbm_step_timed(lbm_ctx* c, int64_t n, double* mean_kernel_us, double*
       float ms = 0.0f;
       LBM_HIP(c, hipEventElapsedTime(&ms, c->events[2 * i], c->events[2 * i + 1]), "hipEventElapsedTime");
       total_ms += ms;
+      if (each) each[done + i] = 1000.0 * double(ms);
     }
     done += chunk;
   }
@@ -620,6 +637,23 @@ lbm_status lbm_step_timed(lbm_ctx* c, int64_t n, double* mean_kernel_us, double*
   *mean_kernel_us = 1000.0 * total_ms / double(n);
   *wall_ms = wms;
   return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_step_timed(lbm_ctx* c, int64_t n, double* mean_kernel_us, double* wall_ms) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (n < 1 || !mean_kernel_us || !wall_ms) return fail(c, LBM_EINVAL, "need n >= 1 and outputs");
+  return step_with_events(c, n, nullptr, mean_kernel_us, wall_ms);
+}
+
+lbm_status lbm_step_times(lbm_ctx* c, int64_t n, double* kernel_us, double* wall_ms) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (n < 1 || !kernel_us || !wall_ms) return fail(c, LBM_EINVAL, "need n >= 1 and outputs");
+  double mean = 0.0;
+  return step_with_events(c, n, kernel_us, &mean, wall_ms);
 }
 
 lbm_status lbm_residual(lbm_ctx* c, double* residual, int64_t* at_step) {

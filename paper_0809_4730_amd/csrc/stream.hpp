@@ -5,7 +5,6 @@
 
 #include <hip/hip_runtime.h>
 
-#include <cstdlib>
 #include <type_traits>
 
 #include "common.hpp"
@@ -27,12 +26,10 @@ inline hipError_t with_flag(bool b, F&& f) {
 // every array through 32-bit byte offsets from one base: loads within 2 planes
 // of a pair's base, stores anywhere in an array of up to 21 planes (the
 // magnetic populations), so it needs 21 * stride * elem_bytes < 2^32 (FP32:
-// lattices up to ~51 M nodes).  LBM_WIDE_OFFSETS=1 in the environment forces
-// the 64-bit form (read at each launch, so that tests can run both forms on
-// small lattices).
+// lattices up to ~51 M nodes).  g.wide (lbm_launch.offsets = 1) forces the
+// 64-bit form, so that tests can run both forms on small lattices.
 inline bool wide_offsets(const GridArgs& g, size_t elem_bytes) {
-  const char* e = std::getenv("LBM_WIDE_OFFSETS");
-  if (e && e[0] == '1') return true;
+  if (g.wide) return true;
   return 21.0 * static_cast<double>(g.stride) * static_cast<double>(elem_bytes) >= 4294967296.0;
 }
 

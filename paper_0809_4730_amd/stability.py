@@ -83,13 +83,13 @@ def envelope(nus, u_maxes, **kw):
 
 # ------------------------------------------------------------ batched ----
 def march_batch(points, H=64, width=4, max_steps=20000, tol=1e-9, storage="f64",
-                rates_mode="paper"):
+                rates_mode="paper", launch=None):
     """Verdicts for many (nu, u_max, gamma) points in one batched march (one
     launch per step for all points).  Returns [(STABLE | UNSTABLE, step)]."""
     members = [(g, default_rates(nu, g, rates_mode), (poiseuille_force(nu, um, H), 0.0, 0.0))
                for nu, um, g in points]
     out = batch_run((width, width, H), ("periodic", "periodic", "wall"), members,
-                    storage=storage, tol=tol, max_steps=max_steps)
+                    storage=storage, tol=tol, max_steps=max_steps, launch=launch)
     return [(UNSTABLE if v == "unstable" else STABLE, step) for v, step, _ in out]
 
 

@@ -87,6 +87,8 @@ def _grid_params(pkg, **kw):
     p.gamma_m, p.chi, p.eta, p.mu = 0.1, 0.01, 0.025, 1.0
     p.rounding = kw.get("rounding", 0)
     p.lattice = kw.get("lattice", 0)
+    for k in ("xcd_chunk", "store", "offsets"):
+        setattr(p.launch, k, kw.get(k, 0))
     return g, p
 
 
@@ -96,6 +98,8 @@ def _grid_params(pkg, **kw):
     # stochastic rounding: 16-bit storage and the flow step without mhd only
     dict(rounding=2, storage=2), dict(rounding=1, storage=1), dict(rounding=1, storage=0),
     dict(rounding=1, storage=2, mhd=1), dict(rounding=1, storage=0, lattice=1, n=(8, 8, 1)),
+    # launch shape fields
+    dict(xcd_chunk=-1), dict(store=3), dict(store=-1), dict(offsets=2),
 ])
 def test_validation_rejects(lib, bad):
     import paper_0809_4730_amd as pkg
@@ -263,11 +267,16 @@ def test_batch_workspace_and_validation(lib):
     members[1].s[9] = 2.5
     res = (pkg._MemberResult * 2)()
     st = lib.lbm_batch_run(ctypes.byref(g), pkg.F64, 1.0, 2, members, None, 0, None, 1e-9, 100, 10,
-                           100, res)
+                           100, None, res)
     assert st == -1 and b"member 1" in lib.lbm_last_error(None)
     members[1].s[9] = 1.0
+    bad = pkg._Launch()
+    bad.offsets = 2
     st = lib.lbm_batch_run(ctypes.byref(g), pkg.F64, 1.0, 2, members, None, 0, None, 1e-9, 100, 10,
-                           100, res)
+                           100, ctypes.byref(bad), res)
+    assert st == -1 and b"offsets" in lib.lbm_last_error(None)
+    st = lib.lbm_batch_run(ctypes.byref(g), pkg.F64, 1.0, 2, members, None, 0, None, 1e-9, 100, 10,
+                           100, None, res)
     assert st == -2  # no workspace: rejected before any device call
 
 
@@ -282,6 +291,7 @@ def test_ctypes_mirrors_match_the_c_header(tmp_path):
     if gcc is None:
         pytest.skip("gcc not available")
     mirrors = {"lbm_grid": pkg._Grid, "lbm_params": pkg._Params, "lbm_record": pkg._Record,
+               "lbm_launch": pkg._Launch,
                "lbm_member": pkg._Member, "lbm_member_result": pkg._MemberResult}
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "lbm_capi.h"', "int main(void) {"]
     for cname, py in mirrors.items():

@@ -1,0 +1,272 @@
+"""The kernels the benchmark times, in the launch shapes it times them, against
+the FP64 oracle; the store and launch forms bit for bit; the failure path of
+the instability detector; the residual history within a bound computed from
+the measured velocity differences; the binding on a side stream.
+
+Parity bars (FP32 storage, FP32 collision): one step from a seeded random
+state within 2e-6 relative of the oracle's FP64 step from the same
+FP32-representable state (one FP32 rounding of each stored value is 6e-8 of
+it; the collision's FP32 arithmetic adds a few more).  Over n steps the
+rounding errors of the steps add at most: in the orthonormal moment basis the
+collision scales every non-conserved moment by 1 - s_k with |1 - s_k| < 1
+and streaming with bounce-back permutes values, so the linear part of the
+step does not amplify an L2 error, and the nonlinear terms are O(Ma) smaller.
+The bound after n steps is therefore n * 2e-6 * |d0| / |d_n|.
+"""
+import numpy as np
+import pytest
+
+from oracle import adjoint as oadj
+from oracle import glbe
+from paper_0809_4730_amd import inputs
+from tests.gpu_util import announce, rel
+
+pytestmark = pytest.mark.gpu
+PER, WALL = "periodic", "wall"
+STEP_TOL = 2e-6
+
+
+def _duct_sim(shape, storage, gamma, **kw):
+    import torch
+
+    import paper_0809_4730_amd as pkg
+    cfg = inputs.DUCT64
+    dt = torch.float64 if storage == "f64" else torch.float32
+    F = torch.tensor(inputs.duct_force(shape, cfg["F0"]), dtype=dt, device="cuda")
+    return pkg.Simulation(shape, cfg["bc"], gamma, pkg.default_rates(cfg["nu"], gamma),
+                          storage=storage, force=F, **kw)
+
+
+def test_duct64_fp32_bench_kernel_one_and_fifty_steps():
+    """The 64^3 FP32 duct at gamma = 0.1 in its default launch shape (row-aligned
+    waves, one slab per XCD, cacheable stores, 32-bit offsets): 1 and 50 steps
+    from a seeded random state against the oracle, node by node."""
+    import torch
+    announce("64^3 fp32 duct, bench launch shape, 1 + 49 steps")
+    shape, gamma = (64, 64, 64), 0.1
+    cfg = inputs.DUCT64
+    sim = _duct_sim(shape, "f32", gamma)
+    lp = sim.launch
+    assert lp["store"] == "cached" and lp["offsets"] == "narrow"
+    assert lp["xcd_chunk"] >= (64 ** 3 // 256 + 7) // 8  # one slab per XCD
+    d0 = inputs.random_deviations(shape, seed=11, amp=1e-3, dtype=np.float32)
+    F = inputs.duct_force(shape, cfg["F0"]).astype(np.float32).astype(np.float64)
+    s = glbe.rates(cfg["nu"], gamma)
+    sim.set_state(torch.from_numpy(d0).cuda())
+    sim.step(1)
+    out1 = sim.get_state().double().cpu().numpy()
+    ref = d0.astype(np.float64)
+    ref, _ = glbe.step(ref, F, gamma, s, cfg["bc"])
+    assert rel(out1, ref) < STEP_TOL
+    assert rel(out1 - d0, ref - d0) < 10 * STEP_TOL
+    sim.step(49)
+    for _ in range(49):
+        ref, _ = glbe.step(ref, F, gamma, s, cfg["bc"])
+    out50 = sim.get_state().double().cpu().numpy()
+    bound = 50 * STEP_TOL * np.linalg.norm(d0) / np.linalg.norm(ref)
+    err = rel(out50, ref)
+    announce("50 steps: rel %.3e, bound %.3e" % (err, bound))
+    assert err < bound
+
+
+@pytest.mark.parametrize("check", [False, True])
+def test_duct256_fp32_bench_kernel_after_a_march(check):
+    """The 256^3 FP32 duct at gamma = 1 in the benchmark's launch shape
+    (create-time XCD chunk, streaming stores): from a seeded random state, 18
+    (or 19) steps on the GPU, then one more plain (or residual-check) step
+    compared with the oracle at 4000 sampled nodes, corners included."""
+    import torch
+    cfg = inputs.DUCT256
+    shape = cfg["shape"]
+    announce("256^3 fp32, %s step after a march" % ("check" if check else "plain"))
+    sim = _duct_sim(shape, "f32", cfg["gamma"])
+    assert sim.launch["store"] == "streaming"
+    d0 = inputs.random_deviations(shape, seed=12, amp=1e-3, dtype=np.float32)
+    sim.set_state(torch.from_numpy(d0).cuda())
+    del d0
+    n0 = 19 if check else 18  # the step after n0 is a check step when n0 + 1 = 20
+    sim.step(n0)
+    mid = sim.get_state().cpu().numpy().astype(np.float64)
+    sim.step(1)
+    out = sim.get_state()
+    nodes = inputs.random_nodes(shape, 4000, seed=12)
+    F = inputs.duct_force(shape, cfg["F0"]).astype(np.float32).astype(np.float64)
+    s = glbe.rates(cfg["nu"], cfg["gamma"])
+    ref = glbe.step_nodes(mid, F, cfg["gamma"], s, cfg["bc"], nodes)
+    idx = torch.tensor(nodes, device="cuda")
+    got = out[:, idx[:, 2], idx[:, 1], idx[:, 0]].double().cpu().numpy()
+    assert rel(got, ref) < STEP_TOL
+    if check:
+        h = sim.history(4)
+        assert int(h[-1, 0]) == 20 and np.isfinite(h[-1, 1]) and h[-1, 6] == 0
+    sim.close()
+    del sim, out, mid
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64", "bf16"])
+def test_store_forms_bitwise_on_a_row_aligned_lattice(storage):
+    """Cacheable and streaming stores on a row-aligned lattice (64 x 6 x 10: the
+    row-aligned variant the benchmark's lattices take), residual checks on."""
+    import torch
+
+    import paper_0809_4730_amd as pkg
+    announce("store forms, row-aligned 64x6x10 %s" % storage)
+    shape, bc = (64, 6, 10), (PER, WALL, WALL)
+    dt = torch.float64 if storage == "f64" else torch.float32
+    F = torch.tensor(inputs.random_force(shape, seed=13, amp=1e-5), dtype=dt, device="cuda")
+    out = []
+    for store in ("cached", "streaming"):
+        sim = pkg.Simulation(shape, bc, 0.2, glbe.rates(0.05, 0.2), storage=storage, force=F,
+                             launch=dict(store=store))
+        assert sim.launch["store"] == store
+        sim.step(33)
+        out.append((sim.get_state(), sim.history(8)))
+    assert torch.equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+
+
+def test_nonfinite_force_is_detected_and_a_checkpoint_recovers():
+    """Failure path of the instability detector: a non-finite force value at
+    one node (ordinary IEEE arithmetic; nothing traps) reaches the populations
+    and the next residual check counts it, so lbm_residual and
+    lbm_run_to_residual report LBM_EUNSTABLE; the state stays readable.  A
+    checkpoint taken before, loaded into a context with a larger gamma, marches
+    to the tolerance."""
+    import torch
+
+    import paper_0809_4730_amd as pkg
+    announce("non-finite force -> EUNSTABLE, recovery from a checkpoint")
+    shape, bc = (16, 12, 10), (PER, WALL, WALL)
+    F = torch.tensor(inputs.duct_force(shape, 1e-5), dtype=torch.float32, device="cuda")
+    sim = pkg.Simulation(shape, bc, 0.1, glbe.rates(0.131, 0.1), storage="f32", force=F)
+    sim.step(20)
+    r, t = sim.residual()
+    assert t == 20 and np.isfinite(r)
+    ckpt = sim.get_state().clone()
+    bad = F.clone()
+    bad[0, 5, 6, 7] = float("nan")
+    sim.set_force(bad)
+    sim.step(10)
+    with pytest.raises(pkg.LbmError) as e:
+        sim.residual()
+    assert e.value.status == -4
+    h = sim.history(1)
+    assert int(h[0, 0]) == 30 and h[0, 6] >= 1
+    state = sim.get_state()
+    assert not bool(torch.isfinite(state).all())
+    with pytest.raises(pkg.LbmError) as e:
+        sim.run_to_residual(1e-8, 100, poll_every=10)
+    assert e.value.status == -4
+    sim.close()
+    rec = pkg.Simulation(shape, bc, 0.5, glbe.rates(0.131, 0.5), storage="f32", force=F)
+    rec.set_state(ckpt, step=20)
+    steps, r = rec.run_to_residual(1e-6, 40000, poll_every=500)
+    assert steps > 20 and r < 1e-6
+    assert bool(torch.isfinite(rec.get_state()).all())
+
+
+@pytest.mark.parametrize("gamma", [0.5, 1.0])
+def test_steady_adjoint_from_the_oracle_state_to_1e12(gamma):
+    """FP64 steady adjoint on the 2 x 4 x 4 duct from exactly the oracle's
+    converged state (loaded with set_state), iterated to a relative change of
+    1e-15: equal to the oracle's dense bordered transposed solve at that same
+    state to 1e-12."""
+    import torch
+
+    import paper_0809_4730_amd as pkg
+    announce("steady adjoint from the oracle state, gamma=%g" % gamma)
+    shape, bc = (2, 4, 4), (PER, WALL, WALL)
+    s = glbe.rates(0.131, gamma)
+    nx, ny, nz = shape
+    F = np.zeros((3, nz, ny, nx))
+    y = np.arange(ny) + 0.5
+    F[0] = 1e-5 * (1.0 + 0.3 * np.sin(2 * np.pi * y / ny))[None, :, None]
+    fl = glbe.Flow(shape, bc, F, gamma, s)
+    assert fl.run_to(1e-14, 100000)
+    ref, _ = oadj.steady_gradient_dense(fl.post, fl.F, gamma, s, bc)
+    sim = pkg.Simulation(shape, bc, gamma, s, storage="f64",
+                         force=torch.tensor(F, dtype=torch.float64, device="cuda"))
+    sim.set_state(torch.tensor(fl.post, dtype=torch.float64, device="cuda"), step=fl.t)
+    grad, iters, change = sim.adjoint_steady(tol=1e-15, max_iter=400000)
+    assert change < 1e-15, change
+    err = rel(grad.cpu().numpy(), ref)
+    announce("iters %d change %.2e rel %.3e" % (iters, change, err))
+    assert err < 1e-12
+
+
+def test_residual_history_within_the_measured_velocity_bound():
+    """FP64 residual history of the 1 x 16 x 16 duct against the oracle's.  With
+    a = u_t - u_(t-10) and b = u_t, R = |a|/|b|; the GPU's velocities differ from
+    the oracle's by du_t (measured here with lbm_moments), so
+        |R_gpu - R| <= (|du_t - du_(t-10)| + R |du_t|) / |b_gpu|
+    plus the rounding of the two FP64 reductions (a few units of 1e-16 of R)."""
+    import torch
+
+    import paper_0809_4730_amd as pkg
+    announce("residual history bound")
+    shape, bc, gamma = (1, 16, 16), (PER, WALL, WALL), 0.25
+    s = glbe.rates(0.131, gamma)
+    F = inputs.duct_force(shape)
+    Ft = torch.tensor(F, dtype=torch.float64, device="cuda")
+    sim = pkg.Simulation(shape, bc, gamma, s, storage="f64", force=Ft)
+    probe = pkg.Simulation(shape, bc, gamma, s, storage="f64", force=Ft)
+    post = np.zeros((19,) + F.shape[1:])
+    u_or, u_gpu = {0: np.zeros((3,) + F.shape[1:])}, {0: np.zeros((3,) + F.shape[1:])}
+    for t in range(1, 201):
+        if t % 10 == 0:
+            _, u, _ = probe.moments("f64")  # the velocity of collision t
+            u_gpu[t] = u.cpu().numpy()
+        probe.step(1)
+        post, u = glbe.step(post, F, gamma, s, bc)
+        if t % 10 == 0:
+            u_or[t] = u
+    sim.step(200)
+    hist = {int(h[0]): h[1] for h in sim.history()}
+    assert sorted(hist) == list(range(10, 201, 10))
+    worst = 0.0
+    for t in range(20, 201, 10):
+        a = u_or[t] - u_or[t - 10]
+        R = np.linalg.norm(a) / np.linalg.norm(u_or[t])
+        d_t, d_p = u_gpu[t] - u_or[t], u_gpu[t - 10] - u_or[t - 10]
+        b = np.linalg.norm(u_gpu[t])
+        bound = (np.linalg.norm(d_t - d_p) + R * np.linalg.norm(d_t)) / b + 8e-16 * R + 1e-300
+        worst = max(worst, abs(hist[t] - R) / bound)
+        assert abs(hist[t] - R) <= bound, (t, hist[t], R, bound)
+    announce("largest |dR| / bound: %.3f" % worst)
+
+
+def test_binding_on_a_side_stream_matches_the_current_stream():
+    """A Simulation on its own stream, fed and read from torch's current
+    stream (set_state from a tensor computed just before, set_force, moments,
+    get_state, adjoint): every result equals the same calls on the current
+    stream."""
+    import torch
+
+    import paper_0809_4730_amd as pkg
+    announce("side stream")
+    shape, bc = (16, 10, 12), (PER, WALL, WALL)
+    s = glbe.rates(0.1, 0.4)
+
+    def run(stream):
+        F = torch.tensor(inputs.duct_force(shape, 1e-5), dtype=torch.float64, device="cuda")
+        sim = pkg.Simulation(shape, bc, 0.4, s, storage="f64", force=F * 1.0, stream=stream)
+        d0 = torch.tensor(inputs.random_deviations(shape, seed=14, amp=1e-4), device="cuda")
+        sim.set_state(d0 * 0.5 + d0 * 0.5)  # a fresh temporary from the current stream
+        sim.step(25)
+        sim.set_force(F * 2.0)
+        sim.step(25)
+        rho, u, _ = sim.moments("f64")
+        st = sim.get_state()
+        grad = sim.adjoint_unrolled(20, 5)
+        return [rho.clone(), u.clone(), st.clone(), grad.clone(), sim.history(8)]
+
+    ref = run(None)
+    side = torch.cuda.Stream()
+    got = run(side)
+    torch.cuda.synchronize()
+    for a, b in zip(ref, got):
+        if torch.is_tensor(a):
+            assert torch.equal(a, b)
+        else:
+            assert np.array_equal(a, b)

@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 BOUNDS_STEADY = {"f32": 1e-5, "bf16": 0.05, "f16": 0.01}
 
 
-def _sim(shape, storage, gamma):
+def _sim(shape, storage, gamma, **kw):
     import torch
 
     import paper_0809_4730_amd as pkg
@@ -25,7 +25,7 @@ def _sim(shape, storage, gamma):
     dt = torch.float64 if storage == "f64" else torch.float32
     F = torch.tensor(inputs.duct_force(shape, cfg["F0"]), dtype=dt, device="cuda")
     return pkg.Simulation(shape, cfg["bc"], gamma, pkg.default_rates(cfg["nu"], gamma),
-                          storage=storage, force=F)
+                          storage=storage, force=F, **kw)
 
 
 def test_precision_forms_at_steady_state_duct64():
@@ -68,7 +68,7 @@ def test_precision_forms_transient_duct256():
         assert err < {"f32": 1e-5, "bf16": 0.05, "f16": 0.02}[st]
 
 
-def test_create_time_launch_shape_choice_keeps_the_rest_state(monkeypatch):
+def test_create_time_launch_shape_choice_keeps_the_rest_state():
     """256^3 FP32 (2.5 GB of populations): lbm_create times three workgroup
     mappings on the plain step, then restores the rest state.  The state is
     zero and the step counter 0 after create, and the first 12 steps (one
@@ -76,7 +76,6 @@ def test_create_time_launch_shape_choice_keeps_the_rest_state(monkeypatch):
     import torch
     announce("create-time launch shape, 256^3")
     shape, gamma = (256, 256, 256), 1.0
-    monkeypatch.delenv("LBM_XCD_CHUNK", raising=False)
     tuned = _sim(shape, "f32", gamma)
     assert tuned.t == 0
     assert int(torch.count_nonzero(tuned.get_state())) == 0
@@ -85,9 +84,7 @@ def test_create_time_launch_shape_choice_keeps_the_rest_state(monkeypatch):
     h = tuned.history(4)
     del tuned
     torch.cuda.empty_cache()
-    monkeypatch.setenv("LBM_XCD_CHUNK", "2")
-    fixed = _sim(shape, "f32", gamma)
-    monkeypatch.delenv("LBM_XCD_CHUNK", raising=False)
+    fixed = _sim(shape, "f32", gamma, launch=dict(xcd_chunk=2))
     fixed.step(12)
     assert torch.equal(a, fixed.get_state())
     assert np.array_equal(h, fixed.history(4))

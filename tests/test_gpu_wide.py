@@ -3,11 +3,12 @@ identical results.
 
 The kernels address populations from a launch-uniform base pointer with either
 32-bit byte offsets (when every offset of the launch fits) or 64-bit ones
-(larger lattices).  LBM_WIDE_OFFSETS=1 forces the 64-bit form, so that it runs
-on the small lattices of these tests; only addressing differs, so states,
-residual histories and verdicts must agree bit for bit.  Likewise the
+(larger lattices).  launch=dict(offsets="wide") forces the 64-bit form, so
+that it runs on the small lattices of these tests; only addressing differs, so
+states, residual histories and verdicts must agree bit for bit.  Likewise the
 streaming-store variants, chosen for lattices larger than the last-level cache
-and forced here with LBM_NT_STORE=1, differ only in cache policy."""
+and forced here with launch=dict(store="streaming"), differ only in cache
+policy."""
 import numpy as np
 import pytest
 
@@ -19,16 +20,11 @@ pytestmark = pytest.mark.gpu
 PER, WALL = "periodic", "wall"
 
 
-def _both(monkeypatch, run, var="LBM_WIDE_OFFSETS", off=None):
-    if off is None:
-        monkeypatch.delenv(var, raising=False)
-    else:
-        monkeypatch.setenv(var, off)
-    narrow = run()
-    monkeypatch.setenv(var, "1")
-    wide = run()
-    monkeypatch.delenv(var, raising=False)
-    return narrow, wide
+def _both(run, key="offsets"):
+    """run(launch) with the default form and with the other one forced."""
+    if key == "offsets":
+        return run(None), run(dict(offsets="wide"))
+    return run(dict(store="cached")), run(dict(store="streaming"))
 
 
 def _same(a, b):
@@ -44,7 +40,7 @@ def _same(a, b):
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "bf16", "bf16_sr", "f16_sr"])
-def test_d3q19_step_forms_agree(monkeypatch, storage):
+def test_d3q19_step_forms_agree(storage):
     import torch
     import paper_0809_4730_amd as pkg
     announce("wide vs narrow d3q19 %s" % storage)
@@ -54,87 +50,90 @@ def test_d3q19_step_forms_agree(monkeypatch, storage):
 
     kw = dict(rounding="stochastic", seed=77) if storage.endswith("_sr") else {}
 
-    def run():
+    def run(launch):
         sim = pkg.Simulation(shape, bc, 0.2, glbe.rates(0.05, 0.2), storage=storage.split("_")[0],
-                             force=F, **kw)
+                             force=F, launch=launch, **kw)
         sim.step(47)
         return sim.get_state(), sim.history(16)
-    _same(*_both(monkeypatch, run))
+    _same(*_both(run))
 
 
-def test_moving_wall_and_extended_mhd_forms_agree(monkeypatch):
+def test_moving_wall_and_extended_mhd_forms_agree():
     import paper_0809_4730_amd as pkg
     announce("wide vs narrow moving wall + extended mhd")
     wall_u = np.zeros((6, 3))
     wall_u[5] = (0.02, 0.0, 0.0)
 
-    def run_flow():
+    def run_flow(launch):
         sim = pkg.Simulation((9, 8, 7), (WALL, WALL, WALL), 0.3, glbe.rates(0.05, 0.3),
-                             storage="f32", wall_u=wall_u)
+                             storage="f32", wall_u=wall_u, launch=launch)
         sim.step(31)
         return sim.get_state(), sim.history(8)
 
-    def run_mhd():
+    def run_mhd(launch):
         sim = pkg.Simulation((12, 10, 9), (WALL, WALL, WALL), 0.3, glbe.rates(0.05, 0.3),
-                             storage="f64", wall_u=wall_u,
+                             storage="f64", wall_u=wall_u, launch=launch,
                              mhd=dict(gamma_m=0.3, chi=0.05, eta=0.03, B0=(0.0, 0.02, 0.0),
                                       pad=(2, 2, 1)))
         sim.step(31)
         return sim.get_state(), sim.history(8)
-    _same(*_both(monkeypatch, run_flow))
-    _same(*_both(monkeypatch, run_mhd))
+    _same(*_both(run_flow))
+    _same(*_both(run_mhd))
 
 
-def test_d2q9_forms_agree(monkeypatch):
+def test_d2q9_forms_agree():
     import torch
     import paper_0809_4730_amd as pkg
     announce("wide vs narrow d2q9 / d2q5")
 
     def run_flow(storage="f32", **kw):
-        def run():
+        def run(launch):
             sim = pkg.Simulation((35, 12, 1), (PER, WALL, PER), 0.2, d2q9.rates(0.05, 0.2),
-                                 storage=storage, force=(1e-5, 0.0), lattice="d2q9", **kw)
+                                 storage=storage, force=(1e-5, 0.0), lattice="d2q9",
+                                 launch=launch, **kw)
             sim.step(41)
             return sim.get_state(), sim.history(8)
         return run
 
-    def run_mhd():
+    def run_mhd(launch):
         sim = pkg.Simulation((10, 12, 1), (PER, WALL, PER), 0.2, d2q9.rates(0.05, 0.2),
-                             storage="f64", force=(1e-5, 0.0), lattice="d2q9",
+                             storage="f64", force=(1e-5, 0.0), lattice="d2q9", launch=launch,
                              mhd=dict(gamma_m=0.3, chi=0.05, eta=0.02, B0=(0.0, 0.03)))
         sim.step(41)
         return sim.get_state(), sim.history(8)
-    _same(*_both(monkeypatch, run_flow()))
-    _same(*_both(monkeypatch, run_flow("bf16", rounding="stochastic", seed=80)))
-    _same(*_both(monkeypatch, run_mhd))
+    _same(*_both(run_flow()))
+    _same(*_both(run_flow("bf16", rounding="stochastic", seed=80)))
+    _same(*_both(run_mhd))
 
 
-def test_batch_forms_agree(monkeypatch):
+def test_batch_forms_agree():
     from paper_0809_4730_amd import stability
     announce("wide vs narrow batch")
     pts = [(0.02, 0.05, 1.0), (0.02, 0.05, 1e-3), (0.1, 0.02, 0.3)]
-    narrow, wide = _both(monkeypatch, lambda: stability.march_batch(pts, max_steps=2000))
+    narrow, wide = _both(lambda launch: stability.march_batch(pts, max_steps=2000, launch=launch))
     assert narrow == wide
 
 
-def test_adjoint_forms_agree(monkeypatch):
+def test_adjoint_forms_agree():
     import torch
     import paper_0809_4730_amd as pkg
     announce("wide vs narrow adjoint")
     shape, bc = (6, 8, 8), (PER, WALL, WALL)
     F = torch.tensor(inputs.duct_force(shape, 1e-5), dtype=torch.float64, device="cuda")
 
-    def run():
-        sim = pkg.Simulation(shape, bc, 0.5, glbe.rates(0.131, 0.5), storage="f64", force=F)
+    def run(launch):
+        sim = pkg.Simulation(shape, bc, 0.5, glbe.rates(0.131, 0.5), storage="f64", force=F,
+                             launch=launch)
         sim.run_to_residual(1e-10, 20000, poll_every=500)
         g_s, it, ch = sim.adjoint_steady(tol=1e-8, max_iter=20000)
-        sim2 = pkg.Simulation(shape, bc, 0.5, glbe.rates(0.131, 0.5), storage="f64", force=F)
+        sim2 = pkg.Simulation(shape, bc, 0.5, glbe.rates(0.131, 0.5), storage="f64", force=F,
+                              launch=launch)
         g_u = sim2.adjoint_unrolled(60, 7)
         return g_s, it, g_u
-    _same(*_both(monkeypatch, run))
+    _same(*_both(run))
 
 
-def test_streaming_store_forms_agree(monkeypatch):
+def test_streaming_store_forms_agree():
     """Cacheable and streaming stores: flow (3D, 2D) and coupled (3D, 2D) steps,
     with the residual check on."""
     import torch
@@ -145,35 +144,35 @@ def test_streaming_store_forms_agree(monkeypatch):
                      device="cuda")
 
     def run3(storage, mhd):
-        def run():
+        def run(launch):
             kw = dict(mhd=dict(gamma_m=0.3, chi=0.05, eta=0.03, B0=(0.01, 0.02, -0.01))) if mhd else {}
             if storage.endswith("_sr"):
                 kw = dict(rounding="stochastic", seed=78)
             sim = pkg.Simulation(shape, bc, 0.3, glbe.rates(0.05, 0.3), storage=storage.split("_")[0],
-                                 force=F if storage != "f64" else F.double(), **kw)
+                                 force=F if storage != "f64" else F.double(), launch=launch, **kw)
             sim.step(33)
             return sim.get_state(), sim.history(8)
         return run
 
     def run2(mhd, storage="f32"):
-        def run():
+        def run(launch):
             kw = dict(mhd=dict(gamma_m=0.3, chi=0.05, eta=0.02, B0=(0.0, 0.03))) if mhd else {}
             if storage == "bf16_sr":
                 kw = dict(rounding="stochastic", seed=81)
             sim = pkg.Simulation((20, 12, 1), (PER, WALL, PER), 0.2, d2q9.rates(0.05, 0.2),
                                  storage=storage.split("_")[0], force=(1e-5, 0.0), lattice="d2q9",
-                                 **kw)
+                                 launch=launch, **kw)
             sim.step(41)
             return sim.get_state(), sim.history(8)
         return run
     for run in (run3("f32", False), run3("bf16", False), run3("bf16_sr", False),
                 run3("f16_sr", False), run3("f32", True),
                 run3("f64", True), run2(False), run2(True), run2(False, "bf16_sr")):
-        _same(*_both(monkeypatch, run, "LBM_NT_STORE", "0"))
+        _same(*_both(run, "store"))
 
 
-@pytest.mark.parametrize("chunk", ["1", "3", "100000"])
-def test_results_do_not_depend_on_the_xcd_chunk(monkeypatch, chunk):
+@pytest.mark.parametrize("chunk", [1, 3, 100000])
+def test_results_do_not_depend_on_the_xcd_chunk(chunk):
     """The chunk (timed at create for large lattices) only decides which
     workgroup updates which nodes: states and residual histories are bitwise
     those of the default launch shape."""
@@ -184,31 +183,27 @@ def test_results_do_not_depend_on_the_xcd_chunk(monkeypatch, chunk):
     F = torch.tensor(inputs.random_force(shape, seed=7, amp=1e-5), dtype=torch.float32,
                      device="cuda")
 
-    def run():
+    def run(launch):
         out = []
         for mhd in (False, True):
             kw = dict(mhd=dict(gamma_m=0.3, chi=0.05, eta=0.03, B0=(0.01, 0.02, -0.01))) if mhd else {}
-            sim = pkg.Simulation(shape, bc, 0.3, glbe.rates(0.05, 0.3), storage="f32", force=F, **kw)
+            sim = pkg.Simulation(shape, bc, 0.3, glbe.rates(0.05, 0.3), storage="f32", force=F,
+                                 launch=launch, **kw)
             sim.step(27)
             out += [sim.get_state(), sim.history(8)]
         sim = pkg.Simulation(shape, bc, 0.3, glbe.rates(0.05, 0.3), storage="bf16", force=F,
-                             rounding="stochastic", seed=79)
+                             rounding="stochastic", seed=79, launch=launch)
         sim.step(27)
         out += [sim.get_state(), sim.history(8)]
         sim = pkg.Simulation((20, 12, 1), (PER, WALL, PER), 0.2, d2q9.rates(0.05, 0.2),
-                             storage="f32", force=(1e-5, 0.0), lattice="d2q9")
+                             storage="f32", force=(1e-5, 0.0), lattice="d2q9", launch=launch)
         sim.step(27)
         return out + [sim.get_state(), sim.history(8)]
-    monkeypatch.delenv("LBM_XCD_CHUNK", raising=False)
-    ref = run()
-    monkeypatch.setenv("LBM_XCD_CHUNK", chunk)
-    got = run()
-    monkeypatch.delenv("LBM_XCD_CHUNK", raising=False)
-    _same(ref, got)
+    _same(run(None), run(dict(xcd_chunk=chunk)))
 
 
 @pytest.mark.parametrize("case", ["mhd3d_128", "mhd2d_2048"])
-def test_create_time_shape_choice_coupled_lattices(monkeypatch, case):
+def test_create_time_shape_choice_coupled_lattices(case):
     """Coupled lattices above 512 MB of populations (128^3 flow + induction,
     2048^2 D2Q9 + D2Q5): after the create-time timing of workgroup mappings
     the state is the rest state and the first 12 steps match a context with a
@@ -217,15 +212,14 @@ def test_create_time_shape_choice_coupled_lattices(monkeypatch, case):
     import paper_0809_4730_amd as pkg
     announce("create-time shape choice %s" % case)
 
-    def make():
+    def make(launch=None):
         if case == "mhd3d_128":
             return pkg.Simulation((128, 128, 128), (PER, WALL, PER), 0.1, glbe.rates(0.1, 0.1),
-                                  storage="f32", force=(1e-5, 0.0, 0.0),
+                                  storage="f32", force=(1e-5, 0.0, 0.0), launch=launch,
                                   mhd=dict(gamma_m=0.1, chi=0.01, eta=0.025, B0=(0.0, 0.01, 0.0)))
         return pkg.Simulation((2048, 2048, 1), (PER, WALL, PER), 0.1, d2q9.rates(0.1, 0.1),
-                              storage="f32", force=(1e-6, 0.0), lattice="d2q9",
+                              storage="f32", force=(1e-6, 0.0), lattice="d2q9", launch=launch,
                               mhd=dict(gamma_m=0.1, chi=0.01, eta=0.025, B0=(0.0, 0.01)))
-    monkeypatch.delenv("LBM_XCD_CHUNK", raising=False)
     tuned = make()
     f, g = tuned.get_state()
     assert int(torch.count_nonzero(f)) == 0 and int(torch.count_nonzero(g)) == 0
@@ -235,9 +229,7 @@ def test_create_time_shape_choice_coupled_lattices(monkeypatch, case):
     tuned.close()
     del tuned, f, g
     torch.cuda.empty_cache()
-    monkeypatch.setenv("LBM_XCD_CHUNK", "2")
-    fixed = make()
-    monkeypatch.delenv("LBM_XCD_CHUNK", raising=False)
+    fixed = make(dict(xcd_chunk=2))
     fixed.step(12)
     _same(a, fixed.get_state())
     _same(h, fixed.history(4))
