@@ -1,21 +1,26 @@
 """Benchmark of the fused preconditioned GLBE step on one MI355X.
 
-Workload of the headline line: the square-duct flow on 64x64x64 (walls in y
-and z, periodic x) with F_x = F0 sin(2 pi y/Ly)(1 + cos(2 pi z/Lz)/2),
-F0 = 1e-5, nu = 0.131 (Ma ~ 0.01), FP32 deviation storage, gamma = 0.1.  One
-step = one fused stream-collide pass over all nodes (with the FP64 residual,
-mass and flow-rate reductions every 10th step).  Inputs are resident in HBM
-before the timed region.
+Headline workload: the square-duct flow on 256x256x256 (walls in y and z,
+periodic x) with F_x = F0 sin(2 pi y/Ly)(1 + cos(2 pi z/Lz)/2), F0 = 1e-5,
+nu = 0.131, gamma = 1 (at this size the force drives Ma ~ 0.16, too fast for
+gamma < 1), FP32 deviation storage with FP32 collision, FP64 residual, mass
+and flow rate every 10th step.  One step = one fused stream-collide launch
+over all 16.8 M nodes.  Inputs (state, force field) are resident in HBM
+before the timed region; nothing crosses PCIe inside it.
 
-Prints ONE JSON line with MLUPS, the roofline of the step kernel (HIP events
-around every launch on the library's stream), and the FP64 CPU oracle timed on
-the host.  --extras adds time-to-residual (gamma sweep vs plain gamma = 1),
-256^3 throughput per storage type, the coupled MHD step and the adjoint.
+Prints ONE JSON line: MLUPS of the timed steps; the roofline of the plain
+step kernel from HIP events around every launch on the library's stream
+(algorithmic bytes per launch / mean launch duration); the same for BF16,
+FP16 and FP64 storage at 256^3 and for the cache-resident 64^3 duct; wall
+time to a residual of 1e-8 for gamma < 1 against plain FP64 gamma = 1
+(64^3 duct gamma sweep, 128^3 preconditioning-and-precision ladders); and
+the FP64 CPU oracle timed on the host.  --extras adds the longer studies.
 """
 import argparse
 import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -23,9 +28,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MALL_BYTES = 256 * 1024 * 1024   # last-level cache (Infinity Cache) of the MI355X
 KERNEL_SOURCES = ["paper_0809_4730_amd/csrc/kernels.hip", "paper_0809_4730_amd/csrc/collide.hpp",
                   "paper_0809_4730_amd/csrc/common.hpp", "paper_0809_4730_amd/csrc/stream.hpp",
                   "paper_0809_4730_amd/csrc/lattice.hpp", "paper_0809_4730_amd/csrc/lbm_capi.hip"]
+STORAGE_BYTES = {"f32": 4, "f64": 8, "bf16": 2, "f16": 2}
+METRIC = "MLUPS, % HBM roofline; wall time to 1e-8 residual, gamma<1 vs plain gamma=1"
 
 
 def kernel_hash():
@@ -38,14 +46,16 @@ def kernel_hash():
 
 def algorithmic_bytes_per_node(storage_bytes, force_field, check_every, mhd=False):
     """Bytes one node update must move: each population read once and written
-    once, the force field read once, and the FP64 velocity snapshot read and
-    written on every residual step."""
+    once, the force field read once (compute type), and on a residual step the
+    velocity snapshot (compute type) read and written, amortised over
+    check_every steps."""
+    cb = 8 if storage_bytes == 8 else 4
     b = 2 * 19 * storage_bytes
     if mhd:
-        b += 2 * 21 * 4 if storage_bytes == 4 else 2 * 21 * storage_bytes
+        b += 2 * 21 * cb
     if force_field:
-        b += 3 * (8 if storage_bytes == 8 else 4)
-    b += 2 * 3 * 8 / check_every
+        b += 3 * cb
+    b += 2 * 3 * cb / check_every
     return b
 
 
@@ -65,24 +75,34 @@ def make_sim(shape, storage, gamma, nu=0.131, F0=1e-5, bc=("periodic", "wall", "
                           **kw)
 
 
-def timed_region(sim, steps, warmup):
-    """(MLUPS, wall seconds) of `steps` full steps (residual checks included),
-    bracketed by device synchronisations."""
+def timed_steps(sim, steps, warmup):
+    """W untimed steps, then exactly `steps` steps bracketed by device
+    synchronisations, each step kernel between two HIP events on the library's
+    stream.  Returns (MLUPS, wall s, plain-kernel us list, check-kernel us list)."""
     import torch
-    sim.step(warmup)
+    if warmup > 0:  # the first timed call also creates the library's event pool
+        sim.step_times(1)
+        sim.step(warmup - 1)
     torch.cuda.synchronize()
+    t_first = sim.t + 1
     t0 = time.perf_counter()
-    sim.step(steps)
+    times, _ = sim.step_times(steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return sim.N * steps / wall / 1e6, wall
+    ce = sim._params.check_every
+    plain = [float(us) for i, us in enumerate(times) if (t_first + i) % ce != 0]
+    check = [float(us) for i, us in enumerate(times) if (t_first + i) % ce == 0]
+    return sim.N * steps / wall / 1e6, wall, plain, check
 
 
 def kernel_time_us(sim, launches, warmup=20):
-    """Mean duration of the step kernel: HIP events on the library's stream
-    around `launches` back-to-back launches (sim built with NO_CHECK, so every
-    launch is the same kernel)."""
+    """Mean duration of the step kernel from two HIP events around `launches`
+    back-to-back launches on the library's stream (sim built with NO_CHECK on
+    torch's current stream, so every launch is the same kernel).  For kernels
+    of a few microseconds this is the rate a march achieves; events around
+    each launch would add their own gaps."""
     import torch
+    assert sim._stream == torch.cuda.current_stream(sim.device)
     sim.step(warmup)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -90,37 +110,6 @@ def kernel_time_us(sim, launches, warmup=20):
     e1.record()
     e1.synchronize()
     return 1000.0 * e0.elapsed_time(e1) / launches
-
-
-def measure(shape, storage, gamma, steps, warmup, **kw):
-    """(MLUPS with checks, wall s, mean plain-kernel us)."""
-    import torch
-    sim = make_sim(shape, storage, gamma, **kw)
-    mlups, wall = timed_region(sim, steps, warmup)
-    del sim
-    sim = make_sim(shape, storage, gamma, check_every=NO_CHECK, **kw)
-    us = kernel_time_us(sim, steps)
-    del sim
-    torch.cuda.empty_cache()
-    return mlups, wall, us
-
-
-def copy_bandwidth_GBs(nbytes=4 << 30, reps=10):
-    """Device-to-device copy (read + write) bandwidth of a plain copy kernel."""
-    import torch
-    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    e1.record()
-    e1.synchronize()
-    gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del src, dst
-    torch.cuda.empty_cache()
-    return gbs
 
 
 def traffic_from_profiles(kernel_tag, khash):
@@ -137,29 +126,133 @@ def traffic_from_profiles(kernel_tag, khash):
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(budget_s=12.0):
-    """The FP64 oracle (numpy) on the same duct workload, bounded sample."""
+def population_bytes(shape, storage):
+    n = shape[0] * shape[1] * shape[2]
+    return 2 * 19 * STORAGE_BYTES[storage] * n
+
+
+def step_roofline(shape, storage, gamma, steps, warmup, **kw):
+    """One storage type on one duct: MLUPS over the timed steps (checks
+    included) and the roofline of the plain step kernel."""
+    import torch
+    sim = make_sim(shape, storage, gamma, **kw)
+    launch = sim.launch
+    mlups, wall, plain, check = timed_steps(sim, steps, warmup)
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    N = shape[0] * shape[1] * shape[2]
+    us = statistics.fmean(plain)
+    bpn = algorithmic_bytes_per_node(STORAGE_BYTES[storage], True, NO_CHECK)
+    achieved = bpn * N / (us * 1e-6) / 1e9
+    resident = population_bytes(shape, storage) <= MALL_BYTES
+    return {"storage": storage, "MLUPS": round(mlups, 2), "wall_s": wall,
+            "ms_per_step": 1000.0 * wall / steps, "kernel_us": round(us, 3),
+            "kernel_us_min": round(min(plain), 3), "kernel_us_max": round(max(plain), 3),
+            "check_kernel_us": round(statistics.fmean(check), 3) if check else None,
+            "launches_timed": len(plain), "alg_bytes_per_node": bpn,
+            "alg_bytes_per_launch": int(round(bpn * N)),
+            "achieved_GBs": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "bound": "mall" if resident else "hbm", "launch": launch}
+
+
+def timed_region(sim, steps, warmup):
+    """(MLUPS, wall seconds) of `steps` full steps (residual checks included),
+    bracketed by device synchronisations."""
+    import torch
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return sim.N * steps / wall / 1e6, wall
+
+
+def small_duct_line(steps, warmup):
+    """The 64^3 duct (FP32, gamma = 0.1): 43 MB of populations, resident in the
+    256 MB last-level cache, so a cache rate ("bound": "mall").  MLUPS of
+    `steps` steps with checks; the plain kernel from events around
+    back-to-back launches (kernel_time_us)."""
+    import torch
+    shape = (64, 64, 64)
+    sim = make_sim(shape, "f32", 0.1)
+    launch = sim.launch
+    mlups, wall = timed_region(sim, steps, warmup)
+    sim.close()
+    sim = make_sim(shape, "f32", 0.1, check_every=NO_CHECK)
+    us = kernel_time_us(sim, steps)
+    sim.close()
+    torch.cuda.empty_cache()
+    bpn = algorithmic_bytes_per_node(4, True, NO_CHECK)
+    gbs = bpn * 64 ** 3 / (us * 1e-6) / 1e9
+    return {"storage": "f32", "gamma": 0.1, "MLUPS": round(mlups, 2),
+            "ms_per_step": round(1000.0 * wall / steps, 5), "kernel_us": round(us, 3),
+            "alg_bytes_per_node": bpn, "achieved_GBs": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "bound": "mall", "launch": launch}
+
+
+def copy_bandwidth_GBs(nbytes=4 << 30, reps=10):
+    """Device-to-device copy (read + write) bandwidth of torch's copy kernel."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def _oracle_step_times(shape, bc, F, gamma, s, warm=3, timed=20):
+    """Per-step wall times of the FP64 oracle march (3 warm-up steps first)."""
+    from oracle import glbe
+    fl = glbe.Flow(shape, bc, F, gamma, s)
+    fl.step(warm)
+    out = []
+    for _ in range(timed):
+        t0 = time.perf_counter()
+        fl.step(1)
+        out.append(time.perf_counter() - t0)
+    return out
+
+
+def cpu_baseline():
+    """The FP64 oracle (numpy, dense 19x19 transform through BLAS) on the host:
+    median of 20 steps after 3 warm-ups on a z-slab of the 256^3 duct
+    (256 x 256 x 16 nodes, the force of the slab's planes; the full lattice is
+    processed slab by slab, each slab with the same per-node work), and on the
+    whole 64^3 duct.  value = slab MLUPS."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
     from oracle import glbe
     from paper_0809_4730_amd import inputs
-    shape = (64, 64, 64)
-    F = inputs.duct_force(shape)
-    fl = glbe.Flow(shape, ("periodic", "wall", "wall"), F, 0.1, glbe.rates(0.131, 0.1))
-    fl.step(1)
-    n, t0 = 0, time.perf_counter()
-    while True:
-        fl.step(1)
-        n += 1
-        el = time.perf_counter() - t0
-        if el > budget_s or n >= 200:
-            break
+    bc = ("periodic", "wall", "wall")
+    s = glbe.rates(0.131, 1.0)
+    slab = (256, 256, 16)
+    F256 = inputs.duct_force((256, 256, 256))[:, :slab[2]]
+    t_slab = statistics.median(_oracle_step_times(slab, bc, np.ascontiguousarray(F256), 1.0, s))
+    s01 = glbe.rates(0.131, 0.1)
+    t64 = statistics.median(_oracle_step_times((64, 64, 64), bc, inputs.duct_force((64, 64, 64)),
+                                               0.1, s01))
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    return {"value": round(64 ** 3 * n / el / 1e6, 4), "unit": "MLUPS", "cores": int(threads),
+    n_slab = slab[0] * slab[1] * slab[2]
+    return {"value": round(n_slab / t_slab / 1e6, 4), "unit": "MLUPS", "cores": int(threads),
             "kind": "oracle",
-            "sample": "%d steps of the 64^3 FP64 duct (numpy oracle, dense 19x19 transform); "
-                      "cores = BLAS threads" % n}
+            "sample": "FP64 numpy oracle (dense 19x19 transform via BLAS), median of 20 steps "
+                      "after 3 warm-ups on a 256x256x16 z-slab of the 256^3 duct at gamma=1 "
+                      "(%.3f s per slab step; the 256^3 step is 16 such slabs, %.1f s)"
+                      % (t_slab, 16 * t_slab),
+            "os_cpu_count": os.cpu_count(), "blas_threads": int(threads),
+            "duct64_MLUPS": round(64 ** 3 / t64 / 1e6, 4),
+            "duct64_sample": "whole 64^3 duct, gamma=0.1, median of 20 steps after 3 warm-ups"}
 
 
 def cpu_time_to_residual_poiseuille():
@@ -266,18 +359,11 @@ def extras(args):
             if e["steps"] > 0:
                 e["speedup_vs_f64_gamma1_wall"] = round(ref["wall_s"] / e["wall_s"], 3)
                 e["step_ratio_vs_f64_gamma1"] = round(ref["steps"] / e["steps"], 3)
-    # 256^3 throughput per storage type (kernel roofline at HBM scale)
-    big = []
-    for st, nb in (("f32", 4), ("bf16", 2), ("bf16_sr", 2), ("f16", 2), ("f16_sr", 2), ("f64", 8)):
-        kw = {"rounding": "stochastic"} if st.endswith("_sr") else {}
-        mlups, wall, us = measure((256, 256, 256), st.split("_")[0], 1.0, args.big_steps, 10, **kw)
-        bpn = algorithmic_bytes_per_node(nb, True, NO_CHECK)
-        gbs = bpn * 256 ** 3 / (us * 1e-6) / 1e9
-        big.append({"storage": st, "MLUPS_with_checks": round(mlups, 1), "kernel_us": round(us, 2),
-                    "kernel_MLUPS": round(256 ** 3 / us, 1),
-                    "alg_bytes_per_node": bpn, "achieved_GBs": round(gbs, 1),
-                    "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)})
-    out["duct256_throughput"] = big
+    # 256^3 throughput with stochastic 16-bit stores (the nearest-even forms
+    # are in the headline line)
+    out["duct256_stochastic_rounding"] = [
+        step_roofline((256, 256, 256), st, 1.0, args.big_steps, 10, rounding="stochastic")
+        for st in ("bf16", "f16")]
     out["hbm_copy_GBs"] = round(copy_bandwidth_GBs(), 1)
     # coupled MHD step on the Hartmann workload
     cfg = inputs.HARTMANN
@@ -688,7 +774,7 @@ def precision_steady_256():
     print(json.dumps({"probe": "precision256", **out}), flush=True)
 
 
-def run_ladders(probe, shape, ladders, window, workload):
+def ladder_results(shape, ladders, window, workload):
     """Wall time to a residual of 1e-8 for precision ladders on the duct of
     make_sim, each rung continuing the previous rung's state on the device
     (lbm_convert_state).  ladders: (gamma, rungs) with rungs of (storage,
@@ -769,7 +855,56 @@ def run_ladders(probe, shape, ladders, window, workload):
     for e in out["ladders"]:
         if e["reached"]:
             e["speedup_vs_first"] = round(base / e["wall_s"], 3)
-    print(json.dumps({"probe": probe, **out}), flush=True)
+    return out
+
+
+def run_ladders(probe, shape, ladders, window, workload):
+    print(json.dumps({"probe": probe, **ladder_results(shape, ladders, window, workload)}),
+          flush=True)
+
+
+LADDERS_128 = [
+    (1.0, (("f64", "r", 1e-8),)),
+    (0.1, (("f64", "r", 1e-8),)),
+    (0.1, (("f32", "r", 2e-7), ("f64", "r", 1e-8))),
+    (0.1, (("f16_sr", "e", 1e-5), ("f32", "r", 2e-7), ("f64", "r", 1e-8))),
+]
+
+
+def time_to_residual_block():
+    """The metric's second half: wall time (and steps) to a residual of 1e-8
+    with gamma < 1 and with reduced-precision storage, against plain FP64 at
+    gamma = 1 on the same lattice.  The 256^3 headline lattice runs at
+    gamma = 1 only (Ma ~ 0.16 there), so the gamma comparison is made on the
+    64^3 duct (same force, Ma ~ 0.01) and on the 128^3 duct."""
+    shape = (64, 64, 64)
+    rows = [time_to_residual(shape, "f64", g, 1e-8, 400000) for g in (1.0, 0.5, 0.1, 0.05)]
+    ref = rows[0]
+    for e in rows[1:]:
+        if ref["steps"] > 0 and e["steps"] > 0:
+            e["step_ratio_vs_f64_gamma1"] = round(ref["steps"] / e["steps"], 2)
+            e["wall_ratio_vs_f64_gamma1"] = round(ref["wall_s"] / e["wall_s"], 2)
+    mixed = [time_to_residual_mixed(shape, g, 1e-8, 1e-6, 400000) for g in (1.0, 0.1)]
+    for e in mixed:
+        if ref["steps"] > 0 and e["steps"] > 0:
+            e["wall_ratio_vs_f64_gamma1"] = round(ref["wall_s"] / e["wall_s"], 2)
+    lad = ladder_results((128, 128, 128), LADDERS_128, 100,
+                         "square duct 128^3, nu = 0.131, same force; residual 1e-8; 16-bit "
+                         "rungs end on the relative change of sum |u|^2 per 100 steps")
+    for e in lad["ladders"]:
+        e["wall_ratio_vs_f64_gamma1"] = e.pop("speedup_vs_first", None)
+        e["u_rel_L2_vs_f64_gamma1"] = e.pop("u_rel_L2_vs_first", None)
+    return {"tol": 1e-8,
+            "reference": "plain FP64 storage at gamma = 1 on the same GPU, lattice and force",
+            "duct64_f64_gamma_sweep": rows,
+            "duct64_f32_then_f64": mixed,
+            "duct128_ladders": lad,
+            "paper_context": "Sec. 5: for its low-viscosity plane Poiseuille case the paper "
+                             "reports more than two orders of magnitude fewer steps at "
+                             "gamma = 0.001 than at gamma = 1, and several-fold to one-two "
+                             "orders of magnitude reductions across its problems; it gives "
+                             "no wall times and no hardware (bench.py --extras runs that "
+                             "case: paper_poiseuille)."}
 
 
 def ladder_256():
@@ -869,15 +1004,22 @@ def kernel_probe(name, launches, copy_probe):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5000)
-    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--big-steps", type=int, default=100)
     ap.add_argument("--extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--grid", type=int, default=64, help="cube edge of the duct (64 = headline)")
+    ap.add_argument("--no-ttr", action="store_true", help="skip the time-to-residual block")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="time the headline workload alone (profiler runs)")
+    ap.add_argument("--grid", type=int, default=256, help="cube edge of the duct (256 = headline)")
+    ap.add_argument("--gamma", type=float, default=None,
+                    help="preconditioning parameter (default: 1 at 256^3, 0.1 below)")
     ap.add_argument("--storage", default="f32", choices=["f32", "f64", "bf16", "f16"])
     ap.add_argument("--rounding", default="nearest", choices=["nearest", "stochastic"],
                     help="rounding of 16-bit stores (stochastic: bf16 / f16 only)")
+    ap.add_argument("--xcd-chunk", type=int, default=0,
+                    help="fix the XCD workgroup chunk (0: the library's create-time choice)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--probe", choices=["mhd256", "adjoint128", "d2q9_4096", "precision256",
@@ -887,8 +1029,8 @@ def main():
     ap.add_argument("--launches", type=int, default=30)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the library has no multi-GPU path "
-              "(got --gpus %d)" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU: the library and this benchmark have no "
+              "multi-GPU path (got --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
@@ -900,44 +1042,58 @@ def main():
         kernel_probe(args.probe, args.launches, args.copy_probe)
         return
 
-    shape, gamma, storage = (args.grid,) * 3, 0.1, args.storage
+    shape, storage = (args.grid,) * 3, args.storage
+    gamma = args.gamma if args.gamma is not None else (1.0 if args.grid >= 256 else 0.1)
     if args.rounding == "stochastic" and storage not in ("bf16", "f16"):
         raise SystemExit("--rounding stochastic needs --storage bf16 or f16")
-    rkw = {"rounding": "stochastic"} if args.rounding == "stochastic" else {}
-    mlups, wall, mean_us = measure(shape, storage, gamma, args.steps, args.warmup, **rkw)
-    N = shape[0] * shape[1] * shape[2]
-    sb = {"f32": 4, "f64": 8, "bf16": 2, "f16": 2}[storage]
-    bpn = algorithmic_bytes_per_node(sb, True, NO_CHECK)
-    achieved = bpn * N / (mean_us * 1e-6) / 1e9
+    kw = {"rounding": "stochastic"} if args.rounding == "stochastic" else {}
+    if args.xcd_chunk:
+        kw["launch"] = {"xcd_chunk": args.xcd_chunk}
+    print("headline: duct %s %s gamma=%g, %d + %d steps" % (shape, storage, gamma, args.warmup,
+                                                            args.steps), file=sys.stderr,
+          flush=True)
+    head = step_roofline(shape, storage, gamma, args.steps, args.warmup, **kw)
     khash = kernel_hash()
-    tag = "glbe_step_%s%s_duct%d" % (storage, "_sr" if rkw else "", args.grid)
+    tag = "glbe_step_%s%s_duct%d" % (storage, "_sr" if args.rounding == "stochastic" else "",
+                                     args.grid)
     traffic = traffic_from_profiles(tag, khash)
     line = {
-        "metric": "MLUPS, % HBM roofline; wall time to 1e-8 residual, gamma<1 vs plain gamma=1",
-        "value": round(mlups, 2),
+        "metric": METRIC,
+        "value": head["MLUPS"],
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1000.0 * wall / args.steps, 5),
+        "ms_per_step": round(head["ms_per_step"], 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": storage,
         "data": "synthetic",
         "config": {"workload": "square duct %dx%dx%d, D3Q19 preconditioned MRT-GLBE, "
-                               "spatially varying force F0=1e-5, nu=0.131, gamma=0.1, "
-                               "%s deviation storage%s, FP64 residual every 10 steps"
-                               % (shape + (storage.upper(),
-                                           " (stochastic rounding)" if rkw else "")),
+                               "force F_x=F0 sin(2 pi y/Ly)(1+cos(2 pi z/Lz)/2), F0=1e-5, "
+                               "nu=0.131, gamma=%g, %s deviation storage%s, FP32 collision, "
+                               "FP64 residual, mass and flow rate every 10 steps"
+                               % (shape + (gamma, storage.upper(),
+                                           " (stochastic rounding)" if kw.get("rounding") else "")),
                    "grid": list(shape), "gamma": gamma, "storage": storage,
-                   "rounding": args.rounding},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                   "rounding": args.rounding, "launch": head["launch"]},
+        "roofline": {"bound": head["bound"], "achieved": head["achieved_GBs"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": head["frac"],
                      "traffic": traffic,
+                     "traffic_source": "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE of this kernel "
+                                       "in profiles/traffic.json, used only when taken on the "
+                                       "current kernel sources (kernel_hash), else null",
                      "kernel": "glbe_step<%s, check=false, field=true%s>"
-                               % (storage, ", stochastic" if rkw else ""),
-                     "alg_bytes_per_node": bpn, "mean_kernel_us": round(mean_us, 3),
+                               % (storage, ", stochastic" if kw.get("rounding") else ""),
+                     "timing": "HIP events around each of the %d plain launches of the timed "
+                               "steps, on the library's stream" % head["launches_timed"],
+                     "alg_bytes_per_node": head["alg_bytes_per_node"],
+                     "alg_bytes_per_launch": head["alg_bytes_per_launch"],
+                     "mean_kernel_us": head["kernel_us"],
+                     "min_kernel_us": head["kernel_us_min"],
+                     "max_kernel_us": head["kernel_us_max"],
+                     "check_kernel_us": head["check_kernel_us"],
                      "kernel_hash": khash},
     }
     if args.copy_probe:
@@ -948,7 +1104,21 @@ def main():
         torch.cuda.synchronize()
         line["copy_probe_bytes"] = src.numel() * 4
         del src, dst
+    if not args.only_headline:
+        per = []
+        for st in [x for x in ("bf16", "f16", "f64") if x != storage]:
+            print("storage %s" % st, file=sys.stderr, flush=True)
+            e = step_roofline(shape, st, gamma, args.steps, args.warmup)
+            e.pop("wall_s")
+            per.append(e)
+        line["other_storage"] = per
+        print("64^3 duct (cache-resident)", file=sys.stderr, flush=True)
+        line["duct64_f32_gamma0.1"] = small_duct_line(max(args.steps, 1000), args.warmup)
+        if not args.no_ttr:
+            print("time to residual", file=sys.stderr, flush=True)
+            line["time_to_residual"] = time_to_residual_block()
     if not args.no_cpu:
+        print("cpu baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline()
     if args.extras:
         line["extras"] = extras(args)
