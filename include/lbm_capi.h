@@ -310,6 +310,27 @@ lbm_status lbm_run_to_energy_change(lbm_ctx* ctx, double tol, int64_t max_steps,
  * Lorentz force is included).  Synchronizes. */
 lbm_status lbm_reductions(lbm_ctx* ctx, double* mass_drift, double* flow_rate);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * reductions of lbm_reductions for a population state the caller holds, with
+ * no context and no workspace.  state: device [q][N] in the storage type
+ * (q = 19, or 9 for D2Q9), as lbm_get_state writes it (deviations from
+ * w rho0, post-collision values of the last step); force: device [3][N] in the
+ * compute type for force_mode = FIELD (ignored for UNIFORM); grid and params
+ * as for lbm_create (mhd = 0 only: LBM_EUNSUPPORTED otherwise).  Enqueues on
+ * hip_stream, which must belong to the current device, and writes
+ * out[0] = sum (rho - rho0), out[1] = (1/nx) sum j_x of the streamed state
+ * (FP64, device pointer).  Does not synchronize and allocates nothing: the
+ * partial sums live in a 4 MiB scratch array in device memory that each GPU
+ * holds for the life of the process, so lattices are limited to 26,841,856
+ * nodes (LBM_ENOWS beyond).  All calls on one GPU share that scratch: calls
+ * that overlap in time on one GPU (several host threads, or several streams
+ * of one GPU) race and must be serialized by the caller.  Errors: LBM_EINVAL,
+ * LBM_ENOWS, LBM_EUNSUPPORTED, LBM_EHIP (lbm_last_error(NULL)). */
+lbm_status lbm_reductions_noalloc(const lbm_grid* grid, const lbm_params* params,
+                                  const void* state, const void* force, void* hip_stream,
+                                  double* out);
+
 /* Hydrodynamic fields of the current state into caller device buffers:
  * rho [N], u [3][N] (physical velocity, F/(2 gamma) included), B [3][N]
  * (mhd only; may be NULL).  out_dtype is LBM_F64 or LBM_F32.  Enqueued. */

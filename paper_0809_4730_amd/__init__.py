@@ -144,6 +144,7 @@ def load_library():
         "lbm_run_to_energy_change": [c_void_p, c_double, c_int64, c_int64, P(c_int64),
                                      P(c_double)],
         "lbm_reductions": [c_void_p, P(c_double), P(c_double)],
+        "lbm_reductions_noalloc": [P(_Grid), P(_Params), c_void_p, c_void_p, c_void_p, c_void_p],
         "lbm_moments": [c_void_p, c_int32, c_void_p, c_void_p, c_void_p],
         "lbm_state_bytes": [c_void_p, P(c_size_t)],
         "lbm_get_state": [c_void_p, c_void_p],
@@ -476,6 +477,23 @@ class Simulation:
         m, q = ctypes.c_double(), ctypes.c_double()
         self._c(self._lib.lbm_reductions(self._ctx, ctypes.byref(m), ctypes.byref(q)))
         return m.value, q.value
+
+    def reductions_noalloc(self, state, out):
+        """lbm_reductions_noalloc on this simulation's grid, parameters and force
+        for a state tensor (the layout of get_state): writes (mass drift, flow
+        rate) into the FP64 device tensor `out` (2 elements) on the library's
+        stream; allocates nothing."""
+        torch = _torch()
+        if not (out.dtype == torch.float64 and out.numel() >= 2 and out.is_contiguous()):
+            raise ValueError("out must be a contiguous float64 tensor of 2 elements")
+        state = state.contiguous()
+        self._enter()
+        fptr = self._force_tensor.data_ptr() if self._force_tensor is not None else None
+        _check(self._lib.lbm_reductions_noalloc(ctypes.byref(self._grid), ctypes.byref(self._params),
+                                                state.data_ptr(), fptr, self._stream.cuda_stream,
+                                                out.data_ptr()))
+        self._leave(state, out)
+        return out
 
     def moments(self, dtype="f64"):
         """(rho, u, B) device tensors of the current state; B is None without mhd."""

@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["kernels.hip", "kernels2d.hip", "adjoint.hip", "batch.hip", "lbm_capi.hip"]
+SOURCES = ["kernels.hip", "kernels2d.hip", "adjoint.hip", "batch.hip", "lbm_capi.hip",
+           "noalloc.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

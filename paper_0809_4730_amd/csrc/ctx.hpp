@@ -80,6 +80,7 @@ struct lbm_ctx {
 
 namespace lbm {
 // Helpers defined in lbm_capi.hip.
+std::string validate_params(const lbm_grid* grid, const lbm_params* p);  // "" when valid
 lbm_status fail(lbm_ctx* c, lbm_status s, const std::string& msg);
 lbm_status hip_fail(lbm_ctx* c, hipError_t e, const char* what);
 lbm_status one_step(lbm_ctx* c, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);

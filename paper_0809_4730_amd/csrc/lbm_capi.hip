@@ -134,6 +134,8 @@ Layout make_layout(const lbm_grid* grid, const lbm_params* p) {
 
 namespace lbm {
 
+std::string validate_params(const lbm_grid* grid, const lbm_params* p) { return validate(grid, p); }
+
 lbm_status fail(lbm_ctx* c, lbm_status s, const std::string& msg) {
   if (c) c->err = msg; else g_create_error = msg;
   return s;
