@@ -97,6 +97,9 @@ typedef struct {
                          (non-temporal) stores of the populations */
   int32_t offsets;    /* 0: 32-bit byte offsets wherever they fit, else 64-bit
                          element offsets; 1: 64-bit element offsets always */
+  int32_t load;       /* 0: library's choice; 1: cacheable loads; 2: streaming
+                         (non-temporal) loads of the populations and the force
+                         field, D3Q19 steps with streaming stores only */
 } lbm_launch;
 
 typedef struct {
@@ -227,7 +230,8 @@ lbm_status lbm_workspace_bytes(const lbm_grid* grid, const lbm_params* params, s
  * whose two population buffers fit the 256 MB last-level cache get one
  * contiguous slab per XCD and cacheable stores; up to 512 MB, slabs and
  * streaming stores; above that (lattices that stream from HBM) streaming
- * stores, and lbm_create times a few dozen plain steps on the stream for each
+ * stores (and, for D3Q19, streaming loads), and lbm_create times a few dozen
+ * plain steps on the stream for each
  * of three XCD workgroup mappings (chunks of 2 and 8 workgroups, slabs), keeps
  * the fastest and restores the rest state; it then synchronizes (a few ms to
  * a few tens of ms).  A non-zero launch.xcd_chunk skips the timing.  The
@@ -241,8 +245,9 @@ lbm_status lbm_create(const lbm_grid* grid, const lbm_params* params, const void
                       lbm_ctx** out);
 
 /* The launch shape the context uses (after lbm_create's choice): the XCD
- * chunk in workgroups, store 1 (cacheable) or 2 (streaming), offsets 0 (32-bit
- * byte offsets) or 1 (64-bit element offsets) of the flow step.  Host only.
+ * chunk in workgroups, store and load 1 (cacheable) or 2 (streaming), offsets
+ * 0 (32-bit byte offsets) or 1 (64-bit element offsets) of the flow step.
+ * Host only.
  * Errors: LBM_EINVAL for a NULL argument. */
 lbm_status lbm_get_launch(const lbm_ctx* ctx, lbm_launch* out);
 

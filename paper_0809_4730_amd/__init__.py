@@ -39,7 +39,7 @@ class _Grid(ctypes.Structure):
 
 class _Launch(ctypes.Structure):
     _fields_ = [("xcd_chunk", ctypes.c_int32), ("store", ctypes.c_int32),
-                ("offsets", ctypes.c_int32)]
+                ("offsets", ctypes.c_int32), ("load", ctypes.c_int32)]
 
 
 _STORES = {"auto": 0, "cached": 1, "streaming": 2}
@@ -47,15 +47,16 @@ _STORES = {"auto": 0, "cached": 1, "streaming": 2}
 
 def _launch(launch):
     """lbm_launch from None or dict(xcd_chunk=int, store="auto"|"cached"|"streaming",
-    offsets="auto"|"wide")."""
+    load="auto"|"cached"|"streaming", offsets="auto"|"wide")."""
     out = _Launch()
     if launch:
-        unknown = set(launch) - {"xcd_chunk", "store", "offsets"}
+        unknown = set(launch) - {"xcd_chunk", "store", "offsets", "load"}
         if unknown:
             raise ValueError("unknown launch keys %s" % sorted(unknown))
         out.xcd_chunk = int(launch.get("xcd_chunk", 0))
         out.store = _STORES[launch.get("store", "auto")]
         out.offsets = {"auto": 0, "wide": 1}[launch.get("offsets", "auto")]
+        out.load = _STORES[launch.get("load", "auto")]
     return out
 
 
@@ -273,7 +274,8 @@ class Simulation:
     rounding: "nearest" or "stochastic" (bf16/f16 storage, flow step without mhd): how
               stored populations are rounded; seed: the stochastic rounding seed.
     launch: None (the library's choice) or dict(xcd_chunk=n, store="cached"|"streaming",
-            offsets="wide"): the launch shape (lbm_launch; results do not depend on it).
+            load="cached"|"streaming", offsets="wide"): the launch shape (lbm_launch;
+            results do not depend on it).
     """
 
     def __init__(self, shape, bc, gamma, s, storage="f32", force=(0.0, 0.0, 0.0), rho0=1.0,
@@ -463,7 +465,8 @@ class Simulation:
         offsets="narrow"|"wide") (lbm_get_launch)."""
         lp = _Launch()
         self._c(self._lib.lbm_get_launch(self._ctx, ctypes.byref(lp)))
-        return {"xcd_chunk": lp.xcd_chunk, "store": {1: "cached", 2: "streaming"}[lp.store],
+        pol = {1: "cached", 2: "streaming"}
+        return {"xcd_chunk": lp.xcd_chunk, "store": pol[lp.store], "load": pol[lp.load],
                 "offsets": {0: "narrow", 1: "wide"}[lp.offsets]}
 
     @property

@@ -11,13 +11,9 @@
 
 namespace lbm {
 
-// Build-time knob: LBM_NT_LOAD 1 marks population loads non-temporal (measured
-// slower for FP32, so off).  Streaming stores and the XCD block mapping are
-// chosen per context at create (GridArgs::xcd_chunk, the NT template flag of
-// the step; lbm_params.launch).
-#ifndef LBM_NT_LOAD
-#define LBM_NT_LOAD 0
-#endif
+// Streaming (non-temporal) loads and stores and the XCD block mapping are
+// chosen per context at create (GridArgs::xcd_chunk, the NTL / NT template
+// flags of the steps; lbm_params.launch).
 
 // Build-time knob: LBM_BLOCK threads per workgroup (a multiple of 64).
 #ifndef LBM_BLOCK
@@ -61,6 +57,7 @@ struct GridArgs {
   FastDiv div_nx, div_nxny;
   FastDiv div_chunk;       // division by xcd_chunk
   int32_t wide;            // 1: 64-bit element offsets even where 32-bit byte offsets fit
+  int32_t nt_load;         // 1: streaming population and force loads (launchers: NTL flag)
   uint32_t step;           // the step number a step launch computes (stochastic rounding)
   uint32_t seed;           // stochastic rounding seed
   // Fluid box [flo, fhi) per axis (x, y, z).  The whole lattice, unless the
@@ -118,13 +115,13 @@ struct bf16_t {
 template <typename S>
 struct Storage;
 
-template <typename T>
+// NT: streaming load (the value is used once; do not keep its line in the caches)
+template <bool NT = false, typename T>
 __device__ __forceinline__ T ld_pop(const T* p) {
-#if LBM_NT_LOAD
-  return __builtin_nontemporal_load(p);
-#else
-  return *p;
-#endif
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
 }
 
 template <bool NT, typename T>
@@ -153,7 +150,8 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 template <>
 struct Storage<double> {
   using R = double;
-  __device__ __forceinline__ static R ld(const double* p) { return ld_pop(p); }
+  template <bool NT = false>
+  __device__ __forceinline__ static R ld(const double* p) { return ld_pop<NT>(p); }
   template <bool NT = false>
   __device__ __forceinline__ static void st(double* p, R v) { st_pop<NT>(p, v); }
   template <bool NT = false>
@@ -167,7 +165,8 @@ struct Storage<double> {
 template <>
 struct Storage<float> {
   using R = float;
-  __device__ __forceinline__ static R ld(const float* p) { return ld_pop(p); }
+  template <bool NT = false>
+  __device__ __forceinline__ static R ld(const float* p) { return ld_pop<NT>(p); }
   template <bool NT = false>
   __device__ __forceinline__ static void st(float* p, R v) { st_pop<NT>(p, v); }
   template <bool NT = false>
@@ -180,8 +179,9 @@ struct Storage<float> {
 template <>
 struct Storage<bf16_t> {
   using R = float;
+  template <bool NT = false>
   __device__ __forceinline__ static R ld(const bf16_t* p) {
-    return __uint_as_float(static_cast<uint32_t>(ld_pop(&p->bits)) << 16);
+    return __uint_as_float(static_cast<uint32_t>(ld_pop<NT>(&p->bits)) << 16);
   }
   // round to nearest, ties to even, NaN stays NaN: one v_cvt_pk_bf16_f32 on gfx950
   template <bool NT = false>
@@ -199,7 +199,10 @@ struct Storage<bf16_t> {
 template <>
 struct Storage<_Float16> {
   using R = float;
-  __device__ __forceinline__ static R ld(const _Float16* p) { return static_cast<float>(ld_pop(p)); }
+  template <bool NT = false>
+  __device__ __forceinline__ static R ld(const _Float16* p) {
+    return static_cast<float>(ld_pop<NT>(p));
+  }
   template <bool NT = false>
   __device__ __forceinline__ static void st(_Float16* p, R v) {
     st_pop<NT>(p, static_cast<_Float16>(v));

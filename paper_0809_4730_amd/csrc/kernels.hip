@@ -25,7 +25,7 @@ namespace lbm {
 // field's equilibrium, d_{a j} = g_{a j} - W_a B0_j (j outermost).  At a wall,
 // anti-bounce-back g_a = -g~_opp(a) + 2 W_a B0 (insulating wall, B = B0 there)
 // reads d_a = -d~_opp(a) in deviation form.
-template <typename R, int A, bool WIDE>
+template <typename R, int A, bool WIDE, bool NTL>
 __device__ __forceinline__ void gather_g_dir(const R* __restrict__ gin, int64_t stride, uint32_t n,
                                              const Nbr& b, R (&g)[3][Q7]) {
   int32_t off;
@@ -34,17 +34,17 @@ __device__ __forceinline__ void gather_g_dir(const R* __restrict__ gin, int64_t 
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     const R* base = gin + static_cast<int64_t>(j * Q7 + pair_plane<A>()) * stride;
-    const R v = *elem<WIDE>(base, i);
+    const R v = ld_pop<NTL>(elem<WIDE>(base, i));
     g[j][A] = bounce ? -v : v;
   }
 }
 
-template <typename R, bool WIDE, int A = 0>
+template <typename R, bool WIDE, bool NTL = false, int A = 0>
 __device__ __forceinline__ void gather_g(const R* __restrict__ gin, int64_t stride, uint32_t n,
                                          const Nbr& b, R (&g)[3][Q7]) {
   if constexpr (A < Q7) {
-    gather_g_dir<R, A, WIDE>(gin, stride, n, b, g);
-    gather_g<R, WIDE, A + 1>(gin, stride, n, b, g);
+    gather_g_dir<R, A, WIDE, NTL>(gin, stride, n, b, g);
+    gather_g<R, WIDE, NTL, A + 1>(gin, stride, n, b, g);
   }
 }
 
@@ -161,14 +161,14 @@ __device__ __forceinline__ void store_g(R* __restrict__ gout, const GridArgs& ga
   store_planes<R, NT, WIDE, 3 * Q7>(gout, ga, n, flat);
 }
 
-template <typename R, bool WIDE>
+template <typename R, bool WIDE, bool NTL = false>
 __device__ __forceinline__ void load_force(const GridArgs& g, const CollideArgs<R>& c,
                                            const R* __restrict__ force, bool field, uint32_t n,
                                            R& Fx, R& Fy, R& Fz) {
   if (field) {
-    Fx = *elem<WIDE>(force, n);
-    Fy = *elem<WIDE>(force + g.stride, n);
-    Fz = *elem<WIDE>(force + 2 * g.stride, n);
+    Fx = ld_pop<NTL>(elem<WIDE>(force, n));
+    Fy = ld_pop<NTL>(elem<WIDE>(force + g.stride, n));
+    Fz = ld_pop<NTL>(elem<WIDE>(force + 2 * g.stride, n));
   } else {
     Fx = c.F[0];
     Fy = c.F[1];
@@ -178,8 +178,10 @@ __device__ __forceinline__ void load_force(const GridArgs& g, const CollideArgs<
 
 // ------------------------------------------------------------------ steps --
 // ROWS: every wave lies in one x-row (nx a multiple of 64; neighbours_rows).
-// SR: 16-bit stores with stochastic rounding (store_stochastic).
-template <typename S, bool CHECK, bool FIELD, bool NT, bool MOVING, bool WIDE, bool ROWS, bool SR>
+// SR: 16-bit stores with stochastic rounding (store_stochastic).  NT / NTL:
+// streaming stores / loads.
+template <typename S, bool CHECK, bool FIELD, bool NT, bool NTL, bool MOVING, bool WIDE, bool ROWS,
+          bool SR>
 __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<typename Storage<S>::R> c,
                                                     const S* __restrict__ fin, S* __restrict__ fout,
                                                     const typename Storage<S>::R* __restrict__ force,
@@ -193,9 +195,9 @@ __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<type
   if (n < static_cast<uint32_t>(g.N)) {
     const Nbr b = ROWS ? neighbours_rows(g, n) : neighbours(g, n);
     R f[Q19];
-    gather19<S, MOVING, WIDE>(fin, g.stride, n, b, c, f);
+    gather19<S, MOVING, WIDE, NTL>(fin, g.stride, n, b, c, f);
     R Fx, Fy, Fz;
-    load_force<R, WIDE>(g, c, force, FIELD, n, Fx, Fy, Fz);
+    load_force<R, WIDE, NTL>(g, c, force, FIELD, n, Fx, Fy, Fz);
     const NodeMacro<R> mac = collide19<R>(f, Fx, Fy, Fz, c);
     if constexpr (SR)
       store_stochastic<S, NT, WIDE, Q19>(fout, g, n, f);
@@ -208,8 +210,10 @@ __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<type
 }
 
 // EXT: the induction lattice extends beyond the fluid box; nodes outside it
-// relax g with u = 0 and leave f untouched.  NT: streaming stores.
-template <typename R, bool CHECK, bool FIELD, bool MOVING, bool EXT, bool WIDE, bool NT>
+// relax g with u = 0 and leave f untouched.  NT / NTL: streaming stores /
+// loads.  ROWS (not with EXT): every wave lies in one x-row (neighbours_rows).
+template <typename R, bool CHECK, bool FIELD, bool MOVING, bool EXT, bool WIDE, bool NT, bool NTL,
+          bool ROWS>
 __global__ __launch_bounds__(kBlock) void mhd_step(GridArgs g, CollideArgs<R> c, MagArgs<R> m,
                                                    const R* __restrict__ fin, R* __restrict__ fout,
                                                    const R* __restrict__ gin, R* __restrict__ gout,
@@ -221,18 +225,26 @@ __global__ __launch_bounds__(kBlock) void mhd_step(GridArgs g, CollideArgs<R> c,
   const uint32_t n = static_cast<uint32_t>(lb) * kBlock + threadIdx.x;
   double acc[kPartials] = {};
   if (n < static_cast<uint32_t>(g.N)) {
-    const Coord q = coords(g, n);
-    const Nbr b = neighbours_at(g, q);
+    static_assert(!(ROWS && EXT), "the row-aligned form needs the fluid box to be the lattice");
+    Coord q{};
+    Nbr b;
+    if constexpr (ROWS) {
+      b = neighbours_rows(g, n);
+    } else {
+      q = coords(g, n);
+      b = neighbours_at(g, q);
+    }
     R gg[3][Q7];
-    gather_g<R, WIDE>(gin, g.stride, n, b, gg);
+    gather_g<R, WIDE, NTL>(gin, g.stride, n, b, gg);
     bool fluid = true;
     if constexpr (EXT) fluid = in_box(g, q);
     if (fluid) {
-      const Nbr bf = EXT ? box_walls(g, q, b) : b;
+      Nbr bf = b;
+      if constexpr (EXT) bf = box_walls(g, q, b);
       R f[Q19];
-      gather19<R, MOVING, WIDE>(fin, g.stride, n, bf, c, f);
+      gather19<R, MOVING, WIDE, NTL>(fin, g.stride, n, bf, c, f);
       R Fx, Fy, Fz;
-      load_force<R, WIDE>(g, c, force, FIELD, n, Fx, Fy, Fz);
+      load_force<R, WIDE, NTL>(g, c, force, FIELD, n, Fx, Fy, Fz);
       const Coupled<R> cp = lorentz_solve<R>(f, gg, Fx, Fy, Fz, c, m);
       const NodeMacro<R> mac = collide19<R>(f, cp.Fx, cp.Fy, cp.Fz, c);
       collide_g<R>(gg, cp, mac.ux, mac.uy, mac.uz, m);
@@ -424,37 +436,31 @@ hipError_t launch_glbe_step(const GridArgs& g, const CollideArgs<typename Storag
   const S* a = static_cast<const S*>(fin);
   S* b = static_cast<S*>(fout);
   const R* F = static_cast<const R*>(force);
-  // moving walls: small problems, regular stores
+  // moving walls: small problems, regular loads and stores; streaming loads
+  // only with streaming stores (lattices that stream from HBM)
+  const bool ntl = nt && g.nt_load;
   return with_flag(check, [&](auto CH) {
     return with_flag(field, [&](auto FL) {
       return with_flag(wide_offsets(g, sizeof(R)), [&](auto W) {
         return with_flag(rows_per_wave(g), [&](auto RW) {
-          constexpr bool ch = decltype(CH)::value, fl = decltype(FL)::value,
-                         w = decltype(W)::value, rw = decltype(RW)::value;
-          if constexpr (sizeof(S) == 2) {
-            if (stochastic) {
-              if (c.moving)
-                glbe_step<S, ch, fl, false, true, w, rw, true>
-                    <<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
-              else if (nt)
-                glbe_step<S, ch, fl, true, false, w, rw, true>
-                    <<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
-              else
-                glbe_step<S, ch, fl, false, false, w, rw, true>
-                    <<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
-              return hipGetLastError();
-            }
-          }
-          if (c.moving)
-            glbe_step<S, ch, fl, false, true, w, rw, false>
-                <<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
-          else if (nt)
-            glbe_step<S, ch, fl, true, false, w, rw, false>
-                <<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
-          else
-            glbe_step<S, ch, fl, false, false, w, rw, false>
-                <<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
-          return hipGetLastError();
+          return with_flag(stochastic && sizeof(S) == 2, [&](auto SRF) {
+            constexpr bool ch = decltype(CH)::value, fl = decltype(FL)::value,
+                           w = decltype(W)::value, rw = decltype(RW)::value,
+                           sr = decltype(SRF)::value && sizeof(S) == 2;
+            if (c.moving)
+              glbe_step<S, ch, fl, false, false, true, w, rw, sr>
+                  <<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
+            else if (ntl)
+              glbe_step<S, ch, fl, true, true, false, w, rw, sr>
+                  <<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
+            else if (nt)
+              glbe_step<S, ch, fl, true, false, false, w, rw, sr>
+                  <<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
+            else
+              glbe_step<S, ch, fl, false, false, false, w, rw, sr>
+                  <<<step_grid(g), kBlock, 0, st>>>(g, c, a, b, F, usnap, partials);
+            return hipGetLastError();
+          });
         });
       });
     });
@@ -483,22 +489,36 @@ hipError_t launch_mhd_step(const GridArgs& g, const CollideArgs<R>& c, const Mag
   R* gb = static_cast<R*>(gout);
   const R* F = static_cast<const R*>(force);
   const bool ext = g.flo[0] > 0 || g.flo[1] > 0 || g.flo[2] > 0;
+  const bool plain = !c.moving && !ext;
+  const bool ntl = nt && g.nt_load;
   return with_flag(check, [&](auto CH) {
     return with_flag(field, [&](auto FL) {
-      return with_flag(c.moving != 0, [&](auto MV) {
-        return with_flag(ext, [&](auto EX) {
-          return with_flag(wide_offsets(g, sizeof(R)), [&](auto W) {
-            return with_flag(nt, [&](auto NTF) {
-              // streaming stores only in the plain variant: moving walls and the
-              // extended lattice are the (cache-resident) cavity
-              constexpr bool kNt =
-                  decltype(NTF)::value && !decltype(MV)::value && !decltype(EX)::value;
-              mhd_step<R, decltype(CH)::value, decltype(FL)::value, decltype(MV)::value,
-                       decltype(EX)::value, decltype(W)::value, kNt>
+      return with_flag(wide_offsets(g, sizeof(R)), [&](auto W) {
+        constexpr bool ch = decltype(CH)::value, fl = decltype(FL)::value,
+                       w = decltype(W)::value;
+        if (!plain) {
+          // moving walls and the extended lattice are the (cache-resident)
+          // cavity: per-lane coordinates, regular loads and stores
+          return with_flag(c.moving != 0, [&](auto MV) {
+            return with_flag(ext, [&](auto EX) {
+              mhd_step<R, ch, fl, decltype(MV)::value, decltype(EX)::value, w, false, false, false>
                   <<<step_grid(g), kBlock, 0, st>>>(g, c, m, a, b, ga, gb, F, usnap, partials);
               return hipGetLastError();
             });
           });
+        }
+        return with_flag(rows_per_wave(g), [&](auto RW) {
+          constexpr bool rw = decltype(RW)::value;
+          if (ntl)
+            mhd_step<R, ch, fl, false, false, w, true, true, rw>
+                <<<step_grid(g), kBlock, 0, st>>>(g, c, m, a, b, ga, gb, F, usnap, partials);
+          else if (nt)
+            mhd_step<R, ch, fl, false, false, w, true, false, rw>
+                <<<step_grid(g), kBlock, 0, st>>>(g, c, m, a, b, ga, gb, F, usnap, partials);
+          else
+            mhd_step<R, ch, fl, false, false, w, false, false, rw>
+                <<<step_grid(g), kBlock, 0, st>>>(g, c, m, a, b, ga, gb, F, usnap, partials);
+          return hipGetLastError();
         });
       });
     });

@@ -70,6 +70,7 @@ std::string validate(const lbm_grid* grid, const lbm_params* p) {
   if (p->launch.xcd_chunk < 0) return "launch.xcd_chunk must be >= 0";
   if (p->launch.store < 0 || p->launch.store > 2) return "launch.store must be 0, 1 or 2";
   if (p->launch.offsets != 0 && p->launch.offsets != 1) return "launch.offsets must be 0 or 1";
+  if (p->launch.load < 0 || p->launch.load > 2) return "launch.load must be 0, 1 or 2";
   if (p->check_every < 1) return "check_every must be >= 1";
   if (p->history_len < 1) return "history_len must be >= 1";
   if (p->source_mode != 0 && p->source_mode != 1) return "source_mode must be 0 or 1";
@@ -245,6 +246,10 @@ void choose_launch_shape(lbm_ctx* c) {
     c->tune_chunk = false;
   }
   if (l.store != 0) c->nt_store = l.store == 2;
+  // streaming loads: measured 2-4% faster for the D3Q19 steps at 256^3 and
+  // 2% slower for the D2Q9 step at 4096^2
+  c->ga.nt_load = pop_bytes > 2.0 * kMallBytes && c->p.lattice != LBM_D2Q9;
+  if (l.load != 0) c->ga.nt_load = l.load == 2;
   c->ga.wide = l.offsets;
   set_chunk(c, chunk);
 }
@@ -572,6 +577,7 @@ lbm_status lbm_get_launch(const lbm_ctx* c, lbm_launch* out) {
   if (!c || !out) return fail(nullptr, LBM_EINVAL, "NULL argument");
   out->xcd_chunk = c->ga.xcd_chunk;
   out->store = c->nt_store ? 2 : 1;
+  out->load = (c->nt_store && c->ga.nt_load && c->p.lattice != LBM_D2Q9) ? 2 : 1;
   out->offsets = wide_offsets(c->ga, c->celem()) ? 1 : 0;
   return LBM_OK;
 }

@@ -169,8 +169,9 @@ constexpr int pair_plane() {
 }
 
 // MOVING = false compiles the wall-momentum term out (the plain step); with
-// MOVING = true it is added on bounced links when c.moving is set.
-template <typename S, int A, bool MOVING, bool WIDE>
+// MOVING = true it is added on bounced links when c.moving is set.  NTL:
+// streaming loads.
+template <typename S, int A, bool MOVING, bool WIDE, bool NTL = false>
 __device__ __forceinline__ typename Storage<S>::R gather_one(
     const S* __restrict__ fin, int64_t stride, uint32_t n, const Nbr& b,
     const CollideArgs<typename Storage<S>::R>& c) {
@@ -178,21 +179,22 @@ __device__ __forceinline__ typename Storage<S>::R gather_one(
   int32_t off;
   const bool bounce = pull_source<EX19[A], EY19[A], EZ19[A]>(b, off);
   const S* base = fin + static_cast<int64_t>(pair_plane<A>()) * stride;
-  R v = Storage<S>::ld(elem<WIDE>(base, pull_offset<A>(bounce, off, n, static_cast<uint32_t>(stride))));
+  R v = Storage<S>::template ld<NTL>(
+      elem<WIDE>(base, pull_offset<A>(bounce, off, n, static_cast<uint32_t>(stride))));
   if constexpr (MOVING) {
     if (bounce && c.moving) v += wall_term<R, A>(b, c);
   }
   return v;
 }
 
-template <typename S, bool MOVING, bool WIDE, int A = 0>
+template <typename S, bool MOVING, bool WIDE, bool NTL = false, int A = 0>
 __device__ __forceinline__ void gather19(const S* __restrict__ fin, int64_t stride, uint32_t n,
                                          const Nbr& b,
                                          const CollideArgs<typename Storage<S>::R>& c,
                                          typename Storage<S>::R (&f)[Q19]) {
   if constexpr (A < Q19) {
-    f[A] = gather_one<S, A, MOVING, WIDE>(fin, stride, n, b, c);
-    gather19<S, MOVING, WIDE, A + 1>(fin, stride, n, b, c, f);
+    f[A] = gather_one<S, A, MOVING, WIDE, NTL>(fin, stride, n, b, c);
+    gather19<S, MOVING, WIDE, NTL, A + 1>(fin, stride, n, b, c, f);
   }
 }
 

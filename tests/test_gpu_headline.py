@@ -104,26 +104,32 @@ def test_duct256_fp32_bench_kernel_after_a_march(check):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("storage", ["f32", "f64", "bf16"])
-def test_store_forms_bitwise_on_a_row_aligned_lattice(storage):
-    """Cacheable and streaming stores on a row-aligned lattice (64 x 6 x 10: the
-    row-aligned variant the benchmark's lattices take), residual checks on."""
+@pytest.mark.parametrize("storage", ["f32", "f64", "bf16", "f32_mhd"])
+def test_load_store_forms_bitwise_on_a_row_aligned_lattice(storage):
+    """Cacheable and streaming stores, and streaming loads with them, on a
+    row-aligned lattice (64 x 6 x 10: the row-aligned variant the benchmark's
+    lattices take), residual checks on, flow and coupled steps."""
     import torch
 
     import paper_0809_4730_amd as pkg
-    announce("store forms, row-aligned 64x6x10 %s" % storage)
+    announce("load/store forms, row-aligned 64x6x10 %s" % storage)
     shape, bc = (64, 6, 10), (PER, WALL, WALL)
     dt = torch.float64 if storage == "f64" else torch.float32
     F = torch.tensor(inputs.random_force(shape, seed=13, amp=1e-5), dtype=dt, device="cuda")
+    kw = dict(mhd=dict(gamma_m=0.3, chi=0.05, eta=0.03, B0=(0.01, 0.02, -0.01))) \
+        if storage.endswith("_mhd") else {}
     out = []
-    for store in ("cached", "streaming"):
-        sim = pkg.Simulation(shape, bc, 0.2, glbe.rates(0.05, 0.2), storage=storage, force=F,
-                             launch=dict(store=store))
-        assert sim.launch["store"] == store
+    for store, load in (("cached", "cached"), ("streaming", "cached"), ("streaming", "streaming")):
+        sim = pkg.Simulation(shape, bc, 0.2, glbe.rates(0.05, 0.2), storage=storage.split("_")[0],
+                             force=F, launch=dict(store=store, load=load), **kw)
+        assert sim.launch["store"] == store and sim.launch["load"] == load
         sim.step(33)
-        out.append((sim.get_state(), sim.history(8)))
-    assert torch.equal(out[0][0], out[1][0])
-    assert np.array_equal(out[0][1], out[1][1])
+        st = sim.get_state()
+        out.append((st if torch.is_tensor(st) else torch.cat([st[0].reshape(-1), st[1].reshape(-1)]),
+                    sim.history(8)))
+    for a, b in zip(out[1:], out[:-1]):
+        assert torch.equal(a[0], b[0])
+        assert np.array_equal(a[1], b[1])
 
 
 def test_nonfinite_force_is_detected_and_a_checkpoint_recovers():

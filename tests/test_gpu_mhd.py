@@ -30,7 +30,10 @@ def _random_g(shape, seed, B0, amp=1e-4):
 
 @pytest.mark.parametrize("shape,bc", [((6, 8, 5), (PER, WALL, PER)),
                                       ((5, 6, 7), (WALL, WALL, WALL)),
-                                      ((8, 4, 4), (PER, PER, PER))])
+                                      ((8, 4, 4), (PER, PER, PER)),
+                                      # nx a multiple of 64: the row-aligned form
+                                      ((64, 3, 4), (PER, WALL, WALL)),
+                                      ((128, 2, 3), (WALL, WALL, PER))])
 @pytest.mark.parametrize("nsteps", [1, 40])
 def test_mhd_fp64_matches_oracle(shape, bc, nsteps):
     import torch
