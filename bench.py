@@ -192,6 +192,66 @@ def small_duct_line(steps, warmup):
             "frac": round(gbs / HBM_PEAK_GBS, 4), "bound": "mall", "launch": launch}
 
 
+def mhd256_line(steps, warmup):
+    """The coupled step (D3Q19 flow + D3Q7 induction, Lorentz force) at HBM
+    scale: 256^3 FP32, walls normal to y and to B0 (the Hartmann setting of the
+    coupled workload, Ha = 10, Pm = 0.01, gamma = gamma_m = 0.1).  MLUPS of
+    the timed steps and the plain kernel from per-launch HIP events."""
+    import torch
+
+    import paper_0809_4730_amd as pkg
+    from paper_0809_4730_amd import inputs
+    cfg = inputs.HARTMANN
+    B0, chi = inputs.hartmann_parameters(10.0, 0.01, cfg["shape"][1], cfg["nu"], cfg["eta"])
+    sim = pkg.Simulation((256, 256, 256), cfg["bc"], 0.1, pkg.default_rates(cfg["nu"], 0.1),
+                         storage="f32", force=cfg["F"],
+                         mhd=dict(gamma_m=0.1, chi=chi, eta=cfg["eta"], B0=(0.0, B0, 0.0)))
+    launch = sim.launch
+    mlups, wall, plain, check = timed_steps(sim, steps, warmup)
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    us = statistics.fmean(plain)
+    bpn = 2 * (19 + 21) * 4
+    gbs = bpn * 256 ** 3 / (us * 1e-6) / 1e9
+    return {"workload": "coupled flow + induction step, 256^3, FP32, uniform force",
+            "MLUPS": round(mlups, 2), "kernel_us": round(us, 3),
+            "check_kernel_us": round(statistics.fmean(check), 3) if check else None,
+            "alg_bytes_per_node": bpn, "achieved_GBs": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "bound": "hbm", "launch": launch}
+
+
+def hbm_ceiling(nodes=256 ** 3, reps=10):
+    """What the HBM delivers on this GPU for three copies (lbm_bandwidth_probe):
+    a plain streaming copy of 16-byte vectors, and copies with exactly the
+    FP32 flow step's memory pattern (22 FP32 planes read, 19 written per node)
+    and the coupled step's (40 and 40), XCD chunks of 2, streaming loads and
+    stores, over the 256^3 lattice.
+    Median of `reps` launches, each between two HIP events on the current
+    stream."""
+    import torch
+
+    import paper_0809_4730_amd as pkg
+    src = torch.ones(40 * nodes, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    out = {"nodes": nodes}
+    for pattern, key in ((0, "stream_copy"), (1, "step_pattern_copy"),
+                         (2, "coupled_pattern_copy")):
+        ts = []
+        for _ in range(reps + 2):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            nbytes = pkg.bandwidth_probe(pattern, src, dst, nodes)
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e3)
+        us = statistics.median(ts[2:])
+        out[key] = {"bytes": nbytes, "us": round(us, 2), "GBs": round(nbytes / (us * 1e-6) / 1e9, 1)}
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_bandwidth_GBs(nbytes=4 << 30, reps=10):
     """Device-to-device copy (read + write) bandwidth of torch's copy kernel."""
     import torch
@@ -976,6 +1036,9 @@ def kernel_probe(name, launches, copy_probe):
         us = kernel_time_us(sim, launches, warmup=5)
         alg = 2 * 9 * 4 * sim.N
         kernel = "glbe2_step<float, check=false> (4096^2)"
+    elif name == "hbm_ceiling":
+        print(json.dumps({"probe": name, **hbm_ceiling(reps=launches)}), flush=True)
+        return
     elif name == "precision256":
         precision_steady_256()
         return
@@ -1023,7 +1086,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--probe", choices=["mhd256", "adjoint128", "d2q9_4096", "precision256",
-                                        "ladder256", "ladder128"],
+                                        "ladder256", "ladder128", "hbm_ceiling"],
                     help="only one other measurement: another kernel at HBM scale (for the "
                          "profilers), or the 256^3 precision form at steady state")
     ap.add_argument("--launches", type=int, default=30)
@@ -1105,6 +1168,13 @@ def main():
         line["copy_probe_bytes"] = src.numel() * 4
         del src, dst
     if not args.only_headline:
+        print("hbm ceiling", file=sys.stderr, flush=True)
+        ceil = hbm_ceiling()
+        line["roofline"]["ceiling"] = ceil
+        line["roofline"]["frac_of_step_pattern_copy"] = round(
+            head["achieved_GBs"] / ceil["step_pattern_copy"]["GBs"], 4)
+        line["roofline"]["frac_of_stream_copy"] = round(
+            head["achieved_GBs"] / ceil["stream_copy"]["GBs"], 4)
         per = []
         for st in [x for x in ("bf16", "f16", "f64") if x != storage]:
             print("storage %s" % st, file=sys.stderr, flush=True)
@@ -1114,6 +1184,11 @@ def main():
         line["other_storage"] = per
         print("64^3 duct (cache-resident)", file=sys.stderr, flush=True)
         line["duct64_f32_gamma0.1"] = small_duct_line(max(args.steps, 1000), args.warmup)
+        print("coupled step 256^3", file=sys.stderr, flush=True)
+        mhd = mhd256_line(args.steps, args.warmup)
+        mhd["frac_of_coupled_pattern_copy"] = round(
+            mhd["achieved_GBs"] / ceil["coupled_pattern_copy"]["GBs"], 4)
+        line["mhd256_f32"] = mhd
         if not args.no_ttr:
             print("time to residual", file=sys.stderr, flush=True)
             line["time_to_residual"] = time_to_residual_block()

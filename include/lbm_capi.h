@@ -439,6 +439,24 @@ lbm_status lbm_batch_run(const lbm_grid* grid, int32_t storage, double rho0, int
                          int64_t poll_every, const lbm_launch* launch,
                          lbm_member_result* results);
 
+/* ---------------------------------------------------------- calibration --
+ * The bandwidth the HBM delivers for two copies of FP32 data, timed by the
+ * caller around the launch (the step kernels' roofline fractions are read
+ * against these as well as against the nominal peak).  src and dst are
+ * device buffers of at least 22 * nodes (pattern 2: 40 * nodes) FP32 values
+ * each, 16-byte aligned.
+ * pattern 0: 22 * nodes values copied as 16-byte vectors, one per thread,
+ *            streaming loads and stores (moves 2 * 88 * nodes bytes);
+ * pattern 1: the flow step's pattern without its arithmetic: at each node 22
+ *            planes of stride `nodes` read and 19 written, one value per plane
+ *            and thread, streaming loads and stores, workgroups dealt to the
+ *            XCDs in chunks of xcd_chunk (moves 164 * nodes bytes);
+ * pattern 2: the same with 40 planes read and 40 written, the coupled step's
+ *            pattern (moves 320 * nodes bytes).
+ * Enqueued on hip_stream.  Errors: LBM_EINVAL, LBM_EHIP. */
+lbm_status lbm_bandwidth_probe(int32_t pattern, const void* src, void* dst, int64_t nodes,
+                               int32_t xcd_chunk, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -133,6 +133,7 @@ def load_library():
                           c_void_p, c_double, c_int64, c_int32, c_int64, P(_Launch),
                           P(_MemberResult)],
         "lbm_lattice_velocities": [c_int32, P(c_int32)],
+        "lbm_bandwidth_probe": [c_int32, c_void_p, c_void_p, c_int64, c_int32, c_void_p],
         "lbm_workspace_bytes": [P(_Grid), P(_Params), P(c_size_t)],
         "lbm_create": [P(_Grid), P(_Params), c_void_p, c_void_p, c_size_t, c_void_p, P(c_void_p)],
         "lbm_set_force": [c_void_p, c_void_p],
@@ -197,6 +198,24 @@ def lattice_velocities(q=19):
     out = (ctypes.c_int32 * (3 * q))()
     _check(lib.lbm_lattice_velocities(q, out))
     return np.array(list(out), dtype=np.int64).reshape(q, 3)
+
+
+def bandwidth_probe(pattern, src, dst, nodes, xcd_chunk=2, stream=None):
+    """Enqueue one calibration copy (lbm_bandwidth_probe) between two float32
+    device tensors of at least 22 * nodes (pattern 2: 40 * nodes) elements on
+    `stream` (default: the current stream).  Returns the bytes it moves."""
+    torch = _torch()
+    lib = load_library()
+    planes = 40 if pattern == 2 else 22
+    if src.numel() < planes * nodes or dst.numel() < planes * nodes \
+            or src.dtype != torch.float32 or dst.dtype != torch.float32:
+        raise ValueError("src and dst must be float32 tensors of at least %d * nodes elements"
+                         % planes)
+    if stream is None:
+        stream = torch.cuda.current_stream(src.device)
+    _check(lib.lbm_bandwidth_probe(int(pattern), src.data_ptr(), dst.data_ptr(), int(nodes),
+                                   int(xcd_chunk), stream.cuda_stream))
+    return {0: 2 * 88 * nodes, 1: 164 * nodes, 2: 320 * nodes}[int(pattern)]
 
 
 VERDICTS = {0: "undecided", 1: "converged", 2: "unstable"}

@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblbm.so")
 SOURCES = ["kernels.hip", "kernels2d.hip", "adjoint.hip", "batch.hip", "lbm_capi.hip",
-           "noalloc.hip"]
+           "noalloc.hip", "probe.hip"]
 ARCH = "gfx950"
 
 FLAGS = [
