@@ -999,7 +999,7 @@ def ladder_128():
     ], 100, "square duct 128^3, nu = 0.131, C1 force; residual 1e-8")
 
 
-def kernel_probe(name, launches, copy_probe):
+def kernel_probe(name, launches, copy_probe, launch=None):
     """One JSON line for the profilers: `launches` plain launches of one
     kernel at its HBM-scale size (coupled step 256^3 FP32, steady adjoint
     128^3 FP32, D2Q9 step 4096^2 FP32), timed with HIP events, with its
@@ -1012,7 +1012,7 @@ def kernel_probe(name, launches, copy_probe):
         cfg = inputs.HARTMANN
         B0, chi = inputs.hartmann_parameters(10.0, 0.01, cfg["shape"][1], cfg["nu"], cfg["eta"])
         sim = pkg.Simulation((256, 256, 256), cfg["bc"], 0.1, pkg.default_rates(cfg["nu"], 0.1),
-                             storage="f32", force=cfg["F"], check_every=NO_CHECK,
+                             storage="f32", force=cfg["F"], check_every=NO_CHECK, launch=launch,
                              mhd=dict(gamma_m=0.1, chi=chi, eta=cfg["eta"], B0=(0.0, B0, 0.0)))
         us = kernel_time_us(sim, launches, warmup=5)
         alg = 2 * (19 + 21) * 4 * sim.N
@@ -1032,7 +1032,7 @@ def kernel_probe(name, launches, copy_probe):
     elif name == "d2q9_4096":
         sim = pkg.Simulation((4096, 4096, 1), ("periodic", "wall", "periodic"), 0.1,
                              pkg.default_rates_d2q9(0.1, 0.1), storage="f32", force=(1e-7, 0.0),
-                             check_every=NO_CHECK, lattice="d2q9")
+                             check_every=NO_CHECK, lattice="d2q9", launch=launch)
         us = kernel_time_us(sim, launches, warmup=5)
         alg = 2 * 9 * 4 * sim.N
         kernel = "glbe2_step<float, check=false> (4096^2)"
@@ -1102,7 +1102,8 @@ def main():
     import paper_0809_4730_amd as pkg
     pkg.load_library()
     if args.probe:
-        kernel_probe(args.probe, args.launches, args.copy_probe)
+        kernel_probe(args.probe, args.launches, args.copy_probe,
+                     {"xcd_chunk": args.xcd_chunk} if args.xcd_chunk else None)
         return
 
     shape, storage = (args.grid,) * 3, args.storage
