@@ -339,14 +339,16 @@ __global__ __launch_bounds__(kBlock) void fields_kernel(
 // ---------------------------------------------------------------- finalize --
 // One workgroup per pending check: sum that check's per-workgroup partials in
 // a fixed order and write its history record {step, residual, du2, u2, mass,
-// flow, nonfinite, 0}.  Checks are check_every steps apart.
+// flow, nonfinite, 0}.  Checks are check_every steps apart.  Check first + i
+// takes its partials from slot (slot_first + i) mod pslots and its record to
+// ring entry (first + i) mod history_len.
 __global__ __launch_bounds__(kBlock) void finalize_kernel(const double* __restrict__ partials,
-                                                          int nblocks, int pslots, int64_t first,
-                                                          double step0, double dstep,
+                                                          int nblocks, int pslots, int64_t slot_first,
+                                                          int64_t first, double step0, double dstep,
                                                           double inv_nx, double* __restrict__ ring,
                                                           int history_len) {
   const int64_t k = first + blockIdx.x;
-  const double* p = partials + (k % pslots) * int64_t(nblocks) * kPartials;
+  const double* p = partials + ((slot_first + blockIdx.x) % pslots) * int64_t(nblocks) * kPartials;
   double acc[kPartials] = {};
   for (int b = threadIdx.x; b < nblocks; b += kBlock) {
 #pragma unroll
@@ -369,6 +371,32 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(const double* __restri
     record[5] = acc[3] * inv_nx;
     record[6] = acc[4];
     record[7] = 0.0;
+  }
+}
+
+// First pass of a split finalize for lattices with many workgroups: workgroup
+// (g, i) sums the partials of logical blocks [g span, (g + 1) span) of check
+// first + i (slot (first + i) mod pslots) in a fixed order and writes them to
+// out[i][g]; finalize_kernel then reduces the `groups` sums of each check.
+__global__ __launch_bounds__(kBlock) void finalize_part(const double* __restrict__ partials,
+                                                        int nblocks, int pslots, int64_t first,
+                                                        int span, int groups,
+                                                        double* __restrict__ out) {
+  const int g = blockIdx.x;
+  const int64_t slot = (first + blockIdx.y) % pslots;
+  const double* p = partials + slot * int64_t(nblocks) * kPartials;
+  const int b0 = g * span;
+  const int b1 = b0 + span < nblocks ? b0 + span : nblocks;
+  double acc[kPartials] = {};
+  for (int b = b0 + threadIdx.x; b < b1; b += kBlock) {
+#pragma unroll
+    for (int q = 0; q < kPartials; ++q) acc[q] += p[static_cast<int64_t>(b) * kPartials + q];
+  }
+  block_sum<kPartials>(acc);
+  if (threadIdx.x == 0) {
+    double* o = out + (static_cast<int64_t>(blockIdx.y) * groups + g) * kPartials;
+#pragma unroll
+    for (int q = 0; q < kPartials; ++q) o[q] = acc[q];
   }
 }
 
@@ -575,7 +603,26 @@ hipError_t launch_finalize(const double* partials, int nblocks, int pslots, int6
                            int count, double step0, double dstep, double inv_nx, double* ring,
                            int history_len, hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  finalize_kernel<<<count, kBlock, 0, st>>>(partials, nblocks, pslots, first, step0, dstep, inv_nx,
+  finalize_kernel<<<count, kBlock, 0, st>>>(partials, nblocks, pslots, first, first, step0, dstep,
+                                            inv_nx, ring, history_len);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_split(const double* partials, int nblocks, int pslots, int64_t first,
+                                 int count, double step0, double dstep, double inv_nx,
+                                 double* ring, int history_len, double* scratch,
+                                 int64_t scratch_doubles, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  constexpr int kSpan = 1024;  // logical blocks per first-pass workgroup
+  const int groups = (nblocks + kSpan - 1) / kSpan;
+  if (groups < 4 || count > 65535 || int64_t(count) * groups * kPartials > scratch_doubles)
+    return launch_finalize(partials, nblocks, pslots, first, count, step0, dstep, inv_nx, ring,
+                           history_len, st);
+  finalize_part<<<dim3(groups, count), kBlock, 0, st>>>(partials, nblocks, pslots, first, kSpan,
+                                                        groups, scratch);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  finalize_kernel<<<count, kBlock, 0, st>>>(scratch, groups, count, 0, first, step0, dstep, inv_nx,
                                             ring, history_len);
   return hipGetLastError();
 }

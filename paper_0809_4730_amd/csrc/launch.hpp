@@ -51,6 +51,15 @@ hipError_t launch_finalize(const double* partials, int nblocks, int pslots, int6
                            int count, double step0, double dstep, double inv_nx, double* ring,
                            int history_len, hipStream_t st);
 
+// The same result reduced in two passes (many workgroups sum spans of the
+// partials into `scratch`, then one workgroup per check) for lattices with
+// many workgroups; the single pass when scratch_doubles cannot hold
+// count * ceil(nblocks / 1024) * 5 values or the lattice is small.
+hipError_t launch_finalize_split(const double* partials, int nblocks, int pslots, int64_t first,
+                                 int count, double step0, double dstep, double inv_nx,
+                                 double* ring, int history_len, double* scratch,
+                                 int64_t scratch_doubles, hipStream_t st);
+
 template <typename S>
 hipError_t launch_fill_zero(void* p, int64_t count, hipStream_t st);
 

@@ -260,9 +260,13 @@ lbm_status flush_checks(lbm_ctx* c) {
   const int64_t count = c->checks - c->finalized;
   if (count <= 0) return LBM_OK;
   const double step0 = double(c->first_check_step + c->finalized * c->p.check_every);
-  LBM_HIP(c, launch_finalize(c->partials(), c->L.nblocks, c->L.pslots, c->finalized, int(count),
-                             step0, double(c->p.check_every), 1.0 / (c->grid.n[0] - 2 * c->p.mag_pad[0]), c->ring(),
-                             c->p.history_len, c->stream),
+  // the reductions' partials region (nblocks x 5 doubles) is the first pass's
+  // scratch: lbm_reductions uses it only between its own two stream-ordered launches
+  LBM_HIP(c, launch_finalize_split(c->partials(), c->L.nblocks, c->L.pslots, c->finalized,
+                                   int(count), step0, double(c->p.check_every),
+                                   1.0 / (c->grid.n[0] - 2 * c->p.mag_pad[0]), c->ring(),
+                                   c->p.history_len, c->fpartials(),
+                                   int64_t(c->L.nblocks) * kPartials, c->stream),
           "finalize launch");
   c->finalized = c->checks;
   return LBM_OK;
@@ -409,17 +413,20 @@ lbm_status read_records(lbm_ctx* c, int64_t first, int64_t count, std::vector<do
   const lbm_status fs = flush_checks(c);
   if (fs != LBM_OK) return fs;
   out.assign(size_t(count) * kRecordDoubles, 0.0);
+  if (count <= 0) return LBM_OK;
+  // the records occupy at most two contiguous ranges of the ring
   const int64_t len = c->p.history_len;
-  std::vector<double> ring(size_t(len) * kRecordDoubles);
-  LBM_HIP(c, hipMemcpyAsync(ring.data(), c->ring(), ring.size() * sizeof(double),
+  const int64_t slot0 = first % len;
+  const int64_t n1 = std::min(count, len - slot0);
+  const size_t rec = kRecordDoubles * sizeof(double);
+  LBM_HIP(c, hipMemcpyAsync(out.data(), c->ring() + slot0 * kRecordDoubles, size_t(n1) * rec,
                             hipMemcpyDeviceToHost, c->stream),
           "history copy");
+  if (count > n1)
+    LBM_HIP(c, hipMemcpyAsync(out.data() + n1 * kRecordDoubles, c->ring(), size_t(count - n1) * rec,
+                              hipMemcpyDeviceToHost, c->stream),
+            "history copy");
   LBM_HIP(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
-  for (int64_t i = 0; i < count; ++i) {
-    const int64_t slot = (first + i) % len;
-    std::memcpy(&out[size_t(i) * kRecordDoubles], &ring[size_t(slot) * kRecordDoubles],
-                kRecordDoubles * sizeof(double));
-  }
   return LBM_OK;
 }
 
