@@ -229,9 +229,9 @@ def hbm_ceiling(nodes=256 ** 3, reps=10):
     a plain streaming copy of 16-byte vectors, and copies with exactly the
     FP32 flow step's memory pattern (22 FP32 planes read, 19 written per node)
     and the coupled step's (40 and 40), XCD chunks of 2, streaming loads and
-    stores, over the 256^3 lattice.
-    Median of `reps` launches, each between two HIP events on the current
-    stream."""
+    stores, over the 256^3 lattice; each with no cap on the waves per SIMD and
+    with the steps' cap of 5.  Median of `reps` launches, each between two HIP
+    events on the current stream; the best of the two caps is the ceiling."""
     import torch
 
     import paper_0809_4730_amd as pkg
@@ -240,16 +240,23 @@ def hbm_ceiling(nodes=256 ** 3, reps=10):
     out = {"nodes": nodes}
     for pattern, key in ((0, "stream_copy"), (1, "step_pattern_copy"),
                          (2, "coupled_pattern_copy")):
-        ts = []
-        for _ in range(reps + 2):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            nbytes = pkg.bandwidth_probe(pattern, src, dst, nodes)
-            e1.record()
-            e1.synchronize()
-            ts.append(e0.elapsed_time(e1) * 1e3)
-        us = statistics.median(ts[2:])
-        out[key] = {"bytes": nbytes, "us": round(us, 2), "GBs": round(nbytes / (us * 1e-6) / 1e9, 1)}
+        best = None
+        for waves in (8, 5):
+            ts = []
+            for _ in range(reps + 2):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                nbytes = pkg.bandwidth_probe(pattern, src, dst, nodes, waves=waves)
+                e1.record()
+                e1.synchronize()
+                ts.append(e0.elapsed_time(e1) * 1e3)
+            us = statistics.median(ts[2:])
+            e = {"bytes": nbytes, "waves": waves, "us": round(us, 2),
+                 "GBs": round(nbytes / (us * 1e-6) / 1e9, 1)}
+            out["%s_waves%d" % (key, waves)] = e
+            if best is None or e["GBs"] > best["GBs"]:
+                best = e
+        out[key] = best
     del src, dst
     torch.cuda.empty_cache()
     return out

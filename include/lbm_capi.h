@@ -100,6 +100,10 @@ typedef struct {
   int32_t load;       /* 0: library's choice; 1: cacheable loads; 2: streaming
                          (non-temporal) loads of the populations and the force
                          field, D3Q19 steps with streaming stores only */
+  int32_t waves;      /* 0: library's choice; 3..7: at most this many waves per
+                         SIMD run the D3Q19 step kernels (each workgroup
+                         reserves an unused share of the compute unit's LDS);
+                         8: no cap beyond the kernels' own register use */
 } lbm_launch;
 
 typedef struct {
@@ -230,8 +234,9 @@ lbm_status lbm_workspace_bytes(const lbm_grid* grid, const lbm_params* params, s
  * whose two population buffers fit the 256 MB last-level cache get one
  * contiguous slab per XCD and cacheable stores; up to 512 MB, slabs and
  * streaming stores; above that (lattices that stream from HBM) streaming
- * stores (and, for D3Q19, streaming loads), and lbm_create times a few dozen
- * plain steps on the stream for each
+ * stores (and, for D3Q19, streaming loads and a cap of 5 waves per SIMD for
+ * FP32 storage and for the coupled step, 6 for 16-bit storage, none for FP64),
+ * and lbm_create times a few dozen plain steps on the stream for each
  * of three XCD workgroup mappings (chunks of 2 and 8 workgroups, slabs), keeps
  * the fastest and restores the rest state; it then synchronizes (a few ms to
  * a few tens of ms).  A non-zero launch.xcd_chunk skips the timing.  The
@@ -246,8 +251,8 @@ lbm_status lbm_create(const lbm_grid* grid, const lbm_params* params, const void
 
 /* The launch shape the context uses (after lbm_create's choice): the XCD
  * chunk in workgroups, store and load 1 (cacheable) or 2 (streaming), offsets
- * 0 (32-bit byte offsets) or 1 (64-bit element offsets) of the flow step.
- * Host only.
+ * 0 (32-bit byte offsets) or 1 (64-bit element offsets) of the flow step, and
+ * the cap on waves per SIMD (8: none).  Host only.
  * Errors: LBM_EINVAL for a NULL argument. */
 lbm_status lbm_get_launch(const lbm_ctx* ctx, lbm_launch* out);
 
@@ -453,9 +458,10 @@ lbm_status lbm_batch_run(const lbm_grid* grid, int32_t storage, double rho0, int
  *            XCDs in chunks of xcd_chunk (moves 164 * nodes bytes);
  * pattern 2: the same with 40 planes read and 40 written, the coupled step's
  *            pattern (moves 320 * nodes bytes).
- * Enqueued on hip_stream.  Errors: LBM_EINVAL, LBM_EHIP. */
+ * waves: at most this many waves per SIMD (3..7, as lbm_launch.waves), or 8
+ * for no cap.  Enqueued on hip_stream.  Errors: LBM_EINVAL, LBM_EHIP. */
 lbm_status lbm_bandwidth_probe(int32_t pattern, const void* src, void* dst, int64_t nodes,
-                               int32_t xcd_chunk, void* hip_stream);
+                               int32_t xcd_chunk, int32_t waves, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -39,7 +39,8 @@ class _Grid(ctypes.Structure):
 
 class _Launch(ctypes.Structure):
     _fields_ = [("xcd_chunk", ctypes.c_int32), ("store", ctypes.c_int32),
-                ("offsets", ctypes.c_int32), ("load", ctypes.c_int32)]
+                ("offsets", ctypes.c_int32), ("load", ctypes.c_int32),
+                ("waves", ctypes.c_int32)]
 
 
 _STORES = {"auto": 0, "cached": 1, "streaming": 2}
@@ -47,16 +48,17 @@ _STORES = {"auto": 0, "cached": 1, "streaming": 2}
 
 def _launch(launch):
     """lbm_launch from None or dict(xcd_chunk=int, store="auto"|"cached"|"streaming",
-    load="auto"|"cached"|"streaming", offsets="auto"|"wide")."""
+    load="auto"|"cached"|"streaming", offsets="auto"|"wide", waves=0|3..8)."""
     out = _Launch()
     if launch:
-        unknown = set(launch) - {"xcd_chunk", "store", "offsets", "load"}
+        unknown = set(launch) - {"xcd_chunk", "store", "offsets", "load", "waves"}
         if unknown:
             raise ValueError("unknown launch keys %s" % sorted(unknown))
         out.xcd_chunk = int(launch.get("xcd_chunk", 0))
         out.store = _STORES[launch.get("store", "auto")]
         out.offsets = {"auto": 0, "wide": 1}[launch.get("offsets", "auto")]
         out.load = _STORES[launch.get("load", "auto")]
+        out.waves = int(launch.get("waves", 0))
     return out
 
 
@@ -133,7 +135,7 @@ def load_library():
                           c_void_p, c_double, c_int64, c_int32, c_int64, P(_Launch),
                           P(_MemberResult)],
         "lbm_lattice_velocities": [c_int32, P(c_int32)],
-        "lbm_bandwidth_probe": [c_int32, c_void_p, c_void_p, c_int64, c_int32, c_void_p],
+        "lbm_bandwidth_probe": [c_int32, c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p],
         "lbm_workspace_bytes": [P(_Grid), P(_Params), P(c_size_t)],
         "lbm_create": [P(_Grid), P(_Params), c_void_p, c_void_p, c_size_t, c_void_p, P(c_void_p)],
         "lbm_set_force": [c_void_p, c_void_p],
@@ -200,7 +202,7 @@ def lattice_velocities(q=19):
     return np.array(list(out), dtype=np.int64).reshape(q, 3)
 
 
-def bandwidth_probe(pattern, src, dst, nodes, xcd_chunk=2, stream=None):
+def bandwidth_probe(pattern, src, dst, nodes, xcd_chunk=2, waves=8, stream=None):
     """Enqueue one calibration copy (lbm_bandwidth_probe) between two float32
     device tensors of at least 22 * nodes (pattern 2: 40 * nodes) elements on
     `stream` (default: the current stream).  Returns the bytes it moves."""
@@ -214,7 +216,7 @@ def bandwidth_probe(pattern, src, dst, nodes, xcd_chunk=2, stream=None):
     if stream is None:
         stream = torch.cuda.current_stream(src.device)
     _check(lib.lbm_bandwidth_probe(int(pattern), src.data_ptr(), dst.data_ptr(), int(nodes),
-                                   int(xcd_chunk), stream.cuda_stream))
+                                   int(xcd_chunk), int(waves), stream.cuda_stream))
     return {0: 2 * 88 * nodes, 1: 164 * nodes, 2: 320 * nodes}[int(pattern)]
 
 
@@ -293,8 +295,8 @@ class Simulation:
     rounding: "nearest" or "stochastic" (bf16/f16 storage, flow step without mhd): how
               stored populations are rounded; seed: the stochastic rounding seed.
     launch: None (the library's choice) or dict(xcd_chunk=n, store="cached"|"streaming",
-            load="cached"|"streaming", offsets="wide"): the launch shape (lbm_launch;
-            results do not depend on it).
+            load="cached"|"streaming", offsets="wide", waves=3..8): the launch shape
+            (lbm_launch; results do not depend on it).
     """
 
     def __init__(self, shape, bc, gamma, s, storage="f32", force=(0.0, 0.0, 0.0), rho0=1.0,
@@ -486,7 +488,7 @@ class Simulation:
         self._c(self._lib.lbm_get_launch(self._ctx, ctypes.byref(lp)))
         pol = {1: "cached", 2: "streaming"}
         return {"xcd_chunk": lp.xcd_chunk, "store": pol[lp.store], "load": pol[lp.load],
-                "offsets": {0: "narrow", 1: "wide"}[lp.offsets]}
+                "offsets": {0: "narrow", 1: "wide"}[lp.offsets], "waves": lp.waves}
 
     @property
     def t(self):

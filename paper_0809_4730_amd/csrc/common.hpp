@@ -21,6 +21,7 @@ namespace lbm {
 #endif
 
 constexpr int kBlock = LBM_BLOCK;  // threads per workgroup (4 wave64 by default)
+constexpr uint32_t kLdsPerCu = 160 * 1024;  // LDS bytes per compute unit on gfx950
 static_assert(kBlock % 64 == 0 && kBlock <= 1024, "LBM_BLOCK must be a multiple of 64, at most 1024");
 constexpr int kXcd = 8;       // XCDs on MI355X; workgroups are dealt round-robin
 constexpr int kRecordDoubles = 8;
@@ -58,6 +59,8 @@ struct GridArgs {
   FastDiv div_chunk;       // division by xcd_chunk
   int32_t wide;            // 1: 64-bit element offsets even where 32-bit byte offsets fit
   int32_t nt_load;         // 1: streaming population and force loads (launchers: NTL flag)
+  uint32_t lds_reserve;    // dynamic LDS bytes per workgroup of a 3D step launch: reserved, not
+                           // used, to cap the workgroups per CU (0: no cap)
   uint32_t step;           // the step number a step launch computes (stochastic rounding)
   uint32_t seed;           // stochastic rounding seed
   // Fluid box [flo, fhi) per axis (x, y, z).  The whole lattice, unless the

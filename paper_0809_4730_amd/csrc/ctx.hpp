@@ -52,6 +52,7 @@ struct lbm_ctx {
   int cur = 0;
   bool nt_store = false;  // streaming (cache-bypassing) population stores
   bool tune_chunk = false;  // time the XCD chunk candidates at create
+  int waves = 8;            // cap on waves per SIMD of the 3D step kernels (8: none)
   int64_t step = 0;
   int64_t checks = 0;            // residual checks launched since the last reset
   int64_t finalized = 0;         // checks whose history records have been written

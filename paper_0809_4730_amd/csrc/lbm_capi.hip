@@ -71,6 +71,8 @@ std::string validate(const lbm_grid* grid, const lbm_params* p) {
   if (p->launch.store < 0 || p->launch.store > 2) return "launch.store must be 0, 1 or 2";
   if (p->launch.offsets != 0 && p->launch.offsets != 1) return "launch.offsets must be 0 or 1";
   if (p->launch.load < 0 || p->launch.load > 2) return "launch.load must be 0, 1 or 2";
+  if (p->launch.waves != 0 && (p->launch.waves < 3 || p->launch.waves > 8))
+    return "launch.waves must be 0 or 3..8";
   if (p->check_every < 1) return "check_every must be >= 1";
   if (p->history_len < 1) return "history_len must be >= 1";
   if (p->source_mode != 0 && p->source_mode != 1) return "source_mode must be 0 or 1";
@@ -250,6 +252,19 @@ void choose_launch_shape(lbm_ctx* c) {
   // 2% slower for the D2Q9 step at 4096^2
   c->ga.nt_load = pop_bytes > 2.0 * kMallBytes && c->p.lattice != LBM_D2Q9;
   if (l.load != 0) c->ga.nt_load = l.load == 2;
+  // waves per SIMD: fewer waves in flight stream faster from HBM for the FP32
+  // steps (measured at 256^3: FP32 flow 466 -> 446 us at 5 waves, coupled
+  // 987 -> 973 us) and 16-bit storage at 6 (254 -> 249 us); FP64 already runs 4
+  c->waves = 8;
+  if (pop_bytes > 2.0 * kMallBytes && c->p.lattice != LBM_D2Q9 && c->p.storage != LBM_F64)
+    c->waves = (c->p.storage == LBM_F32 || c->p.mhd) ? 5 : 6;
+  if (l.waves != 0) c->waves = l.waves;
+  c->ga.lds_reserve = 0;
+  if (c->waves < 8) {
+    // the largest multiple of 512 B below an equal share of the CU's LDS, less
+    // 512 B for the kernels' own static LDS
+    c->ga.lds_reserve = (kLdsPerCu / uint32_t(c->waves)) / 512u * 512u - 512u;
+  }
   c->ga.wide = l.offsets;
   set_chunk(c, chunk);
 }
@@ -585,6 +600,7 @@ lbm_status lbm_get_launch(const lbm_ctx* c, lbm_launch* out) {
   out->xcd_chunk = c->ga.xcd_chunk;
   out->store = c->nt_store ? 2 : 1;
   out->load = (c->nt_store && c->ga.nt_load && c->p.lattice != LBM_D2Q9) ? 2 : 1;
+  out->waves = c->p.lattice == LBM_D2Q9 ? 8 : c->waves;
   out->offsets = wide_offsets(c->ga, c->celem()) ? 1 : 0;
   return LBM_OK;
 }

@@ -49,18 +49,21 @@ __global__ __launch_bounds__(kBlock) void plane_copy(GridArgs g, const float* __
 extern "C" {
 
 lbm_status lbm_bandwidth_probe(int32_t pattern, const void* src, void* dst, int64_t nodes,
-                               int32_t xcd_chunk, void* hip_stream) {
+                               int32_t xcd_chunk, int32_t waves, void* hip_stream) {
   if (!src || !dst) return fail(nullptr, LBM_EINVAL, "src and dst must be non-null");
   if (nodes < 1 || nodes >= (int64_t(1) << 31)) return fail(nullptr, LBM_EINVAL, "nodes out of range");
   if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 != 0)
     return fail(nullptr, LBM_EINVAL, "src and dst must be 16-byte aligned");
+  if (waves < 3 || waves > 8) return fail(nullptr, LBM_EINVAL, "waves must be 3..8");
+  // the steps' cap on waves per SIMD: an unused LDS reservation per workgroup
+  const uint32_t lds = waves < 8 ? (kLdsPerCu / uint32_t(waves)) / 512u * 512u - 512u : 0u;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   if (pattern == 0) {
     // 22 planes' worth of FP32 values, copied as 16-byte vectors
     const int64_t count = (22 * nodes) / 4;
     const int64_t blocks = (count + kBlock - 1) / kBlock;
     if (blocks >= (int64_t(1) << 31)) return fail(nullptr, LBM_EINVAL, "too many nodes");
-    copy16<<<dim3(static_cast<uint32_t>(blocks)), kBlock, 0, st>>>(
+    copy16<<<dim3(static_cast<uint32_t>(blocks)), kBlock, lds, st>>>(
         static_cast<const f32x4*>(src), static_cast<f32x4*>(dst), count);
   } else if (pattern == 1 || pattern == 2) {
     if (xcd_chunk < 1) return fail(nullptr, LBM_EINVAL, "xcd_chunk must be >= 1");
@@ -74,11 +77,11 @@ lbm_status lbm_bandwidth_probe(int32_t pattern, const void* src, void* dst, int6
     g.blocks_per_xcd = (bpx0 + chunk - 1) / chunk * chunk;
     g.stride = nodes;
     if (pattern == 1)
-      plane_copy<22, 19><<<step_grid(g), kBlock, 0, st>>>(g, static_cast<const float*>(src),
-                                                          static_cast<float*>(dst));
+      plane_copy<22, 19><<<step_grid(g), kBlock, lds, st>>>(g, static_cast<const float*>(src),
+                                                            static_cast<float*>(dst));
     else
-      plane_copy<40, 40><<<step_grid(g), kBlock, 0, st>>>(g, static_cast<const float*>(src),
-                                                          static_cast<float*>(dst));
+      plane_copy<40, 40><<<step_grid(g), kBlock, lds, st>>>(g, static_cast<const float*>(src),
+                                                            static_cast<float*>(dst));
   } else {
     return fail(nullptr, LBM_EINVAL, "pattern must be 0, 1 or 2");
   }

@@ -87,7 +87,7 @@ def _grid_params(pkg, **kw):
     p.gamma_m, p.chi, p.eta, p.mu = 0.1, 0.01, 0.025, 1.0
     p.rounding = kw.get("rounding", 0)
     p.lattice = kw.get("lattice", 0)
-    for k in ("xcd_chunk", "store", "offsets", "load"):
+    for k in ("xcd_chunk", "store", "offsets", "load", "waves"):
         setattr(p.launch, k, kw.get(k, 0))
     return g, p
 
@@ -100,6 +100,7 @@ def _grid_params(pkg, **kw):
     dict(rounding=1, storage=2, mhd=1), dict(rounding=1, storage=0, lattice=1, n=(8, 8, 1)),
     # launch shape fields
     dict(xcd_chunk=-1), dict(store=3), dict(store=-1), dict(offsets=2), dict(load=3),
+    dict(waves=2), dict(waves=9), dict(waves=-1),
 ])
 def test_validation_rejects(lib, bad):
     import paper_0809_4730_amd as pkg

@@ -87,6 +87,7 @@ def test_duct256_bench_kernel_after_a_march(storage, check):
     announce("256^3 %s, %s step after a march" % (storage, "check" if check else "plain"))
     sim = _duct_sim(shape, storage, cfg["gamma"])
     assert sim.launch["store"] == "streaming" and sim.launch["load"] == "streaming"
+    assert sim.launch["waves"] == {"f32": 5, "f64": 8, "bf16": 6, "f16": 6}[storage]
     tdt = {"f32": torch.float32, "f64": torch.float64, "bf16": torch.bfloat16,
            "f16": torch.float16}[storage]
     d0 = torch.from_numpy(inputs.random_deviations(shape, seed=12, amp=1e-3)).to(tdt)
@@ -130,9 +131,10 @@ def test_duct256_bench_kernel_after_a_march(storage, check):
 
 @pytest.mark.parametrize("storage", ["f32", "f64", "bf16", "f32_mhd"])
 def test_load_store_forms_bitwise_on_a_row_aligned_lattice(storage):
-    """Cacheable and streaming stores, and streaming loads with them, on a
-    row-aligned lattice (64 x 6 x 10: the row-aligned variant the benchmark's
-    lattices take), residual checks on, flow and coupled steps."""
+    """Cacheable and streaming stores, streaming loads with them, and caps on
+    the waves per SIMD, on a row-aligned lattice (64 x 6 x 10: the row-aligned
+    variant the benchmark's lattices take), residual checks on, flow and
+    coupled steps: bit for bit."""
     import torch
 
     import paper_0809_4730_amd as pkg
@@ -143,10 +145,13 @@ def test_load_store_forms_bitwise_on_a_row_aligned_lattice(storage):
     kw = dict(mhd=dict(gamma_m=0.3, chi=0.05, eta=0.03, B0=(0.01, 0.02, -0.01))) \
         if storage.endswith("_mhd") else {}
     out = []
-    for store, load in (("cached", "cached"), ("streaming", "cached"), ("streaming", "streaming")):
+    for store, load, waves in (("cached", "cached", 8), ("streaming", "cached", 8),
+                               ("streaming", "streaming", 8), ("streaming", "streaming", 5),
+                               ("cached", "cached", 3)):
         sim = pkg.Simulation(shape, bc, 0.2, glbe.rates(0.05, 0.2), storage=storage.split("_")[0],
-                             force=F, launch=dict(store=store, load=load), **kw)
+                             force=F, launch=dict(store=store, load=load, waves=waves), **kw)
         assert sim.launch["store"] == store and sim.launch["load"] == load
+        assert sim.launch["waves"] == waves
         sim.step(33)
         st = sim.get_state()
         out.append((st if torch.is_tensor(st) else torch.cat([st[0].reshape(-1), st[1].reshape(-1)]),
@@ -312,9 +317,9 @@ def test_bandwidth_probe_copies_exactly():
     announce("bandwidth probe copies")
     nodes = 3 * 256 + 40
     src = torch.arange(40 * nodes, dtype=torch.float32, device="cuda") * 0.5 - 7.0
-    for pattern, planes in ((0, 22), (1, 19), (2, 40)):
+    for pattern, planes, waves in ((0, 22, 8), (1, 19, 8), (2, 40, 8), (1, 19, 5), (0, 22, 3)):
         dst = torch.full_like(src, -1.0)
-        nbytes = pkg.bandwidth_probe(pattern, src, dst, nodes)
+        nbytes = pkg.bandwidth_probe(pattern, src, dst, nodes, waves=waves)
         torch.cuda.synchronize()
         assert torch.equal(dst[:planes * nodes], src[:planes * nodes])
         assert bool((dst[planes * nodes:] == -1.0).all())
