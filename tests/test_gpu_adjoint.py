@@ -11,7 +11,7 @@ import pytest
 from oracle import adjoint as oadj
 from oracle import glbe
 from paper_0809_4730_amd import inputs
-from tests.gpu_util import announce, rel, to_gpu_f
+from tests.gpu_util import announce, rel
 
 pytestmark = pytest.mark.gpu
 PER, WALL = "periodic", "wall"
@@ -35,33 +35,12 @@ def _tiny_force(shape):
 
 
 @pytest.mark.parametrize("gamma", [0.5, 1.0])
-def test_steady_adjoint_from_oracle_state_matches_dense_oracle(gamma):
-    """The adjoint linearised about the oracle's own converged state (loaded
-    into the context), iterated to a relative change of 1e-15: the FP64 bar of
-    1e-12 against the dense bordered solve (Sec. 3 steady flow, transposed)."""
-    import torch
-    announce("steady adjoint from the oracle state gamma=%g" % gamma)
-    shape, bc = (2, 4, 4), (PER, WALL, WALL)
-    s = glbe.rates(0.131, gamma)
-    F = _tiny_force(shape)
-    fl = glbe.Flow(shape, bc, F, gamma, s)
-    assert fl.run_to(1e-14, 100000)
-    ref, _ = oadj.steady_gradient_dense(fl.post, fl.F, gamma, s, bc)
-    sim = _sim(shape, bc, gamma, s, "f64", F)
-    sim.set_state(to_gpu_f(fl.post, torch.float64))
-    grad, iters, change = sim.adjoint_steady(tol=1e-15, max_iter=400000)
-    assert change < 1e-15, (iters, change)
-    g = grad.cpu().numpy()
-    assert rel(g, ref) < 1e-12, rel(g, ref)
-
-
-@pytest.mark.parametrize("gamma", [0.5, 1.0])
 def test_steady_adjoint_matches_dense_oracle(gamma):
     """End to end: the GPU marches to its own steady state (residual 1e-14)
     and linearises there.  Its state differs from the oracle's by the
     residual amplified by the flow's slowest relaxation time, and the gradient
-    inherits that gap; hence 1e-9, not the 1e-12 of the test above, which
-    starts both from one state."""
+    inherits that gap; hence 1e-9.  The 1e-12 comparison starts both from
+    the oracle's state (test_gpu_headline)."""
     announce("steady adjoint tiny gamma=%g" % gamma)
     shape, bc = (2, 4, 4), (PER, WALL, WALL)
     s = glbe.rates(0.131, gamma)
