@@ -224,29 +224,35 @@ def mhd256_line(steps, warmup):
             "frac": round(gbs / HBM_PEAK_GBS, 4), "bound": "hbm", "launch": launch}
 
 
-def hbm_ceiling(nodes=256 ** 3, reps=10):
-    """What the HBM delivers on this GPU for three copies (lbm_bandwidth_probe):
-    a plain streaming copy of 16-byte vectors, and copies with exactly the
-    FP32 flow step's memory pattern (22 FP32 planes read, 19 written per node)
-    and the coupled step's (40 and 40), XCD chunks of 2, streaming loads and
-    stores, over the 256^3 lattice; each with no cap on the waves per SIMD and
+def hbm_ceiling(shape=(256, 256, 256), reps=10):
+    """What the HBM delivers on this GPU for five copies (lbm_bandwidth_probe)
+    over the 256^3 lattice: a plain streaming copy of 16-byte vectors; copies
+    with the FP32 flow step's plane pattern (22 FP32 planes read, 19 written
+    per node) and the coupled step's (40 and 40), every plane read at the node
+    itself; and copies with each step's exact memory traffic (the steps'
+    neighbour, gather and store code without the arithmetic; walls as in the
+    duct, y and z, and in the coupled workload, y).  XCD chunks of 2,
+    streaming loads and stores; each with no cap on the waves per SIMD and
     with the steps' cap of 5.  Median of `reps` launches, each between two HIP
     events on the current stream; the best of the two caps is the ceiling."""
     import torch
 
     import paper_0809_4730_amd as pkg
+    nodes = shape[0] * shape[1] * shape[2]
     src = torch.ones(40 * nodes, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     out = {"nodes": nodes}
-    for pattern, key in ((0, "stream_copy"), (1, "step_pattern_copy"),
-                         (2, "coupled_pattern_copy")):
+    for pattern, key, walls in ((0, "stream_copy", ()), (1, "step_pattern_copy", ()),
+                                (2, "coupled_pattern_copy", ()),
+                                (3, "step_exact_copy", (False, True, True)),
+                                (4, "coupled_exact_copy", (False, True, False))):
         best = None
         for waves in (8, 5):
             ts = []
             for _ in range(reps + 2):
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record()
-                nbytes = pkg.bandwidth_probe(pattern, src, dst, nodes, waves=waves)
+                nbytes = pkg.bandwidth_probe(pattern, src, dst, shape, walls=walls, waves=waves)
                 e1.record()
                 e1.synchronize()
                 ts.append(e0.elapsed_time(e1) * 1e3)
@@ -1186,6 +1192,8 @@ def main():
             head["achieved_GBs"] / ceil["step_pattern_copy"]["GBs"], 4)
         line["roofline"]["frac_of_stream_copy"] = round(
             head["achieved_GBs"] / ceil["stream_copy"]["GBs"], 4)
+        line["roofline"]["frac_of_exact_pattern_copy"] = round(
+            head["achieved_GBs"] / ceil["step_exact_copy"]["GBs"], 4)
         per = []
         for st in [x for x in ("bf16", "f16", "f64") if x != storage]:
             print("storage %s" % st, file=sys.stderr, flush=True)
@@ -1199,6 +1207,8 @@ def main():
         mhd = mhd256_line(args.steps, args.warmup)
         mhd["frac_of_coupled_pattern_copy"] = round(
             mhd["achieved_GBs"] / ceil["coupled_pattern_copy"]["GBs"], 4)
+        mhd["frac_of_exact_pattern_copy"] = round(
+            mhd["achieved_GBs"] / ceil["coupled_exact_copy"]["GBs"], 4)
         line["mhd256_f32"] = mhd
         if not args.no_ttr:
             print("time to residual", file=sys.stderr, flush=True)

@@ -445,23 +445,38 @@ lbm_status lbm_batch_run(const lbm_grid* grid, int32_t storage, double rho0, int
                          lbm_member_result* results);
 
 /* ---------------------------------------------------------- calibration --
- * The bandwidth the HBM delivers for two copies of FP32 data, timed by the
- * caller around the launch (the step kernels' roofline fractions are read
- * against these as well as against the nominal peak).  src and dst are
- * device buffers of at least 22 * nodes (pattern 2: 40 * nodes) FP32 values
- * each, 16-byte aligned.
+ * The bandwidth the HBM delivers for copies of FP32 data, timed by the caller
+ * around the launch (the step kernels' roofline fractions are read against
+ * these as well as against the nominal peak).  The lattice is nx * ny * nz
+ * nodes (x fastest); src and dst are device buffers of at least 22 * nodes
+ * (patterns 2 and 4: 40 * nodes) FP32 values each, 16-byte aligned, planes of
+ * `nodes` values.
  * pattern 0: 22 * nodes values copied as 16-byte vectors, one per thread,
  *            streaming loads and stores (moves 2 * 88 * nodes bytes);
- * pattern 1: the flow step's pattern without its arithmetic: at each node 22
- *            planes of stride `nodes` read and 19 written, one value per plane
+ * pattern 1: at each node 22 planes read and 19 written, one value per plane
  *            and thread, streaming loads and stores, workgroups dealt to the
  *            XCDs in chunks of xcd_chunk (moves 164 * nodes bytes);
- * pattern 2: the same with 40 planes read and 40 written, the coupled step's
- *            pattern (moves 320 * nodes bytes).
+ * pattern 2: the same with 40 planes read and 40 written (320 * nodes bytes);
+ * pattern 3: the row-aligned FP32 flow step's exact memory traffic without its
+ *            arithmetic (Sec. 2 eq. streaming): planes 0-18 are the D3Q19
+ *            populations in the library's direction order
+ *            (lbm_lattice_velocities), each read at the upstream node with
+ *            periodic wrap, or in the opposite direction's plane at the node
+ *            itself where the link crosses a wall (walls: bit 0 x, bit 1 y,
+ *            bit 2 z); planes 19-21 (the force field) read at the node; dst
+ *            planes 0-18 receive the gathered values, plane 0 plus 0 times the
+ *            sum of the force planes (164 * nodes bytes);
+ * pattern 4: the coupled step's (Sec. 4): planes 0-18 as in pattern 3, planes
+ *            19-39 the D3Q7 populations (component-major, 7 directions per
+ *            component) gathered the same way from the D3Q7 directions, all 40
+ *            written (320 * nodes bytes); the sign of anti-bounce-back, being
+ *            arithmetic, is left out.
+ * Patterns 3 and 4 need nx a multiple of 64 and 21 * nodes * 4 < 2^32.
  * waves: at most this many waves per SIMD (3..7, as lbm_launch.waves), or 8
  * for no cap.  Enqueued on hip_stream.  Errors: LBM_EINVAL, LBM_EHIP. */
-lbm_status lbm_bandwidth_probe(int32_t pattern, const void* src, void* dst, int64_t nodes,
-                               int32_t xcd_chunk, int32_t waves, void* hip_stream);
+lbm_status lbm_bandwidth_probe(int32_t pattern, const void* src, void* dst, int32_t nx, int32_t ny,
+                               int32_t nz, int32_t walls, int32_t xcd_chunk, int32_t waves,
+                               void* hip_stream);
 
 #ifdef __cplusplus
 }

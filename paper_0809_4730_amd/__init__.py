@@ -135,7 +135,8 @@ def load_library():
                           c_void_p, c_double, c_int64, c_int32, c_int64, P(_Launch),
                           P(_MemberResult)],
         "lbm_lattice_velocities": [c_int32, P(c_int32)],
-        "lbm_bandwidth_probe": [c_int32, c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p],
+        "lbm_bandwidth_probe": [c_int32, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32,
+                                c_int32, c_int32, c_void_p],
         "lbm_workspace_bytes": [P(_Grid), P(_Params), P(c_size_t)],
         "lbm_create": [P(_Grid), P(_Params), c_void_p, c_void_p, c_size_t, c_void_p, P(c_void_p)],
         "lbm_set_force": [c_void_p, c_void_p],
@@ -202,22 +203,28 @@ def lattice_velocities(q=19):
     return np.array(list(out), dtype=np.int64).reshape(q, 3)
 
 
-def bandwidth_probe(pattern, src, dst, nodes, xcd_chunk=2, waves=8, stream=None):
+def bandwidth_probe(pattern, src, dst, shape, walls=(False, False, False), xcd_chunk=2, waves=8,
+                    stream=None):
     """Enqueue one calibration copy (lbm_bandwidth_probe) between two float32
-    device tensors of at least 22 * nodes (pattern 2: 40 * nodes) elements on
-    `stream` (default: the current stream).  Returns the bytes it moves."""
+    device tensors of at least 22 * nodes (patterns 2 and 4: 40 * nodes)
+    elements on `stream` (default: the current stream).  shape: (nx, ny, nz),
+    or a node count (a 1 x 1 lattice row) for patterns 0-2; walls: per axis,
+    for patterns 3 and 4.  Returns the bytes it moves."""
     torch = _torch()
     lib = load_library()
-    planes = 40 if pattern == 2 else 22
+    nx, ny, nz = (int(shape), 1, 1) if np.ndim(shape) == 0 else (int(v) for v in shape)
+    nodes = nx * ny * nz
+    planes = 40 if pattern in (2, 4) else 22
     if src.numel() < planes * nodes or dst.numel() < planes * nodes \
             or src.dtype != torch.float32 or dst.dtype != torch.float32:
         raise ValueError("src and dst must be float32 tensors of at least %d * nodes elements"
                          % planes)
+    mask = sum(1 << i for i, w in enumerate(walls) if w)
     if stream is None:
         stream = torch.cuda.current_stream(src.device)
-    _check(lib.lbm_bandwidth_probe(int(pattern), src.data_ptr(), dst.data_ptr(), int(nodes),
+    _check(lib.lbm_bandwidth_probe(int(pattern), src.data_ptr(), dst.data_ptr(), nx, ny, nz, mask,
                                    int(xcd_chunk), int(waves), stream.cuda_stream))
-    return {0: 2 * 88 * nodes, 1: 164 * nodes, 2: 320 * nodes}[int(pattern)]
+    return {0: 2 * 88, 1: 164, 2: 320, 3: 164, 4: 320}[int(pattern)] * nodes
 
 
 VERDICTS = {0: "undecided", 1: "converged", 2: "unstable"}

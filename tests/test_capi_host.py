@@ -281,6 +281,27 @@ def test_batch_workspace_and_validation(lib):
     assert st == -2  # no workspace: rejected before any device call
 
 
+@pytest.mark.parametrize("args,msg", [
+    ((5, 16, 32, 64, 4, 4, 0, 2, 8), b"pattern"),
+    ((1, 0, 32, 64, 4, 4, 0, 2, 8), b"non-null"),
+    ((1, 16, 32, 0, 4, 4, 0, 2, 8), b"nx, ny, nz"),
+    ((1, 16, 32, 1 << 12, 1 << 12, 1 << 8, 0, 2, 8), b"nodes"),
+    ((1, 20, 32, 64, 4, 4, 0, 2, 8), b"aligned"),
+    ((1, 16, 32, 64, 4, 4, 0, 2, 2), b"waves"),
+    ((3, 16, 32, 64, 4, 4, 8, 2, 8), b"walls"),
+    ((1, 16, 32, 64, 4, 4, 0, 0, 8), b"xcd_chunk"),
+    ((3, 16, 32, 96, 4, 4, 0, 2, 8), b"multiple of 64"),
+    ((4, 16, 32, 1024, 1024, 64, 0, 2, 8), b"2^32"),
+])
+def test_bandwidth_probe_validation(lib, args, msg):
+    """Every rejected argument is caught before a launch (the pointers here
+    are never dereferenced)."""
+    pattern, src, dst, nx, ny, nz, walls, chunk, waves = args
+    st = lib.lbm_bandwidth_probe(pattern, ctypes.c_void_p(src), ctypes.c_void_p(dst), nx, ny, nz,
+                                 walls, chunk, waves, None)
+    assert st == -1 and msg in lib.lbm_last_error(None), lib.lbm_last_error(None)
+
+
 def test_ctypes_mirrors_match_the_c_header(tmp_path):
     """The binding's ctypes structures have the size and field offsets the C
     header gives them (compiled here as C99 by gcc)."""

@@ -309,8 +309,8 @@ def test_binding_on_a_side_stream_matches_the_current_stream():
 
 def test_bandwidth_probe_copies_exactly():
     """The calibration copies move the data they claim: the 16-byte copy
-    reproduces 22 planes, the step-pattern copy the first 19 of 22 planes, on a
-    ragged node count."""
+    reproduces 22 planes, the plane-pattern copies the first 19 of 22 planes
+    and all 40, on a ragged node count."""
     import torch
 
     import paper_0809_4730_amd as pkg
@@ -324,6 +324,62 @@ def test_bandwidth_probe_copies_exactly():
         assert torch.equal(dst[:planes * nodes], src[:planes * nodes])
         assert bool((dst[planes * nodes:] == -1.0).all())
         assert nbytes == {0: 2 * 88 * nodes, 1: 164 * nodes, 2: 320 * nodes}[pattern]
+
+
+def _pulled(planes, vel, shape, walls):
+    """Expected gather of one set of direction planes (q, nz, ny, nx): each
+    direction from its upstream node with periodic wrap, or from the opposite
+    direction at the node itself where the link crosses a wall."""
+    nx, ny, nz = shape
+    q = len(vel)
+    opp = [next(b for b in range(q) if all(vel[b] == -vel[a])) for a in range(q)]
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    out = np.empty_like(planes)
+    for a in range(q):
+        ex, ey, ez = vel[a]
+        sx, sy, sz = x - ex, y - ey, z - ez
+        bounce = np.zeros(x.shape, dtype=bool)
+        for w, c, n in ((walls[0], sx, nx), (walls[1], sy, ny), (walls[2], sz, nz)):
+            if w:
+                bounce |= (c < 0) | (c >= n)
+        shifted = planes[a][sz % nz, sy % ny, sx % nx]
+        out[a] = np.where(bounce, planes[opp[a]], shifted)
+    return out
+
+
+@pytest.mark.parametrize("shape,walls", [((64, 6, 5), (False, True, True)),
+                                         ((128, 3, 4), (True, True, False)),
+                                         ((64, 1, 7), (False, False, True))])
+def test_bandwidth_probe_step_patterns_gather_as_the_steps(shape, walls):
+    """The exact-pattern copies read every population where the step reads it
+    (Sec. 2 eq. streaming, the D3Q7 lattice of Sec. 4): compared value by value
+    with a gather computed here from the lattice velocity tables alone."""
+    import torch
+
+    import paper_0809_4730_amd as pkg
+    announce("bandwidth probe step patterns %s walls %s" % (shape, walls))
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    v19 = pkg.lattice_velocities(19)
+    v7 = pkg.lattice_velocities(7)
+    host = (np.arange(40 * N, dtype=np.float32) * 0.25 + 1.0).reshape(40, nz, ny, nx)
+    src = torch.tensor(host.reshape(-1), device="cuda")
+    want_f = _pulled(host[:19], v19, shape, walls)
+    want_g = np.concatenate([_pulled(host[19 + 7 * j:26 + 7 * j], v7, shape, walls)
+                             for j in range(3)])
+    for pattern in (3, 4):
+        for waves in (8, 5):
+            dst = torch.full_like(src, -1.0)
+            nbytes = pkg.bandwidth_probe(pattern, src, dst, shape, walls=walls, waves=waves)
+            torch.cuda.synchronize()
+            got = dst.cpu().numpy().reshape(40, nz, ny, nx)
+            assert np.array_equal(got[:19], want_f)
+            if pattern == 3:
+                assert (got[19:] == -1.0).all()
+                assert nbytes == 164 * N
+            else:
+                assert np.array_equal(got[19:], want_g)
+                assert nbytes == 320 * N
 
 
 def test_history_records_of_a_large_lattice_equal_direct_sums():
