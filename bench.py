@@ -1015,6 +1015,81 @@ def ladder_128():
     ], 100, "square duct 128^3, nu = 0.131, C1 force; residual 1e-8")
 
 
+def oracle_time_to_steady(budget_s=900.0):
+    """The FP64 oracle (numpy, on the host) marched to R < 1e-8 where that is
+    tractable: the 64^3 duct (nu = 0.131, its force) at gamma = 0.1, 0.05 and
+    1, and the coupled Hartmann channel 32 x 32 x 128 (Ha = 10, Pm = 0.01,
+    gamma = gamma_m = 0.1), each beside the FP64 GPU march of the same case,
+    whose crossing step it must equal (both check the residual every 10 steps).
+    The oracle's time for a case is estimated from three timed steps and the
+    GPU's step count; a case that would not fit in what is left of budget_s is
+    skipped and says so.  Progress goes to stderr every 500 steps."""
+    import numpy as np
+
+    import paper_0809_4730_amd as pkg
+    from oracle import glbe, mhd
+    from paper_0809_4730_amd import inputs
+    tol = 1e-8
+    d = inputs.DUCT64
+    h = inputs.HARTMANN
+    B0, chi = inputs.hartmann_parameters(10.0, 0.01, h["shape"][1], h["nu"], h["eta"])
+    mag = dict(gamma_m=0.1, chi=chi, eta=h["eta"], B0=(0.0, B0, 0.0))
+
+    def duct(g):
+        F = inputs.duct_force(d["shape"], d["F0"])
+        return ("64^3 duct, gamma %g" % g,
+                lambda: make_sim(d["shape"], "f64", g, nu=d["nu"], F0=d["F0"], bc=d["bc"]),
+                lambda: glbe.Flow(d["shape"], d["bc"], F, g, glbe.rates(d["nu"], g)),
+                d["shape"])
+
+    def hartmann():
+        g = 0.1
+        return ("Hartmann 32x32x128, Ha 10, Pm 0.01, gamma = gamma_m = 0.1",
+                lambda: pkg.Simulation(h["shape"], h["bc"], g, pkg.default_rates(h["nu"], g),
+                                       storage="f64", force=h["F"], mhd=mag),
+                lambda: mhd.MHDFlow(h["shape"], h["bc"], np.array(h["F"]), g,
+                                    glbe.rates(h["nu"], g), mag["gamma_m"], chi, h["eta"],
+                                    mag["B0"]),
+                h["shape"])
+
+    t_start = time.perf_counter()
+    cases = []
+    for name, gpu, cpu, shape in (duct(0.1), duct(0.05), hartmann(), duct(1.0)):
+        nodes = shape[0] * shape[1] * shape[2]
+        ge = time_to_residual(None, "f64", None, tol, 400000, make=gpu)
+        e = {"case": name, "gpu_steps": ge["steps"], "gpu_wall_s": ge["wall_s"]}
+        fl = cpu()
+        t0 = time.perf_counter()
+        fl.step(3, check_every=10 ** 9)
+        t_step = (time.perf_counter() - t0) / 3
+        fl = cpu()
+        est = t_step * ge["steps"]
+        left = budget_s - (time.perf_counter() - t_start)
+        e["oracle_s_per_step"] = round(t_step, 4)
+        e["oracle_MLUPS"] = round(nodes / t_step / 1e6, 3)
+        if ge["steps"] <= 0 or est > left:
+            e["oracle"] = "skipped: estimated %.0f s, %.0f s of the budget left" % (est, left)
+            cases.append(e)
+            print(json.dumps(e), file=sys.stderr, flush=True)
+            continue
+        t0 = time.perf_counter()
+        reached = False
+        while not reached and fl.t < 400000:
+            reached = fl.run_to(tol, fl.t + 500)
+            print("%s: oracle step %d, R %.3e" % (name, fl.t, fl.history[-1][1] if fl.history
+                                                  else float("nan")), file=sys.stderr, flush=True)
+        e["oracle_steps"] = fl.t if reached else -1
+        e["oracle_wall_s"] = round(time.perf_counter() - t0, 2)
+        e["steps_equal"] = e["oracle_steps"] == ge["steps"]
+        e["gpu_speedup_wall"] = round(e["oracle_wall_s"] / ge["wall_s"], 1)
+        cases.append(e)
+        print(json.dumps(e), file=sys.stderr, flush=True)
+    from threadpoolctl import threadpool_info
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return {"probe": "oracle_steady", "tol": tol, "os_cpu_count": os.cpu_count(),
+            "blas_threads": int(threads), "cases": cases}
+
+
 def kernel_probe(name, launches, copy_probe, launch=None):
     """One JSON line for the profilers: `launches` plain launches of one
     kernel at its HBM-scale size (coupled step 256^3 FP32, steady adjoint
@@ -1054,6 +1129,9 @@ def kernel_probe(name, launches, copy_probe, launch=None):
         kernel = "glbe2_step<float, check=false> (4096^2)"
     elif name == "hbm_ceiling":
         print(json.dumps({"probe": name, **hbm_ceiling(reps=launches)}), flush=True)
+        return
+    elif name == "oracle_steady":
+        print(json.dumps(oracle_time_to_steady()), flush=True)
         return
     elif name == "precision256":
         precision_steady_256()
@@ -1102,7 +1180,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--probe", choices=["mhd256", "adjoint128", "d2q9_4096", "precision256",
-                                        "ladder256", "ladder128", "hbm_ceiling"],
+                                        "ladder256", "ladder128", "hbm_ceiling", "oracle_steady"],
                     help="only one other measurement: another kernel at HBM scale (for the "
                          "profilers), or the 256^3 precision form at steady state")
     ap.add_argument("--launches", type=int, default=30)
