@@ -233,8 +233,9 @@ def hbm_ceiling(shape=(256, 256, 256), reps=10):
     neighbour, gather and store code without the arithmetic; walls as in the
     duct, y and z, and in the coupled workload, y).  XCD chunks of 2,
     streaming loads and stores; each with no cap on the waves per SIMD and
-    with the steps' cap of 5.  Median of `reps` launches, each between two HIP
-    events on the current stream; the best of the two caps is the ceiling."""
+    with the steps' caps of 5 and 3.  Median of `reps` launches, each between
+    two HIP events on the current stream; the best of the caps is the
+    ceiling."""
     import torch
 
     import paper_0809_4730_amd as pkg
@@ -247,7 +248,7 @@ def hbm_ceiling(shape=(256, 256, 256), reps=10):
                                 (3, "step_exact_copy", (False, True, True)),
                                 (4, "coupled_exact_copy", (False, True, False))):
         best = None
-        for waves in (8, 5):
+        for waves in (8, 5, 3):
             ts = []
             for _ in range(reps + 2):
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -234,8 +234,9 @@ lbm_status lbm_workspace_bytes(const lbm_grid* grid, const lbm_params* params, s
  * whose two population buffers fit the 256 MB last-level cache get one
  * contiguous slab per XCD and cacheable stores; up to 512 MB, slabs and
  * streaming stores; above that (lattices that stream from HBM) streaming
- * stores (and, for D3Q19, streaming loads and a cap of 5 waves per SIMD for
- * FP32 storage and for the coupled step, 6 for 16-bit storage, none for FP64),
+ * stores (and, for D3Q19, streaming loads and a cap on the waves per SIMD: 5
+ * for FP32 storage, 6 for 16-bit storage, 3 for FP64 storage and for the
+ * coupled step),
  * and lbm_create times a few dozen plain steps on the stream for each
  * of three XCD workgroup mappings (chunks of 2 and 8 workgroups, slabs), keeps
  * the fastest and restores the rest state; it then synchronizes (a few ms to

@@ -252,12 +252,13 @@ void choose_launch_shape(lbm_ctx* c) {
   // 2% slower for the D2Q9 step at 4096^2
   c->ga.nt_load = pop_bytes > 2.0 * kMallBytes && c->p.lattice != LBM_D2Q9;
   if (l.load != 0) c->ga.nt_load = l.load == 2;
-  // waves per SIMD: fewer waves in flight stream faster from HBM for the FP32
-  // steps (measured at 256^3: FP32 flow 466 -> 446 us at 5 waves, coupled
-  // 987 -> 973 us) and 16-bit storage at 6 (254 -> 249 us); FP64 already runs 4
+  // waves per SIMD: fewer waves in flight stream faster from HBM (measured at
+  // 256^3: FP32 flow 466 -> 446 us at 5 waves, 16-bit storage 254 -> 249 us at
+  // 6; the FP64 flow step, 4 waves by its registers, 963 -> 933 us at 3, and
+  // the coupled step, 5 by its registers, 967 -> 949 us at 3)
   c->waves = 8;
-  if (pop_bytes > 2.0 * kMallBytes && c->p.lattice != LBM_D2Q9 && c->p.storage != LBM_F64)
-    c->waves = (c->p.storage == LBM_F32 || c->p.mhd) ? 5 : 6;
+  if (pop_bytes > 2.0 * kMallBytes && c->p.lattice != LBM_D2Q9)
+    c->waves = (c->p.storage == LBM_F64 || c->p.mhd) ? 3 : c->p.storage == LBM_F32 ? 5 : 6;
   if (l.waves != 0) c->waves = l.waves;
   c->ga.lds_reserve = 0;
   if (c->waves < 8) {
