@@ -101,9 +101,9 @@ typedef struct {
                          (non-temporal) loads of the populations and the force
                          field, D3Q19 steps with streaming stores only */
   int32_t waves;      /* 0: library's choice; 3..7: at most this many waves per
-                         SIMD run the D3Q19 step kernels (each workgroup
-                         reserves an unused share of the compute unit's LDS);
-                         8: no cap beyond the kernels' own register use */
+                         SIMD run the step kernels (each workgroup reserves an
+                         unused share of the compute unit's LDS); 8: no cap
+                         beyond the kernels' own register use */
 } lbm_launch;
 
 typedef struct {
@@ -234,9 +234,10 @@ lbm_status lbm_workspace_bytes(const lbm_grid* grid, const lbm_params* params, s
  * whose two population buffers fit the 256 MB last-level cache get one
  * contiguous slab per XCD and cacheable stores; up to 512 MB, slabs and
  * streaming stores; above that (lattices that stream from HBM) streaming
- * stores (and, for D3Q19, streaming loads and a cap on the waves per SIMD: 5
- * for FP32 storage, 6 for 16-bit storage, 3 for FP64 storage and for the
- * coupled step),
+ * stores, a cap on the waves per SIMD (D3Q19: 5 for FP32 storage, 6 for
+ * 16-bit storage, 3 for FP64 storage and for the coupled step; D2Q9: 6 for
+ * FP32, 4 for FP64, 5 for the coupled FP32 step, none otherwise) and, for
+ * D3Q19, streaming loads,
  * and lbm_create times a few dozen plain steps on the stream for each
  * of three XCD workgroup mappings (chunks of 2 and 8 workgroups, slabs), keeps
  * the fastest and restores the rest state; it then synchronizes (a few ms to

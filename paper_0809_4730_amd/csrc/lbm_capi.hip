@@ -255,10 +255,18 @@ void choose_launch_shape(lbm_ctx* c) {
   // waves per SIMD: fewer waves in flight stream faster from HBM (measured at
   // 256^3: FP32 flow 466 -> 446 us at 5 waves, 16-bit storage 254 -> 249 us at
   // 6; the FP64 flow step, 4 waves by its registers, 963 -> 933 us at 3, and
-  // the coupled step, 5 by its registers, 967 -> 949 us at 3)
+  // the coupled step, 5 by its registers, 967 -> 949 us at 3; D2Q9 at 4096^2:
+  // FP32 207 -> 200 us at 6, FP64 456 -> 423 us at 4, the coupled D2Q9 + D2Q5
+  // step 454 -> 434 us at 5, while 16-bit storage runs slower under any cap)
   c->waves = 8;
-  if (pop_bytes > 2.0 * kMallBytes && c->p.lattice != LBM_D2Q9)
-    c->waves = (c->p.storage == LBM_F64 || c->p.mhd) ? 3 : c->p.storage == LBM_F32 ? 5 : 6;
+  if (pop_bytes > 2.0 * kMallBytes) {
+    if (c->p.lattice != LBM_D2Q9)
+      c->waves = (c->p.storage == LBM_F64 || c->p.mhd) ? 3 : c->p.storage == LBM_F32 ? 5 : 6;
+    else if (c->p.storage == LBM_F32)
+      c->waves = c->p.mhd ? 5 : 6;
+    else if (c->p.storage == LBM_F64 && !c->p.mhd)
+      c->waves = 4;
+  }
   if (l.waves != 0) c->waves = l.waves;
   c->ga.lds_reserve = 0;
   if (c->waves < 8) {
@@ -601,7 +609,7 @@ lbm_status lbm_get_launch(const lbm_ctx* c, lbm_launch* out) {
   out->xcd_chunk = c->ga.xcd_chunk;
   out->store = c->nt_store ? 2 : 1;
   out->load = (c->nt_store && c->ga.nt_load && c->p.lattice != LBM_D2Q9) ? 2 : 1;
-  out->waves = c->p.lattice == LBM_D2Q9 ? 8 : c->waves;
+  out->waves = c->waves;
   out->offsets = wide_offsets(c->ga, c->celem()) ? 1 : 0;
   return LBM_OK;
 }

@@ -223,3 +223,31 @@ def test_d2q5_hartmann_fp32_closed_form():
     assert fl.run_to(1e-10, 60000)
     assert rel(u, fl.u[0][:, 0]) < 1e-4 and rel(b, fl.B[0][:, 0]) < 1e-3
     assert eu < 0.03 and eb < 0.025
+
+
+@pytest.mark.parametrize("storage,mhd", [("f32", False), ("f64", False), ("bf16", False),
+                                         ("f32", True)])
+def test_wave_caps_and_store_forms_bitwise(storage, mhd):
+    """The D2Q9 flow and coupled D2Q9 + D2Q5 steps under caps on the waves per
+    SIMD and with both store forms, residual checks on: bit for bit."""
+    import torch
+
+    import paper_0809_4730_amd as pkg
+    announce("d2q9 wave caps %s mhd=%s" % (storage, mhd))
+    nx, ny = 96, 37
+    gamma = 0.3
+    kw = dict(mhd=dict(gamma_m=0.4, chi=0.05, eta=0.03, B0=(0.01, 0.02))) if mhd else {}
+    out = []
+    for store, waves in (("cached", 8), ("streaming", 8), ("streaming", 6), ("cached", 4),
+                         ("streaming", 3)):
+        sim = pkg.Simulation((nx, ny, 1), (PER, WALL, PER), gamma, d.rates(0.05, gamma),
+                             storage=storage, force=(1e-5, -2e-6), lattice="d2q9",
+                             launch=dict(store=store, waves=waves), **kw)
+        assert sim.launch["waves"] == waves
+        sim.step(41)
+        st = sim.get_state()
+        out.append((st if torch.is_tensor(st) else torch.cat([st[0].reshape(-1), st[1].reshape(-1)]),
+                    sim.history(8)))
+    for a, b in zip(out[1:], out[:-1]):
+        assert torch.equal(a[0], b[0])
+        assert np.array_equal(a[1], b[1])
