@@ -159,15 +159,6 @@ def velocity_source(F, u):
     return w * (3.0 * (eF - uF) + 9.0 * eu * eF)
 
 
-def velocity_equilibrium(rho, u):
-    """f^eq = w rho [1 + 3 e.u + 9/2 (e.u)^2 - 3/2 u.u] (Sec. 2), D2Q9."""
-    e = E9.astype(float)
-    eu = np.tensordot(e, u, axes=(1, 0))
-    uu = (u * u).sum(axis=0)
-    w = W9.reshape((Q9,) + (1,) * np.ndim(rho))
-    return w * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu)
-
-
 # ------------------------------------------------------------- collision ---
 def collide(d, F, gamma, s, rho0=1.0):
     """One preconditioned D2Q9 collision with forcing (Sec. 3, eq. prelax_term):

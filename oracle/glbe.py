@@ -253,11 +253,6 @@ def flow_rate(post, F, gamma, bc, rho0=1.0):
     return j[0].sum() / post.shape[3]
 
 
-def mass_drift(post, bc):
-    """sum over nodes of rho - rho0, from the streamed populations."""
-    return stream(post, bc).sum()
-
-
 def residual(u_now, u_prev):
     """Relative L2 residual ||u(t) - u(t-10)||_2 / ||u(t)||_2 over all nodes and
     components (Sec. 5 defines the unnormalised norm; reading: relative, FP64)."""
