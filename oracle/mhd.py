@@ -165,6 +165,53 @@ def step(post_f, post_g, F_ext, p, bc, wall_u=None, pad=(0, 0, 0)):
     return new_f, new_g, u, B
 
 
+def wall_g(opp_value, a, jc, B_wall):
+    """Anti-bounce-back of direction a, component jc, at an insulating wall
+    (B = B_wall there, Sec. 4): g_a = -g~_opp(a) + 2 W_a B_wall."""
+    return -opp_value + 2.0 * W7[a] * B_wall[jc]
+
+
+def step_nodes(post_f, post_g, F_ext, p, bc, nodes):
+    """One coupled step evaluated only at the given nodes (for large-lattice
+    parity), for a lattice without an extended induction layer or moving
+    walls: at each node the pulled flow populations (Sec. 2 eq. streaming,
+    halfway bounce-back), the pulled induction populations (Sec. 4 eq.
+    mstreaming, anti-bounce-back at walls), the self-consistent fields and
+    both collisions.
+
+    nodes: (n, 3) integer array of (x, y, z).  post_f (19, nz, ny, nx),
+    post_g (3, 7, nz, ny, nx) (full g, any float dtype; gathered values are
+    taken to FP64).  Returns ((19, n) post-collision flow deviations,
+    (3, 7, n) post-collision g)."""
+    rho0 = p.get("rho0", 1.0)
+    nodes = np.asarray(nodes)
+    nz, ny, nx = post_f.shape[1:]
+    dims = (nx, ny, nz)
+    n = len(nodes)
+    x, y, z = nodes[:, 0], nodes[:, 1], nodes[:, 2]
+    f = np.empty((glbe.Q19, n))
+    for a in range(glbe.Q19):
+        src, bounce = glbe.upstream(nodes, glbe.E19[a], dims, bc)
+        srcc = np.where(bounce[:, None], nodes, src)
+        f[a] = np.where(bounce, post_f[glbe.OPP19[a], z, y, x],
+                        post_f[a, srcc[:, 2], srcc[:, 1], srcc[:, 0]])
+    g = np.empty((3, Q7, n))
+    for a in range(Q7):
+        src, bounce = glbe.upstream(nodes, E7[a], dims, bc)
+        srcc = np.where(bounce[:, None], nodes, src)
+        for jc in range(3):
+            wall = wall_g(post_g[jc, OPP7[a], z, y, x].astype(np.float64), a, jc, p["B_wall"])
+            g[jc, a] = np.where(bounce, wall, post_g[jc, a, srcc[:, 2], srcc[:, 1], srcc[:, 0]])
+    if np.ndim(F_ext) == 4:
+        Fn = np.asarray(F_ext[:, z, y, x], dtype=np.float64)
+    else:
+        Fn = np.broadcast_to(np.asarray(F_ext, dtype=float).reshape(3, 1), (3, n))
+    rho, u, B, J, F = coupled_fields(f, g, Fn, p["gamma"], p["gamma_m"], p["chi"], p["eta"],
+                                     p.get("mu", 1.0), rho0)
+    return (glbe.collide(f, F, p["gamma"], p["s"], rho0),
+            collide_g(g, B, u, p["chi"], p["gamma_m"], p["eta"]))
+
+
 def initial_g(shape_xyz, B0, dtype=np.float64):
     """Rest state with uniform applied field: g_{a j} = W_a B0_j."""
     nx, ny, nz = shape_xyz

@@ -130,6 +130,60 @@ def test_duct256_bench_kernel_one_step(storage, check):
     torch.cuda.empty_cache()
 
 
+def test_coupled256_bench_kernel_one_step():
+    """The coupled step at 256^3 in the benchmark's launch shape (FP32, walls
+    normal to y and B0: the coupled workload's Hartmann setting Ha = 10,
+    Pm = 0.01, gamma = gamma_m = 0.1; create-time XCD chunk, streaming loads
+    and stores, row-aligned waves, 3 waves per SIMD): one step from a seeded
+    random state against the oracle's coupled step from the same state at
+    4000 sampled nodes, corners included.  Bars as for the FP32 coupled step
+    on the Hartmann lattice: f 2e-6, g 1e-6 relative, g's deviation from
+    W B0 (what FP32 stores) 1e-5."""
+    import torch
+
+    import paper_0809_4730_amd as pkg
+    from oracle import mhd
+    from tests.gpu_util import perms
+    announce("256^3 coupled step, bench launch shape")
+    cfg = inputs.HARTMANN
+    shape = (256, 256, 256)
+    nx, ny, nz = shape
+    B0, chi = inputs.hartmann_parameters(10.0, 0.01, cfg["shape"][1], cfg["nu"], cfg["eta"])
+    B0v = np.array([0.0, B0, 0.0])
+    gamma = 0.1
+    s = glbe.rates(cfg["nu"], gamma)
+    F = np.array(cfg["F"], dtype=np.float32).astype(np.float64)
+    sim = pkg.Simulation(shape, cfg["bc"], gamma, s, storage="f32", force=tuple(F),
+                         mhd=dict(gamma_m=0.1, chi=chi, eta=cfg["eta"], B0=tuple(B0v)))
+    assert sim.launch["waves"] == 3
+    assert sim.launch["store"] == "streaming" and sim.launch["load"] == "streaming"
+    p19, p7 = perms()
+    f0 = inputs.random_deviations(shape, seed=31, amp=1e-3, dtype=np.float32)
+    dev = inputs.random_deviations(shape, seed=32, amp=1e-4, q=21,
+                                   dtype=np.float32).reshape(3, 7, nz, ny, nx)
+    sim.set_state(torch.from_numpy(np.ascontiguousarray(f0[p19])).cuda(),
+                  torch.from_numpy(np.ascontiguousarray(dev[:, p7])).cuda())
+    sim.step(1)
+    fg, gg = sim.get_state()
+    nodes = inputs.random_nodes(shape, 4000, seed=31)
+    idx = torch.tensor(nodes, device="cuda")
+    got_f = fg[:, idx[:, 2], idx[:, 1], idx[:, 0]].double().cpu().numpy()
+    got_g = gg[:, :, idx[:, 2], idx[:, 1], idx[:, 0]].double().cpu().numpy()
+    sim.close()
+    del sim, fg, gg
+    torch.cuda.empty_cache()
+    g0 = mhd.initial_g(shape, B0v)
+    g0 += dev
+    del dev
+    p = dict(gamma=gamma, s=s, gamma_m=0.1, chi=chi, eta=cfg["eta"], B_wall=B0v)
+    ref_f, ref_g = mhd.step_nodes(f0, g0, F, p, cfg["bc"], nodes)
+    del g0, f0
+    rest = mhd.initial_g((len(nodes), 1, 1), B0v)[:, :, 0, 0, :]
+    assert rel(got_f, ref_f[p19]) < STEP_TOL
+    assert rel(got_g + rest[:, p7], ref_g[:, p7]) < 1e-6
+    assert rel(got_g, (ref_g - rest)[:, p7]) < 1e-5
+
+
 @pytest.mark.parametrize("storage", ["f32", "f64", "bf16", "f32_mhd"])
 def test_load_store_forms_bitwise_on_a_row_aligned_lattice(storage):
     """Cacheable and streaming stores, streaming loads with them, and caps on

@@ -1,4 +1,4 @@
-"""Pins of the two oracle routines the full-size GPU parity tests rest on.
+"""Pins of the oracle routines the full-size GPU parity tests rest on.
 
 * ``glbe.step_nodes`` (one step evaluated at chosen nodes, for lattices too
   large for the whole-lattice oracle) must equal ``glbe.step`` -- the
@@ -19,6 +19,8 @@
       Q = ny [F (H^3/6 + H/12) / (2 nu) + H F (16 Lambda - 3) / (24 nu)].
   Planted mistakes (Q of the unstreamed post-collision state; j without the
   half-force F/(2 gamma), which is 6 nu/(gamma H^2) of Q here) must fail it.
+* ``mhd.step_nodes`` (the coupled step at chosen nodes) must equal
+  ``mhd.step`` at every node (below).
 """
 import numpy as np
 import pytest
@@ -138,3 +140,68 @@ def test_flow_rate_pin_catches_a_dropped_half_force(monkeypatch):
     q = glbe.flow_rate(fl.post, fl.F, gamma, fl.bc)
     want = _q_exact(shape, nu, Lam, F)
     assert abs(q - want) > 1e-3 * want
+
+
+# ----------------------------------------------------- coupled sampled nodes --
+# ``mhd.step_nodes`` (the coupled step at chosen nodes, for the full-size
+# coupled parity test) against ``mhd.step`` (numpy.roll streaming of both
+# lattices, Sec. 2 eq. streaming and Sec. 4 eq. mstreaming with
+# anti-bounce-back) at every node; a wrong periodic wrap or a wrong sign of
+# anti-bounce-back planted in it must fail.
+MHD_GRIDS = [
+    ((6, 8, 5), (PER, WALL, PER)),
+    ((5, 7, 9), (WALL, WALL, WALL)),
+    ((33, 3, 4), (PER, WALL, WALL)),
+    ((4, 5, 3), (PER, PER, PER)),
+]
+
+
+def _compare_mhd(shape, bc, seed, uniform=False):
+    from oracle import mhd
+    nx, ny, nz = shape
+    B0 = np.array([0.01, 0.03, -0.02])
+    f0 = inputs.random_deviations(shape, seed=seed, amp=1e-3)
+    g0 = mhd.initial_g(shape, B0) + inputs.random_deviations(
+        shape, seed=seed + 1, amp=1e-4, q=21).reshape(3, 7, nz, ny, nx)
+    F = np.array([1e-5, 2e-6, -3e-6]) if uniform else inputs.random_force(shape, seed, amp=1e-4)
+    Ff = inputs.uniform_force(shape, F) if uniform else F
+    p = dict(gamma=0.2, s=glbe.rates(0.05, 0.2), gamma_m=0.3, chi=0.05, eta=0.02, B_wall=B0)
+    fo, go, _, _ = mhd.step(f0, g0, Ff, p, bc)
+    nodes = _all_nodes(shape)
+    gf, gg = mhd.step_nodes(f0, g0, F, p, bc, nodes)
+    wf = fo[:, nodes[:, 2], nodes[:, 1], nodes[:, 0]]
+    wg = go[:, :, nodes[:, 2], nodes[:, 1], nodes[:, 0]]
+    rest = mhd.initial_g(shape, B0)[:, :, nodes[:, 2], nodes[:, 1], nodes[:, 0]]
+    ef = float(np.max(np.abs(gf - wf)) / np.max(np.abs(wf)))
+    eg = float(np.max(np.abs(gg - wg)) / np.max(np.abs(wg - rest)))
+    return max(ef, eg)
+
+
+@pytest.mark.parametrize("shape,bc", MHD_GRIDS)
+@pytest.mark.parametrize("uniform", [False, True])
+def test_mhd_step_nodes_equals_step_at_every_node(shape, bc, uniform):
+    assert _compare_mhd(shape, bc, seed=5, uniform=uniform) < 1e-13
+
+
+def test_mhd_step_nodes_pin_catches_a_wrong_wrap(monkeypatch):
+    """Planted in the oracle: the periodic wrap clamps instead of wrapping."""
+    def clamped(nodes, e, dims, bc):
+        src = nodes - np.asarray(e)[None, :]
+        bounce = np.zeros(len(nodes), dtype=bool)
+        for c in range(3):
+            if bc[c] == WALL:
+                bounce |= (src[:, c] < 0) | (src[:, c] >= dims[c])
+            else:
+                src[:, c] = np.clip(src[:, c], 0, dims[c] - 1)
+        return src, bounce
+
+    monkeypatch.setattr(glbe, "upstream", clamped)
+    assert _compare_mhd((6, 8, 5), (PER, WALL, PER), seed=5) > 1e-3
+
+
+def test_mhd_step_nodes_pin_catches_a_wrong_wall_sign(monkeypatch):
+    """Planted in the oracle: anti-bounce-back with the wrong sign."""
+    from oracle import mhd
+    from oracle.lattice import W7
+    monkeypatch.setattr(mhd, "wall_g", lambda v, a, jc, Bw: v + 2.0 * W7[a] * Bw[jc])
+    assert _compare_mhd((6, 8, 5), (PER, WALL, PER), seed=5) > 1e-3
