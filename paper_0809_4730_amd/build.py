@@ -34,24 +34,25 @@ def hipcc():
     return path
 
 
-def _compile(src, defines=(), build_dir=BUILD):
+def _compile(src, defines=(), build_dir=BUILD, extra=()):
     obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc()] + FLAGS + ["-D" + d for d in defines] + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc()] + FLAGS + list(extra) + ["-D" + d for d in defines] + \
+        ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr))
     return obj
 
 
-def build(verbose=False, defines=(), out=None):
+def build(verbose=False, defines=(), out=None, extra_flags=()):
     """Compile every HIP source for gfx950 and link liblbm.so next to this file
-    (or to ``out``, with extra preprocessor ``defines`` such as the tuning
-    knobs in csrc/common.hpp)."""
+    (or to ``out``, with extra preprocessor ``defines`` such as LBM_BLOCK in
+    csrc/common.hpp, and extra compiler flags, e.g. host-only sanitizers)."""
     out = out or LIB
     build_dir = BUILD if out == LIB else out + ".objs"
     os.makedirs(build_dir, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, defines, build_dir), SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, defines, build_dir, extra_flags), SOURCES))
     tmp = out + ".tmp"
     cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
