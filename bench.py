@@ -9,7 +9,7 @@ over all 16.8 M nodes.  Inputs (state, force field) are resident in HBM
 before the timed region; nothing crosses PCIe inside it.
 
 Prints ONE JSON line: MLUPS of the timed steps; the roofline of the plain
-step kernel from HIP events around every launch on the library's stream
+step kernel from HIP events attached to every launch on the library's stream
 (algorithmic bytes per launch / mean launch duration); the same for BF16,
 FP16 and FP64 storage at 256^3 and for the cache-resident 64^3 duct; wall
 time to a residual of 1e-8 for gamma < 1 against plain FP64 gamma = 1
@@ -1245,8 +1245,9 @@ def main():
                                        "current kernel sources (kernel_hash), else null",
                      "kernel": "glbe_step<%s, check=false, field=true%s>"
                                % (storage, ", stochastic" if kw.get("rounding") else ""),
-                     "timing": "HIP events around each of the %d plain launches of the timed "
-                               "steps, on the library's stream" % head["launches_timed"],
+                     "timing": "HIP events attached to each of the %d plain launches of the "
+                               "timed steps (hipExtLaunchKernel), on the library's stream"
+                               % head["launches_timed"],
                      "alg_bytes_per_node": head["alg_bytes_per_node"],
                      "alg_bytes_per_launch": head["alg_bytes_per_launch"],
                      "mean_kernel_us": head["kernel_us"],

@@ -270,10 +270,11 @@ lbm_status lbm_set_force(lbm_ctx* ctx, const void* force);
  * does not synchronize and does not report instability (see lbm_residual). */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
 
-/* Like lbm_step, but brackets every step kernel with HIP events on the stream,
- * synchronizes, and returns the mean kernel duration in microseconds (events
- * measure the kernel alone, not launch gaps) and the wall time of the whole
- * call in milliseconds. */
+/* Like lbm_step, but times every step kernel with a pair of HIP events
+ * attached to its own dispatch on the stream (hipExtLaunchKernel: no marker
+ * packets between the steps), synchronizes, and returns the mean kernel
+ * duration in microseconds (the kernel alone, not launch gaps) and the wall
+ * time of the whole call in milliseconds. */
 lbm_status lbm_step_timed(lbm_ctx* ctx, int64_t n, double* mean_kernel_us, double* wall_ms);
 
 /* Like lbm_step_timed, but writes every step's kernel duration in

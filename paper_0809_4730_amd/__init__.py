@@ -449,8 +449,8 @@ class Simulation:
         return us.value, ms.value
 
     def step_times(self, n):
-        """n steps with HIP events around every step kernel on the library's
-        stream (lbm_step_times): (numpy array of n kernel durations in us,
+        """n steps with HIP events attached to every step kernel's launch on the
+        library's stream (lbm_step_times): (numpy array of n kernel durations in us,
         wall time of the call in ms).  Step i of the call is step self.t + i + 1."""
         buf = (ctypes.c_double * int(n))()
         ms = ctypes.c_double()

@@ -476,17 +476,17 @@ hipError_t launch_glbe_step(const GridArgs& g, const CollideArgs<typename Storag
                            w = decltype(W)::value, rw = decltype(RW)::value,
                            sr = decltype(SRF)::value && sizeof(S) == 2;
             if (c.moving)
-              glbe_step<S, ch, fl, false, false, true, w, rw, sr>
-                  <<<step_grid(g), kBlock, g.lds_reserve, st>>>(g, c, a, b, F, usnap, partials);
+              launch_step(glbe_step<S, ch, fl, false, false, true, w, rw, sr>, step_grid(g), g.lds_reserve, st,
+                        g, c, a, b, F, usnap, partials);
             else if (ntl)
-              glbe_step<S, ch, fl, true, true, false, w, rw, sr>
-                  <<<step_grid(g), kBlock, g.lds_reserve, st>>>(g, c, a, b, F, usnap, partials);
+              launch_step(glbe_step<S, ch, fl, true, true, false, w, rw, sr>, step_grid(g), g.lds_reserve, st,
+                        g, c, a, b, F, usnap, partials);
             else if (nt)
-              glbe_step<S, ch, fl, true, false, false, w, rw, sr>
-                  <<<step_grid(g), kBlock, g.lds_reserve, st>>>(g, c, a, b, F, usnap, partials);
+              launch_step(glbe_step<S, ch, fl, true, false, false, w, rw, sr>, step_grid(g), g.lds_reserve, st,
+                        g, c, a, b, F, usnap, partials);
             else
-              glbe_step<S, ch, fl, false, false, false, w, rw, sr>
-                  <<<step_grid(g), kBlock, g.lds_reserve, st>>>(g, c, a, b, F, usnap, partials);
+              launch_step(glbe_step<S, ch, fl, false, false, false, w, rw, sr>, step_grid(g), g.lds_reserve, st,
+                        g, c, a, b, F, usnap, partials);
             return hipGetLastError();
           });
         });
@@ -529,8 +529,8 @@ hipError_t launch_mhd_step(const GridArgs& g, const CollideArgs<R>& c, const Mag
           // cavity: per-lane coordinates, regular loads and stores
           return with_flag(c.moving != 0, [&](auto MV) {
             return with_flag(ext, [&](auto EX) {
-              mhd_step<R, ch, fl, decltype(MV)::value, decltype(EX)::value, w, false, false, false>
-                  <<<step_grid(g), kBlock, g.lds_reserve, st>>>(g, c, m, a, b, ga, gb, F, usnap, partials);
+              launch_step(mhd_step<R, ch, fl, decltype(MV)::value, decltype(EX)::value, w, false, false, false>, step_grid(g), g.lds_reserve, st,
+                        g, c, m, a, b, ga, gb, F, usnap, partials);
               return hipGetLastError();
             });
           });
@@ -538,14 +538,14 @@ hipError_t launch_mhd_step(const GridArgs& g, const CollideArgs<R>& c, const Mag
         return with_flag(rows_per_wave(g), [&](auto RW) {
           constexpr bool rw = decltype(RW)::value;
           if (ntl)
-            mhd_step<R, ch, fl, false, false, w, true, true, rw>
-                <<<step_grid(g), kBlock, g.lds_reserve, st>>>(g, c, m, a, b, ga, gb, F, usnap, partials);
+            launch_step(mhd_step<R, ch, fl, false, false, w, true, true, rw>, step_grid(g), g.lds_reserve, st,
+                        g, c, m, a, b, ga, gb, F, usnap, partials);
           else if (nt)
-            mhd_step<R, ch, fl, false, false, w, true, false, rw>
-                <<<step_grid(g), kBlock, g.lds_reserve, st>>>(g, c, m, a, b, ga, gb, F, usnap, partials);
+            launch_step(mhd_step<R, ch, fl, false, false, w, true, false, rw>, step_grid(g), g.lds_reserve, st,
+                        g, c, m, a, b, ga, gb, F, usnap, partials);
           else
-            mhd_step<R, ch, fl, false, false, w, false, false, rw>
-                <<<step_grid(g), kBlock, g.lds_reserve, st>>>(g, c, m, a, b, ga, gb, F, usnap, partials);
+            launch_step(mhd_step<R, ch, fl, false, false, w, false, false, rw>, step_grid(g), g.lds_reserve, st,
+                        g, c, m, a, b, ga, gb, F, usnap, partials);
           return hipGetLastError();
         });
       });

@@ -278,13 +278,13 @@ hipError_t launch_glbe2_step(const GridArgs& g, const CollideArgs<typename Stora
                          nts = decltype(NTS)::value, w = decltype(W)::value;
           if constexpr (sizeof(S) == 2) {
             if (stochastic) {
-              glbe2_step<S, ch, fl, nts, w, true>
-                  <<<step_grid(g), kBlock, g.lds_reserve, st>>>(g, c, a, b, F, usnap, partials);
+              launch_step(glbe2_step<S, ch, fl, nts, w, true>, step_grid(g), g.lds_reserve, st,
+                        g, c, a, b, F, usnap, partials);
               return hipGetLastError();
             }
           }
-          glbe2_step<S, ch, fl, nts, w, false>
-              <<<step_grid(g), kBlock, g.lds_reserve, st>>>(g, c, a, b, F, usnap, partials);
+          launch_step(glbe2_step<S, ch, fl, nts, w, false>, step_grid(g), g.lds_reserve, st,
+                        g, c, a, b, F, usnap, partials);
           return hipGetLastError();
         });
       });
@@ -317,9 +317,9 @@ hipError_t launch_mhd2_step(const GridArgs& g, const CollideArgs<R>& c, const Ma
     return with_flag(field, [&](auto FL) {
       return with_flag(wide_offsets(g, sizeof(R)), [&](auto W) {
         return with_flag(nt, [&](auto NTF) {
-          mhd2_step<R, decltype(CH)::value, decltype(FL)::value, decltype(W)::value,
-                    decltype(NTF)::value>
-              <<<step_grid(g), kBlock, g.lds_reserve, st>>>(g, c, m, a, b, ga, gb, F, usnap, partials);
+          launch_step(mhd2_step<R, decltype(CH)::value, decltype(FL)::value, decltype(W)::value,
+                    decltype(NTF)::value>, step_grid(g), g.lds_reserve, st,
+                        g, c, m, a, b, ga, gb, F, usnap, partials);
           return hipGetLastError();
         });
       });

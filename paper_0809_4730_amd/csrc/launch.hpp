@@ -2,11 +2,32 @@
 // adjoint.hip); used by the C-ABI layer.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
 
 namespace lbm {
+
+// Start and stop events for the next step-kernel launch on this thread.  The
+// timed step sets them; launch_step attaches them to the kernel's own dispatch
+// (hipExtLaunchKernelGGL), so that they time the kernel alone without marker
+// packets between the launches, and consumes them.  Null: an ordinary launch.
+struct StepEvents {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+};
+StepEvents& step_events();
+
+// Launch of a step kernel (kBlock threads per workgroup, `lds` bytes of
+// dynamic LDS reserved) carrying this thread's step events, if any; errors are
+// read by the caller's hipGetLastError, as after a <<<>>> launch.
+template <typename F, typename... Args>
+inline void launch_step(F kernel, dim3 grid, uint32_t lds, hipStream_t st, Args... args) {
+  StepEvents& ev = step_events();
+  hipExtLaunchKernelGGL(kernel, grid, dim3(kBlock), lds, st, ev.start, ev.stop, 0u, args...);
+  ev = StepEvents{};
+}
 
 template <typename S>
 hipError_t launch_glbe_step(const GridArgs& g, const CollideArgs<typename Storage<S>::R>& c,

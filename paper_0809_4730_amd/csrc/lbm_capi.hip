@@ -137,6 +137,11 @@ Layout make_layout(const lbm_grid* grid, const lbm_params* p) {
 
 namespace lbm {
 
+StepEvents& step_events() {
+  static thread_local StepEvents ev;
+  return ev;
+}
+
 std::string validate_params(const lbm_grid* grid, const lbm_params* p) { return validate(grid, p); }
 
 lbm_status fail(lbm_ctx* c, lbm_status s, const std::string& msg) {
@@ -312,9 +317,13 @@ lbm_status one_step(lbm_ctx* c, hipEvent_t ev0, hipEvent_t ev1) {
     const lbm_status s = flush_checks(c);
     if (s != LBM_OK) return s;
   }
-  if (ev0) LBM_HIP(c, hipEventRecord(ev0, c->stream), "hipEventRecord");
-  LBM_HIP(c, launch_step_kernel(c, check), "step kernel launch");
-  if (ev1) LBM_HIP(c, hipEventRecord(ev1, c->stream), "hipEventRecord");
+  // ev0 / ev1 (timed steps) ride on the step kernel's own dispatch
+  step_events() = StepEvents{ev0, ev1};
+  const hipError_t le = launch_step_kernel(c, check);
+  const bool taken = step_events().start == nullptr;
+  step_events() = StepEvents{};
+  LBM_HIP(c, le, "step kernel launch");
+  if (!taken) return fail(c, LBM_ESTATE, "step kernel launched without its timing events");
   c->cur ^= 1;
   c->step = next;
   if (check) ++c->checks;
@@ -641,8 +650,9 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
 
 namespace {
 
-// n steps with a pair of HIP events around every step kernel on the context's
-// stream; each[i] (if non-null) receives step i's kernel duration in us.
+// n steps with a pair of HIP events attached to every step kernel's dispatch
+// on the context's stream (no marker packets between the steps); each[i] (if
+// non-null) receives step i's kernel duration in us.
 lbm_status step_with_events(lbm_ctx* c, int64_t n, double* each, double* mean_kernel_us,
                             double* wall_ms) {
   constexpr int kPool = 512;
@@ -661,7 +671,9 @@ lbm_status step_with_events(lbm_ctx* c, int64_t n, double* each, double* mean_ke
       const lbm_status s = one_step(c, c->events[2 * i], c->events[2 * i + 1]);
       if (s != LBM_OK) return s;
     }
-    LBM_HIP(c, hipEventSynchronize(c->events[2 * (chunk - 1) + 1]), "hipEventSynchronize");
+    // a marker after the chunk: the step events are kernel timestamps
+    LBM_HIP(c, hipEventRecord(wall1, c->stream), "hipEventRecord");
+    LBM_HIP(c, hipEventSynchronize(wall1), "hipEventSynchronize");
     for (int64_t i = 0; i < chunk; ++i) {
       float ms = 0.0f;
       LBM_HIP(c, hipEventElapsedTime(&ms, c->events[2 * i], c->events[2 * i + 1]), "hipEventElapsedTime");
