@@ -236,3 +236,40 @@ def test_create_time_shape_choice_coupled_lattices(case):
     fixed.close()
     del fixed, a
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("storage,n", [("f32", 384), ("f64", 320)])
+def test_lattices_past_the_32_bit_offsets_match_the_oracle(storage, n):
+    """The largest lattices take the 64-bit form by themselves (FP32 beyond
+    about 51 M nodes, FP64 beyond about 25.6 M): the duct at 384^3 (FP32,
+    56.6 M nodes) and 320^3 (FP64, 32.8 M nodes) in their automatic launch
+    shape, one step from a seeded random state against the oracle's step from
+    the same state at 4000 sampled nodes (corners included): FP32 2e-6, FP64
+    1e-12 relative."""
+    import torch
+
+    import paper_0809_4730_amd as pkg
+    from tests.gpu_util import perms, rel
+    shape = (n, n, n)
+    announce("%s duct %d^3, automatic 64-bit offsets" % (storage, n))
+    cfg = inputs.DUCT256
+    dt = torch.float64 if storage == "f64" else torch.float32
+    ndt = np.float64 if storage == "f64" else np.float32
+    F = inputs.duct_force(shape, cfg["F0"], dtype=ndt)
+    s = glbe.rates(cfg["nu"], cfg["gamma"])
+    sim = pkg.Simulation(shape, cfg["bc"], cfg["gamma"], s, storage=storage,
+                         force=torch.from_numpy(F).cuda())
+    assert sim.launch["offsets"] == "wide"
+    p19, _ = perms()
+    d0 = inputs.random_deviations(shape, seed=41, amp=1e-3, dtype=ndt)
+    sim.set_state(torch.from_numpy(np.ascontiguousarray(d0[p19])).cuda().to(dt))
+    sim.step(1)
+    out = sim.get_state()
+    nodes = inputs.random_nodes(shape, 4000, seed=41)
+    idx = torch.tensor(nodes, device="cuda")
+    got = out[:, idx[:, 2], idx[:, 1], idx[:, 0]].double().cpu().numpy()
+    sim.close()
+    del sim, out
+    torch.cuda.empty_cache()
+    ref = glbe.step_nodes(d0, F.astype(np.float64), cfg["gamma"], s, cfg["bc"], nodes)[p19]
+    assert rel(got, ref) < (1e-12 if storage == "f64" else 2e-6)
