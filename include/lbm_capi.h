@@ -239,7 +239,7 @@ lbm_status lbm_workspace_bytes(const lbm_grid* grid, const lbm_params* params, s
  * FP32, 4 for FP64, 5 for the coupled FP32 step, none otherwise) and, for
  * D3Q19, streaming loads,
  * and lbm_create times a few dozen plain steps on the stream for each
- * of three XCD workgroup mappings (chunks of 2 and 8 workgroups, slabs), keeps
+ * of five XCD workgroup mappings (chunks of 1, 2, 4 and 8 workgroups, slabs), keeps
  * the fastest and restores the rest state; it then synchronizes (a few ms to
  * a few tens of ms).  A non-zero launch.xcd_chunk skips the timing.  The
  * mapping decides only which workgroup updates which nodes: results are the

@@ -221,10 +221,12 @@ hipError_t launch_step_kernel(lbm_ctx* c, bool check) {
 //    neighbour rows hit its own L2; stores stay cacheable.
 //  * <= 512 MB (partly MALL-resident): slabs, streaming stores.
 //  * larger (streams from HBM): streaming stores, and the chunk is timed at
-//    create (tune_launch_shape) among 2, 8 and whole slabs.  No rule of the
-//    lattice shape picked the winner: chunks of 2 beat slabs by 7% for the 256^3
-//    flow step, slabs beat chunks by 22% for the 2048^2 coupled 2D step, and
-//    chunks of 8 lead for 16-bit storage by 2-3%.
+//    create (tune_launch_shape) among 1, 2, 4, 8 and whole slabs.  No rule of
+//    the lattice shape picked the winner: chunks of 2 beat slabs by 7% for the
+//    256^3 flow step, slabs beat chunks by 22% for the 2048^2 coupled 2D step,
+//    chunks of 8 lead for 16-bit storage by 2-3%, and chunks of 1, 2 and 4 lie
+//    within 1-2% of each other for the 256^3 steps, which of them ahead varying
+//    from box to box.
 // Non-zero fields of lbm_params.launch override the choice.
 void set_chunk(lbm_ctx* c, int chunk) {
   const int bpx0 = (c->L.nblocks + kXcd - 1) / kXcd;
@@ -390,8 +392,8 @@ hipError_t zero_populations(lbm_ctx* c) {
 hipError_t tune_launch_shape(lbm_ctx* c) {
   if (!c->tune_chunk) return hipSuccess;
   const int bpx0 = (c->L.nblocks + kXcd - 1) / kXcd;
-  constexpr int kCand = 3;
-  const int cand[kCand] = {2, 8, bpx0};
+  constexpr int kCand = 5;
+  const int cand[kCand] = {1, 2, 4, 8, bpx0};
   // launches per timing: ~2 ms at ~5.5 TB/s (each step moves the population bytes)
   const int reps =
       static_cast<int>(std::max(4.0, std::min(32.0, 2e-3 * 5.5e12 / population_bytes(c))));
