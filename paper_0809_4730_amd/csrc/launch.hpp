@@ -20,13 +20,18 @@ struct StepEvents {
 StepEvents& step_events();
 
 // Launch of a step kernel (kBlock threads per workgroup, `lds` bytes of
-// dynamic LDS reserved) carrying this thread's step events, if any; errors are
-// read by the caller's hipGetLastError, as after a <<<>>> launch.
+// dynamic LDS reserved): with this thread's step events attached when the
+// timed step has set them, else an ordinary launch (the form that HIP graph
+// capture records).  Errors are read by the caller's hipGetLastError.
 template <typename F, typename... Args>
 inline void launch_step(F kernel, dim3 grid, uint32_t lds, hipStream_t st, Args... args) {
   StepEvents& ev = step_events();
-  hipExtLaunchKernelGGL(kernel, grid, dim3(kBlock), lds, st, ev.start, ev.stop, 0u, args...);
-  ev = StepEvents{};
+  if (ev.start || ev.stop) {
+    hipExtLaunchKernelGGL(kernel, grid, dim3(kBlock), lds, st, ev.start, ev.stop, 0u, args...);
+    ev = StepEvents{};
+  } else {
+    hipLaunchKernelGGL(kernel, grid, dim3(kBlock), lds, st, args...);
+  }
 }
 
 template <typename S>
