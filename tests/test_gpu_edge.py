@@ -7,11 +7,14 @@
 * A single periodic node under a uniform force: every collision adds F/gamma to
   the momentum (the conserved-moment rule of Sec. 3), so after n steps
   j = n F/gamma exactly in FP64, and the mass does not change.
+* A fully periodic lattice from a random state under a random force field:
+  total mass constant, total momentum grown by n sum F / gamma.
 * An unstable march reports the instability and keeps its state readable."""
 import numpy as np
 import pytest
 
 from oracle import d2q9, glbe
+from paper_0809_4730_amd import inputs
 from tests.gpu_util import announce
 
 pytestmark = pytest.mark.gpu
@@ -79,3 +82,42 @@ def test_unstable_march_reports_and_keeps_state():
     h = sim.history(1000)
     assert (h[:, 6] > 0).any() or not np.isfinite(h[:, 1]).all() or h[:, 1].max() > 1e-2
     assert not bool(torch.isfinite(st).all()) or h[:, 1].max() > 1e-2
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_periodic_lattice_conserves_mass_and_gains_force_momentum(storage, tol):
+    """On a fully periodic lattice streaming permutes the populations, so from
+    any state the total mass stays where it is and the total momentum of the
+    stored populations, sum e f, grows by exactly sum F / gamma per step (the
+    collision conserves mass and adds the force's momentum, Sec. 3): a seeded
+    random state and force field, 1 and 40 steps."""
+    import torch
+
+    import paper_0809_4730_amd as pkg
+    from tests.gpu_util import perms
+    announce("periodic conservation %s" % storage)
+    shape, gamma = (16, 12, 10), 0.3
+    bc = (PER, PER, PER)
+    dt = torch.float64 if storage == "f64" else torch.float32
+    ndt = np.float64 if storage == "f64" else np.float32
+    d0 = inputs.random_deviations(shape, seed=61, amp=1e-3).astype(ndt)
+    F = (inputs.random_force(shape, seed=61, amp=1e-5) + 1e-5).astype(ndt)
+    sim = pkg.Simulation(shape, bc, gamma, glbe.rates(0.05, gamma), storage=storage,
+                         force=torch.from_numpy(F).cuda())
+    p19, _ = perms()
+    sim.set_state(torch.from_numpy(np.ascontiguousarray(d0[p19])).cuda())
+    e = pkg.lattice_velocities(19).astype(np.float64)        # library direction order
+    f0 = d0[p19].astype(np.float64)
+    m0 = f0.sum()
+    P0 = np.tensordot(e.T, f0, axes=(1, 0)).reshape(3, -1).sum(axis=1)
+    dP = F.astype(np.float64).reshape(3, -1).sum(axis=1) / gamma
+    done = 0
+    for n in (1, 40):
+        sim.step(n - done)
+        done = n
+        f = sim.get_state().double().cpu().numpy()
+        P = np.tensordot(e.T, f, axes=(1, 0)).reshape(3, -1).sum(axis=1)
+        scale = np.abs(P0).max() + n * np.abs(dP).max()
+        assert abs(f.sum() - m0) < tol * np.abs(f0).sum()
+        assert np.abs(P - (P0 + n * dP)).max() < tol * scale, (P, P0 + n * dP)
+    sim.close()
