@@ -1,8 +1,12 @@
-"""Step launches captured into a HIP graph (torch.cuda.graph on the library's
-stream) and replayed: each replay advances the state exactly as the same
-number of eager steps does, bit for bit.  Residual checks are off so that the
-captured work is the step kernels alone; every replay is followed by eager work
-and a device synchronisation before it is checked."""
+"""How step kernels are launched, checked against plain eager steps bit for bit.
+
+* Step launches captured into a HIP graph (torch.cuda.graph on the library's
+  stream) and replayed: each replay advances the state exactly as the same
+  number of eager steps does.  Residual checks are off so that the captured
+  work is the step kernels alone; every replay is followed by eager work and a
+  device synchronisation before it is checked.
+* Timed steps (HIP events attached to each step kernel's launch) compute what
+  plain steps compute: states and residual histories."""
 import numpy as np
 import pytest
 
@@ -55,3 +59,44 @@ def test_replayed_step_graph_equals_eager_steps(mhd):
         assert bool(torch.isfinite(a[0] if mhd else a).all())
     cap.close()
     ref.close()
+
+
+@pytest.mark.parametrize("case", ["flow", "mhd", "d2q9"])
+def test_timed_steps_compute_what_plain_steps_compute(case):
+    """lbm_step_times (events attached to each step kernel's launch) over 700
+    steps, more than one batch of its event pool, residual checks on: the state
+    and the residual history equal those of 700 plain steps bit for bit, and
+    every step's duration is positive and finite; lbm_step_timed likewise."""
+    import torch
+
+    import paper_0809_4730_amd as pkg
+    announce("timed steps, %s" % case)
+    gamma = 0.3
+    if case == "d2q9":
+        shape, bc = (64, 37, 1), (PER, WALL, PER)
+        kw = dict(lattice="d2q9")
+        s = pkg.default_rates_d2q9(0.05, gamma)
+        F = (1e-5, -2e-6, 0.0)
+    else:
+        shape, bc = (64, 6, 10), (PER, WALL, WALL)
+        kw = dict(mhd=dict(gamma_m=0.4, chi=0.05, eta=0.03, B0=(0.01, 0.02, -0.01))) \
+            if case == "mhd" else {}
+        s = glbe.rates(0.05, gamma)
+        F = (1e-5, 0.0, 0.0)
+    sims = [pkg.Simulation(shape, bc, gamma, s, storage="f32", force=F, **kw) for _ in range(3)]
+    t, wall_ms = sims[0].step_times(700)
+    assert len(t) == 700 and np.all(np.isfinite(t)) and np.all(t > 0) and wall_ms > 0
+    mean_us, wall2 = sims[1].step_timed(700)
+    assert mean_us > 0 and wall2 > 0
+    sims[2].step(700)
+    torch.cuda.synchronize()
+    states = [sim.get_state() for sim in sims]
+    hists = [sim.history(100) for sim in sims]
+    for st, h in zip(states[:2], hists[:2]):
+        if case == "mhd":
+            assert torch.equal(st[0], states[2][0]) and torch.equal(st[1], states[2][1])
+        else:
+            assert torch.equal(st, states[2])
+        assert np.array_equal(h, hists[2])
+    for sim in sims:
+        sim.close()
