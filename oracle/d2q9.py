@@ -185,6 +185,31 @@ def step(post, F, gamma, s, bc, rho0=1.0):
     return collide(f, F, gamma, s, rho0), u
 
 
+def step_nodes(post, F, gamma, s, bc, nodes, rho0=1.0):
+    """One step evaluated only at the given nodes (for large-lattice parity):
+    each population pulled from its upstream node (periodic wrap), or from the
+    opposite direction at the node itself where the link crosses a wall
+    (halfway bounce-back), then the collision at those nodes.  nodes: (n, 2)
+    integer (x, y); post (9, ny, nx); F (2,) or (2, ny, nx).  Returns (9, n)."""
+    nodes = np.asarray(nodes)
+    ny, nx = post.shape[1:]
+    n = len(nodes)
+    nodes3 = np.stack([nodes[:, 0], nodes[:, 1], np.zeros(n, dtype=nodes.dtype)], axis=1)
+    dims, bc3 = (nx, ny, 1), (bc[0], bc[1], PERIODIC)
+    e3 = _embed(E9)
+    x, y = nodes[:, 0], nodes[:, 1]
+    f = np.empty((Q9, n))
+    for a in range(Q9):
+        src, bounce = glbe.upstream(nodes3, e3[a], dims, bc3)
+        srcc = np.where(bounce[:, None], nodes3, src)
+        f[a] = np.where(bounce, post[OPP9[a], y, x], post[a, srcc[:, 1], srcc[:, 0]])
+    if np.ndim(F) == 3:
+        Fn = np.asarray(F[:, y, x], dtype=np.float64)
+    else:
+        Fn = np.broadcast_to(np.asarray(F, dtype=float).reshape(2, 1), (2, n))
+    return collide(f, Fn, gamma, s, rho0)
+
+
 class Flow2D:
     """Time march of the D2Q9 GLBE, residual every check_every steps."""
 

@@ -251,3 +251,35 @@ def test_wave_caps_and_store_forms_bitwise(storage, mhd):
     for a, b in zip(out[1:], out[:-1]):
         assert torch.equal(a[0], b[0])
         assert np.array_equal(a[1], b[1])
+
+
+def test_d2q9_4096_launch_shape_one_step_at_sampled_nodes():
+    """D2Q9 at 4096^2 (FP32, periodic x, walls in y) in the launch shape such a
+    lattice gets (streaming stores, create-time XCD chunk, 6 waves per SIMD):
+    one step from a seeded random state against the oracle's step from the same
+    state at 4000 sampled nodes (corners included), 2e-6 relative."""
+    import torch
+
+    import paper_0809_4730_amd as pkg
+    announce("d2q9 4096^2 sampled nodes")
+    nx = ny = 4096
+    bc, gamma = (PER, WALL), 0.1
+    s = d.rates(0.1, gamma)
+    F = np.array([1e-5, -2e-6], dtype=np.float32).astype(np.float64)
+    sim = _sim((nx, ny), bc, gamma, s, "f32", (F[0], F[1], 0.0))
+    assert sim.launch["store"] == "streaming" and sim.launch["waves"] == 6
+    rng = np.random.default_rng(71)
+    f0 = (1e-3 * rng.uniform(-1.0, 1.0, (9, ny, nx))).astype(np.float32)
+    sim.set_state(_to_f(f0.astype(np.float64), torch.float32))
+    sim.step(1)
+    out = sim.get_state()
+    pick = np.random.default_rng(72).choice(nx * ny, 4000, replace=False)
+    nodes = np.stack([pick % nx, pick // nx], axis=1)
+    nodes[:4] = [(0, 0), (nx - 1, 0), (0, ny - 1), (nx - 1, ny - 1)]
+    idx = torch.tensor(nodes, device="cuda")
+    got = out[:, 0, idx[:, 1], idx[:, 0]].double().cpu().numpy()
+    sim.close()
+    del sim, out
+    torch.cuda.empty_cache()
+    ref = d.step_nodes(f0, F, gamma, s, bc, nodes)[_perm(9)]
+    assert rel(got, ref) < 2e-6

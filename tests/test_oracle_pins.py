@@ -205,3 +205,47 @@ def test_mhd_step_nodes_pin_catches_a_wrong_wall_sign(monkeypatch):
     from oracle.lattice import W7
     monkeypatch.setattr(mhd, "wall_g", lambda v, a, jc, Bw: v + 2.0 * W7[a] * Bw[jc])
     assert _compare_mhd((6, 8, 5), (PER, WALL, PER), seed=5) > 1e-3
+
+
+# ------------------------------------------------------------ D2Q9 sampled --
+# ``d2q9.step_nodes`` against ``d2q9.step`` at every node (periodic, wall and
+# mixed axes; field and uniform force); a planted wrong wrap must fail.
+D2_GRIDS = [((9, 7), (PER, WALL)), ((6, 5), (WALL, WALL)), ((5, 8), (PER, PER)),
+            ((33, 3), (WALL, PER))]
+
+
+def _compare_d2(shape, bc, seed, uniform=False):
+    from oracle import d2q9
+    nx, ny = shape
+    rng = np.random.default_rng(seed)
+    d0 = 1e-3 * rng.uniform(-1.0, 1.0, (9, ny, nx))
+    F = np.array([2e-5, -1e-5]) if uniform else 1e-4 * rng.uniform(-1.0, 1.0, (2, ny, nx))
+    Ff = np.broadcast_to(F.reshape(2, 1, 1), (2, ny, nx)) if uniform else F
+    s = d2q9.rates(0.05, 0.3)
+    ref, _ = d2q9.step(d0, Ff, 0.3, s, bc)
+    y, x = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    nodes = np.stack([x.ravel(), y.ravel()], axis=1)
+    got = d2q9.step_nodes(d0, F, 0.3, s, bc, nodes)
+    want = ref[:, nodes[:, 1], nodes[:, 0]]
+    return float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+
+
+@pytest.mark.parametrize("shape,bc", D2_GRIDS)
+@pytest.mark.parametrize("uniform", [False, True])
+def test_d2q9_step_nodes_equals_step_at_every_node(shape, bc, uniform):
+    assert _compare_d2(shape, bc, seed=7, uniform=uniform) < 1e-15
+
+
+def test_d2q9_step_nodes_pin_catches_a_wrong_wrap(monkeypatch):
+    def clamped(nodes, e, dims, bc):
+        src = nodes - np.asarray(e)[None, :]
+        bounce = np.zeros(len(nodes), dtype=bool)
+        for c in range(3):
+            if bc[c] == WALL:
+                bounce |= (src[:, c] < 0) | (src[:, c] >= dims[c])
+            else:
+                src[:, c] = np.clip(src[:, c], 0, dims[c] - 1)
+        return src, bounce
+
+    monkeypatch.setattr(glbe, "upstream", clamped)
+    assert _compare_d2((9, 7), (PER, WALL), seed=7) > 1e-3
