@@ -1091,6 +1091,46 @@ def oracle_time_to_steady(budget_s=900.0):
             "blas_threads": int(threads), "cases": cases}
 
 
+def shard_shares(launches=40):
+    """One GPU's share of the 256^3 lattice when it is split into z-slabs over
+    k = 1, 2, 4, 8 GPUs: the plain step kernel on a 256 x 256 x (256/k) slab,
+    z periodic standing in for the halo planes a neighbour would fill, in the
+    slab's own automatic launch shape; FP32 flow step (walls in y) and FP32
+    coupled step (the Hartmann setting).  Median of `launches` launches (HIP
+    events attached to each), after 5 warm-up steps."""
+    import numpy as np
+    import torch
+
+    import paper_0809_4730_amd as pkg
+    from paper_0809_4730_amd import inputs
+    h = inputs.HARTMANN
+    B0, chi = inputs.hartmann_parameters(10.0, 0.01, h["shape"][1], h["nu"], h["eta"])
+    bc = ("periodic", "wall", "periodic")
+    rows = []
+    for k in (1, 2, 4, 8):
+        shape = (256, 256, 256 // k)
+        for kind in ("flow", "coupled"):
+            if kind == "flow":
+                sim = make_sim(shape, "f32", 1.0, bc=bc, check_every=NO_CHECK)
+                bpn = 164
+            else:
+                sim = pkg.Simulation(shape, bc, 0.1, pkg.default_rates(h["nu"], 0.1), storage="f32",
+                                     force=h["F"], check_every=NO_CHECK,
+                                     mhd=dict(gamma_m=0.1, chi=chi, eta=h["eta"], B0=(0.0, B0, 0.0)))
+                bpn = 320
+            sim.step(5)
+            t, _ = sim.step_times(launches)
+            us = float(np.median(t))
+            rows.append({"gpus": k, "slab": list(shape), "step": kind, "kernel_us": round(us, 2),
+                         "alg_GBs": round(bpn * sim.N / (us * 1e-6) / 1e9, 1),
+                         "launch": sim.launch})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+            sim.close()
+            del sim
+            torch.cuda.empty_cache()
+    return {"probe": "shares", "rows": rows}
+
+
 def kernel_probe(name, launches, copy_probe, launch=None):
     """One JSON line for the profilers: `launches` plain launches of one
     kernel at its HBM-scale size (coupled step 256^3 FP32, steady adjoint
@@ -1133,6 +1173,9 @@ def kernel_probe(name, launches, copy_probe, launch=None):
         return
     elif name == "oracle_steady":
         print(json.dumps(oracle_time_to_steady()), flush=True)
+        return
+    elif name == "shares":
+        print(json.dumps(shard_shares(launches)), flush=True)
         return
     elif name == "precision256":
         precision_steady_256()
@@ -1181,7 +1224,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--probe", choices=["mhd256", "adjoint128", "d2q9_4096", "precision256",
-                                        "ladder256", "ladder128", "hbm_ceiling", "oracle_steady"],
+                                        "ladder256", "ladder128", "hbm_ceiling", "oracle_steady",
+                                        "shares"],
                     help="only one other measurement: another kernel at HBM scale (for the "
                          "profilers), or the 256^3 precision form at steady state")
     ap.add_argument("--launches", type=int, default=30)
