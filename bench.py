@@ -9,8 +9,9 @@ over all 16.8 M nodes.  Inputs (state, force field) are resident in HBM
 before the timed region; nothing crosses PCIe inside it.
 
 Prints ONE JSON line: MLUPS of the timed steps; the roofline of the plain
-step kernel from HIP events attached to every launch on the library's stream
-(algorithmic bytes per launch / mean launch duration); the same for BF16,
+step kernel from a HIP event on every launch on the library's stream
+(algorithmic bytes per launch / mean time from one step kernel's end to the
+next one's); the same for BF16,
 FP16 and FP64 storage at 256^3 and for the cache-resident 64^3 duct; wall
 time to a residual of 1e-8 for gamma < 1 against plain FP64 gamma = 1
 (64^3 duct gamma sweep, 128^3 preconditioning-and-precision ladders); and
@@ -77,8 +78,9 @@ def make_sim(shape, storage, gamma, nu=0.131, F0=1e-5, bc=("periodic", "wall", "
 
 def timed_steps(sim, steps, warmup):
     """W untimed steps, then exactly `steps` steps bracketed by device
-    synchronisations, each step kernel between two HIP events on the library's
-    stream; the timed region ends with the residual checks' partial sums
+    synchronisations, each step kernel's launch on the library's stream carrying
+    a HIP event (a step's duration: from the previous step kernel's end to its
+    own, the kernel and the dispatch gap before it); the timed region ends with the residual checks' partial sums
     reduced into the history and its last record read.  Returns (MLUPS,
     wall s, plain-kernel us list, check-kernel us list)."""
     import torch
@@ -1096,8 +1098,8 @@ def shard_shares(launches=40):
     k = 1, 2, 4, 8 GPUs: the plain step kernel on a 256 x 256 x (256/k) slab,
     z periodic standing in for the halo planes a neighbour would fill, in the
     slab's own automatic launch shape; FP32 flow step (walls in y) and FP32
-    coupled step (the Hartmann setting).  Median of `launches` launches (HIP
-    events attached to each), after 5 warm-up steps."""
+    coupled step (the Hartmann setting).  Median of `launches` launches (a HIP
+    event on each, timed end to end), after 5 warm-up steps."""
     import numpy as np
     import torch
 
@@ -1289,8 +1291,10 @@ def main():
                                        "current kernel sources (kernel_hash), else null",
                      "kernel": "glbe_step<%s, check=false, field=true%s>"
                                % (storage, ", stochastic" if kw.get("rounding") else ""),
-                     "timing": "HIP events attached to each of the %d plain launches of the "
-                               "timed steps (hipExtLaunchKernel), on the library's stream"
+                     "timing": "HIP events on the dispatches of the timed steps "
+                               "(hipExtLaunchKernel), on the library's stream; mean over the "
+                               "%d plain launches of the time from the previous step "
+                               "kernel's end to each one's end"
                                % head["launches_timed"],
                      "alg_bytes_per_node": head["alg_bytes_per_node"],
                      "alg_bytes_per_launch": head["alg_bytes_per_launch"],

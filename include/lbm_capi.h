@@ -270,14 +270,18 @@ lbm_status lbm_set_force(lbm_ctx* ctx, const void* force);
  * does not synchronize and does not report instability (see lbm_residual). */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
 
-/* Like lbm_step, but times every step kernel with a pair of HIP events
- * attached to its own dispatch on the stream (hipExtLaunchKernel: no marker
- * packets between the steps), synchronizes, and returns the mean kernel
- * duration in microseconds (the kernel alone, not launch gaps) and the wall
- * time of the whole call in milliseconds. */
+/* Like lbm_step, but times every step kernel with a HIP event attached to its
+ * own dispatch on the stream (hipExtLaunchKernel), synchronizes, and returns
+ * the mean step duration in microseconds and the wall time of the whole call
+ * in milliseconds.  A step's duration runs from the end of the previous step
+ * kernel to the end of its own: the kernel plus the dispatch gap before it (a
+ * fraction of a microsecond).  The first step of every 512, and a step that
+ * first reduces pending residual checks, is timed from a start event on its
+ * own dispatch instead (the kernel alone).  No marker packets sit between the
+ * steps otherwise, so the call marches at the rate of lbm_step. */
 lbm_status lbm_step_timed(lbm_ctx* ctx, int64_t n, double* mean_kernel_us, double* wall_ms);
 
-/* Like lbm_step_timed, but writes every step's kernel duration in
+/* Like lbm_step_timed, but writes every step's duration in
  * microseconds to the host array kernel_us[n] (step i of the call is the
  * context's step t0 + i + 1, a residual-check step when that number is a
  * multiple of check_every).  Synchronizes. */

@@ -449,9 +449,10 @@ class Simulation:
         return us.value, ms.value
 
     def step_times(self, n):
-        """n steps with HIP events attached to every step kernel's launch on the
-        library's stream (lbm_step_times): (numpy array of n kernel durations in us,
-        wall time of the call in ms).  Step i of the call is step self.t + i + 1."""
+        """n steps, each step kernel's launch on the library's stream carrying a
+        HIP event (lbm_step_times): (numpy array of n step durations in us, each
+        from the previous step kernel's end to its own, wall time of the call in
+        ms).  Step i of the call is step self.t + i + 1."""
         buf = (ctypes.c_double * int(n))()
         ms = ctypes.c_double()
         self._c(self._lib.lbm_step_times(self._ctx, int(n), buf, ctypes.byref(ms)))

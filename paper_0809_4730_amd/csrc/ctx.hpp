@@ -84,7 +84,8 @@ namespace lbm {
 std::string validate_params(const lbm_grid* grid, const lbm_params* p);  // "" when valid
 lbm_status fail(lbm_ctx* c, lbm_status s, const std::string& msg);
 lbm_status hip_fail(lbm_ctx* c, hipError_t e, const char* what);
-lbm_status one_step(lbm_ctx* c, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+lbm_status one_step(lbm_ctx* c, hipEvent_t start = nullptr, hipEvent_t stop = nullptr,
+                    bool* with_start = nullptr);
 void choose_launch_shape(lbm_ctx* c);
 lbm_status flush_checks(lbm_ctx* c);
 void reset_checks(lbm_ctx* c, int64_t step);

@@ -10,9 +10,11 @@
 namespace lbm {
 
 // Start and stop events for the next step-kernel launch on this thread.  The
-// timed step sets them; launch_step attaches them to the kernel's own dispatch
-// (hipExtLaunchKernelGGL), so that they time the kernel alone without marker
-// packets between the launches, and consumes them.  Null: an ordinary launch.
+// timed step sets them (the start one only where the previous stream work was
+// not a step kernel: a start event costs a marker packet before the dispatch,
+// several microseconds per launch); launch_step attaches them to the kernel's
+// own dispatch (hipExtLaunchKernelGGL) and consumes them.  Both null: an
+// ordinary launch.
 struct StepEvents {
   hipEvent_t start = nullptr;
   hipEvent_t stop = nullptr;

@@ -312,20 +312,27 @@ void reset_checks(lbm_ctx* c, int64_t step) {
 }
 
 // Enqueue one step (its partial sums kept for a later batched finalize).
-lbm_status one_step(lbm_ctx* c, hipEvent_t ev0, hipEvent_t ev1) {
+// Timed steps: `stop` rides on the step kernel's own dispatch (its end
+// timestamp), and `start` too when *with_start is set on entry or this step
+// first enqueued the reduction of pending checks; *with_start tells the caller
+// which on return.
+lbm_status one_step(lbm_ctx* c, hipEvent_t start, hipEvent_t stop, bool* with_start) {
   const int64_t next = c->step + 1;
   const bool check = (next % c->p.check_every) == 0;
+  bool flushed = false;
   if (check && c->checks - c->finalized >= c->L.pslots) {
     const lbm_status s = flush_checks(c);
     if (s != LBM_OK) return s;
+    flushed = true;
   }
-  // ev0 / ev1 (timed steps) ride on the step kernel's own dispatch
-  step_events() = StepEvents{ev0, ev1};
+  const bool attach_start = start && (!with_start || *with_start || flushed);
+  step_events() = StepEvents{attach_start ? start : nullptr, stop};
   const hipError_t le = launch_step_kernel(c, check);
-  const bool taken = step_events().start == nullptr;
+  const bool taken = step_events().start == nullptr && step_events().stop == nullptr;
   step_events() = StepEvents{};
   LBM_HIP(c, le, "step kernel launch");
   if (!taken) return fail(c, LBM_ESTATE, "step kernel launched without its timing events");
+  if (with_start) *with_start = attach_start;
   c->cur ^= 1;
   c->step = next;
   if (check) ++c->checks;
@@ -652,9 +659,14 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
 
 namespace {
 
-// n steps with a pair of HIP events attached to every step kernel's dispatch
-// on the context's stream (no marker packets between the steps); each[i] (if
-// non-null) receives step i's kernel duration in us.
+// n steps on the context's stream, each step kernel's dispatch carrying a stop
+// event (its end timestamp).  Step i's duration runs from the previous step
+// kernel's end to its own: the kernel plus the dispatch gap before it, which
+// is what a march pays.  The first step of each chunk of kPool (after a host
+// synchronization) and a step that first enqueues the reduction of pending
+// checks carry a start event as well and are timed from it.  Start events on
+// every dispatch would add a marker packet, several microseconds, per step.
+// each[i] (if non-null) receives step i's duration in us.
 lbm_status step_with_events(lbm_ctx* c, int64_t n, double* each, double* mean_kernel_us,
                             double* wall_ms) {
   constexpr int kPool = 512;
@@ -669,8 +681,10 @@ lbm_status step_with_events(lbm_ctx* c, int64_t n, double* each, double* mean_ke
   int64_t done = 0;
   while (done < n) {
     const int64_t chunk = std::min<int64_t>(kPool, n - done);
+    bool started[kPool];
     for (int64_t i = 0; i < chunk; ++i) {
-      const lbm_status s = one_step(c, c->events[2 * i], c->events[2 * i + 1]);
+      started[i] = (i == 0);
+      const lbm_status s = one_step(c, c->events[2 * i], c->events[2 * i + 1], &started[i]);
       if (s != LBM_OK) return s;
     }
     // a marker after the chunk: the step events are kernel timestamps
@@ -678,7 +692,8 @@ lbm_status step_with_events(lbm_ctx* c, int64_t n, double* each, double* mean_ke
     LBM_HIP(c, hipEventSynchronize(wall1), "hipEventSynchronize");
     for (int64_t i = 0; i < chunk; ++i) {
       float ms = 0.0f;
-      LBM_HIP(c, hipEventElapsedTime(&ms, c->events[2 * i], c->events[2 * i + 1]), "hipEventElapsedTime");
+      const hipEvent_t from = started[i] ? c->events[2 * i] : c->events[2 * i - 1];
+      LBM_HIP(c, hipEventElapsedTime(&ms, from, c->events[2 * i + 1]), "hipEventElapsedTime");
       total_ms += ms;
       if (each) each[done + i] = 1000.0 * double(ms);
     }

@@ -61,12 +61,15 @@ def test_replayed_step_graph_equals_eager_steps(mhd):
     ref.close()
 
 
-@pytest.mark.parametrize("case", ["flow", "mhd", "d2q9"])
+@pytest.mark.parametrize("case", ["flow", "flow_short_ring", "mhd", "d2q9"])
 def test_timed_steps_compute_what_plain_steps_compute(case):
-    """lbm_step_times (events attached to each step kernel's launch) over 700
-    steps, more than one batch of its event pool, residual checks on: the state
-    and the residual history equal those of 700 plain steps bit for bit, and
-    every step's duration is positive and finite; lbm_step_timed likewise."""
+    """lbm_step_times (an event on each step kernel's launch) over 700 steps,
+    more than one batch of its event pool, residual checks on: the state and
+    the residual history equal those of 700 plain steps bit for bit, every
+    step's duration is positive and finite, and the durations (each from the
+    previous step kernel's end) sum to no more than the call's wall time;
+    lbm_step_timed likewise.  With a ring of 6 history records the reduction
+    of pending checks runs inside the timed calls every 60 steps."""
     import torch
 
     import paper_0809_4730_amd as pkg
@@ -81,17 +84,21 @@ def test_timed_steps_compute_what_plain_steps_compute(case):
         shape, bc = (64, 6, 10), (PER, WALL, WALL)
         kw = dict(mhd=dict(gamma_m=0.4, chi=0.05, eta=0.03, B0=(0.01, 0.02, -0.01))) \
             if case == "mhd" else {}
+        if case == "flow_short_ring":
+            kw = dict(history_len=6)
         s = glbe.rates(0.05, gamma)
         F = (1e-5, 0.0, 0.0)
     sims = [pkg.Simulation(shape, bc, gamma, s, storage="f32", force=F, **kw) for _ in range(3)]
     t, wall_ms = sims[0].step_times(700)
     assert len(t) == 700 and np.all(np.isfinite(t)) and np.all(t > 0) and wall_ms > 0
+    assert t.sum() / 1000.0 <= wall_ms * (1.0 + 1e-6)
     mean_us, wall2 = sims[1].step_timed(700)
-    assert mean_us > 0 and wall2 > 0
+    assert mean_us > 0 and wall2 > 0 and 700 * mean_us / 1000.0 <= wall2 * (1.0 + 1e-6)
     sims[2].step(700)
     torch.cuda.synchronize()
     states = [sim.get_state() for sim in sims]
     hists = [sim.history(100) for sim in sims]
+    assert len(hists[2]) == (6 if case == "flow_short_ring" else 70)
     for st, h in zip(states[:2], hists[:2]):
         if case == "mhd":
             assert torch.equal(st[0], states[2][0]) and torch.equal(st[1], states[2][1])
