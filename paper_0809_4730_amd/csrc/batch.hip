@@ -53,10 +53,13 @@ __global__ __launch_bounds__(kBlock) void batch_step(GridArgs g, BatchArgs ba,
     const uint32_t n = base + local;
     R f[Q19];
     gather19<S, false, WIDE>(fin, g.stride, n, b, c, f);
+    R uold[3];
+    if constexpr (CHECK) load_usnap<R, WIDE, false>(g, usnap, n, uold);
     const NodeMacro<R> mac = collide19<R>(f, c.F[0], c.F[1], c.F[2], c);
     store19<S, false, WIDE>(fout, g, n, f);
     if constexpr (CHECK)
-      check_node<R, WIDE>(g, usnap, n, mac.drho, mac.jx, mac.jy, mac.jz, mac.ux, mac.uy, mac.uz, acc);
+      check_node<R, WIDE, false>(g, usnap, n, uold, mac.drho, mac.jx, mac.jy, mac.jz, mac.ux,
+                                 mac.uy, mac.uz, acc);
   }
   if constexpr (CHECK) write_partials(partials, lb, acc);
 }

@@ -198,13 +198,16 @@ __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<type
     gather19<S, MOVING, WIDE, NTL>(fin, g.stride, n, b, c, f);
     R Fx, Fy, Fz;
     load_force<R, WIDE, NTL>(g, c, force, FIELD, n, Fx, Fy, Fz);
+    R uold[3];
+    if constexpr (CHECK) load_usnap<R, WIDE, NTL>(g, usnap, n, uold);
     const NodeMacro<R> mac = collide19<R>(f, Fx, Fy, Fz, c);
     if constexpr (SR)
       store_stochastic<S, NT, WIDE, Q19>(fout, g, n, f);
     else
       store19<S, NT, WIDE>(fout, g, n, f);
     if constexpr (CHECK)
-      check_node<R, WIDE>(g, usnap, n, mac.drho, mac.jx, mac.jy, mac.jz, mac.ux, mac.uy, mac.uz, acc);
+      check_node<R, WIDE, NT>(g, usnap, n, uold, mac.drho, mac.jx, mac.jy, mac.jz, mac.ux, mac.uy,
+                              mac.uz, acc);
   }
   if constexpr (CHECK) write_partials(partials, lb, acc);
 }
@@ -245,12 +248,15 @@ __global__ __launch_bounds__(kBlock) void mhd_step(GridArgs g, CollideArgs<R> c,
       gather19<R, MOVING, WIDE, NTL>(fin, g.stride, n, bf, c, f);
       R Fx, Fy, Fz;
       load_force<R, WIDE, NTL>(g, c, force, FIELD, n, Fx, Fy, Fz);
+      R uold[3];
+      if constexpr (CHECK) load_usnap<R, WIDE, NTL>(g, usnap, n, uold);
       const Coupled<R> cp = lorentz_solve<R>(f, gg, Fx, Fy, Fz, c, m);
       const NodeMacro<R> mac = collide19<R>(f, cp.Fx, cp.Fy, cp.Fz, c);
       collide_g<R>(gg, cp, mac.ux, mac.uy, mac.uz, m);
       store19<R, NT, WIDE>(fout, g, n, f);
       if constexpr (CHECK)
-        check_node<R, WIDE>(g, usnap, n, mac.drho, mac.jx, mac.jy, mac.jz, mac.ux, mac.uy, mac.uz, acc);
+        check_node<R, WIDE, NT>(g, usnap, n, uold, mac.drho, mac.jx, mac.jy, mac.jz, mac.ux,
+                                mac.uy, mac.uz, acc);
     } else {
       const Coupled<R> cp = field_only<R>(gg, m);
       collide_g<R>(gg, cp, R(0), R(0), R(0), m);

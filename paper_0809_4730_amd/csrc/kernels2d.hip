@@ -66,17 +66,27 @@ __device__ __forceinline__ void load_force2(const GridArgs& g, const CollideArgs
   }
 }
 
-// FP64 residual bookkeeping of one node with a two-component velocity snapshot.
+// The node's two-component velocity snapshot of the previous check, loaded
+// with the populations so that its latency hides behind theirs.
 template <typename R, bool WIDE>
+__device__ __forceinline__ void load_usnap2(const GridArgs& g, const R* __restrict__ usnap, uint32_t n,
+                                            R (&uold)[2]) {
+#pragma unroll
+  for (int k = 0; k < 2; ++k) uold[k] = *elem<WIDE>(usnap + static_cast<int64_t>(k) * g.stride, n);
+}
+
+// FP64 residual bookkeeping of one node, given its snapshot from load_usnap2.
+template <typename R, bool WIDE, bool NT>
 __device__ __forceinline__ void check_node2(const GridArgs& g, R* __restrict__ usnap, uint32_t n,
-                                            const NodeMacro<R>& mac, double (&acc)[kPartials]) {
+                                            const R (&uold)[2], const NodeMacro<R>& mac,
+                                            double (&acc)[kPartials]) {
   const R ur[2] = {mac.ux, mac.uy};
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
     R* p = elem<WIDE>(usnap + static_cast<int64_t>(k) * g.stride, n);
     const double uk = static_cast<double>(ur[k]);
-    const double d = uk - static_cast<double>(*p);
-    *p = ur[k];
+    const double d = uk - static_cast<double>(uold[k]);
+    st_pop<NT>(p, ur[k]);
     acc[0] += d * d;
     acc[1] += uk * uk;
   }
@@ -164,12 +174,14 @@ __global__ __launch_bounds__(kBlock) void glbe2_step(GridArgs g, CollideArgs<typ
     gather9<S, WIDE>(fin, g.stride, n, b, f);
     R Fx, Fy;
     load_force2<R, WIDE>(g, c, force, FIELD, n, Fx, Fy);
+    R uold[2];
+    if constexpr (CHECK) load_usnap2<R, WIDE>(g, usnap, n, uold);
     const NodeMacro<R> mac = collide9<R>(f, Fx, Fy, c);
     if constexpr (SR)
       store_stochastic<S, NT, WIDE, Q9>(fout, g, n, f);
     else
       store9<S, NT, WIDE>(fout, g, n, f);
-    if constexpr (CHECK) check_node2<R, WIDE>(g, usnap, n, mac, acc);
+    if constexpr (CHECK) check_node2<R, WIDE, NT>(g, usnap, n, uold, mac, acc);
   }
   if constexpr (CHECK) write_partials(partials, lb, acc);
 }
@@ -193,6 +205,8 @@ __global__ __launch_bounds__(kBlock) void mhd2_step(GridArgs g, CollideArgs<R> c
     gather_g5<R, WIDE>(gin, g.stride, n, b, gg);
     R Fx, Fy;
     load_force2<R, WIDE>(g, c, force, FIELD, n, Fx, Fy);
+    R uold[2];
+    if constexpr (CHECK) load_usnap2<R, WIDE>(g, usnap, n, uold);
     const Coupled2<R> cp = lorentz_solve2<R>(f, gg, Fx, Fy, c, m);
     const NodeMacro<R> mac = collide9<R>(f, cp.Fx, cp.Fy, c);
     collide_g5<R>(gg, cp, mac.ux, mac.uy, m);
@@ -203,7 +217,7 @@ __global__ __launch_bounds__(kBlock) void mhd2_step(GridArgs g, CollideArgs<R> c
 #pragma unroll
       for (int a = 0; a < Q5; ++a) gflat[j * Q5 + a] = gg[j][a];
     store_planes<R, NT, WIDE, 2 * Q5>(gout, g, n, gflat);
-    if constexpr (CHECK) check_node2<R, WIDE>(g, usnap, n, mac, acc);
+    if constexpr (CHECK) check_node2<R, WIDE, NT>(g, usnap, n, uold, mac, acc);
   }
   if constexpr (CHECK) write_partials(partials, lb, acc);
 }

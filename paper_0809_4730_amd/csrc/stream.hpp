@@ -303,20 +303,30 @@ __device__ __forceinline__ void store_stochastic(S* __restrict__ fout, const Gri
   }
 }
 
-// Residual / reduction bookkeeping of one node, accumulated in FP64.  The
-// velocity snapshot is kept in the compute type R: u is an R value, so the
-// FP64 difference of two snapshots is exact.
-template <typename R, bool WIDE>
+// The node's velocity snapshot of the previous check, loaded with the
+// populations (before the collision) so that its latency hides behind theirs.
+template <typename R, bool WIDE, bool NTL>
+__device__ __forceinline__ void load_usnap(const GridArgs& g, const R* __restrict__ usnap, uint32_t n,
+                                           R (&uold)[3]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) uold[k] = ld_pop<NTL>(elem<WIDE>(usnap + static_cast<int64_t>(k) * g.stride, n));
+}
+
+// Residual / reduction bookkeeping of one node, accumulated in FP64, given the
+// snapshot `uold` from load_usnap.  The velocity snapshot is kept in the
+// compute type R: u is an R value, so the FP64 difference of two snapshots is
+// exact.
+template <typename R, bool WIDE, bool NT>
 __device__ __forceinline__ void check_node(const GridArgs& g, R* __restrict__ usnap, uint32_t n,
-                                           R drho, R jx, R jy, R jz, R ux, R uy, R uz,
-                                           double (&acc)[kPartials]) {
+                                           const R (&uold)[3], R drho, R jx, R jy, R jz, R ux,
+                                           R uy, R uz, double (&acc)[kPartials]) {
   const R ur[3] = {ux, uy, uz};
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     R* p = elem<WIDE>(usnap + static_cast<int64_t>(k) * g.stride, n);
     const double uk = static_cast<double>(ur[k]);
-    const double d = uk - static_cast<double>(*p);
-    *p = ur[k];
+    const double d = uk - static_cast<double>(uold[k]);
+    st_pop<NT>(p, ur[k]);
     acc[0] += d * d;
     acc[1] += uk * uk;
   }
