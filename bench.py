@@ -235,9 +235,10 @@ def hbm_ceiling(shape=(256, 256, 256), reps=10):
     neighbour, gather and store code without the arithmetic; walls as in the
     duct, y and z, and in the coupled workload, y).  XCD chunks of 2,
     streaming loads and stores; each with no cap on the waves per SIMD and
-    with the steps' caps of 5 and 3.  Median of `reps` launches, each between
-    two HIP events on the current stream; the best of the caps is the
-    ceiling."""
+    with the steps' caps of 5 and 3.  Mean of `reps` back-to-back launches
+    between two HIP events on the current stream, after two warm-up launches
+    (like the steps' durations, the dispatch gaps included); the best of the
+    caps is the ceiling."""
     import torch
 
     import paper_0809_4730_amd as pkg
@@ -251,15 +252,15 @@ def hbm_ceiling(shape=(256, 256, 256), reps=10):
                                 (4, "coupled_exact_copy", (False, True, False))):
         best = None
         for waves in (8, 5, 3):
-            ts = []
-            for _ in range(reps + 2):
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record()
+            for _ in range(2):
+                pkg.bandwidth_probe(pattern, src, dst, shape, walls=walls, waves=waves)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
                 nbytes = pkg.bandwidth_probe(pattern, src, dst, shape, walls=walls, waves=waves)
-                e1.record()
-                e1.synchronize()
-                ts.append(e0.elapsed_time(e1) * 1e3)
-            us = statistics.median(ts[2:])
+            e1.record()
+            e1.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / reps
             e = {"bytes": nbytes, "waves": waves, "us": round(us, 2),
                  "GBs": round(nbytes / (us * 1e-6) / 1e9, 1)}
             out["%s_waves%d" % (key, waves)] = e
