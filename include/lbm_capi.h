@@ -28,7 +28,9 @@
  *   - Device memory is owned by the caller.  The library allocates no device
  *     memory: the caller provides one workspace (size from lbm_workspace_bytes)
  *     and, for the adjoint, one adjoint workspace.  The library owns only the
- *     host-side context object.
+ *     host-side context object and, with it, 4 KB of pinned host memory
+ *     (hipHostMalloc) that history reads copy through; lbm_destroy frees
+ *     both.
  *   - All device work is enqueued on the caller's HIP stream given at
  *     lbm_create.  Calls documented as "synchronizes" wait for that stream.
  *   - A context is not thread-safe; distinct contexts are independent.
@@ -278,7 +280,9 @@ lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
  * fraction of a microsecond).  The first step of every 512, and a step that
  * first reduces pending residual checks, is timed from a start event on its
  * own dispatch instead (the kernel alone).  No marker packets sit between the
- * steps otherwise, so the call marches at the rate of lbm_step. */
+ * steps otherwise, so the call marches at the rate of lbm_step.  Before it
+ * returns, the call also reduces the pending residual checks into the history
+ * (the records are the same as when lbm_history does it). */
 lbm_status lbm_step_timed(lbm_ctx* ctx, int64_t n, double* mean_kernel_us, double* wall_ms);
 
 /* Like lbm_step_timed, but writes every step's duration in

@@ -63,6 +63,18 @@ struct lbm_ctx {
   lbm::MagArgs<float> mf;
   std::string err;
   std::vector<hipEvent_t> events;
+  // pinned host staging for history reads of up to kHostRecs records (a copy
+  // into pageable memory costs tens of microseconds more); null if the
+  // allocation failed, and then reads go to pageable memory
+  static constexpr int64_t kHostRecs = 64;
+  double* host_rec = nullptr;
+
+  lbm_ctx() = default;
+  lbm_ctx(const lbm_ctx&) = delete;
+  lbm_ctx& operator=(const lbm_ctx&) = delete;
+  ~lbm_ctx() {
+    if (host_rec) (void)hipHostFree(host_rec);
+  }
 
   void* f(int i) const { return ws + L.f[i]; }
   void* g(int i) const { return p.mhd ? static_cast<void*>(ws + L.g[i]) : nullptr; }

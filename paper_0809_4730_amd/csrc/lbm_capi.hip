@@ -461,14 +461,17 @@ lbm_status read_records(lbm_ctx* c, int64_t first, int64_t count, std::vector<do
   const int64_t slot0 = first % len;
   const int64_t n1 = std::min(count, len - slot0);
   const size_t rec = kRecordDoubles * sizeof(double);
-  LBM_HIP(c, hipMemcpyAsync(out.data(), c->ring() + slot0 * kRecordDoubles, size_t(n1) * rec,
+  // through the pinned staging buffer when the records fit in it
+  double* dst = (c->host_rec && count <= lbm_ctx::kHostRecs) ? c->host_rec : out.data();
+  LBM_HIP(c, hipMemcpyAsync(dst, c->ring() + slot0 * kRecordDoubles, size_t(n1) * rec,
                             hipMemcpyDeviceToHost, c->stream),
           "history copy");
   if (count > n1)
-    LBM_HIP(c, hipMemcpyAsync(out.data() + n1 * kRecordDoubles, c->ring(), size_t(count - n1) * rec,
+    LBM_HIP(c, hipMemcpyAsync(dst + n1 * kRecordDoubles, c->ring(), size_t(count - n1) * rec,
                               hipMemcpyDeviceToHost, c->stream),
             "history copy");
   LBM_HIP(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  if (dst != out.data()) std::copy(dst, dst + count * kRecordDoubles, out.begin());
   return LBM_OK;
 }
 
@@ -564,6 +567,12 @@ lbm_status lbm_create(const lbm_grid* grid, const lbm_params* params, const void
   if (workspace_bytes < L.total) return fail(nullptr, LBM_ENOWS, "workspace too small");
 
   lbm_ctx* c = new lbm_ctx();
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->host_rec),
+                    size_t(lbm_ctx::kHostRecs) * kRecordDoubles * sizeof(double),
+                    hipHostMallocDefault) != hipSuccess) {
+    c->host_rec = nullptr;
+    (void)hipGetLastError();  // reads fall back to pageable memory
+  }
   c->grid = *grid;
   c->p = *params;
   c->L = L;
@@ -666,7 +675,8 @@ namespace {
 // synchronization) and a step that first enqueues the reduction of pending
 // checks carry a start event as well and are timed from it.  Start events on
 // every dispatch would add a marker packet, several microseconds, per step.
-// each[i] (if non-null) receives step i's duration in us.
+// The pending residual checks are reduced before the call returns.  each[i]
+// (if non-null) receives step i's duration in us.
 lbm_status step_with_events(lbm_ctx* c, int64_t n, double* each, double* mean_kernel_us,
                             double* wall_ms) {
   constexpr int kPool = 512;
@@ -687,7 +697,15 @@ lbm_status step_with_events(lbm_ctx* c, int64_t n, double* each, double* mean_ke
       const lbm_status s = one_step(c, c->events[2 * i], c->events[2 * i + 1], &started[i]);
       if (s != LBM_OK) return s;
     }
-    // a marker after the chunk: the step events are kernel timestamps
+    if (done + chunk == n) {
+      // the pending residual checks reduced behind the last step on the GPU
+      // (the records do not depend on when), so that reading the history
+      // after the call waits for nothing but the copy
+      const lbm_status s = flush_checks(c);
+      if (s != LBM_OK) return s;
+    }
+    // a marker after the chunk (after the whole call for the last one): the
+    // step events are kernel timestamps
     LBM_HIP(c, hipEventRecord(wall1, c->stream), "hipEventRecord");
     LBM_HIP(c, hipEventSynchronize(wall1), "hipEventSynchronize");
     for (int64_t i = 0; i < chunk; ++i) {
@@ -699,8 +717,6 @@ lbm_status step_with_events(lbm_ctx* c, int64_t n, double* each, double* mean_ke
     }
     done += chunk;
   }
-  LBM_HIP(c, hipEventRecord(wall1, c->stream), "hipEventRecord");
-  LBM_HIP(c, hipEventSynchronize(wall1), "hipEventSynchronize");
   float wms = 0.0f;
   LBM_HIP(c, hipEventElapsedTime(&wms, wall0, wall1), "hipEventElapsedTime");
   *mean_kernel_us = 1000.0 * total_ms / double(n);
