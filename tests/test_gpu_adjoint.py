@@ -164,7 +164,7 @@ def test_unrolled_adjoint_matches_oracle_elementwise():
         sim = _sim(shape, bc, gamma, s, "f64", F)
         grads.append(sim.adjoint_unrolled(n, K).cpu().numpy())
         assert sim.t == n
-    assert rel(grads[0], ref) < 1e-11, rel(grads[0], ref)
+    assert rel(grads[0], ref) < 1e-12, rel(grads[0], ref)
     # checkpoint spacing changes only where states are recomputed, not the result
     assert np.array_equal(grads[0], grads[1]) and np.array_equal(grads[0], grads[2])
 

@@ -64,7 +64,7 @@ def test_extended_domain_fp64_matches_oracle(shape, bc, pad, nsteps):
     _, u_o, _, _, _ = mhd.coupled_fields(f_s, g_s[(slice(None), slice(None)) + box], Ff, gamma,
                                          gm, p["chi"], p["eta"])
     ug = ug.cpu().numpy()
-    assert rel(ug[(slice(None),) + box], u_o) < 1e-11
+    assert rel(ug[(slice(None),) + box], u_o) < 1e-12
     assert np.all(ug[:, outside] == 0.0)
     assert np.all(rho.cpu().numpy()[outside] == 1.0)
     assert rel(Bg.cpu().numpy(), g_s.sum(axis=1)) < 1e-14

@@ -102,7 +102,7 @@ def test_d2q9_fp64_matches_oracle(shape, bc, nsteps):
     fs = d.stream(fo, bc)
     _, rho_o, _, u_o = d.fields(fs, F, gamma)
     ug = ug.cpu().numpy()[:, 0]
-    assert rel(ug[:2], u_o) < 1e-11
+    assert rel(ug[:2], u_o) < 1e-12
     assert np.all(ug[2] == 0.0)
     assert rel(rho.cpu().numpy()[0], rho_o) < 1e-14
 
@@ -188,9 +188,14 @@ def test_d2q5_mhd_fp64_matches_oracle(shape, bc, nsteps):
         fo, go, u, B = d.mhd_step(fo, go, Ff, pp, bc)
     assert rel(_from_f(fg), fo) < 1e-12
     assert rel(_from_g(gg, B0), go) < 1e-13
-    _, ug, Bg = sim.moments("f64")
+    rho_g, ug, Bg = sim.moments("f64")
     fs, gs = d.stream(fo, bc), d.stream_g(go, bc, B0)
-    _, u_o, B_o, _, _ = d.coupled_fields(fs, gs, Ff, gamma, gm, p["chi"], p["eta"])
+    rho_o, u_o, B_o, _, _ = d.coupled_fields(fs, gs, Ff, gamma, gm, p["chi"], p["eta"])
+    # u is a cancelling sum of populations much larger than it: the momentum
+    # rho u is held to the 1e-12 bar against the populations it sums, u itself
+    # to 1e-11 relative to u (measured up to 4.9e-13)
+    mom_g = rho_g.cpu().numpy()[0] * ug.cpu().numpy()[:2, 0]
+    assert np.linalg.norm(mom_g - rho_o * u_o) < 1e-12 * np.linalg.norm(fs)
     assert rel(ug.cpu().numpy()[:2, 0], u_o) < 1e-11
     assert rel(Bg.cpu().numpy()[:2, 0], B_o) < 1e-14
     assert np.all(Bg.cpu().numpy()[2] == 0.0)

@@ -255,7 +255,7 @@ def test_poiseuille_workload_matches_oracle_and_parabola():
         ug = u[0].cpu().numpy()
         assert np.ptp(ug, axis=(1, 2)).max() < 1e-17
         uo = fl.velocity()[0][:, 0, 0]
-        assert rel(ug[:, 0, 0], uo) < 1e-11
+        assert rel(ug[:, 0, 0], uo) < 1e-12  # measured 3.7e-14 (gamma 1), 1.4e-15 (0.1)
         z = np.arange(H) + 0.5
         par = cfg["F"][0] * z * (H - z) / (2 * cfg["nu"])
         assert rel(ug[:, 0, 0], par) < 5e-3
