@@ -1287,6 +1287,8 @@ def main():
         "roofline": {"bound": head["bound"], "achieved": head["achieved_GBs"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": head["frac"],
                      "traffic": traffic,
+                     "frac_counter_traffic": (round(traffic / (head["kernel_us"] * 1e-6) / 1e9
+                                                    / HBM_PEAK_GBS, 4) if traffic else None),
                      "traffic_source": "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE of this kernel "
                                        "in profiles/traffic.json, used only when taken on the "
                                        "current kernel sources (kernel_hash), else null",
