@@ -69,6 +69,32 @@ def test_duct64_fp32_bench_kernel_one_and_fifty_steps():
     assert err < bound
 
 
+def test_duct64_fp64_steady_state_matches_oracle():
+    """The 64^3 duct (its force, nu = 0.131) marched in FP64 storage at
+    gamma = 0.05 to a residual of 1e-8 (the Sec. 5 stopping rule, checked every
+    10 steps): the GPU crosses at the oracle's step, and at that step its
+    state and velocity equal the oracle's to 1e-12 relative.  The oracle
+    takes some 40 s for the 580 steps."""
+    announce("64^3 fp64 duct, gamma 0.05, steady state against the oracle")
+    shape, gamma, tol = (64, 64, 64), 0.05, 1e-8
+    cfg = inputs.DUCT64
+    sim = _duct_sim(shape, "f64", gamma)
+    steps, r = sim.run_to_residual(tol, 20000, poll_every=100)
+    assert steps > 0 and r < tol
+    sim.close()
+    fl = glbe.Flow(shape, cfg["bc"], inputs.duct_force(shape, cfg["F0"]), gamma,
+                   glbe.rates(cfg["nu"], gamma))
+    assert fl.run_to(tol, 20000)
+    assert fl.t == steps
+    sim = _duct_sim(shape, "f64", gamma)
+    sim.step(steps)
+    err_f = rel(sim.get_state().cpu().numpy(), fl.post)
+    _, u, _ = sim.moments("f64")
+    err_u = rel(u.cpu().numpy(), fl.velocity())
+    announce("steady state at step %d: state rel %.3e, u rel %.3e" % (steps, err_f, err_u))
+    assert err_f < 1e-12 and err_u < 1e-12
+
+
 @pytest.mark.parametrize("storage,check", [("f32", False), ("f32", True), ("f64", False),
                                            ("bf16", False), ("f16", True)])
 def test_duct256_bench_kernel_one_step(storage, check):
