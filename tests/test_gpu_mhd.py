@@ -144,6 +144,51 @@ def test_hartmann_workload(Ha, Pm):
     assert rel(uo, uex) < tol and rel(bo, bex) < tol
 
 
+def test_hartmann_fp64_steady_state_matches_oracle():
+    """The Hartmann workload (32x32x128, Ha = 10, Pm = 0.01, gamma = gamma_m =
+    0.1) in FP64 storage marched to R < 1e-8.  x and z are periodic and the
+    flow is homogeneous along them, so the oracle marches one 1 x 32 x 1
+    column (its residual equals the whole lattice's): both cross at the same
+    step, and there the GPU's flow and induction populations at every (x, z)
+    equal the oracle's column to 1e-12 relative (deviations from the rest
+    state), its velocity and induced field likewise."""
+    import torch
+    announce("hartmann fp64 steady state against the oracle")
+    cfg = inputs.HARTMANN
+    shape, ny = cfg["shape"], cfg["shape"][1]
+    gamma, gm = cfg["gamma"], cfg["gamma_m"]
+    B0, chi = inputs.hartmann_parameters(10.0, 0.01, ny, cfg["nu"], cfg["eta"])
+    B0v = np.array([0.0, B0, 0.0])
+    p = dict(gamma_m=gm, chi=chi, eta=cfg["eta"], B0=tuple(B0v))
+    s = glbe.rates(cfg["nu"], gamma)
+    sim = _mhd_sim(shape, cfg["bc"], gamma, s, "f64", cfg["F"], p)
+    steps, r = sim.run_to_residual(1e-8, 100000, poll_every=100)
+    assert steps > 0 and r < 1e-8
+    sim.close()
+    col = (1, ny, 1)
+    fl = mhd.MHDFlow(col, cfg["bc"], np.array(cfg["F"]), gamma, s, gm, chi, cfg["eta"], B0v)
+    assert fl.run_to(1e-8, 100000)
+    assert fl.t == steps
+    sim = _mhd_sim(shape, cfg["bc"], gamma, s, "f64", cfg["F"], p)
+    sim.step(steps)
+    fg, gg = sim.get_state()
+    f = from_gpu_f(fg)
+    g = from_gpu_g(gg, B0v) - mhd.initial_g(shape, B0v)
+    fo = np.broadcast_to(fl.post_f, f.shape)
+    go = np.broadcast_to(fl.post_g - mhd.initial_g(col, B0v), g.shape)
+    err_f, err_g = rel(f, fo), rel(g, go)
+    _, ug, Bg = sim.moments("f64")
+    Ff = inputs.uniform_force(col, np.array(cfg["F"]))
+    f_s = glbe.stream(fl.post_f, cfg["bc"])
+    g_s = mhd.stream_g(fl.post_g, cfg["bc"], B0v)
+    _, u_o, B_o, _, _ = mhd.coupled_fields(f_s, g_s, Ff, gamma, gm, chi, cfg["eta"])
+    ug, bg = ug.cpu().numpy(), Bg.cpu().numpy() - B0v.reshape(3, 1, 1, 1)
+    err_u = rel(ug, np.broadcast_to(u_o, ug.shape))
+    err_b = rel(bg, np.broadcast_to(B_o - B0v.reshape(3, 1, 1, 1), bg.shape))
+    announce("step %d: f %.3e, g %.3e, u %.3e, b %.3e" % (steps, err_f, err_g, err_u, err_b))
+    assert max(err_f, err_g, err_u, err_b) < 1e-12
+
+
 def test_paper_hartmann_preconditioning_ordering():
     """The paper's (gamma, gamma_m) findings on its own Hartmann case (Re = 286,
     Ha = 71.6, Pm = 1e-6, nu = eta = 0.004, half-width 64), FP64 to 1e-8: at
