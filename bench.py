@@ -30,9 +30,14 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 MALL_BYTES = 256 * 1024 * 1024   # last-level cache (Infinity Cache) of the MI355X
+# the step kernels, their launch (shape, wave cap, timing events) and the
+# constants they are given: a change to any of these invalidates the counter
+# traffic taken on them
 KERNEL_SOURCES = ["paper_0809_4730_amd/csrc/kernels.hip", "paper_0809_4730_amd/csrc/collide.hpp",
                   "paper_0809_4730_amd/csrc/common.hpp", "paper_0809_4730_amd/csrc/stream.hpp",
-                  "paper_0809_4730_amd/csrc/lattice.hpp", "paper_0809_4730_amd/csrc/lbm_capi.hip"]
+                  "paper_0809_4730_amd/csrc/lattice.hpp", "paper_0809_4730_amd/csrc/lbm_capi.hip",
+                  "paper_0809_4730_amd/csrc/launch.hpp", "paper_0809_4730_amd/csrc/ctx.hpp",
+                  "paper_0809_4730_amd/csrc/args.hpp"]
 STORAGE_BYTES = {"f32": 4, "f64": 8, "bf16": 2, "f16": 2}
 METRIC = "MLUPS, % HBM roofline; wall time to 1e-8 residual, gamma<1 vs plain gamma=1"
 
