@@ -59,6 +59,9 @@ struct GridArgs {
   FastDiv div_chunk;       // division by xcd_chunk
   int32_t wide;            // 1: 64-bit element offsets even where 32-bit byte offsets fit
   int32_t nt_load;         // 1: streaming population and force loads (launchers: NTL flag)
+  int32_t force_cached;    // 1: a force field read with streaming population loads keeps
+                           // cacheable loads (it fits in the last-level cache, where the
+                           // streaming traffic leaves it; launchers: the step's load policy)
   uint32_t lds_reserve;    // dynamic LDS bytes per workgroup of a 3D step launch: reserved, not
                            // used, to cap the workgroups per CU (0: no cap)
   uint32_t step;           // the step number a step launch computes (stochastic rounding)

@@ -178,9 +178,13 @@ __device__ __forceinline__ void load_force(const GridArgs& g, const CollideArgs<
 
 // ------------------------------------------------------------------ steps --
 // ROWS: every wave lies in one x-row (nx a multiple of 64; neighbours_rows).
-// SR: 16-bit stores with stochastic rounding (store_stochastic).  NT / NTL:
-// streaming stores / loads.
-template <typename S, bool CHECK, bool FIELD, bool NT, bool NTL, bool MOVING, bool WIDE, bool ROWS,
+// SR: 16-bit stores with stochastic rounding (store_stochastic).  NT:
+// streaming stores.  LOADS: kLoadCached, kLoadStream (streaming loads of
+// populations, force and snapshot) or kLoadStreamKeepForce (streaming loads
+// except the force field's, which stays in the last-level cache).
+constexpr int kLoadCached = 0, kLoadStream = 1, kLoadStreamKeepForce = 2;
+
+template <typename S, bool CHECK, bool FIELD, bool NT, int LOADS, bool MOVING, bool WIDE, bool ROWS,
           bool SR>
 __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<typename Storage<S>::R> c,
                                                     const S* __restrict__ fin, S* __restrict__ fout,
@@ -195,9 +199,10 @@ __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<type
   if (n < static_cast<uint32_t>(g.N)) {
     const Nbr b = ROWS ? neighbours_rows(g, n) : neighbours(g, n);
     R f[Q19];
+    constexpr bool NTL = LOADS != kLoadCached;
     gather19<S, MOVING, WIDE, NTL>(fin, g.stride, n, b, c, f);
     R Fx, Fy, Fz;
-    load_force<R, WIDE, NTL>(g, c, force, FIELD, n, Fx, Fy, Fz);
+    load_force<R, WIDE, LOADS == kLoadStream>(g, c, force, FIELD, n, Fx, Fy, Fz);
     R uold[3];
     if constexpr (CHECK) load_usnap<R, WIDE, NTL>(g, usnap, n, uold);
     const NodeMacro<R> mac = collide19<R>(f, Fx, Fy, Fz, c);
@@ -482,17 +487,20 @@ hipError_t launch_glbe_step(const GridArgs& g, const CollideArgs<typename Storag
                            w = decltype(W)::value, rw = decltype(RW)::value,
                            sr = decltype(SRF)::value && sizeof(S) == 2;
             if (c.moving)
-              launch_step(glbe_step<S, ch, fl, false, false, true, w, rw, sr>, step_grid(g), g.lds_reserve, st,
-                        g, c, a, b, F, usnap, partials);
+              launch_step(glbe_step<S, ch, fl, false, kLoadCached, true, w, rw, sr>, step_grid(g),
+                          g.lds_reserve, st, g, c, a, b, F, usnap, partials);
+            else if (ntl && fl && g.force_cached)
+              launch_step(glbe_step<S, ch, fl, true, fl ? kLoadStreamKeepForce : kLoadStream, false, w, rw, sr>,
+                          step_grid(g), g.lds_reserve, st, g, c, a, b, F, usnap, partials);
             else if (ntl)
-              launch_step(glbe_step<S, ch, fl, true, true, false, w, rw, sr>, step_grid(g), g.lds_reserve, st,
-                        g, c, a, b, F, usnap, partials);
+              launch_step(glbe_step<S, ch, fl, true, kLoadStream, false, w, rw, sr>, step_grid(g),
+                          g.lds_reserve, st, g, c, a, b, F, usnap, partials);
             else if (nt)
-              launch_step(glbe_step<S, ch, fl, true, false, false, w, rw, sr>, step_grid(g), g.lds_reserve, st,
-                        g, c, a, b, F, usnap, partials);
+              launch_step(glbe_step<S, ch, fl, true, kLoadCached, false, w, rw, sr>, step_grid(g),
+                          g.lds_reserve, st, g, c, a, b, F, usnap, partials);
             else
-              launch_step(glbe_step<S, ch, fl, false, false, false, w, rw, sr>, step_grid(g), g.lds_reserve, st,
-                        g, c, a, b, F, usnap, partials);
+              launch_step(glbe_step<S, ch, fl, false, kLoadCached, false, w, rw, sr>, step_grid(g),
+                          g.lds_reserve, st, g, c, a, b, F, usnap, partials);
             return hipGetLastError();
           });
         });

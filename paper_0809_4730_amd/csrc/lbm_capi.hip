@@ -259,6 +259,14 @@ void choose_launch_shape(lbm_ctx* c) {
   // 2% slower for the D2Q9 step at 4096^2
   c->ga.nt_load = pop_bytes > 2.0 * kMallBytes && c->p.lattice != LBM_D2Q9;
   if (l.load != 0) c->ga.nt_load = l.load == 2;
+  // the force field, read again by every step, keeps cacheable loads when it
+  // fits in the last-level cache with room to spare: the streaming population
+  // traffic then leaves it there (256^3: an FP32 field of 201 MB, FP32 step
+  // 439-445 -> 434-438 us, BF16 249 -> 243 us); an FP64 field of 403 MB does
+  // not fit, and cacheable loads of it measured 4% slower
+  const double force_bytes =
+      c->field() ? 3.0 * double(c->L.stride) * double(compute_bytes(c->p.storage)) : 0.0;
+  c->ga.force_cached = force_bytes <= 0.8 * kMallBytes;
   // waves per SIMD: fewer waves in flight stream faster from HBM (measured at
   // 256^3: FP32 flow 466 -> 446 us at 5 waves, 16-bit storage 254 -> 249 us at
   // 6; the FP64 flow step, 4 waves by its registers, 963 -> 933 us at 3, and
