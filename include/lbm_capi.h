@@ -239,7 +239,9 @@ lbm_status lbm_workspace_bytes(const lbm_grid* grid, const lbm_params* params, s
  * stores, a cap on the waves per SIMD (D3Q19: 5 for FP32 storage, 6 for
  * 16-bit storage, 3 for FP64 storage and for the coupled step; D2Q9: 6 for
  * FP32, 4 for FP64, 5 for the coupled FP32 step, none otherwise) and, for
- * D3Q19, streaming loads,
+ * D3Q19, streaming loads (of the flow step's force field only while that
+ * field is larger than 80% of the last-level cache; a smaller one keeps
+ * cacheable loads and stays in that cache from step to step),
  * and lbm_create times a few dozen plain steps on the stream for each
  * of five XCD workgroup mappings (chunks of 1, 2, 4 and 8 workgroups, slabs), keeps
  * the fastest and restores the rest state; it then synchronizes (a few ms to
