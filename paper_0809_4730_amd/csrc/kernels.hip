@@ -218,9 +218,10 @@ __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<type
 }
 
 // EXT: the induction lattice extends beyond the fluid box; nodes outside it
-// relax g with u = 0 and leave f untouched.  NT / NTL: streaming stores /
-// loads.  ROWS (not with EXT): every wave lies in one x-row (neighbours_rows).
-template <typename R, bool CHECK, bool FIELD, bool MOVING, bool EXT, bool WIDE, bool NT, bool NTL,
+// relax g with u = 0 and leave f untouched.  NT: streaming stores; LOADS: the
+// load policy, as for glbe_step.  ROWS (not with EXT): every wave lies in one
+// x-row (neighbours_rows).
+template <typename R, bool CHECK, bool FIELD, bool MOVING, bool EXT, bool WIDE, bool NT, int LOADS,
           bool ROWS>
 __global__ __launch_bounds__(kBlock) void mhd_step(GridArgs g, CollideArgs<R> c, MagArgs<R> m,
                                                    const R* __restrict__ fin, R* __restrict__ fout,
@@ -242,6 +243,7 @@ __global__ __launch_bounds__(kBlock) void mhd_step(GridArgs g, CollideArgs<R> c,
       q = coords(g, n);
       b = neighbours_at(g, q);
     }
+    constexpr bool NTL = LOADS != kLoadCached;
     R gg[3][Q7];
     gather_g<R, WIDE, NTL>(gin, g.stride, n, b, gg);
     bool fluid = true;
@@ -252,7 +254,7 @@ __global__ __launch_bounds__(kBlock) void mhd_step(GridArgs g, CollideArgs<R> c,
       R f[Q19];
       gather19<R, MOVING, WIDE, NTL>(fin, g.stride, n, bf, c, f);
       R Fx, Fy, Fz;
-      load_force<R, WIDE, NTL>(g, c, force, FIELD, n, Fx, Fy, Fz);
+      load_force<R, WIDE, LOADS == kLoadStream>(g, c, force, FIELD, n, Fx, Fy, Fz);
       R uold[3];
       if constexpr (CHECK) load_usnap<R, WIDE, NTL>(g, usnap, n, uold);
       const Coupled<R> cp = lorentz_solve<R>(f, gg, Fx, Fy, Fz, c, m);
@@ -543,7 +545,7 @@ hipError_t launch_mhd_step(const GridArgs& g, const CollideArgs<R>& c, const Mag
           // cavity: per-lane coordinates, regular loads and stores
           return with_flag(c.moving != 0, [&](auto MV) {
             return with_flag(ext, [&](auto EX) {
-              launch_step(mhd_step<R, ch, fl, decltype(MV)::value, decltype(EX)::value, w, false, false, false>, step_grid(g), g.lds_reserve, st,
+              launch_step(mhd_step<R, ch, fl, decltype(MV)::value, decltype(EX)::value, w, false, kLoadCached, false>, step_grid(g), g.lds_reserve, st,
                         g, c, m, a, b, ga, gb, F, usnap, partials);
               return hipGetLastError();
             });
@@ -551,15 +553,18 @@ hipError_t launch_mhd_step(const GridArgs& g, const CollideArgs<R>& c, const Mag
         }
         return with_flag(rows_per_wave(g), [&](auto RW) {
           constexpr bool rw = decltype(RW)::value;
-          if (ntl)
-            launch_step(mhd_step<R, ch, fl, false, false, w, true, true, rw>, step_grid(g), g.lds_reserve, st,
-                        g, c, m, a, b, ga, gb, F, usnap, partials);
+          if (ntl && fl && g.force_cached)
+            launch_step(mhd_step<R, ch, fl, false, false, w, true, fl ? kLoadStreamKeepForce : kLoadStream, rw>,
+                        step_grid(g), g.lds_reserve, st, g, c, m, a, b, ga, gb, F, usnap, partials);
+          else if (ntl)
+            launch_step(mhd_step<R, ch, fl, false, false, w, true, kLoadStream, rw>, step_grid(g),
+                        g.lds_reserve, st, g, c, m, a, b, ga, gb, F, usnap, partials);
           else if (nt)
-            launch_step(mhd_step<R, ch, fl, false, false, w, true, false, rw>, step_grid(g), g.lds_reserve, st,
-                        g, c, m, a, b, ga, gb, F, usnap, partials);
+            launch_step(mhd_step<R, ch, fl, false, false, w, true, kLoadCached, rw>, step_grid(g),
+                        g.lds_reserve, st, g, c, m, a, b, ga, gb, F, usnap, partials);
           else
-            launch_step(mhd_step<R, ch, fl, false, false, w, false, false, rw>, step_grid(g), g.lds_reserve, st,
-                        g, c, m, a, b, ga, gb, F, usnap, partials);
+            launch_step(mhd_step<R, ch, fl, false, false, w, false, kLoadCached, rw>, step_grid(g),
+                        g.lds_reserve, st, g, c, m, a, b, ga, gb, F, usnap, partials);
           return hipGetLastError();
         });
       });

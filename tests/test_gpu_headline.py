@@ -156,21 +156,24 @@ def test_duct256_bench_kernel_one_step(storage, check):
     torch.cuda.empty_cache()
 
 
-def test_coupled256_bench_kernel_one_step():
+@pytest.mark.parametrize("force", ["uniform", "field"])
+def test_coupled256_bench_kernel_one_step(force):
     """The coupled step at 256^3 in the benchmark's launch shape (FP32, walls
     normal to y and B0: the coupled workload's Hartmann setting Ha = 10,
     Pm = 0.01, gamma = gamma_m = 0.1; create-time XCD chunk, streaming loads
-    and stores, row-aligned waves, 3 waves per SIMD): one step from a seeded
-    random state against the oracle's coupled step from the same state at
-    4000 sampled nodes, corners included.  Bars as for the FP32 coupled step
-    on the Hartmann lattice: f 2e-6, g 1e-6 relative, g's deviation from
-    W B0 (what FP32 stores) 1e-5."""
+    and stores, row-aligned waves, 3 waves per SIMD), with the workload's
+    uniform force and with a force field (201 MB, which keeps cacheable loads
+    while the populations stream): one step from a seeded random state
+    against the oracle's coupled step from the same state at 4000 sampled
+    nodes, corners included.  Bars as for the FP32 coupled step on the
+    Hartmann lattice: f 2e-6, g 1e-6 relative, g's deviation from W B0 (what
+    FP32 stores) 1e-5."""
     import torch
 
     import paper_0809_4730_amd as pkg
     from oracle import mhd
     from tests.gpu_util import perms
-    announce("256^3 coupled step, bench launch shape")
+    announce("256^3 coupled step, bench launch shape, %s force" % force)
     cfg = inputs.HARTMANN
     shape = (256, 256, 256)
     nx, ny, nz = shape
@@ -178,9 +181,17 @@ def test_coupled256_bench_kernel_one_step():
     B0v = np.array([0.0, B0, 0.0])
     gamma = 0.1
     s = glbe.rates(cfg["nu"], gamma)
-    F = np.array(cfg["F"], dtype=np.float32).astype(np.float64)
-    sim = pkg.Simulation(shape, cfg["bc"], gamma, s, storage="f32", force=tuple(F),
+    if force == "uniform":
+        F = np.array(cfg["F"], dtype=np.float32).astype(np.float64)
+        F_lib = tuple(F)
+    else:
+        F32 = inputs.duct_force(shape, 1e-5, dtype=np.float32)
+        F_lib = torch.from_numpy(F32).cuda()
+        F = F32.astype(np.float64)
+        del F32
+    sim = pkg.Simulation(shape, cfg["bc"], gamma, s, storage="f32", force=F_lib,
                          mhd=dict(gamma_m=0.1, chi=chi, eta=cfg["eta"], B0=tuple(B0v)))
+    del F_lib
     assert sim.launch["waves"] == 3
     assert sim.launch["store"] == "streaming" and sim.launch["load"] == "streaming"
     p19, p7 = perms()
