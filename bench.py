@@ -1268,6 +1268,16 @@ def main():
     tag = "glbe_step_%s%s_duct%d" % (storage, "_sr" if args.rounding == "stochastic" else "",
                                      args.grid)
     traffic = traffic_from_profiles(tag, khash)
+    # the library keeps cacheable loads for a force field that fits in 80% of
+    # the 256 MB last-level cache (documented at lbm_create); its bytes are then
+    # served from that cache, and only the populations must cross HBM
+    cb = 8 if storage == "f64" else 4
+    N_nodes = shape[0] * shape[1] * shape[2]
+    force_fits = 3 * cb * N_nodes <= 0.8 * MALL_BYTES
+    force_policy = ("cacheable: the field (%d MB) fits in the last-level cache"
+                    if force_fits else "streaming: the field (%d MB) exceeds the last-level cache") \
+        % (3 * cb * N_nodes // 10 ** 6)
+    pop_only_gbs = 2 * 19 * STORAGE_BYTES[storage] * N_nodes / (head["kernel_us"] * 1e-6) / 1e9
     line = {
         "metric": METRIC,
         "value": head["MLUPS"],
@@ -1294,6 +1304,8 @@ def main():
                      "traffic": traffic,
                      "frac_counter_traffic": (round(traffic / (head["kernel_us"] * 1e-6) / 1e9
                                                     / HBM_PEAK_GBS, 4) if traffic else None),
+                     "force_field_loads": force_policy,
+                     "frac_populations_only": round(pop_only_gbs / HBM_PEAK_GBS, 4),
                      "traffic_source": "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE of this kernel "
                                        "in profiles/traffic.json, used only when taken on the "
                                        "current kernel sources (kernel_hash), else null",
