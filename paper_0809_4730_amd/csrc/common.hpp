@@ -62,6 +62,8 @@ struct GridArgs {
   int32_t force_cached;    // 1: a force field read with streaming population loads keeps
                            // cacheable loads (it fits in the last-level cache, where the
                            // streaming traffic leaves it; launchers: the step's load policy)
+  int32_t rest_cached;     // 1: without a cached force field, the rest population's two
+                           // planes keep cacheable loads and stores (launchers, likewise)
   uint32_t lds_reserve;    // dynamic LDS bytes per workgroup of a 3D step launch: reserved, not
                            // used, to cap the workgroups per CU (0: no cap)
   uint32_t step;           // the step number a step launch computes (stochastic rounding)

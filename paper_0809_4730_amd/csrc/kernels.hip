@@ -180,9 +180,11 @@ __device__ __forceinline__ void load_force(const GridArgs& g, const CollideArgs<
 // ROWS: every wave lies in one x-row (nx a multiple of 64; neighbours_rows).
 // SR: 16-bit stores with stochastic rounding (store_stochastic).  NT:
 // streaming stores.  LOADS: kLoadCached, kLoadStream (streaming loads of
-// populations, force and snapshot) or kLoadStreamKeepForce (streaming loads
-// except the force field's, which stays in the last-level cache).
-constexpr int kLoadCached = 0, kLoadStream = 1, kLoadStreamKeepForce = 2;
+// populations, force and snapshot), kLoadStreamKeepForce (streaming loads
+// except the force field's, which stays in the last-level cache) or
+// kLoadStreamKeepRest (streaming loads and stores except the rest
+// population's, whose two planes stay in that cache from step to step).
+constexpr int kLoadCached = 0, kLoadStream = 1, kLoadStreamKeepForce = 2, kLoadStreamKeepRest = 3;
 
 template <typename S, bool CHECK, bool FIELD, bool NT, int LOADS, bool MOVING, bool WIDE, bool ROWS,
           bool SR>
@@ -199,8 +201,8 @@ __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<type
   if (n < static_cast<uint32_t>(g.N)) {
     const Nbr b = ROWS ? neighbours_rows(g, n) : neighbours(g, n);
     R f[Q19];
-    constexpr bool NTL = LOADS != kLoadCached;
-    gather19<S, MOVING, WIDE, NTL>(fin, g.stride, n, b, c, f);
+    constexpr bool NTL = LOADS != kLoadCached, KEEP0 = LOADS == kLoadStreamKeepRest;
+    gather19<S, MOVING, WIDE, NTL, KEEP0>(fin, g.stride, n, b, c, f);
     R Fx, Fy, Fz;
     load_force<R, WIDE, LOADS == kLoadStream>(g, c, force, FIELD, n, Fx, Fy, Fz);
     R uold[3];
@@ -209,7 +211,7 @@ __global__ __launch_bounds__(kBlock) void glbe_step(GridArgs g, CollideArgs<type
     if constexpr (SR)
       store_stochastic<S, NT, WIDE, Q19>(fout, g, n, f);
     else
-      store19<S, NT, WIDE>(fout, g, n, f);
+      store19<S, NT, WIDE, KEEP0>(fout, g, n, f);
     if constexpr (CHECK)
       check_node<R, WIDE, NT>(g, usnap, n, uold, mac.drho, mac.jx, mac.jy, mac.jz, mac.ux, mac.uy,
                               mac.uz, acc);
@@ -243,7 +245,7 @@ __global__ __launch_bounds__(kBlock) void mhd_step(GridArgs g, CollideArgs<R> c,
       q = coords(g, n);
       b = neighbours_at(g, q);
     }
-    constexpr bool NTL = LOADS != kLoadCached;
+    constexpr bool NTL = LOADS != kLoadCached, KEEP0 = LOADS == kLoadStreamKeepRest;
     R gg[3][Q7];
     gather_g<R, WIDE, NTL>(gin, g.stride, n, b, gg);
     bool fluid = true;
@@ -252,7 +254,7 @@ __global__ __launch_bounds__(kBlock) void mhd_step(GridArgs g, CollideArgs<R> c,
       Nbr bf = b;
       if constexpr (EXT) bf = box_walls(g, q, b);
       R f[Q19];
-      gather19<R, MOVING, WIDE, NTL>(fin, g.stride, n, bf, c, f);
+      gather19<R, MOVING, WIDE, NTL, KEEP0>(fin, g.stride, n, bf, c, f);
       R Fx, Fy, Fz;
       load_force<R, WIDE, LOADS == kLoadStream>(g, c, force, FIELD, n, Fx, Fy, Fz);
       R uold[3];
@@ -260,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void mhd_step(GridArgs g, CollideArgs<R> c,
       const Coupled<R> cp = lorentz_solve<R>(f, gg, Fx, Fy, Fz, c, m);
       const NodeMacro<R> mac = collide19<R>(f, cp.Fx, cp.Fy, cp.Fz, c);
       collide_g<R>(gg, cp, mac.ux, mac.uy, mac.uz, m);
-      store19<R, NT, WIDE>(fout, g, n, f);
+      store19<R, NT, WIDE, KEEP0>(fout, g, n, f);
       if constexpr (CHECK)
         check_node<R, WIDE, NT>(g, usnap, n, uold, mac.drho, mac.jx, mac.jy, mac.jz, mac.ux,
                                 mac.uy, mac.uz, acc);
@@ -494,6 +496,10 @@ hipError_t launch_glbe_step(const GridArgs& g, const CollideArgs<typename Storag
             else if (ntl && fl && g.force_cached)
               launch_step(glbe_step<S, ch, fl, true, fl ? kLoadStreamKeepForce : kLoadStream, false, w, rw, sr>,
                           step_grid(g), g.lds_reserve, st, g, c, a, b, F, usnap, partials);
+            else if (ntl && !fl && !sr && g.rest_cached)
+              launch_step(glbe_step<S, ch, fl, true, (!fl && !sr) ? kLoadStreamKeepRest : kLoadStream, false,
+                                    w, rw, sr>,
+                          step_grid(g), g.lds_reserve, st, g, c, a, b, F, usnap, partials);
             else if (ntl)
               launch_step(glbe_step<S, ch, fl, true, kLoadStream, false, w, rw, sr>, step_grid(g),
                           g.lds_reserve, st, g, c, a, b, F, usnap, partials);
@@ -555,6 +561,9 @@ hipError_t launch_mhd_step(const GridArgs& g, const CollideArgs<R>& c, const Mag
           constexpr bool rw = decltype(RW)::value;
           if (ntl && fl && g.force_cached)
             launch_step(mhd_step<R, ch, fl, false, false, w, true, fl ? kLoadStreamKeepForce : kLoadStream, rw>,
+                        step_grid(g), g.lds_reserve, st, g, c, m, a, b, ga, gb, F, usnap, partials);
+          else if (ntl && !fl && g.rest_cached)
+            launch_step(mhd_step<R, ch, fl, false, false, w, true, fl ? kLoadStream : kLoadStreamKeepRest, rw>,
                         step_grid(g), g.lds_reserve, st, g, c, m, a, b, ga, gb, F, usnap, partials);
           else if (ntl)
             launch_step(mhd_step<R, ch, fl, false, false, w, true, kLoadStream, rw>, step_grid(g),

@@ -267,6 +267,14 @@ void choose_launch_shape(lbm_ctx* c) {
   const double force_bytes =
       c->field() ? 3.0 * double(c->L.stride) * double(compute_bytes(c->p.storage)) : 0.0;
   c->ga.force_cached = force_bytes <= 0.8 * kMallBytes;
+  // without a force field to keep, the rest population's plane in both
+  // population buffers (read at the node itself, written there) takes its
+  // place: read back from the cache one step later and overwritten the step
+  // after, it spares HBM both its read and its write (coupled FP32 step at
+  // 256^3, uniform force: 927-937 -> 907-918 us; with the FP32 flow step's
+  // force field kept as well the cache overflows: 437 -> 461 us)
+  const double rest_bytes = 2.0 * double(c->L.stride) * double(storage_bytes(c->p.storage));
+  c->ga.rest_cached = !c->field() && rest_bytes <= 0.8 * kMallBytes;
   // waves per SIMD: fewer waves in flight stream faster from HBM (measured at
   // 256^3: FP32 flow 466 -> 446 us at 5 waves, 16-bit storage 254 -> 249 us at
   // 6; the FP64 flow step, 4 waves by its registers, 963 -> 933 us at 3, and

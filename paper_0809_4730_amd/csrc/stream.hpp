@@ -187,14 +187,16 @@ __device__ __forceinline__ typename Storage<S>::R gather_one(
   return v;
 }
 
-template <typename S, bool MOVING, bool WIDE, bool NTL = false, int A = 0>
+// KEEP0: the rest population's plane keeps cacheable loads under NTL (with
+// cacheable stores, store19's KEEP0, it stays in the last-level cache).
+template <typename S, bool MOVING, bool WIDE, bool NTL = false, bool KEEP0 = false, int A = 0>
 __device__ __forceinline__ void gather19(const S* __restrict__ fin, int64_t stride, uint32_t n,
                                          const Nbr& b,
                                          const CollideArgs<typename Storage<S>::R>& c,
                                          typename Storage<S>::R (&f)[Q19]) {
   if constexpr (A < Q19) {
-    f[A] = gather_one<S, A, MOVING, WIDE, NTL>(fin, stride, n, b, c);
-    gather19<S, MOVING, WIDE, NTL, A + 1>(fin, stride, n, b, c, f);
+    f[A] = gather_one<S, A, MOVING, WIDE, (KEEP0 && A == 0) ? false : NTL>(fin, stride, n, b, c);
+    gather19<S, MOVING, WIDE, NTL, KEEP0, A + 1>(fin, stride, n, b, c, f);
   }
 }
 
@@ -202,27 +204,36 @@ __device__ __forceinline__ void gather19(const S* __restrict__ fin, int64_t stri
 // plane's byte offset in the scalar offset and the node's in the vector offset
 // (no address arithmetic per store; wide_offsets keeps every offset below
 // 2^32).
-template <typename S, bool NT, bool WIDE, int Q>
+// KEEP0: plane 0 takes cacheable stores even under NT.
+template <typename S, bool NT, bool WIDE, int Q, bool KEEP0 = false>
 __device__ __forceinline__ void store_planes(S* __restrict__ out, const GridArgs& g, uint32_t n,
                                              const typename Storage<S>::R (&v)[Q]) {
   if constexpr (WIDE) {
 #pragma unroll
-    for (int a = 0; a < Q; ++a)
-      Storage<S>::template st<NT>(out + static_cast<int64_t>(a) * g.stride + n, v[a]);
+    for (int a = 0; a < Q; ++a) {
+      if (KEEP0 && a == 0)
+        Storage<S>::template st<false>(out + n, v[a]);
+      else
+        Storage<S>::template st<NT>(out + static_cast<int64_t>(a) * g.stride + n, v[a]);
+    }
   } else {
     const __amdgpu_buffer_rsrc_t r = raw_rsrc(out);
     const uint32_t plane = static_cast<uint32_t>(g.stride) * static_cast<uint32_t>(sizeof(S));
     const uint32_t voff = n * static_cast<uint32_t>(sizeof(S));
 #pragma unroll
-    for (int a = 0; a < Q; ++a)
-      Storage<S>::template st_buf<NT>(r, voff, static_cast<uint32_t>(a) * plane, v[a]);
+    for (int a = 0; a < Q; ++a) {
+      if (KEEP0 && a == 0)
+        Storage<S>::template st_buf<false>(r, voff, 0u, v[a]);
+      else
+        Storage<S>::template st_buf<NT>(r, voff, static_cast<uint32_t>(a) * plane, v[a]);
+    }
   }
 }
 
-template <typename S, bool NT, bool WIDE>
+template <typename S, bool NT, bool WIDE, bool KEEP0 = false>
 __device__ __forceinline__ void store19(S* __restrict__ fout, const GridArgs& g, uint32_t n,
                                         const typename Storage<S>::R (&f)[Q19]) {
-  store_planes<S, NT, WIDE, Q19>(fout, g, n, f);
+  store_planes<S, NT, WIDE, Q19, KEEP0>(fout, g, n, f);
 }
 
 // 32-bit finalizer of MurmurHash3 (a bijection with full avalanche).

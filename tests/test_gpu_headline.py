@@ -156,6 +156,52 @@ def test_duct256_bench_kernel_one_step(storage, check):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_duct256_uniform_force_keeps_the_rest_plane(storage):
+    """The 256^3 duct with a uniform force (no field to keep in the
+    last-level cache, so the rest population's planes keep cacheable loads
+    and stores while the others stream): one step from a seeded state
+    against the oracle at 4000 sampled nodes (FP32 2e-6; BF16 one rounding
+    plus the FP32 bar), and three steps bit for bit equal to the same steps
+    with every load and store cacheable."""
+    import torch
+
+    import paper_0809_4730_amd as pkg
+    cfg = inputs.DUCT256
+    shape = cfg["shape"]
+    announce("256^3 %s, uniform force, rest plane cached" % storage)
+    F = (1e-6, 2e-7, 0.0)
+    s = glbe.rates(cfg["nu"], cfg["gamma"])
+    tdt = torch.float32 if storage == "f32" else torch.bfloat16
+    d0 = torch.from_numpy(inputs.random_deviations(shape, seed=13, amp=1e-3)).to(tdt)
+    outs = []
+    for launch in (None, dict(load="cached", store="cached")):
+        sim = pkg.Simulation(shape, cfg["bc"], cfg["gamma"], s, storage=storage, force=F,
+                             launch=launch)
+        if launch is None:
+            assert sim.launch["load"] == "streaming" and sim.launch["store"] == "streaming"
+        sim.set_state(d0.cuda())
+        sim.step(1)
+        outs.append(sim.get_state())
+        sim.step(2)
+        outs.append(sim.get_state())
+        sim.close()
+        del sim
+    assert torch.equal(outs[0], outs[2]) and torch.equal(outs[1], outs[3])
+    nodes = inputs.random_nodes(shape, 4000, seed=13)
+    idx = torch.tensor(nodes, device="cuda")
+    got = outs[0][:, idx[:, 2], idx[:, 1], idx[:, 0]].double().cpu().numpy()
+    del outs
+    torch.cuda.empty_cache()
+    F32 = np.array(F, dtype=np.float32).astype(np.float64)
+    ref = glbe.step_nodes(d0.double().numpy(), inputs.uniform_force(shape, F32), cfg["gamma"], s,
+                          cfg["bc"], nodes)
+    if storage == "f32":
+        assert rel(got, ref) < STEP_TOL
+    else:
+        assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + STEP_TOL * np.abs(ref).max())
+
+
 @pytest.mark.parametrize("force", ["uniform", "field"])
 def test_coupled256_bench_kernel_one_step(force):
     """The coupled step at 256^3 in the benchmark's launch shape (FP32, walls
