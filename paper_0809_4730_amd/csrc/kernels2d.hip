@@ -18,22 +18,28 @@ namespace lbm {
 
 // Opposite directions are adjacent planes (pairs 1-2, 3-4, ...), as in 3D, so
 // the pull offsets are taken relative to each pair's lower plane.
-template <typename S, bool WIDE, int A = 0>
+// KEEP0: streaming loads of the moving populations' planes, the rest
+// population's plane read cacheable (with store9's KEEP0 it stays in the
+// last-level cache from step to step).
+template <typename S, bool WIDE, bool KEEP0 = false, int A = 0>
 __device__ __forceinline__ void gather9(const S* __restrict__ fin, int64_t stride, uint32_t n,
                                         const Nbr& b, typename Storage<S>::R (&f)[Q9]) {
   if constexpr (A < Q9) {
     int32_t off;
     const bool bounce = pull_source<EX9[A], EY9[A], 0>(b, off);
     const S* base = fin + static_cast<int64_t>(pair_plane<A>()) * stride;
-    f[A] = Storage<S>::ld(elem<WIDE>(base, pull_offset<A>(bounce, off, n, static_cast<uint32_t>(stride))));
-    gather9<S, WIDE, A + 1>(fin, stride, n, b, f);
+    f[A] = Storage<S>::template ld<KEEP0 && A != 0>(
+        elem<WIDE>(base, pull_offset<A>(bounce, off, n, static_cast<uint32_t>(stride))));
+    gather9<S, WIDE, KEEP0, A + 1>(fin, stride, n, b, f);
   }
 }
 
-template <typename S, bool NT, bool WIDE>
+// KEEP0: the rest population's plane keeps cacheable stores under NT, so that
+// with the step's cacheable loads it stays in the last-level cache.
+template <typename S, bool NT, bool WIDE, bool KEEP0 = false>
 __device__ __forceinline__ void store9(S* __restrict__ fout, const GridArgs& g, uint32_t n,
                                        const typename Storage<S>::R (&f)[Q9]) {
-  store_planes<S, NT, WIDE, Q9>(fout, g, n, f);
+  store_planes<S, NT, WIDE, Q9, KEEP0>(fout, g, n, f);
 }
 
 // Anti-bounce-back at a wall in deviation form: d_a = -d~_opp(a).
@@ -156,8 +162,9 @@ __device__ __forceinline__ void collide_g5(R (&g)[2][Q5], const Coupled2<R>& cp,
   }
 }
 
-// SR: 16-bit stores with stochastic rounding (store_stochastic).
-template <typename S, bool CHECK, bool FIELD, bool NT, bool WIDE, bool SR>
+// SR: 16-bit stores with stochastic rounding (store_stochastic).  KEEP0:
+// streaming loads and stores except the rest population's (gather9, store9).
+template <typename S, bool CHECK, bool FIELD, bool NT, bool WIDE, bool SR, bool KEEP0 = false>
 __global__ __launch_bounds__(kBlock) void glbe2_step(GridArgs g, CollideArgs<typename Storage<S>::R> c,
                                                      const S* __restrict__ fin, S* __restrict__ fout,
                                                      const typename Storage<S>::R* __restrict__ force,
@@ -171,7 +178,7 @@ __global__ __launch_bounds__(kBlock) void glbe2_step(GridArgs g, CollideArgs<typ
   if (n < static_cast<uint32_t>(g.N)) {
     const Nbr b = neighbours(g, n);
     R f[Q9];
-    gather9<S, WIDE>(fin, g.stride, n, b, f);
+    gather9<S, WIDE, KEEP0>(fin, g.stride, n, b, f);
     R Fx, Fy;
     load_force2<R, WIDE>(g, c, force, FIELD, n, Fx, Fy);
     R uold[2];
@@ -180,7 +187,7 @@ __global__ __launch_bounds__(kBlock) void glbe2_step(GridArgs g, CollideArgs<typ
     if constexpr (SR)
       store_stochastic<S, NT, WIDE, Q9>(fout, g, n, f);
     else
-      store9<S, NT, WIDE>(fout, g, n, f);
+      store9<S, NT, WIDE, KEEP0>(fout, g, n, f);
     if constexpr (CHECK) check_node2<R, WIDE, NT>(g, usnap, n, uold, mac, acc);
   }
   if constexpr (CHECK) write_partials(partials, lb, acc);
@@ -297,7 +304,15 @@ hipError_t launch_glbe2_step(const GridArgs& g, const CollideArgs<typename Stora
               return hipGetLastError();
             }
           }
-          launch_step(glbe2_step<S, ch, fl, nts, w, false>, step_grid(g), g.lds_reserve, st,
+          // 4-byte storage at HBM scale with no force field: the rest plane stays in
+          // the last-level cache, the other planes stream (4096^2 FP32 step
+          // 197.1-197.5 -> 194.1-194.5 us; 16-bit storage measured 2% slower, and
+          // the FP64 rest planes do not fit)
+          if (nts && !fl && sizeof(S) == 4 && g.rest_cached)
+            launch_step(glbe2_step<S, ch, fl, nts, w, false, nts && !fl && sizeof(S) == 4>, step_grid(g),
+                        g.lds_reserve, st, g, c, a, b, F, usnap, partials);
+          else
+            launch_step(glbe2_step<S, ch, fl, nts, w, false>, step_grid(g), g.lds_reserve, st,
                         g, c, a, b, F, usnap, partials);
           return hipGetLastError();
         });

@@ -60,11 +60,11 @@ def _from_g(t, B0):
     return out + _rest_g((a.shape[3], a.shape[2]), B0)
 
 
-def _sim(shape, bc, gamma, s, storage, force, mhd=None):
+def _sim(shape, bc, gamma, s, storage, force, mhd=None, launch=None):
     import paper_0809_4730_amd as pkg
     nx, ny = shape
     return pkg.Simulation((nx, ny, 1), (bc[0], bc[1], PER), gamma, s, storage=storage, force=force,
-                          mhd=mhd, lattice="d2q9")
+                          mhd=mhd, lattice="d2q9", launch=launch)
 
 
 def _field_force(shape, seed, amp=1e-5):
@@ -288,3 +288,36 @@ def test_d2q9_4096_launch_shape_one_step_at_sampled_nodes():
     torch.cuda.empty_cache()
     ref = d.step_nodes(f0, F, gamma, s, bc, nodes)[_perm(9)]
     assert rel(got, ref) < 2e-6
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_d2q9_4096_rest_plane_kept_bitwise(storage):
+    """D2Q9 at 4096^2 with a uniform force (no field to keep in the last-level
+    cache, so with FP32 storage the rest population's plane keeps cacheable
+    loads and stores while the other planes stream; BF16 keeps its
+    streaming stores and cacheable loads): three steps from a seeded state bit
+    for bit equal to the same steps with every store cacheable.  The oracle
+    comparison of this launch shape is the FP32 sampled-node test above."""
+    import torch
+    announce("d2q9 4096^2 %s, rest plane cached" % storage)
+    nx = ny = 4096
+    bc, gamma = (PER, WALL), 0.1
+    s = d.rates(0.1, gamma)
+    tdt = torch.float32 if storage == "f32" else torch.bfloat16
+    rng = np.random.default_rng(73)
+    f0 = _to_f(1e-3 * rng.uniform(-1.0, 1.0, (9, ny, nx)), tdt)
+    outs = []
+    for launch in (None, dict(store="cached")):
+        sim = _sim((nx, ny), bc, gamma, s, storage, (1e-5, -2e-6, 0.0), launch=launch)
+        if launch is None:
+            assert sim.launch["store"] == "streaming"
+        sim.set_state(f0)
+        sim.step(1)
+        outs.append(sim.get_state())
+        sim.step(2)
+        outs.append(sim.get_state())
+        sim.close()
+        del sim
+    assert torch.equal(outs[0], outs[2]) and torch.equal(outs[1], outs[3])
+    del outs
+    torch.cuda.empty_cache()
