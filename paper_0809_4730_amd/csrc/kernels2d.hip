@@ -43,7 +43,8 @@ __device__ __forceinline__ void store9(S* __restrict__ fout, const GridArgs& g, 
 }
 
 // Anti-bounce-back at a wall in deviation form: d_a = -d~_opp(a).
-template <typename R, bool WIDE, int A = 0>
+// NTL: streaming loads.
+template <typename R, bool WIDE, bool NTL = false, int A = 0>
 __device__ __forceinline__ void gather_g5(const R* __restrict__ gin, int64_t stride, uint32_t n,
                                           const Nbr& b, R (&g)[2][Q5]) {
   if constexpr (A < Q5) {
@@ -52,10 +53,10 @@ __device__ __forceinline__ void gather_g5(const R* __restrict__ gin, int64_t str
     const uint32_t i = pull_offset<A>(bounce, off, n, static_cast<uint32_t>(stride));
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      const R v = *elem<WIDE>(gin + static_cast<int64_t>(j * Q5 + pair_plane<A>()) * stride, i);
+      const R v = ld_pop<NTL>(elem<WIDE>(gin + static_cast<int64_t>(j * Q5 + pair_plane<A>()) * stride, i));
       g[j][A] = bounce ? -v : v;
     }
-    gather_g5<R, WIDE, A + 1>(gin, stride, n, b, g);
+    gather_g5<R, WIDE, NTL, A + 1>(gin, stride, n, b, g);
   }
 }
 
@@ -193,7 +194,9 @@ __global__ __launch_bounds__(kBlock) void glbe2_step(GridArgs g, CollideArgs<typ
   if constexpr (CHECK) write_partials(partials, lb, acc);
 }
 
-template <typename R, bool CHECK, bool FIELD, bool WIDE, bool NT>
+// KEEP0: streaming loads and stores except the rest flow population's
+// (gather9, store9); the induction populations stream.
+template <typename R, bool CHECK, bool FIELD, bool WIDE, bool NT, bool KEEP0 = false>
 __global__ __launch_bounds__(kBlock) void mhd2_step(GridArgs g, CollideArgs<R> c, MagArgs<R> m,
                                                     const R* __restrict__ fin, R* __restrict__ fout,
                                                     const R* __restrict__ gin, R* __restrict__ gout,
@@ -207,9 +210,9 @@ __global__ __launch_bounds__(kBlock) void mhd2_step(GridArgs g, CollideArgs<R> c
   if (n < static_cast<uint32_t>(g.N)) {
     const Nbr b = neighbours(g, n);
     R f[Q9];
-    gather9<R, WIDE>(fin, g.stride, n, b, f);
+    gather9<R, WIDE, KEEP0>(fin, g.stride, n, b, f);
     R gg[2][Q5];
-    gather_g5<R, WIDE>(gin, g.stride, n, b, gg);
+    gather_g5<R, WIDE, KEEP0>(gin, g.stride, n, b, gg);
     R Fx, Fy;
     load_force2<R, WIDE>(g, c, force, FIELD, n, Fx, Fy);
     R uold[2];
@@ -217,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void mhd2_step(GridArgs g, CollideArgs<R> c
     const Coupled2<R> cp = lorentz_solve2<R>(f, gg, Fx, Fy, c, m);
     const NodeMacro<R> mac = collide9<R>(f, cp.Fx, cp.Fy, c);
     collide_g5<R>(gg, cp, mac.ux, mac.uy, m);
-    store9<R, NT, WIDE>(fout, g, n, f);
+    store9<R, NT, WIDE, KEEP0>(fout, g, n, f);
     R gflat[2 * Q5];
 #pragma unroll
     for (int j = 0; j < 2; ++j)
@@ -346,9 +349,15 @@ hipError_t launch_mhd2_step(const GridArgs& g, const CollideArgs<R>& c, const Ma
     return with_flag(field, [&](auto FL) {
       return with_flag(wide_offsets(g, sizeof(R)), [&](auto W) {
         return with_flag(nt, [&](auto NTF) {
-          launch_step(mhd2_step<R, decltype(CH)::value, decltype(FL)::value, decltype(W)::value,
-                    decltype(NTF)::value>, step_grid(g), g.lds_reserve, st,
+          constexpr bool keep = decltype(NTF)::value && !decltype(FL)::value && sizeof(R) == 4;
+          if (keep && g.rest_cached)
+            launch_step(mhd2_step<R, decltype(CH)::value, decltype(FL)::value, decltype(W)::value,
+                                  decltype(NTF)::value, keep>, step_grid(g), g.lds_reserve, st,
                         g, c, m, a, b, ga, gb, F, usnap, partials);
+          else
+            launch_step(mhd2_step<R, decltype(CH)::value, decltype(FL)::value, decltype(W)::value,
+                      decltype(NTF)::value>, step_grid(g), g.lds_reserve, st,
+                          g, c, m, a, b, ga, gb, F, usnap, partials);
           return hipGetLastError();
         });
       });

@@ -321,3 +321,30 @@ def test_d2q9_4096_rest_plane_kept_bitwise(storage):
     assert torch.equal(outs[0], outs[2]) and torch.equal(outs[1], outs[3])
     del outs
     torch.cuda.empty_cache()
+
+
+def test_coupled_d2q9_4096_rest_plane_kept_bitwise():
+    """The coupled D2Q9 + D2Q5 step at 4096^2, FP32, uniform force (the rest
+    flow population's plane keeps cacheable loads and stores, the other flow
+    planes and the induction planes stream): three steps bit for bit equal to
+    the same steps with every store cacheable (and so every load cacheable)."""
+    import torch
+
+    import paper_0809_4730_amd as pkg
+    announce("coupled d2q9 4096^2 f32, rest plane cached")
+    mhd = dict(gamma_m=0.4, chi=0.05, eta=0.03, B0=(0.01, 0.02))
+    states = []
+    for launch in (None, dict(store="cached")):
+        sim = pkg.Simulation((4096, 4096, 1), (PER, WALL, PER), 0.3, d.rates(0.05, 0.3),
+                             storage="f32", force=(1e-5, -2e-6), lattice="d2q9", launch=launch,
+                             mhd=mhd)
+        if launch is None:
+            assert sim.launch["store"] == "streaming"
+        sim.step(3)
+        f, g = sim.get_state()
+        states.append(torch.cat([f.reshape(-1), g.reshape(-1)]))
+        sim.close()
+        del sim
+    assert torch.equal(states[0], states[1]) and bool(states[0].abs().max() > 0)
+    del states
+    torch.cuda.empty_cache()
